@@ -1,0 +1,203 @@
+"""Serial-EMD CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+ctypes wrappers around ``semd_oracle.c``: a plain scalar FP64 implementation
+of Serial-EMD (arXiv 2106.15319, Sec. 2.1, 2.2, 3.2 and 3.3).  Only the tests,
+the smoke check and the CPU-baseline leg of the benchmark may import this
+module; the product path (the HIP library and its binding) never does.
+
+Every function takes and returns numpy float64 arrays on the host.  X is an
+M x N matrix whose columns are the signals (Sec. 3.2); it is passed as a
+column-major buffer, i.e. ``X.ravel(order="F")``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_DIR = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_DIR, "semd_oracle.c")
+_LIB = os.path.join(_DIR, "libsemd_oracle.so")
+
+_d = C.POINTER(C.c_double)
+_i64 = C.POINTER(C.c_int64)
+_int = C.POINTER(C.c_int)
+
+
+class Stats(C.Structure):
+    _fields_ = [("min_gap", C.c_double), ("n_sifts", C.c_int64), ("n_equal", C.c_int64)]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc: scalar FP64, no contraction, no fast-math."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+               "-shared", "-Wall", "-Wextra", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        L.semd_ref_serial_length.restype = C.c_int64
+        L.semd_ref_serial_length.argtypes = [C.c_int64] * 3
+        L.semd_ref_serialize.argtypes = [_d, C.c_int64, C.c_int64, C.c_int64, _d]
+        L.semd_ref_deserialize.argtypes = [_d, C.c_int64, C.c_int64, C.c_int64, _d]
+        L.semd_ref_extrema.argtypes = [_d, C.c_int64, _i64, _i64, _i64, _i64]
+        L.semd_ref_spline_solve.argtypes = [_d, _d, C.c_int64, _d]
+        L.semd_ref_spline_eval.argtypes = [_d, _d, _d, C.c_int64, C.c_int64, _d]
+        L.semd_ref_envelope.argtypes = [_d, C.c_int64, _i64, C.c_int64, _d]
+        L.semd_ref_emd.argtypes = [_d, C.c_int64, C.c_int, C.c_int, _d, _int, C.POINTER(Stats)]
+        L.semd_ref_decompose.argtypes = [_d, C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_int,
+                                         _d, _int, C.POINTER(Stats)]
+        L.semd_ref_decompose_slices.argtypes = [_d, C.c_int64, C.c_int64, C.c_int, C.c_int,
+                                                _d, _int]
+        L.semd_ref_splitmix64.restype = C.c_uint64
+        L.semd_ref_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
+        L.semd_ref_noise.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.c_int64, _d]
+        L.semd_ref_eemd.argtypes = [_d, C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_int,
+                                    C.c_int, C.c_double, C.c_uint64, C.c_uint64, _d]
+        for name in ("semd_ref_serialize", "semd_ref_deserialize", "semd_ref_extrema",
+                     "semd_ref_spline_solve", "semd_ref_spline_eval", "semd_ref_envelope",
+                     "semd_ref_emd", "semd_ref_decompose", "semd_ref_decompose_slices",
+                     "semd_ref_noise", "semd_ref_eemd"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(_d)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise ValueError(f"oracle {what} failed with code {rc}")
+
+
+def serial_length(M: int, N: int, D: int) -> int:
+    return int(lib().semd_ref_serial_length(M, N, D))
+
+
+def serialize(Xcol: np.ndarray, M: int, N: int, D: int) -> np.ndarray:
+    """Sec. 3.2: column-major X (M*N) -> serialized x (M*N + D*N - D)."""
+    X = _f64(Xcol)
+    x = np.empty(serial_length(M, N, D))
+    _check(lib().semd_ref_serialize(_p(X), M, N, D, _p(x)), "serialize")
+    return x
+
+
+def deserialize(y: np.ndarray, M: int, N: int, D: int) -> np.ndarray:
+    """Sec. 3.3: serialized y -> column-major M*N (transition samples dropped)."""
+    y = _f64(y)
+    out = np.empty(M * N)
+    _check(lib().semd_ref_deserialize(_p(y), M, N, D, _p(out)), "deserialize")
+    return out
+
+
+def extrema(h: np.ndarray):
+    """Sec. 2.1 Step 1: sorted maxima and minima index arrays."""
+    h = _f64(h)
+    L = h.size
+    imax = np.empty(L // 2 + 2, dtype=np.int64)
+    imin = np.empty(L // 2 + 2, dtype=np.int64)
+    na, ni = C.c_int64(), C.c_int64()
+    _check(lib().semd_ref_extrema(_p(h), L, imax.ctypes.data_as(_i64), C.byref(na),
+                                  imin.ctypes.data_as(_i64), C.byref(ni)), "extrema")
+    return imax[: na.value].copy(), imin[: ni.value].copy()
+
+
+def spline_solve(t, y) -> np.ndarray:
+    t, y = _f64(t), _f64(y)
+    Mpp = np.empty(t.size)
+    _check(lib().semd_ref_spline_solve(_p(t), _p(y), t.size, _p(Mpp)), "spline_solve")
+    return Mpp
+
+
+def spline_eval(t, y, Mpp, L: int) -> np.ndarray:
+    t, y, Mpp = _f64(t), _f64(y), _f64(Mpp)
+    out = np.empty(L)
+    _check(lib().semd_ref_spline_eval(_p(t), _p(y), _p(Mpp), t.size, L, _p(out)), "spline_eval")
+    return out
+
+
+def envelope(h, idx) -> np.ndarray:
+    """Sec. 2.1 Step 2: mirrored natural-spline envelope through h[idx]."""
+    h = _f64(h)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    env = np.empty(h.size)
+    _check(lib().semd_ref_envelope(_p(h), h.size, idx.ctypes.data_as(_i64), idx.size, _p(env)),
+           "envelope")
+    return env
+
+
+def emd(x, K: int, S: int, with_stats: bool = False):
+    """Sec. 2.1: (K+1, L) slots (IMFs, zero fill, residue in slot K) and n_imfs."""
+    x = _f64(x)
+    L = x.size
+    out = np.empty((K + 1) * L)
+    n = C.c_int()
+    st = Stats()
+    _check(lib().semd_ref_emd(_p(x), L, K, S, _p(out), C.byref(n), C.byref(st)), "emd")
+    res = (out.reshape(K + 1, L), n.value)
+    if with_stats:
+        return res + ({"min_gap": st.min_gap, "n_sifts": st.n_sifts, "n_equal": st.n_equal},)
+    return res
+
+
+def decompose(Xcol, M: int, N: int, D: int, K: int, S: int, with_stats: bool = False):
+    """Serial-EMD (Sec. 3): (K+1, M*N) column-major slots and n_imfs."""
+    X = _f64(Xcol)
+    out = np.empty((K + 1) * M * N)
+    n = C.c_int()
+    st = Stats()
+    _check(lib().semd_ref_decompose(_p(X), M, N, D, K, S, _p(out), C.byref(n), C.byref(st)),
+           "decompose")
+    res = (out.reshape(K + 1, M * N), n.value)
+    if with_stats:
+        return res + ({"min_gap": st.min_gap, "n_sifts": st.n_sifts, "n_equal": st.n_equal},)
+    return res
+
+
+def decompose_slices(Xcol, M: int, N: int, K: int, S: int):
+    """Standard-version EMD: each column on its own.  ((K+1, M*N), n_imfs[N])."""
+    X = _f64(Xcol)
+    out = np.empty((K + 1) * M * N)
+    n = np.empty(N, dtype=np.int32)
+    _check(lib().semd_ref_decompose_slices(_p(X), M, N, K, S, _p(out),
+                                           n.ctypes.data_as(_int)), "decompose_slices")
+    return out.reshape(K + 1, M * N), n
+
+
+def splitmix64(state: int, n: int) -> int:
+    return int(lib().semd_ref_splitmix64(state & (2**64 - 1), n & (2**64 - 1)))
+
+
+def noise(seed: int, item: int, m: int, L: int) -> np.ndarray:
+    w = np.empty(L)
+    _check(lib().semd_ref_noise(seed, item, m, L, _p(w)), "noise")
+    return w
+
+
+def eemd(Xcol, M: int, N: int, D: int, K: int, S: int, NR: int, beta: float, seed: int,
+         item: int = 0) -> np.ndarray:
+    """Sec. 2.2 EEMD of the serialized signal: (K+1, M*N) mean slots."""
+    X = _f64(Xcol)
+    out = np.empty((K + 1) * M * N)
+    _check(lib().semd_ref_eemd(_p(X), M, N, D, K, S, NR, float(beta), seed, item, _p(out)),
+           "eemd")
+    return out.reshape(K + 1, M * N)

@@ -1,0 +1,97 @@
+/*
+ * Serial-EMD CPU oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, scalar FP64 implementation of what the Serial-EMD hot path
+ * computes (Zhang et al., "Serial-EMD: Fast Empirical Mode Decomposition Method
+ * for Multi-dimensional Signals Based on Serialization", arXiv 2106.15319).
+ * It is the parity authority for the HIP library and is used only by the
+ * tests, the smoke check and the CPU-baseline leg of the benchmark.  It shares
+ * no code with the HIP library (no header, helper, table or generator).
+ *
+ * All pointers are host memory.  All arrays are plain C arrays of doubles
+ * (or int64 for indices).  Functions return 0 on success, a negative value on
+ * invalid arguments.  Nothing here allocates memory it does not free.
+ *
+ * Layout: X is M x N column-major (fibre i = column i, element (m,i) at m+M*i),
+ * as in Sec. 3.2 (the signals are the columns of X).
+ */
+#ifndef SEMD_ORACLE_H
+#define SEMD_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Sec. 3.2, final truncation: length of the serialized signal, M*N + D*N - D. */
+int64_t semd_ref_serial_length(int64_t M, int64_t N, int64_t D);
+
+/* Sec. 3.2 (vector a, sub-matrices X_A and X_B, transitions E, block matrix T,
+ * vec(T), truncation).  X: M*N doubles; x: serial_length doubles. */
+int semd_ref_serialize(const double* X, int64_t M, int64_t N, int64_t D, double* x);
+
+/* Sec. 3.3 (append D zeros, reshape to (M+D) x N, keep rows 1..M).
+ * y: serial_length doubles; out: M*N doubles. */
+int semd_ref_deserialize(const double* y, int64_t M, int64_t N, int64_t D, double* out);
+
+/* Sec. 2.1 Step 1: local maxima / minima of h (plateau-middle rule, endpoints
+ * excluded).  Index lists are written in increasing order; imax and imin must
+ * hold at least L/2+1 entries each. */
+int semd_ref_extrema(const double* h, int64_t L, int64_t* imax, int64_t* nmax,
+                     int64_t* imin, int64_t* nmin);
+
+/* Natural cubic spline through (t[j], y[j]), j<n, n>=3, t strictly increasing:
+ * second derivatives Mpp[j] (Mpp[0] = Mpp[n-1] = 0) by the Thomas algorithm. */
+int semd_ref_spline_solve(const double* t, const double* y, int64_t n, double* Mpp);
+
+/* Evaluate that spline at the integers k = 0..L-1 (t[0] < 0 <= L-1 < t[n-1]). */
+int semd_ref_spline_eval(const double* t, const double* y, const double* Mpp,
+                         int64_t n, int64_t L, double* out);
+
+/* Sec. 2.1 Step 2: envelope of h through the extrema idx[0..n-1] (n>=1), with
+ * min(2,n) mirrored knots per end; env: L doubles. */
+int semd_ref_envelope(const double* h, int64_t L, const int64_t* idx, int64_t n, double* env);
+
+/* Decision statistics of one decomposition, for the tie-aware comparison. */
+typedef struct {
+  double min_gap;      /* min |h[k+1]-h[k]| over every adjacent unequal pair   */
+                       /* seen by an extremum test after the very first one   */
+  int64_t n_sifts;     /* sifts performed                                      */
+  int64_t n_equal;     /* adjacent equal pairs seen after the first test       */
+} semd_ref_stats;
+
+/* Sec. 2.1 Steps 1-5 with a fixed number S of sifts per IMF and at most K IMFs.
+ * imfs: (K+1)*L doubles; slot k < *n_imfs = IMF k, slots *n_imfs..K-1 = 0,
+ * slot K = residue.  stats may be NULL. */
+int semd_ref_emd(const double* x, int64_t L, int K, int S, double* imfs, int* n_imfs,
+                 semd_ref_stats* stats);
+
+/* Serial-EMD: serialize (Sec. 3.2), EMD (Sec. 2.1), deserialize (Sec. 3.3).
+ * out: (K+1)*M*N doubles in the same slot convention. */
+int semd_ref_decompose(const double* X, int64_t M, int64_t N, int64_t D, int K, int S,
+                       double* out, int* n_imfs, semd_ref_stats* stats);
+
+/* Standard-version (slice-wise) EMD: every column of X decomposed on its own,
+ * no serialization (Sec. 4 opening).  out: (K+1)*M*N; n_imfs: N ints. */
+int semd_ref_decompose_slices(const double* X, int64_t M, int64_t N, int K, int S,
+                              double* out, int* n_imfs);
+
+/* SplitMix64 (Steele, Lea & Flood 2014): the n-th output (n >= 1) of the
+ * generator whose state starts at `state`. */
+uint64_t semd_ref_splitmix64(uint64_t state, uint64_t n);
+
+/* White noise for EEMD realization m of item `item`: L samples, each the
+ * Irwin-Hall sum of 12 uniforms minus 6 (zero mean, unit variance). */
+int semd_ref_noise(uint64_t seed, uint64_t item, uint64_t m, int64_t L, double* w);
+
+/* Sec. 2.2 EEMD on the serialized signal: x_m = x + beta*w_m for m < NR,
+ * EMD of each, slot-wise mean over m (zero slots included).  beta is absolute.
+ * out: (K+1)*M*N doubles (mean IMFs, mean residue in slot K). */
+int semd_ref_eemd(const double* X, int64_t M, int64_t N, int64_t D, int K, int S, int NR,
+                  double beta, uint64_t seed, uint64_t item, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
