@@ -1,0 +1,164 @@
+/*
+ * semd.h -- C ABI of the MI355X (gfx950) Serial-EMD library, libsemd.so.
+ *
+ * Serial-EMD (Zhang et al., arXiv 2106.15319) decomposes a set of N equally
+ * long signals -- the columns of an M x N matrix X (Sec. 3.2) -- by
+ * serializing them into one 1D signal of length L = M*N + D*N - D with linear
+ * cross-fade transitions of length D between neighbouring columns (Sec. 3.2),
+ * running 1D EMD on it (Sec. 2.1; EEMD, Sec. 2.2) and slicing the IMFs back to
+ * M x N by dropping the transition samples (Sec. 3.3).
+ *
+ * Conventions shared by every call:
+ *  - Arrays are FP64.  Device pointers point to HIP device memory of the
+ *    current device; [host] marks host memory.
+ *  - X is column-major: element (m, i) at m + M*i, column i = signal i.  With
+ *    ndim > 2, dims[1..ndim-1] are flattened column-major into N.
+ *  - Output slots: imfs_out holds (max_imfs + 1) slots of M*N doubles each.
+ *    Slot k < n_imfs is IMF k (k = 0 is the highest-frequency mode), slots
+ *    n_imfs .. max_imfs-1 are zero (the zero-fill convention of Sec. 4.3) and
+ *    slot max_imfs is the residue r of eq. (1), so sum of all slots = X.
+ *  - Sifting: sift_iters (S) sifts per IMF; an IMF ends early when its
+ *    candidate has no maximum, no minimum or fewer than 3 extrema; the
+ *    decomposition stops when the residue is in that state or max_imfs IMFs
+ *    exist (the paper leaves the stopping rule open, Sec. 2.1 Step 5).
+ *  - Envelopes: natural cubic splines through the extrema (one per equal-valued
+ *    run, at its floor-middle; end samples excluded) plus min(2, n) knots
+ *    mirrored about each end sample (boundary_rule SEMD_BOUNDARY_MIRROR).
+ *  - Every call validates its arguments on the host first; on an invalid
+ *    argument it returns SEMD_EINVAL, records a message for semd_last_error()
+ *    and enqueues nothing.  Work is enqueued on `stream` and the call returns
+ *    without waiting for it; a launch failure returns SEMD_EDEVICE.
+ *  - Input containing NaN or Inf is not decomposed: its n_imfs entry is set to
+ *    -SEMD_ENONFINITE and all of its slots to zero.
+ *  - The library never writes to the input and never frees caller memory.
+ *    Outputs must not overlap inputs.  Calls that overlap on one stream are
+ *    ordered; on different streams they are independent.
+ */
+#ifndef SEMD_H
+#define SEMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SEMD_ABI_VERSION 1
+
+typedef enum {
+  SEMD_OK = 0,
+  SEMD_EINVAL = 1,       /* invalid argument; nothing enqueued             */
+  SEMD_ENOMEM = 2,       /* a device or pinned allocation failed           */
+  SEMD_EDEVICE = 3,      /* a HIP call or kernel launch failed             */
+  SEMD_EBUSY = 4,        /* serving engine: request exceeds free budget    */
+  SEMD_ENONFINITE = 5,   /* input holds NaN/Inf (reported via n_imfs)      */
+  SEMD_EUNSUPPORTED = 6  /* valid request this build cannot run            */
+} semd_status;
+
+typedef enum { SEMD_BOUNDARY_MIRROR = 0 } semd_boundary;
+
+/* Method parameters.  transition_len is D of Sec. 3.2 (0 <= D <= M);
+ * max_imfs is K >= 1; sift_iters is S >= 1; ensemble is the number NR >= 1 of
+ * EEMD realizations (Sec. 2.2, used by semd_eemd_batch only); seed keys the
+ * EEMD noise. */
+typedef struct {
+  int32_t transition_len;
+  int32_t max_imfs;
+  int32_t sift_iters;
+  int32_t boundary_rule;
+  int32_t ensemble;
+  int32_t reserved; /* must be 0 */
+  uint64_t seed;
+} semd_params;
+
+/* One signal of a batch.  signal: device, M*N doubles (M = dims[0], N =
+ * product of dims[1..ndim-1]); imfs_out: device, (K+1)*M*N doubles;
+ * n_imfs_out: device, one int32, or NULL.  noise_sigma is the absolute EEMD
+ * noise amplitude beta of Sec. 2.2 (semd_eemd_batch only), item_id selects the
+ * item's noise streams. */
+typedef struct {
+  const double* signal;
+  double* imfs_out;
+  int32_t* n_imfs_out;
+  int64_t dims[4];
+  int32_t ndim;
+  int32_t reserved; /* must be 0 */
+  double noise_sigma;
+  uint64_t item_id;
+} semd_item;
+
+/* ---- information ------------------------------------------------------- */
+
+/* ABI version (SEMD_ABI_VERSION). */
+int semd_abi_version(void);
+
+/* Message of the last failed call on this host thread ("" if none). */
+const char* semd_last_error(void);
+
+/* Sec. 3.2: serialized length M*N + D*N - D, or -1 if M < 1, N < 1 or D is
+ * outside [0, M]. */
+int64_t semd_serial_length(int64_t M, int64_t N, int64_t D);
+
+/* Longest serialized signal the single-workgroup on-chip path takes (longer
+ * signals go to the multi-workgroup streaming path). */
+int64_t semd_resident_max_length(void);
+
+/* ---- the method --------------------------------------------------------- */
+
+/* Serial-EMD of one signal (Sec. 3): serialize, EMD, deserialize.  D is the
+ * paper's recommended 20% of the signal length, round(0.2*M) (Sec. 4.1); no
+ * ensemble.  dims: [host], ndim >= 1 entries. */
+int semd_decompose(const double* signal, const int64_t* dims, int ndim, int max_imfs,
+                   int sift_iters, int boundary_rule, double* imfs_out, hipStream_t stream);
+
+/* Serial-EMD of one signal with explicit parameters (p->ensemble is ignored),
+ * launched on its own: the plain one-signal-per-launch path.  n_imfs_out:
+ * device int32 or NULL.  p: [host]. */
+int semd_decompose_ex(const double* signal, const int64_t* dims, int ndim,
+                      const semd_params* p, double* imfs_out, int32_t* n_imfs_out,
+                      hipStream_t stream);
+
+/* Serial-EMD of n independent signals of any shapes in one batched launch
+ * (p->ensemble ignored).  items, p: [host]; the items array may be reused as
+ * soon as the call returns. */
+int semd_decompose_batch(const semd_item* items, int n, const semd_params* p,
+                         hipStream_t stream);
+
+/* Serial-EEMD (Sec. 2.2 applied to the serialized signal, Sec. 3.3): for each
+ * item, NR = p->ensemble realizations x + beta*w_m (beta = item noise_sigma,
+ * w_m white noise with zero mean and unit variance drawn from SplitMix64
+ * streams keyed by (p->seed, item_id, m)), each decomposed by EMD, and the
+ * slot-wise mean over m written to imfs_out (zero-filled slots included).
+ * n_imfs_out receives the largest IMF count over the realizations. */
+int semd_eemd_batch(const semd_item* items, int n, const semd_params* p, hipStream_t stream);
+
+/* ---- single steps (each runs the kernels of the full path) -------------- */
+
+/* Sec. 3.2: x (device, L doubles) = serialization of X with transition D. */
+int semd_serialize(const double* X, const int64_t* dims, int ndim, int D, double* x,
+                   hipStream_t stream);
+
+/* Sec. 3.3: out (device, M*N doubles) = y (device, L doubles) with the
+ * transition samples removed. */
+int semd_deserialize(const double* y, const int64_t* dims, int ndim, int D, double* out,
+                     hipStream_t stream);
+
+/* Sec. 2.1 Step 1 on a 1D signal h (device, L doubles, 3 <= L <=
+ * semd_resident_max_length()): imax / imin (device, each L/2+1 int32) receive
+ * the maxima / minima indices in increasing order, counts (device, 2 int32)
+ * their numbers. */
+int semd_extrema(const double* h, int64_t L, int32_t* imax, int32_t* imin, int32_t* counts,
+                 hipStream_t stream);
+
+/* Sec. 2.2 Step 1 noise: w (device, L doubles) = the white-noise stream of
+ * realization m of item `item` under `seed`, as used by semd_eemd_batch. */
+int semd_noise(uint64_t seed, uint64_t item, uint64_t m, int64_t L, double* w,
+               hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SEMD_H */

@@ -1,0 +1,292 @@
+"""Python binding of libsemd (Serial-EMD on MI355X).
+
+Thin ctypes marshalling over the C ABI declared in ``include/semd.h``: every
+function below has the name of the C entry point it calls, takes torch tensors
+that live on the current HIP device, passes their device pointers and the
+current torch stream, and raises ``SemdError`` on a non-zero status.  All the
+arithmetic runs in the library's HIP kernels; there is no fallback.
+
+Layout: a set of N signals of length M is an M x N column-major matrix, i.e.
+a 1D float64 tensor whose element (m, i) sits at m + M*i (Sec. 3.2 of the
+paper).  A (C, L) row-major batch of channels is exactly that with M = L,
+N = C; an (H, W) row-major image is passed as ``img.t().contiguous()`` with
+M = H, N = W, so that its columns are the signals.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Sequence
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "_lib", "libsemd.so")
+
+SEMD_OK = 0
+SEMD_EINVAL = 1
+SEMD_ENOMEM = 2
+SEMD_EDEVICE = 3
+SEMD_EBUSY = 4
+SEMD_ENONFINITE = 5
+SEMD_EUNSUPPORTED = 6
+SEMD_BOUNDARY_MIRROR = 0
+
+
+class SemdError(RuntimeError):
+    def __init__(self, code: int, what: str, msg: str):
+        super().__init__(f"{what} failed with status {code}: {msg}")
+        self.code = code
+
+
+class semd_params(C.Structure):
+    _fields_ = [("transition_len", C.c_int32), ("max_imfs", C.c_int32),
+                ("sift_iters", C.c_int32), ("boundary_rule", C.c_int32),
+                ("ensemble", C.c_int32), ("reserved", C.c_int32), ("seed", C.c_uint64)]
+
+
+class semd_item(C.Structure):
+    _fields_ = [("signal", C.c_void_p), ("imfs_out", C.c_void_p), ("n_imfs_out", C.c_void_p),
+                ("dims", C.c_int64 * 4), ("ndim", C.c_int32), ("reserved", C.c_int32),
+                ("noise_sigma", C.c_double), ("item_id", C.c_uint64)]
+
+
+_EXPORTS = {
+    # name: (restype, argtypes)
+    "semd_abi_version": (C.c_int, []),
+    "semd_last_error": (C.c_char_p, []),
+    "semd_serial_length": (C.c_int64, [C.c_int64, C.c_int64, C.c_int64]),
+    "semd_resident_max_length": (C.c_int64, []),
+    "semd_decompose": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_int, C.c_int, C.c_int,
+                                 C.c_int, C.c_void_p, C.c_void_p]),
+    "semd_decompose_ex": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_int,
+                                    C.POINTER(semd_params), C.c_void_p, C.c_void_p,
+                                    C.c_void_p]),
+    "semd_decompose_batch": (C.c_int, [C.POINTER(semd_item), C.c_int, C.POINTER(semd_params),
+                                       C.c_void_p]),
+    "semd_eemd_batch": (C.c_int, [C.POINTER(semd_item), C.c_int, C.POINTER(semd_params),
+                                  C.c_void_p]),
+    "semd_serialize": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_int, C.c_int,
+                                 C.c_void_p, C.c_void_p]),
+    "semd_deserialize": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_int, C.c_int,
+                                   C.c_void_p, C.c_void_p]),
+    "semd_extrema": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_void_p]),
+    "semd_noise": (C.c_int, [C.c_uint64, C.c_uint64, C.c_uint64, C.c_int64, C.c_void_p,
+                             C.c_void_p]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libsemd.so (built in-tree by ``paper_2106_15319_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libsemd.so is not built ({LIB_PATH}); run "
+                              "`python -m paper_2106_15319_amd.build` first")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _EXPORTS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_names() -> list[str]:
+    return list(_EXPORTS)
+
+
+def _check(rc: int, what: str):
+    if rc != SEMD_OK:
+        raise SemdError(rc, what, lib().semd_last_error().decode())
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _dev_f64(t: torch.Tensor, name: str) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a tensor on the HIP device")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 tensor")
+    return t.data_ptr()
+
+
+def _dims(dims: Sequence[int]):
+    arr = (C.c_int64 * len(dims))(*[int(d) for d in dims])
+    return arr, len(dims)
+
+
+def _params(D: int, K: int, S: int, NR: int = 1, seed: int = 0,
+            boundary_rule: int = SEMD_BOUNDARY_MIRROR) -> semd_params:
+    return semd_params(int(D), int(K), int(S), int(boundary_rule), int(NR), 0,
+                       int(seed) & (2**64 - 1))
+
+
+# ---------------------------------------------------------------------------
+# entry points (same names as the C ABI)
+# ---------------------------------------------------------------------------
+
+def semd_abi_version() -> int:
+    return int(lib().semd_abi_version())
+
+
+def semd_serial_length(M: int, N: int, D: int) -> int:
+    return int(lib().semd_serial_length(M, N, D))
+
+
+def semd_resident_max_length() -> int:
+    return int(lib().semd_resident_max_length())
+
+
+def semd_decompose(signal: torch.Tensor, dims: Sequence[int], max_imfs: int, sift_iters: int,
+                   boundary_rule: int = SEMD_BOUNDARY_MIRROR, imfs_out: torch.Tensor | None = None,
+                   stream=None) -> torch.Tensor:
+    """Serial-EMD with D = round(0.2 M); returns imfs_out ((K+1) x M*N)."""
+    d, nd = _dims(dims)
+    MN = 1
+    for v in dims:
+        MN *= int(v)
+    if imfs_out is None:
+        imfs_out = torch.empty((max_imfs + 1, MN), dtype=torch.float64, device=signal.device)
+    _check(lib().semd_decompose(_dev_f64(signal, "signal"), d, nd, max_imfs, sift_iters,
+                                boundary_rule, _dev_f64(imfs_out, "imfs_out"), _stream(stream)),
+           "semd_decompose")
+    return imfs_out
+
+
+def semd_decompose_ex(signal: torch.Tensor, dims: Sequence[int], D: int, max_imfs: int,
+                      sift_iters: int, imfs_out: torch.Tensor | None = None,
+                      n_imfs_out: torch.Tensor | None = None, stream=None):
+    """Plain path: one signal per launch.  Returns (imfs_out, n_imfs_out)."""
+    d, nd = _dims(dims)
+    MN = 1
+    for v in dims:
+        MN *= int(v)
+    dev = signal.device
+    if imfs_out is None:
+        imfs_out = torch.empty((max_imfs + 1, MN), dtype=torch.float64, device=dev)
+    if n_imfs_out is None:
+        n_imfs_out = torch.empty(1, dtype=torch.int32, device=dev)
+    p = _params(D, max_imfs, sift_iters)
+    _check(lib().semd_decompose_ex(_dev_f64(signal, "signal"), d, nd, C.byref(p),
+                                   _dev_f64(imfs_out, "imfs_out"), n_imfs_out.data_ptr(),
+                                   _stream(stream)), "semd_decompose_ex")
+    return imfs_out, n_imfs_out
+
+
+def _items(signals, dims_list, outs, counts, sigmas=None, item_ids=None):
+    n = len(signals)
+    arr = (semd_item * max(n, 1))()
+    for i in range(n):
+        it = arr[i]
+        it.signal = _dev_f64(signals[i], f"signals[{i}]")
+        it.imfs_out = _dev_f64(outs[i], f"imfs_out[{i}]")
+        it.n_imfs_out = counts[i].data_ptr() if counts is not None else None
+        dims = list(dims_list[i])
+        if not 1 <= len(dims) <= 4:
+            raise ValueError("dims must have 1..4 entries")
+        for k, v in enumerate(dims):
+            it.dims[k] = int(v)
+        it.ndim = len(dims)
+        it.reserved = 0
+        it.noise_sigma = float(sigmas[i]) if sigmas is not None else 0.0
+        it.item_id = int(item_ids[i]) if item_ids is not None else i
+    return arr, n
+
+
+def semd_decompose_batch(signals: Sequence[torch.Tensor], dims_list: Sequence[Sequence[int]],
+                         outs: Sequence[torch.Tensor], counts: torch.Tensor | None, D: int,
+                         max_imfs: int, sift_iters: int, stream=None) -> None:
+    """Batched path: every signal in one launch.  counts: int32 tensor of
+    len(signals) entries (or None)."""
+    cviews = [counts[i:i + 1] for i in range(len(signals))] if counts is not None else None
+    arr, n = _items(signals, dims_list, outs, cviews)
+    p = _params(D, max_imfs, sift_iters)
+    _check(lib().semd_decompose_batch(arr, n, C.byref(p), _stream(stream)),
+           "semd_decompose_batch")
+
+
+def semd_eemd_batch(signals: Sequence[torch.Tensor], dims_list: Sequence[Sequence[int]],
+                    outs: Sequence[torch.Tensor], counts: torch.Tensor | None, D: int,
+                    max_imfs: int, sift_iters: int, ensemble: int, seed: int,
+                    noise_sigmas: Sequence[float], item_ids: Sequence[int] | None = None,
+                    stream=None) -> None:
+    """Serial-EEMD of every signal (NR = ensemble realizations each)."""
+    cviews = [counts[i:i + 1] for i in range(len(signals))] if counts is not None else None
+    arr, n = _items(signals, dims_list, outs, cviews, noise_sigmas, item_ids)
+    p = _params(D, max_imfs, sift_iters, ensemble, seed)
+    _check(lib().semd_eemd_batch(arr, n, C.byref(p), _stream(stream)), "semd_eemd_batch")
+
+
+def semd_serialize(X: torch.Tensor, dims: Sequence[int], D: int, x: torch.Tensor | None = None,
+                   stream=None) -> torch.Tensor:
+    d, nd = _dims(dims)
+    M = int(dims[0])
+    N = X.numel() // M
+    if x is None:
+        x = torch.empty(M * N + D * N - D, dtype=torch.float64, device=X.device)
+    _check(lib().semd_serialize(_dev_f64(X, "X"), d, nd, int(D), _dev_f64(x, "x"),
+                                _stream(stream)), "semd_serialize")
+    return x
+
+
+def semd_deserialize(y: torch.Tensor, dims: Sequence[int], D: int,
+                     out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    d, nd = _dims(dims)
+    MN = 1
+    for v in dims:
+        MN *= int(v)
+    if out is None:
+        out = torch.empty(MN, dtype=torch.float64, device=y.device)
+    _check(lib().semd_deserialize(_dev_f64(y, "y"), d, nd, int(D), _dev_f64(out, "out"),
+                                  _stream(stream)), "semd_deserialize")
+    return out
+
+
+def semd_extrema(h: torch.Tensor, stream=None):
+    """(maxima indices, minima indices) of a 1D device signal, as int32 tensors."""
+    L = h.numel()
+    imax = torch.empty(L // 2 + 1, dtype=torch.int32, device=h.device)
+    imin = torch.empty(L // 2 + 1, dtype=torch.int32, device=h.device)
+    counts = torch.empty(2, dtype=torch.int32, device=h.device)
+    _check(lib().semd_extrema(_dev_f64(h, "h"), L, imax.data_ptr(), imin.data_ptr(),
+                              counts.data_ptr(), _stream(stream)), "semd_extrema")
+    c = counts.cpu()
+    return imax[: int(c[0])], imin[: int(c[1])]
+
+
+def semd_noise(seed: int, item: int, m: int, L: int, w: torch.Tensor | None = None,
+               device="cuda", stream=None) -> torch.Tensor:
+    if w is None:
+        w = torch.empty(L, dtype=torch.float64, device=device)
+    _check(lib().semd_noise(int(seed) & (2**64 - 1), int(item), int(m), int(L),
+                            _dev_f64(w, "w"), _stream(stream)), "semd_noise")
+    return w
+
+
+# ---------------------------------------------------------------------------
+# conveniences
+# ---------------------------------------------------------------------------
+
+def decompose(X: torch.Tensor, M: int, N: int, D: int, K: int, S: int, stream=None):
+    """Serial-EMD of one column-major M x N signal set (plain path)."""
+    return semd_decompose_ex(X, [M, N], D, K, S, stream=stream)
+
+
+def decompose_batch(Xs: Sequence[torch.Tensor], shapes: Sequence[tuple[int, int]], D: int, K: int,
+                    S: int, stream=None):
+    """Serial-EMD of many signal sets in one launch; returns (outs, counts)."""
+    dev = Xs[0].device
+    outs = [torch.empty((K + 1, M * N), dtype=torch.float64, device=dev) for (M, N) in shapes]
+    counts = torch.empty(len(Xs), dtype=torch.int32, device=dev)
+    semd_decompose_batch(Xs, [list(s) for s in shapes], outs, counts, D, K, S, stream=stream)
+    return outs, counts

@@ -1,0 +1,378 @@
+// C ABI of libsemd (declared in include/semd.h): argument validation, work
+// descriptors, stream-ordered workspaces and kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "semd.h"
+#include "semd_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(SEMD_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define SEMD_HIP(call, what)                      \
+  do {                                            \
+    hipError_t e_ = (call);                       \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+// (M, N) from column-major dims: M = dims[0], N = product of the rest.
+int parse_dims(const int64_t* dims, int ndim, int64_t* M, int64_t* N) {
+  if (!dims) return fail(SEMD_EINVAL, "dims is NULL");
+  if (ndim < 1 || ndim > 4) return fail(SEMD_EINVAL, "ndim must be in [1, 4], got %d", ndim);
+  int64_t n = 1;
+  for (int d = 0; d < ndim; ++d) {
+    if (dims[d] < 1) return fail(SEMD_EINVAL, "dims[%d] = %lld < 1", d, (long long)dims[d]);
+    if (d > 0) {
+      if (n > (int64_t(1) << 40) / dims[d]) return fail(SEMD_EINVAL, "signal too large");
+      n *= dims[d];
+    }
+  }
+  *M = dims[0];
+  *N = n;
+  return SEMD_OK;
+}
+
+int check_params(const semd_params* p, bool ensemble) {
+  if (!p) return fail(SEMD_EINVAL, "params is NULL");
+  if (p->max_imfs < 1) return fail(SEMD_EINVAL, "max_imfs must be >= 1");
+  if (p->max_imfs > 64) return fail(SEMD_EINVAL, "max_imfs must be <= 64");
+  if (p->sift_iters < 1) return fail(SEMD_EINVAL, "sift_iters must be >= 1");
+  if (p->boundary_rule != SEMD_BOUNDARY_MIRROR)
+    return fail(SEMD_EINVAL, "unknown boundary_rule %d", p->boundary_rule);
+  if (p->transition_len < 0) return fail(SEMD_EINVAL, "transition_len must be >= 0");
+  if (p->reserved != 0) return fail(SEMD_EINVAL, "params.reserved must be 0");
+  if (ensemble && p->ensemble < 1) return fail(SEMD_EINVAL, "ensemble must be >= 1");
+  return SEMD_OK;
+}
+
+// Pinned staging blocks for host -> device descriptor uploads; a block is
+// reused once the copy recorded on it has completed.
+struct PinnedBlock {
+  void* host = nullptr;
+  size_t bytes = 0;
+  hipEvent_t ev = nullptr;
+};
+std::mutex g_pool_mu;
+std::vector<std::unique_ptr<PinnedBlock>> g_pool;
+
+int upload(const void* src, size_t bytes, hipStream_t s, void** d_out) {
+  PinnedBlock* blk = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    for (auto& b : g_pool)
+      if (b->bytes >= bytes && hipEventQuery(b->ev) == hipSuccess) { blk = b.get(); break; }
+    if (!blk) {
+      auto nb = std::make_unique<PinnedBlock>();
+      nb->bytes = std::max<size_t>(bytes, 64 * 1024);
+      if (hipHostMalloc(&nb->host, nb->bytes, hipHostMallocDefault) != hipSuccess)
+        return fail(SEMD_ENOMEM, "pinned staging allocation of %zu bytes failed", nb->bytes);
+      if (hipEventCreateWithFlags(&nb->ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipHostFree(nb->host);
+        return fail(SEMD_EDEVICE, "event creation failed");
+      }
+      blk = nb.get();
+      g_pool.push_back(std::move(nb));
+    }
+    std::memcpy(blk->host, src, bytes);
+    hipError_t e = hipMallocAsync(d_out, bytes, s);
+    if (e != hipSuccess) return fail(SEMD_ENOMEM, "device allocation of %zu bytes failed", bytes);
+    e = hipMemcpyAsync(*d_out, blk->host, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+    e = hipEventRecord(blk->ev, s);
+    if (e != hipSuccess) return hip_fail(e, "event record");
+  }
+  return SEMD_OK;
+}
+
+struct Shape {
+  int64_t M, N, L;
+};
+
+int shape_of(const int64_t* dims, int ndim, int D, Shape* sh) {
+  int rc = parse_dims(dims, ndim, &sh->M, &sh->N);
+  if (rc) return rc;
+  if (D > sh->M)
+    return fail(SEMD_EINVAL, "transition_len %d exceeds the fibre length %lld", D,
+                (long long)sh->M);
+  sh->L = sh->M * sh->N + (int64_t)D * sh->N - D;
+  return SEMD_OK;
+}
+
+// Decompose `work` (host descriptors whose r fields are offsets into one
+// workspace of total_L doubles) on the resident path.
+int run_resident(std::vector<semd::WorkItem>& work, int64_t total_L, int K, int S,
+                 hipStream_t stream) {
+  if (work.empty()) return SEMD_OK;
+  // longest first, so the tail of the grid holds the short items
+  std::stable_sort(work.begin(), work.end(),
+                   [](const semd::WorkItem& a, const semd::WorkItem& b) { return a.L > b.L; });
+  double* ws = nullptr;
+  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&ws),
+                                sizeof(double) * (size_t)std::max<int64_t>(total_L, 1), stream);
+  if (e != hipSuccess) return fail(SEMD_ENOMEM, "workspace of %lld doubles", (long long)total_L);
+  for (auto& w : work) w.r = ws + reinterpret_cast<intptr_t>(w.r);
+  void* d_items = nullptr;
+  int rc = upload(work.data(), work.size() * sizeof(semd::WorkItem), stream, &d_items);
+  if (rc) { (void)hipFreeAsync(ws, stream); return rc; }
+  // one launch per thread-count class, so each class gets its own LDS size
+  size_t i0 = 0;
+  while (i0 < work.size() && rc == SEMD_OK) {
+    const int nt = semd::resident_threads(work[i0].L);
+    size_t i1 = i0;
+    while (i1 < work.size() && semd::resident_threads(work[i1].L) == nt) ++i1;
+    const auto* d = static_cast<const semd::WorkItem*>(d_items) + i0;
+    e = semd::launch_resident(d, (int)(i1 - i0), work[i0].L, K, S, stream);
+    if (e != hipSuccess) rc = hip_fail(e, "resident kernel launch");
+    i0 = i1;
+  }
+  (void)hipFreeAsync(d_items, stream);
+  (void)hipFreeAsync(ws, stream);
+  return rc;
+}
+
+semd::WorkItem make_work(const double* X, double* out, int32_t* n_imfs, const Shape& sh, int D,
+                         int64_t r_offset) {
+  semd::WorkItem w{};
+  w.X = X;
+  w.out = out;
+  w.n_imfs = n_imfs;
+  w.r = reinterpret_cast<double*>(static_cast<intptr_t>(r_offset));
+  w.M = sh.M;
+  w.N = sh.N;
+  w.D = D;
+  w.L = (int32_t)sh.L;
+  w.beta = 0.0;
+  w.key = 0;
+  w.flags = 0;
+  return w;
+}
+
+int check_items(const semd_item* items, int n, int D, std::vector<Shape>& shapes) {
+  if (n < 0) return fail(SEMD_EINVAL, "n must be >= 0");
+  if (n > 0 && !items) return fail(SEMD_EINVAL, "items is NULL");
+  shapes.resize(n);
+  for (int i = 0; i < n; ++i) {
+    const semd_item& it = items[i];
+    if (!it.signal || !it.imfs_out) return fail(SEMD_EINVAL, "item %d: NULL signal or output", i);
+    if (it.reserved != 0) return fail(SEMD_EINVAL, "item %d: reserved must be 0", i);
+    int rc = shape_of(it.dims, it.ndim, D, &shapes[i]);
+    if (rc) {
+      char msg[sizeof(g_err)];
+      std::snprintf(msg, sizeof(msg), "%s", g_err);
+      return fail(rc, "item %d: %s", i, msg);
+    }
+    if (shapes[i].L > semd::kResidentMaxL)
+      return fail(SEMD_EUNSUPPORTED,
+                  "item %d: serialized length %lld exceeds the on-chip path limit %d", i,
+                  (long long)shapes[i].L, semd::kResidentMaxL);
+  }
+  return SEMD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int semd_abi_version(void) { return SEMD_ABI_VERSION; }
+
+const char* semd_last_error(void) { return g_err; }
+
+int64_t semd_serial_length(int64_t M, int64_t N, int64_t D) {
+  if (M < 1 || N < 1 || D < 0 || D > M) return -1;
+  return M * N + D * N - D;
+}
+
+int64_t semd_resident_max_length(void) { return semd::kResidentMaxL; }
+
+int semd_decompose_ex(const double* signal, const int64_t* dims, int ndim, const semd_params* p,
+                      double* imfs_out, int32_t* n_imfs_out, hipStream_t stream) {
+  g_err[0] = 0;
+  int rc = check_params(p, false);
+  if (rc) return rc;
+  if (!signal || !imfs_out) return fail(SEMD_EINVAL, "NULL signal or output");
+  Shape sh;
+  rc = shape_of(dims, ndim, p->transition_len, &sh);
+  if (rc) return rc;
+  if (sh.L > semd::kResidentMaxL)
+    return fail(SEMD_EUNSUPPORTED, "serialized length %lld exceeds the on-chip path limit %d",
+                (long long)sh.L, semd::kResidentMaxL);
+  std::vector<semd::WorkItem> work{
+      make_work(signal, imfs_out, n_imfs_out, sh, p->transition_len, 0)};
+  return run_resident(work, sh.L, p->max_imfs, p->sift_iters, stream);
+}
+
+int semd_decompose(const double* signal, const int64_t* dims, int ndim, int max_imfs,
+                   int sift_iters, int boundary_rule, double* imfs_out, hipStream_t stream) {
+  g_err[0] = 0;
+  int64_t M, N;
+  int rc = parse_dims(dims, ndim, &M, &N);
+  if (rc) return rc;
+  semd_params p{};
+  p.transition_len = (int32_t)std::llround(0.2 * (double)M);
+  p.max_imfs = max_imfs;
+  p.sift_iters = sift_iters;
+  p.boundary_rule = boundary_rule;
+  p.ensemble = 1;
+  return semd_decompose_ex(signal, dims, ndim, &p, imfs_out, nullptr, stream);
+}
+
+int semd_decompose_batch(const semd_item* items, int n, const semd_params* p,
+                         hipStream_t stream) {
+  g_err[0] = 0;
+  int rc = check_params(p, false);
+  if (rc) return rc;
+  std::vector<Shape> shapes;
+  rc = check_items(items, n, p->transition_len, shapes);
+  if (rc) return rc;
+  std::vector<semd::WorkItem> work;
+  work.reserve(n);
+  int64_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    work.push_back(make_work(items[i].signal, items[i].imfs_out, items[i].n_imfs_out, shapes[i],
+                             p->transition_len, off));
+    off += shapes[i].L;
+  }
+  return run_resident(work, off, p->max_imfs, p->sift_iters, stream);
+}
+
+int semd_eemd_batch(const semd_item* items, int n, const semd_params* p, hipStream_t stream) {
+  g_err[0] = 0;
+  int rc = check_params(p, true);
+  if (rc) return rc;
+  std::vector<Shape> shapes;
+  rc = check_items(items, n, p->transition_len, shapes);
+  if (rc) return rc;
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(items[i].noise_sigma) || items[i].noise_sigma < 0)
+      return fail(SEMD_EINVAL, "item %d: noise_sigma must be finite and >= 0", i);
+  const int K = p->max_imfs, NR = p->ensemble;
+  // Realization outputs are staged in waves of items that fit the budget.
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = size_t(8) << 30;
+  const size_t budget = std::max<size_t>(free_b / 4, size_t(256) << 20);
+  int i0 = 0;
+  while (i0 < n) {
+    size_t bytes = 0;
+    int i1 = i0;
+    while (i1 < n) {
+      const size_t b = (size_t)NR * (sizeof(double) * ((size_t)(K + 1) * shapes[i1].M * shapes[i1].N +
+                                                       shapes[i1].L) + sizeof(int32_t));
+      if (i1 > i0 && bytes + b > budget) break;
+      bytes += b;
+      ++i1;
+    }
+    // per-realization slots and counts of this wave
+    size_t slots = 0;
+    for (int i = i0; i < i1; ++i) slots += (size_t)NR * (K + 1) * shapes[i].M * shapes[i].N;
+    double* buf = nullptr;
+    int32_t* cnt = nullptr;
+    if (hipMallocAsync(reinterpret_cast<void**>(&buf), sizeof(double) * std::max<size_t>(slots, 1),
+                       stream) != hipSuccess)
+      return fail(SEMD_ENOMEM, "EEMD realization buffer of %zu doubles", slots);
+    if (hipMallocAsync(reinterpret_cast<void**>(&cnt),
+                       sizeof(int32_t) * (size_t)NR * (i1 - i0), stream) != hipSuccess) {
+      (void)hipFreeAsync(buf, stream);
+      return fail(SEMD_ENOMEM, "EEMD count buffer");
+    }
+    std::vector<semd::WorkItem> work;
+    work.reserve((size_t)NR * (i1 - i0));
+    int64_t off = 0;
+    size_t so = 0;
+    for (int i = i0; i < i1; ++i) {
+      const size_t per = (size_t)(K + 1) * shapes[i].M * shapes[i].N;
+      for (int m = 0; m < NR; ++m) {
+        semd::WorkItem w = make_work(items[i].signal, buf + so + (size_t)m * per,
+                                     cnt + (size_t)(i - i0) * NR + m, shapes[i],
+                                     p->transition_len, off);
+        w.beta = items[i].noise_sigma;
+        w.key = semd::noise_key(p->seed, items[i].item_id, (uint64_t)m);
+        w.flags = 1;
+        work.push_back(w);
+        off += shapes[i].L;
+      }
+      so += (size_t)NR * per;
+    }
+    rc = run_resident(work, off, K, p->sift_iters, stream);
+    so = 0;
+    for (int i = i0; i < i1 && rc == SEMD_OK; ++i) {
+      const int64_t per = (int64_t)(K + 1) * shapes[i].M * shapes[i].N;
+      hipError_t e = semd::launch_ensemble_mean(buf + so, NR, per, items[i].imfs_out, stream);
+      if (e == hipSuccess && items[i].n_imfs_out)
+        e = semd::launch_max_count(cnt + (size_t)(i - i0) * NR, NR, items[i].n_imfs_out, stream);
+      if (e != hipSuccess) rc = hip_fail(e, "ensemble mean launch");
+      so += (size_t)NR * per;
+    }
+    (void)hipFreeAsync(cnt, stream);
+    (void)hipFreeAsync(buf, stream);
+    if (rc) return rc;
+    i0 = i1;
+  }
+  return SEMD_OK;
+}
+
+int semd_serialize(const double* X, const int64_t* dims, int ndim, int D, double* x,
+                   hipStream_t stream) {
+  g_err[0] = 0;
+  if (!X || !x) return fail(SEMD_EINVAL, "NULL input or output");
+  if (D < 0) return fail(SEMD_EINVAL, "D must be >= 0");
+  Shape sh;
+  int rc = shape_of(dims, ndim, D, &sh);
+  if (rc) return rc;
+  hipError_t e = semd::launch_serialize(X, sh.M, sh.N, D, x, stream);
+  return e == hipSuccess ? SEMD_OK : hip_fail(e, "serialize launch");
+}
+
+int semd_deserialize(const double* y, const int64_t* dims, int ndim, int D, double* out,
+                     hipStream_t stream) {
+  g_err[0] = 0;
+  if (!y || !out) return fail(SEMD_EINVAL, "NULL input or output");
+  if (D < 0) return fail(SEMD_EINVAL, "D must be >= 0");
+  Shape sh;
+  int rc = shape_of(dims, ndim, D, &sh);
+  if (rc) return rc;
+  hipError_t e = semd::launch_deserialize(y, sh.M, sh.N, D, out, stream);
+  return e == hipSuccess ? SEMD_OK : hip_fail(e, "deserialize launch");
+}
+
+int semd_extrema(const double* h, int64_t L, int32_t* imax, int32_t* imin, int32_t* counts,
+                 hipStream_t stream) {
+  g_err[0] = 0;
+  if (!h || !imax || !imin || !counts) return fail(SEMD_EINVAL, "NULL pointer");
+  if (L < 3 || L > semd::kResidentMaxL)
+    return fail(SEMD_EINVAL, "L must be in [3, %d]", semd::kResidentMaxL);
+  hipError_t e = semd::launch_extrema(h, (int)L, imax, imin, counts, stream);
+  return e == hipSuccess ? SEMD_OK : hip_fail(e, "extrema launch");
+}
+
+int semd_noise(uint64_t seed, uint64_t item, uint64_t m, int64_t L, double* w,
+               hipStream_t stream) {
+  g_err[0] = 0;
+  if (!w) return fail(SEMD_EINVAL, "NULL output");
+  if (L < 0) return fail(SEMD_EINVAL, "L must be >= 0");
+  if (L == 0) return SEMD_OK;
+  hipError_t e = semd::launch_noise(semd::noise_key(seed, item, m), L, w, stream);
+  return e == hipSuccess ? SEMD_OK : hip_fail(e, "noise launch");
+}
+
+}  // extern "C"

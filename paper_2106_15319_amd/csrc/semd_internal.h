@@ -1,0 +1,74 @@
+// Internal interfaces between the C ABI layer (semd_api.hip) and the kernels
+// (semd_kernels.hip).  Not installed; callers use include/semd.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace semd {
+
+// One unit of resident-path work: one serialized signal (optionally one EEMD
+// realization of it) decomposed by one workgroup.
+struct WorkItem {
+  const double* X;   // device, M*N column-major input
+  double* out;       // device, (K+1)*M*N output slots
+  int32_t* n_imfs;   // device, one int32 or nullptr
+  double* r;         // device workspace, L doubles (residue, serialized)
+  int64_t M;         // fibre length (rows of X)
+  int64_t N;         // number of fibres (columns of X)
+  int32_t D;         // transition length
+  int32_t L;         // serialized length M*N + D*N - D
+  double beta;       // EEMD noise amplitude
+  uint64_t key;      // SplitMix64 stream key of this realization
+  int32_t flags;     // bit 0: add beta * noise to the serialized signal
+  int32_t pad;
+};
+
+// Longest serialized signal the resident kernel handles (threads x samples
+// per thread of its largest instance).
+constexpr int kResidentMaxL = 16384;
+
+// Dynamic LDS bytes the resident kernel needs for a batch whose longest
+// signal is maxL, when launched with nt threads.
+size_t resident_lds_bytes(int maxL, int nt);
+
+// Threads per workgroup the resident kernel uses for signals up to maxL.
+int resident_threads(int maxL);
+
+// Launch the resident kernel over `n` work items (device array), all with
+// L <= maxL.  Returns hipSuccess or the launch error.
+hipError_t launch_resident(const WorkItem* d_items, int n, int maxL, int K, int S,
+                           hipStream_t stream);
+
+// Extrema of one 1D signal (3 <= L <= kResidentMaxL) through the resident
+// detection/compaction code: indices to imax/imin, counts[0..1].
+hipError_t launch_extrema(const double* h, int L, int32_t* imax, int32_t* imin,
+                          int32_t* counts, hipStream_t stream);
+
+hipError_t launch_serialize(const double* X, int64_t M, int64_t N, int D, double* x,
+                            hipStream_t stream);
+hipError_t launch_deserialize(const double* y, int64_t M, int64_t N, int D, double* out,
+                              hipStream_t stream);
+hipError_t launch_noise(uint64_t key, int64_t L, double* w, hipStream_t stream);
+
+// Slot-wise mean over NR realization buffers: src holds NR consecutive blocks
+// of `count` doubles; dst[i] = (sum_m src[m*count + i]) / NR, summed in m order.
+hipError_t launch_ensemble_mean(const double* src, int NR, int64_t count, double* dst,
+                                hipStream_t stream);
+// n_out[0] = max over m of n_src[m] (error codes, negative, take precedence).
+hipError_t launch_max_count(const int32_t* n_src, int NR, int32_t* n_out, hipStream_t stream);
+
+// SplitMix64: n-th output of the generator started at `state`.
+__host__ __device__ inline uint64_t splitmix64(uint64_t state, uint64_t n) {
+  uint64_t z = state + n * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Stream key of realization m of item `item` under `seed`.
+__host__ __device__ inline uint64_t noise_key(uint64_t seed, uint64_t item, uint64_t m) {
+  return splitmix64(splitmix64(seed, item + 1), m + 1);
+}
+
+}  // namespace semd

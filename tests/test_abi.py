@@ -1,0 +1,106 @@
+"""The C ABI library loads, exports every declared entry point, and rejects
+invalid arguments on the host before touching the device (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_2106_15319_amd as semd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "semd.h")
+
+BOGUS = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(semd_[a-z_0-9]+)\s*\(",
+                                 text, flags=re.M)))
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    L = semd.lib()
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(semd.exported_names()) == names
+
+
+def test_abi_version_and_limits():
+    assert semd.semd_abi_version() == 1
+    assert semd.semd_resident_max_length() >= 16384
+
+
+@pytest.mark.parametrize("M,N,D,want", [(4, 2, 2, 10), (1000, 3, 0, 3000), (1000, 3, 50, 3100),
+                                        (112, 92, 20, 12124), (5, 1, 5, 5), (5, 2, 6, -1),
+                                        (0, 3, 0, -1), (3, 0, 0, -1), (3, 3, -1, -1)])
+def test_serial_length(M, N, D, want):
+    assert semd.semd_serial_length(M, N, D) == want
+
+
+def _p(**kw):
+    p = semd.semd_params(kw.get("D", 0), kw.get("K", 6), kw.get("S", 10), kw.get("b", 0),
+                         kw.get("NR", 1), kw.get("res", 0), 0)
+    return p
+
+
+@pytest.mark.parametrize("kw,dims,code", [
+    (dict(K=0), [100, 3], semd.SEMD_EINVAL),
+    (dict(S=0), [100, 3], semd.SEMD_EINVAL),
+    (dict(b=1), [100, 3], semd.SEMD_EINVAL),
+    (dict(D=101), [100, 3], semd.SEMD_EINVAL),
+    (dict(D=-1), [100, 3], semd.SEMD_EINVAL),
+    (dict(res=7), [100, 3], semd.SEMD_EINVAL),
+    (dict(), [0, 3], semd.SEMD_EINVAL),
+    (dict(), [100, -2], semd.SEMD_EINVAL),
+])
+def test_decompose_ex_rejects_invalid_arguments(kw, dims, code):
+    L = semd.lib()
+    p = _p(**kw)
+    d = (C.c_int64 * len(dims))(*dims)
+    rc = L.semd_decompose_ex(BOGUS, d, len(dims), C.byref(p), BOGUS, None, None)
+    assert rc == code
+    assert L.semd_last_error().decode()
+
+
+def test_null_pointers_rejected():
+    L = semd.lib()
+    p = _p()
+    d = (C.c_int64 * 2)(100, 3)
+    assert L.semd_decompose_ex(None, d, 2, C.byref(p), BOGUS, None, None) == semd.SEMD_EINVAL
+    assert L.semd_decompose_ex(BOGUS, d, 2, C.byref(p), None, None, None) == semd.SEMD_EINVAL
+    assert L.semd_decompose_ex(BOGUS, None, 2, C.byref(p), BOGUS, None, None) == semd.SEMD_EINVAL
+    assert L.semd_decompose_ex(BOGUS, d, 0, C.byref(p), BOGUS, None, None) == semd.SEMD_EINVAL
+    assert L.semd_decompose_ex(BOGUS, d, 2, None, BOGUS, None, None) == semd.SEMD_EINVAL
+    assert L.semd_serialize(None, d, 2, 0, BOGUS, None) == semd.SEMD_EINVAL
+    assert L.semd_extrema(BOGUS, 2, BOGUS, BOGUS, BOGUS, None) == semd.SEMD_EINVAL
+    assert L.semd_noise(1, 2, 3, 10, None, None) == semd.SEMD_EINVAL
+
+
+def test_batch_validation():
+    L = semd.lib()
+    p = _p()
+    items = (semd.semd_item * 2)()
+    for it in items:
+        it.signal = 0x1000
+        it.imfs_out = 0x2000
+        it.dims[0], it.dims[1] = 100, 3
+        it.ndim = 2
+    items[1].ndim = 5
+    assert L.semd_decompose_batch(items, 2, C.byref(p), None) == semd.SEMD_EINVAL
+    assert "item 1" in L.semd_last_error().decode()
+    items[1].ndim = 2
+    items[1].reserved = 3
+    assert L.semd_decompose_batch(items, 2, C.byref(p), None) == semd.SEMD_EINVAL
+    items[1].reserved = 0
+    items[0].noise_sigma = -1.0
+    pe = _p(NR=4)
+    assert L.semd_eemd_batch(items, 2, C.byref(pe), None) == semd.SEMD_EINVAL
+    pe = _p(NR=0)
+    assert L.semd_eemd_batch(items, 2, C.byref(pe), None) == semd.SEMD_EINVAL
+    assert L.semd_decompose_batch(items, -1, C.byref(p), None) == semd.SEMD_EINVAL
+    assert L.semd_decompose_batch(None, 2, C.byref(p), None) == semd.SEMD_EINVAL

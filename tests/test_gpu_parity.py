@@ -1,0 +1,251 @@
+"""HIP path against the CPU oracle, element by element, through the C ABI.
+
+Sizes span several thread blocks and ragged tails; the tolerance for every
+floating-point output is 1e-8 * max|x| (integer and index outputs, the
+serialization, deserialization and noise must be bit-exact)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2106_15319_amd as semd
+import workloads
+from parity import TIE, TOL, assert_parity, compare
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+# --------------------------------------------------------------------------
+# single steps
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("M,N,D", [(4, 2, 2), (1000, 3, 0), (1000, 3, 50), (112, 92, 20),
+                                   (128, 128, 26), (7, 5, 7), (1, 9, 1), (33, 1, 0)])
+def test_serialize_deserialize_bit_exact(M, N, D):
+    rng = np.random.default_rng(M * 7 + N + D)
+    X = rng.standard_normal(M * N) * 10.0 ** rng.integers(-5, 5, M * N)
+    x = host(semd.semd_serialize(dev(X), [M, N], D))
+    want = oracle.serialize(X, M, N, D)
+    assert x.tobytes() == want.tobytes()
+    y = rng.standard_normal(want.size)
+    back = host(semd.semd_deserialize(dev(y), [M, N], D))
+    assert back.tobytes() == oracle.deserialize(y, M, N, D).tobytes()
+
+
+def test_noise_bit_exact_million_draws():
+    for (seed, item, m) in [(0, 0, 0), (2106_15319, 17, 63)]:
+        w = host(semd.semd_noise(seed, item, m, 1_000_000))
+        assert w.tobytes() == oracle.noise(seed, item, m, 1_000_000).tobytes()
+
+
+def _plateau_signal(rng, L):
+    h = np.round(rng.standard_normal(L) * 2.0)
+    # long flat runs across many 16-sample blocks, touching and not touching ends
+    for _ in range(4):
+        a = int(rng.integers(0, L))
+        b = min(L, a + int(rng.integers(1, 400)))
+        h[a:b] = h[a]
+    return h
+
+
+@pytest.mark.parametrize("L", [3, 4, 5, 17, 31, 1000, 4095, 4096, 4097, 10304, 16383, 16384])
+def test_extrema_identical_index_sets(L):
+    rng = np.random.default_rng(L)
+    for h in (rng.standard_normal(L), _plateau_signal(rng, L), np.zeros(L),
+              np.arange(L, dtype=float), np.cos(np.arange(L) * 2.1)):
+        imax, imin = semd.semd_extrema(dev(h))
+        rmax, rmin = oracle.extrema(h)
+        assert np.array_equal(imax.cpu().numpy(), rmax)
+        assert np.array_equal(imin.cpu().numpy(), rmin)
+
+
+def test_extrema_constant_blocks_across_threads():
+    # runs that cover whole 16-sample blocks and start inside another block
+    L = 8000
+    h = np.zeros(L)
+    h[1000:1700] = 5.0   # max plateau spanning ~44 blocks
+    h[3000:3333] = -2.0  # min plateau
+    h[5000:] = 1.0       # run touching the end: not an extremum
+    h[0:37] = 3.0        # run touching the start: not an extremum
+    imax, imin = semd.semd_extrema(dev(h))
+    rmax, rmin = oracle.extrema(h)
+    assert np.array_equal(imax.cpu().numpy(), rmax) and np.array_equal(imin.cpu().numpy(), rmin)
+    # the zero run 37..999 between 3 and 5 is a minimum plateau too
+    assert list(rmax) == [1349] and list(rmin) == [518, 3166]
+
+
+@pytest.mark.parametrize("L", [50, 1001, 4096, 9999, 16384])
+def test_single_sift(L):
+    rng = np.random.default_rng(100 + L)
+    x = np.cumsum(rng.standard_normal(L)) + 3 * np.sin(np.arange(L) / 7.0)
+    out, n = semd.semd_decompose_ex(dev(x), [L, 1], 0, 1, 1)
+    ref, nr = oracle.emd(x, 1, 1)
+    r = compare(host(out), int(host(n)[0]), ref, nr, np.abs(x).max())
+    assert r["ok"], r
+
+
+# --------------------------------------------------------------------------
+# whole decompositions
+# --------------------------------------------------------------------------
+
+def _check_item(X, M, N, D, K, S, out, n, ties):
+    ref, nr, st = oracle.decompose(X, M, N, D, K, S, with_stats=True)
+    r = compare(out, n, ref, nr, np.abs(X).max(), st["min_gap"])
+    if r["tie"]:
+        ties.append(r)
+    assert_parity(r, f"M={M} N={N} D={D}")
+    return r
+
+
+@pytest.mark.parametrize("D", [0, 50])
+def test_config0_series(D):
+    it = workloads.config0()
+    out, n = semd.semd_decompose_ex(dev(it.X), [it.M, it.N], D, 6, 10)
+    ties = []
+    r = _check_item(it.X, it.M, it.N, D, 6, 10, host(out)[:], int(host(n)[0]), ties)
+    assert r["n_gpu"] >= 3
+
+
+@pytest.mark.parametrize("D", [0, 20])
+def test_config2_faces_batch_subset(D):
+    items = workloads.config2(12)
+    Xs = [dev(i.X) for i in items]
+    outs, counts = semd.decompose_batch(Xs, [(i.M, i.N) for i in items], D, 8, 10)
+    counts = host(counts)
+    ties = []
+    for k, i in enumerate(items):
+        _check_item(i.X, i.M, i.N, D, 8, 10, host(outs[k]), int(counts[k]), ties)
+    assert len(ties) <= 1
+
+
+def test_config1_textures_subset():
+    items = workloads.config1(4)
+    ties = []
+    for i in items:
+        out, n = semd.semd_decompose_ex(dev(i.X), [i.M, i.N], 0, 8, 10)
+        _check_item(i.X, i.M, i.N, 0, 8, 10, host(out), int(host(n)[0]), ties)
+    assert len(ties) <= 1
+
+
+def test_batch_equals_plain_bit_exact():
+    items = workloads.config2(3) + workloads.config1(1, size=64)
+    shapes = [(i.M, i.N) for i in items]
+    Xs = [dev(i.X) for i in items]
+    outs, counts = semd.decompose_batch(Xs, shapes, 10, 8, 10)
+    for k, i in enumerate(items):
+        o, n = semd.semd_decompose_ex(Xs[k], [i.M, i.N], 10, 8, 10)
+        assert host(o).tobytes() == host(outs[k]).tobytes()
+        assert int(host(n)[0]) == int(host(counts)[k])
+
+
+def test_uneven_batch_mixed_lengths():
+    rng = np.random.default_rng(5)
+    shapes = [(int(m), int(c)) for m, c in zip(rng.integers(3, 2000, 9), rng.integers(1, 8, 9))]
+    shapes = [(M, N) for (M, N) in shapes if M * N <= 16384] + [(16384, 1), (5, 1), (2, 1)]
+    Xs = [workloads.series(workloads.rng_for(9, k), N, M) for k, (M, N) in enumerate(shapes)]
+    outs, counts = semd.decompose_batch([dev(x) for x in Xs], shapes, 0, 6, 10)
+    counts = host(counts)
+    ties = []
+    for k, (M, N) in enumerate(shapes):
+        _check_item(Xs[k], M, N, 0, 6, 10, host(outs[k]), int(counts[k]), ties)
+    assert len(ties) <= 1
+
+
+def test_determinism():
+    it = workloads.config2(1)[0]
+    a, _ = semd.semd_decompose_ex(dev(it.X), [it.M, it.N], 20, 8, 10)
+    b, _ = semd.semd_decompose_ex(dev(it.X), [it.M, it.N], 20, 8, 10)
+    assert host(a).tobytes() == host(b).tobytes()
+
+
+# --------------------------------------------------------------------------
+# edge cases
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("L", [1, 2, 3])
+def test_tiny_signals(L):
+    x = np.array([1.0, -2.0, 0.5][:L])
+    out, n = semd.semd_decompose_ex(dev(x), [L, 1], 0, 4, 10)
+    ref, nr = oracle.emd(x, 4, 10)
+    assert int(host(n)[0]) == nr == 0
+    assert np.array_equal(host(out), ref)
+
+
+def test_monotone_and_on_grid_cosine():
+    x = np.linspace(-3.0, 5.0, 300) ** 3
+    out, n = semd.semd_decompose_ex(dev(x), [300, 1], 0, 6, 10)
+    assert int(host(n)[0]) == 0 and np.array_equal(host(out)[6], x)
+    s = math.sqrt(0.5)
+    L = 8 * 700 + 1
+    c = np.array([1.0, s, 0.0, -s, -1.0, -s, 0.0, s])[np.arange(L) % 8]
+    out, n = semd.semd_decompose_ex(dev(c), [L, 1], 0, 6, 10)
+    o = host(out)
+    assert int(host(n)[0]) == 1
+    assert np.abs(o[0] - c).max() <= 1e-12 and np.abs(o[6]).max() <= 1e-12
+
+
+def test_non_finite_input_reported():
+    x = np.ones(500)
+    x[123] = np.nan
+    out, n = semd.semd_decompose_ex(dev(x), [500, 1], 0, 3, 10)
+    assert int(host(n)[0]) == -semd.SEMD_ENONFINITE
+    assert np.all(host(out) == 0.0)
+
+
+def test_largest_resident_signal():
+    L = semd.semd_resident_max_length()
+    rng = np.random.default_rng(77)
+    x = rng.standard_normal(L)  # white noise: the densest knot sets
+    out, n = semd.semd_decompose_ex(dev(x), [L, 1], 0, 3, 4)
+    ref, nr, st = oracle.emd(x, 3, 4, with_stats=True)
+    r = compare(host(out), int(host(n)[0]), ref, nr, np.abs(x).max(), st["min_gap"])
+    assert_parity(r, "white noise at the largest resident length")
+
+
+def test_alternating_signal_worst_case_knots():
+    L = 16384
+    k = np.arange(L)
+    x = np.where(k % 2 == 0, 1.0, -1.0) * (1.0 + 0.001 * np.sin(k / 50.0))
+    out, n = semd.semd_decompose_ex(dev(x), [L, 1], 0, 2, 2)
+    ref, nr, st = oracle.emd(x, 2, 2, with_stats=True)
+    r = compare(host(out), int(host(n)[0]), ref, nr, np.abs(x).max(), st["min_gap"])
+    assert_parity(r, "alternating signal")
+
+
+# --------------------------------------------------------------------------
+# EEMD
+# --------------------------------------------------------------------------
+
+def test_eemd_matches_oracle():
+    it = workloads.config0()
+    M, N, D, K, S, NR, seed = it.M, it.N, 50, 6, 10, 8, 1234
+    x = oracle.serialize(it.X, M, N, D)
+    beta = 0.2 * float(x.std())
+    out = torch.empty((K + 1, M * N), dtype=torch.float64, device=DEV)
+    cnt = torch.empty(1, dtype=torch.int32, device=DEV)
+    semd.semd_eemd_batch([dev(it.X)], [[M, N]], [out], cnt, D, K, S, NR, seed, [beta], [5])
+    ref = oracle.eemd(it.X, M, N, D, K, S, NR, beta, seed, 5)
+    err = np.abs(host(out) - ref).max()
+    assert err <= TOL * np.abs(it.X).max(), err
+    assert 1 <= int(host(cnt)[0]) <= K
+
+
+def test_eemd_zero_noise_single_realization_is_emd():
+    it = workloads.config2(1)[0]
+    out = torch.empty((9, it.M * it.N), dtype=torch.float64, device=DEV)
+    semd.semd_eemd_batch([dev(it.X)], [[it.M, it.N]], [out], None, 20, 8, 10, 1, 0, [0.0])
+    plain, _ = semd.semd_decompose_ex(dev(it.X), [it.M, it.N], 20, 8, 10)
+    assert np.array_equal(host(out), host(plain))
