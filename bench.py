@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Serial-EMD throughput on one MI355X.
+
+Workload (one step): the 1,024 face-like 112 x 92 images (uint8-valued, as
+float64) serialized column by column to 10,304-sample signals (D = 0), each
+decomposed into up to 8 IMFs with 10 sifts per IMF, all in one batched
+launch.  Inputs and outputs stay resident in HBM; the timed region holds K
+such steps between two synchronizations.
+
+Reported beside the batched throughput: the plain path (one launch per
+image, same images, same parameters), per-step and per-image latency
+percentiles, the roofline position of the dominant kernel, and the CPU
+oracle timed on the host over the same images.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# flops per sample per sift (extrema 2, two envelope evaluations 25 each,
+# mean and update 3) and per knot per sift (one Thomas row 16 + 2), as
+# written in the method; see the design notes
+FLOPS_PER_SAMPLE_SIFT = 55
+FLOPS_PER_KNOT = 18
+FP64_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBPS = 8000.0
+
+
+def pct(a, q):
+    return float(np.percentile(np.asarray(a), q))
+
+
+def cpu_baseline(items, D, K, S, threads):
+    """The oracle over the same images on the host, one image per task."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+
+    oracle.lib()
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(lambda it: oracle.decompose(it.X, it.M, it.N, D, K, S), items))
+    dt = time.perf_counter() - t0
+    samples = sum(it.M * it.N for it in items)
+    return samples / dt, dt, samples
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--D", type=int, default=0)
+    ap.add_argument("--plain-items", type=int, default=256)
+    ap.add_argument("--cpu-items", type=int, default=1024)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the independent "
+              "signals of a batch would shard across GPUs with no exchange", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_2106_15319_amd as semd
+    import workloads
+
+    assert torch.cuda.is_available(), "bench.py needs the HIP device"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    K, S, D = 8, 10, args.D
+    items = workloads.config2(args.batch)
+    M, N = items[0].M, items[0].N
+    MN = M * N
+    L = M * N + D * N - D
+    n = len(items)
+
+    X = torch.from_numpy(np.stack([it.X for it in items])).to(dev)
+    out = torch.empty((n, K + 1, MN), dtype=torch.float64, device=dev)
+    counts = torch.zeros(n, dtype=torch.int32, device=dev)
+    stats = torch.zeros((n, 3), dtype=torch.int64, device=dev)
+    shapes = [[M, N]] * n
+
+    # work statistics of one decomposition of the batch (untimed)
+    pb_stats = semd.PreparedBatch([X[i] for i in range(n)], shapes, [out[i] for i in range(n)],
+                                  counts, D, K, S, stats=stats)
+    pb_stats.run()
+    torch.cuda.synchronize()
+    st = stats.sum(0).cpu().numpy()
+    n_sifts, n_knots, sample_sifts = int(st[0]), int(st[1]), int(st[2])
+    n_imfs = counts.cpu().numpy()
+
+    pb = semd.PreparedBatch([X[i] for i in range(n)], shapes, [out[i] for i in range(n)],
+                            counts, D, K, S)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        pb.run()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        pb.run()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = [a.elapsed_time(b) for a, b in ev]
+    ms_per_step = wall * 1e3 / args.steps
+    value = n * MN / (ms_per_step / 1e3)
+
+    # plain path: one launch per image, same images
+    npl = min(args.plain_items, n)
+    outs1 = [torch.empty((K + 1, MN), dtype=torch.float64, device=dev) for _ in range(npl)]
+    cnt1 = torch.empty(npl, dtype=torch.int32, device=dev)
+    for i in range(min(4, npl)):
+        semd.semd_decompose_ex(X[i], [M, N], D, K, S, outs1[i], cnt1[i:i + 1])
+    torch.cuda.synchronize()
+    pev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(npl)]
+    t1 = time.perf_counter()
+    for i, (a, b) in enumerate(pev):
+        a.record(stream)
+        semd.semd_decompose_ex(X[i], [M, N], D, K, S, outs1[i], cnt1[i:i + 1])
+        b.record(stream)
+    torch.cuda.synchronize()
+    plain_wall = time.perf_counter() - t1
+    plain_ms = [a.elapsed_time(b) for a, b in pev]
+    plain_value = npl * MN / plain_wall
+    same = all(torch.equal(outs1[i], out[i]) for i in range(npl))
+
+    # roofline of the dominant kernel (the resident decomposition kernel: one
+    # launch per step), algorithmic FP64 flops over its measured duration
+    kern_ms = float(np.mean(step_ms))
+    flops = FLOPS_PER_SAMPLE_SIFT * sample_sifts + FLOPS_PER_KNOT * n_knots
+    achieved = flops / (kern_ms / 1e3) / 1e12
+    b_io = 8 * MN * n * (K + 2)
+    b_stream = b_io + 16 * sample_sifts + 16 * L * int(n_imfs.sum())
+
+    res = {
+        "metric": "samples decomposed/s/GPU (batched+served vs plain), p50/p99 latency, "
+                  "%HBM peak",
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"face-like images 112x92 (uint8-valued) x {n}, serialized "
+                               f"column-wise, D={D}, batched Serial-EMD",
+                   "batch": n, "M": M, "N": N, "D": D, "L": L, "max_imfs": K,
+                   "sift_iters": S},
+        "latency_ms": {"step_p50": pct(step_ms, 50), "step_p99": pct(step_ms, 99)},
+        "plain": {"value": plain_value, "unit": "samples/s", "images": npl,
+                  "image_p50_ms": pct(plain_ms, 50), "image_p99_ms": pct(plain_ms, 99),
+                  "batched_over_plain": value / plain_value, "outputs_identical": same},
+        "work": {"sifts": n_sifts, "knots": n_knots, "sample_sifts": sample_sifts,
+                 "mean_imfs": float(n_imfs.mean())},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "resident_emd_kernel<1024,16>", "kernel_ms": kern_ms,
+                     "flops_per_launch": flops},
+        "hbm": {"algorithmic_io_bytes": b_io,
+                "io_GBps": b_io / (kern_ms / 1e3) / 1e9,
+                "io_frac_of_peak": b_io / (kern_ms / 1e3) / 1e9 / HBM_PEAK_GBPS,
+                "stream_equivalent_GBps": b_stream / (kern_ms / 1e3) / 1e9},
+    }
+    if not args.no_cpu:
+        threads = min(16, os.cpu_count() or 1)
+        ncpu = min(args.cpu_items, n)
+        rate, dt, samples = cpu_baseline(items[:ncpu], D, K, S, threads)
+        res["cpu_baseline"] = {"value": rate, "unit": "samples/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"{ncpu} of the {n} images, {samples} input samples, "
+                                         f"{dt:.1f} s wall on {threads} threads"}
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

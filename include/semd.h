@@ -76,13 +76,17 @@ typedef struct {
 
 /* One signal of a batch.  signal: device, M*N doubles (M = dims[0], N =
  * product of dims[1..ndim-1]); imfs_out: device, (K+1)*M*N doubles;
- * n_imfs_out: device, one int32, or NULL.  noise_sigma is the absolute EEMD
+ * n_imfs_out: device, one int32, or NULL.  stats_out: device, 3 int64, or
+ * NULL: receives the number of sifts performed, the number of envelope knots
+ * used (mirrored knots included) and the number of sample-sifts (sum over
+ * sifts of L); semd_decompose_batch only.  noise_sigma is the absolute EEMD
  * noise amplitude beta of Sec. 2.2 (semd_eemd_batch only), item_id selects the
  * item's noise streams. */
 typedef struct {
   const double* signal;
   double* imfs_out;
   int32_t* n_imfs_out;
+  int64_t* stats_out;
   int64_t dims[4];
   int32_t ndim;
   int32_t reserved; /* must be 0 */

@@ -47,7 +47,7 @@ class semd_params(C.Structure):
 
 class semd_item(C.Structure):
     _fields_ = [("signal", C.c_void_p), ("imfs_out", C.c_void_p), ("n_imfs_out", C.c_void_p),
-                ("dims", C.c_int64 * 4), ("ndim", C.c_int32), ("reserved", C.c_int32),
+                ("stats_out", C.c_void_p), ("dims", C.c_int64 * 4), ("ndim", C.c_int32), ("reserved", C.c_int32),
                 ("noise_sigma", C.c_double), ("item_id", C.c_uint64)]
 
 
@@ -183,7 +183,7 @@ def semd_decompose_ex(signal: torch.Tensor, dims: Sequence[int], D: int, max_imf
     return imfs_out, n_imfs_out
 
 
-def _items(signals, dims_list, outs, counts, sigmas=None, item_ids=None):
+def _items(signals, dims_list, outs, counts, sigmas=None, item_ids=None, stats=None):
     n = len(signals)
     arr = (semd_item * max(n, 1))()
     for i in range(n):
@@ -191,6 +191,7 @@ def _items(signals, dims_list, outs, counts, sigmas=None, item_ids=None):
         it.signal = _dev_f64(signals[i], f"signals[{i}]")
         it.imfs_out = _dev_f64(outs[i], f"imfs_out[{i}]")
         it.n_imfs_out = counts[i].data_ptr() if counts is not None else None
+        it.stats_out = stats[i].data_ptr() if stats is not None else None
         dims = list(dims_list[i])
         if not 1 <= len(dims) <= 4:
             raise ValueError("dims must have 1..4 entries")
@@ -205,11 +206,14 @@ def _items(signals, dims_list, outs, counts, sigmas=None, item_ids=None):
 
 def semd_decompose_batch(signals: Sequence[torch.Tensor], dims_list: Sequence[Sequence[int]],
                          outs: Sequence[torch.Tensor], counts: torch.Tensor | None, D: int,
-                         max_imfs: int, sift_iters: int, stream=None) -> None:
+                         max_imfs: int, sift_iters: int, stats: torch.Tensor | None = None,
+                         stream=None) -> None:
     """Batched path: every signal in one launch.  counts: int32 tensor of
-    len(signals) entries (or None)."""
+    len(signals) entries (or None); stats: int64 tensor (len(signals), 3) of
+    (sifts, knots, sample-sifts) per signal (or None)."""
     cviews = [counts[i:i + 1] for i in range(len(signals))] if counts is not None else None
-    arr, n = _items(signals, dims_list, outs, cviews)
+    sviews = [stats[i] for i in range(len(signals))] if stats is not None else None
+    arr, n = _items(signals, dims_list, outs, cviews, stats=sviews)
     p = _params(D, max_imfs, sift_iters)
     _check(lib().semd_decompose_batch(arr, n, C.byref(p), _stream(stream)),
            "semd_decompose_batch")
@@ -290,3 +294,24 @@ def decompose_batch(Xs: Sequence[torch.Tensor], shapes: Sequence[tuple[int, int]
     counts = torch.empty(len(Xs), dtype=torch.int32, device=dev)
     semd_decompose_batch(Xs, [list(s) for s in shapes], outs, counts, D, K, S, stream=stream)
     return outs, counts
+
+
+class PreparedBatch:
+    """A semd_item array built once and handed to semd_decompose_batch (or
+    semd_eemd_batch) on every call, for loops that decompose the same buffers
+    repeatedly without rebuilding the descriptors."""
+
+    def __init__(self, signals, dims_list, outs, counts=None, D=0, max_imfs=8, sift_iters=10,
+                 stats=None, ensemble=1, seed=0, noise_sigmas=None, item_ids=None):
+        cviews = [counts[i:i + 1] for i in range(len(signals))] if counts is not None else None
+        sviews = [stats[i] for i in range(len(signals))] if stats is not None else None
+        self._keep = (list(signals), list(outs), counts, stats)
+        self.items, self.n = _items(signals, dims_list, outs, cviews, noise_sigmas, item_ids,
+                                    sviews)
+        self.params = _params(D, max_imfs, sift_iters, ensemble, seed)
+        self.eemd = ensemble > 1 or noise_sigmas is not None
+
+    def run(self, stream=None) -> None:
+        fn = lib().semd_eemd_batch if self.eemd else lib().semd_decompose_batch
+        _check(fn(self.items, self.n, C.byref(self.params), _stream(stream)),
+               "semd_eemd_batch" if self.eemd else "semd_decompose_batch")

@@ -119,28 +119,36 @@ int shape_of(const int64_t* dims, int ndim, int D, Shape* sh) {
   return SEMD_OK;
 }
 
-// Decompose `work` (host descriptors whose r fields are offsets into one
-// workspace of total_L doubles) on the resident path.
-int run_resident(std::vector<semd::WorkItem>& work, int64_t total_L, int K, int S,
+// Decompose `work` (host descriptors whose r fields hold offsets, in
+// doubles, into one workspace of ws_doubles) on the resident path.  Each item
+// owns 2 L doubles of it: the residue and a parking slot for an envelope.
+int run_resident(std::vector<semd::WorkItem>& work, int64_t ws_doubles, int K, int S,
                  hipStream_t stream) {
   if (work.empty()) return SEMD_OK;
-  // longest first, so the tail of the grid holds the short items
+  // longest first, so the tail of each launch holds the short items
   std::stable_sort(work.begin(), work.end(),
                    [](const semd::WorkItem& a, const semd::WorkItem& b) { return a.L > b.L; });
   double* ws = nullptr;
   hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&ws),
-                                sizeof(double) * (size_t)std::max<int64_t>(total_L, 1), stream);
-  if (e != hipSuccess) return fail(SEMD_ENOMEM, "workspace of %lld doubles", (long long)total_L);
-  for (auto& w : work) w.r = ws + reinterpret_cast<intptr_t>(w.r);
+                                sizeof(double) * (size_t)std::max<int64_t>(ws_doubles, 1), stream);
+  if (e != hipSuccess)
+    return fail(SEMD_ENOMEM, "workspace of %lld doubles", (long long)ws_doubles);
+  for (auto& w : work) {
+    w.r = ws + reinterpret_cast<intptr_t>(w.r);
+    w.u = w.r + w.L;
+  }
   void* d_items = nullptr;
   int rc = upload(work.data(), work.size() * sizeof(semd::WorkItem), stream, &d_items);
   if (rc) { (void)hipFreeAsync(ws, stream); return rc; }
-  // one launch per thread-count class, so each class gets its own LDS size
+  // one launch per launch-shape class, each with the LDS its longest item needs
+  auto same = [](const semd::ResidentClass& a, const semd::ResidentClass& b) {
+    return a.nt == b.nt && a.c == b.c;
+  };
   size_t i0 = 0;
   while (i0 < work.size() && rc == SEMD_OK) {
-    const int nt = semd::resident_threads(work[i0].L);
+    const semd::ResidentClass cls = semd::resident_class(work[i0].L);
     size_t i1 = i0;
-    while (i1 < work.size() && semd::resident_threads(work[i1].L) == nt) ++i1;
+    while (i1 < work.size() && same(semd::resident_class(work[i1].L), cls)) ++i1;
     const auto* d = static_cast<const semd::WorkItem*>(d_items) + i0;
     e = semd::launch_resident(d, (int)(i1 - i0), work[i0].L, K, S, stream);
     if (e != hipSuccess) rc = hip_fail(e, "resident kernel launch");
@@ -152,11 +160,12 @@ int run_resident(std::vector<semd::WorkItem>& work, int64_t total_L, int K, int 
 }
 
 semd::WorkItem make_work(const double* X, double* out, int32_t* n_imfs, const Shape& sh, int D,
-                         int64_t r_offset) {
+                         int64_t r_offset, int64_t* stats = nullptr) {
   semd::WorkItem w{};
   w.X = X;
   w.out = out;
   w.n_imfs = n_imfs;
+  w.stats = stats;
   w.r = reinterpret_cast<double*>(static_cast<intptr_t>(r_offset));
   w.M = sh.M;
   w.N = sh.N;
@@ -219,7 +228,7 @@ int semd_decompose_ex(const double* signal, const int64_t* dims, int ndim, const
                 (long long)sh.L, semd::kResidentMaxL);
   std::vector<semd::WorkItem> work{
       make_work(signal, imfs_out, n_imfs_out, sh, p->transition_len, 0)};
-  return run_resident(work, sh.L, p->max_imfs, p->sift_iters, stream);
+  return run_resident(work, 2 * sh.L, p->max_imfs, p->sift_iters, stream);
 }
 
 int semd_decompose(const double* signal, const int64_t* dims, int ndim, int max_imfs,
@@ -250,8 +259,8 @@ int semd_decompose_batch(const semd_item* items, int n, const semd_params* p,
   int64_t off = 0;
   for (int i = 0; i < n; ++i) {
     work.push_back(make_work(items[i].signal, items[i].imfs_out, items[i].n_imfs_out, shapes[i],
-                             p->transition_len, off));
-    off += shapes[i].L;
+                             p->transition_len, off, items[i].stats_out));
+    off += 2 * shapes[i].L;
   }
   return run_resident(work, off, p->max_imfs, p->sift_iters, stream);
 }
@@ -277,7 +286,7 @@ int semd_eemd_batch(const semd_item* items, int n, const semd_params* p, hipStre
     int i1 = i0;
     while (i1 < n) {
       const size_t b = (size_t)NR * (sizeof(double) * ((size_t)(K + 1) * shapes[i1].M * shapes[i1].N +
-                                                       shapes[i1].L) + sizeof(int32_t));
+                                                       2 * shapes[i1].L) + sizeof(int32_t));
       if (i1 > i0 && bytes + b > budget) break;
       bytes += b;
       ++i1;
@@ -309,7 +318,7 @@ int semd_eemd_batch(const semd_item* items, int n, const semd_params* p, hipStre
         w.key = semd::noise_key(p->seed, items[i].item_id, (uint64_t)m);
         w.flags = 1;
         work.push_back(w);
-        off += shapes[i].L;
+        off += 2 * shapes[i].L;
       }
       so += (size_t)NR * per;
     }

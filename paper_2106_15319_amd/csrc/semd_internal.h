@@ -13,7 +13,9 @@ struct WorkItem {
   const double* X;   // device, M*N column-major input
   double* out;       // device, (K+1)*M*N output slots
   int32_t* n_imfs;   // device, one int32 or nullptr
+  int64_t* stats;    // device, 3 int64 (sifts, knots, sample-sifts) or nullptr
   double* r;         // device workspace, L doubles (residue, serialized)
+  double* u;         // device workspace, L doubles (upper envelope, when parked)
   int64_t M;         // fibre length (rows of X)
   int64_t N;         // number of fibres (columns of X)
   int32_t D;         // transition length
@@ -28,12 +30,17 @@ struct WorkItem {
 // per thread of its largest instance).
 constexpr int kResidentMaxL = 16384;
 
-// Dynamic LDS bytes the resident kernel needs for a batch whose longest
-// signal is maxL, when launched with nt threads.
-size_t resident_lds_bytes(int maxL, int nt);
+// Launch shape of the resident kernel: threads per workgroup and samples per
+// thread, chosen from the longest signal of a launch.
+struct ResidentClass {
+  int nt;
+  int c;
+};
+ResidentClass resident_class(int maxL);
 
-// Threads per workgroup the resident kernel uses for signals up to maxL.
-int resident_threads(int maxL);
+// Bytes of the kernel's reusable LDS area for signals up to maxL samples,
+// at most max_area.
+size_t resident_area_bytes(int maxL, int nt, size_t max_area);
 
 // Launch the resident kernel over `n` work items (device array), all with
 // L <= maxL.  Returns hipSuccess or the launch error.

@@ -16,6 +16,8 @@
 //   mean and update (Steps 3-4)  fused into the lower-envelope evaluation.
 // Serialization (Sec. 3.2) and the EEMD noise (Sec. 2.2) are fused into the
 // first load; deserialization (Sec. 3.3) into the IMF and residue stores.
+#include <algorithm>
+
 #include "semd_internal.h"
 
 namespace semd {
@@ -151,7 +153,7 @@ __device__ __forceinline__ void detect_extrema(const double (&h)[C], int base, i
   cmax = 0;
   cmin = 0;
   int cur = carry;
-#pragma unroll
+#pragma unroll 1
   for (int c = 0; c < C; ++c) {
     if (c < nv) {
       const int k = base + c;
@@ -181,7 +183,7 @@ __device__ __forceinline__ void emit_knots(const double (&h)[C], unsigned bits, 
   const int hi = 2 * (L - 1);
   int g = first;
   int start = carry >> 2;
-#pragma unroll
+#pragma unroll 1
   for (int c = 0; c < C; ++c) {
     if (c < nv) {
       const int k = base + c;
@@ -202,6 +204,20 @@ __device__ __forceinline__ void emit_knots(const double (&h)[C], unsigned bits, 
 }
 
 // ---------------------------------------------------------------------------
+// Arithmetic helpers
+// ---------------------------------------------------------------------------
+
+// 1/x for positive normal x: the hardware reciprocal estimate refined by two
+// Newton-Raphson steps r <- r + r (1 - x r); within an ulp of 1/x.
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// ---------------------------------------------------------------------------
 // Natural cubic spline (Sec. 2.1 Step 2): second derivatives
 // ---------------------------------------------------------------------------
 
@@ -210,161 +226,188 @@ __device__ __forceinline__ void emit_knots(const double (&h)[C], unsigned bits, 
 //       = 6 ((y_{j+1} - y_j)/g_j - (y_j - y_{j-1})/g_{j-1}).
 // The interior unknowns are cut into chunks of kChunk; one thread solves a
 // chunk by a forward Thomas sweep that starts kHalo rows before the chunk and
-// a backward sweep that starts kHalo rows after it, joined at the chunk's last
-// row.  Windows that reach the true ends of the system are exact; elsewhere
-// the dropped coupling beyond the window is damped by at least (2-sqrt 3)^kHalo
-// (the system is symmetric and diagonally dominant by a factor 2 in every
-// row, so its Jacobi-scaled inverse decays geometrically), far below FP64
-// rounding.
-template <int NT>
-__device__ void spline_second_derivs(const int16_t* __restrict__ kt,
-                                     const double* __restrict__ ky, double* __restrict__ km,
-                                     int n, int tid) {
-  const int nint = n - 2;
-  const int nch = (nint + kChunk - 1) / kChunk;
-  for (int ch = tid; ch < nch; ch += NT) {
-    const int s = 1 + ch * kChunk;
-    const int e = min(s + kChunk - 1, n - 2);
-    const int ws = max(1, s - kHalo);
-    const int we = min(n - 2, e + kHalo);
+// a backward sweep that starts kHalo rows after it (run interleaved, they are
+// independent), joined at the chunk's last row, then back-substitutes.
+// Windows that reach the true ends of the system are exact; elsewhere the
+// dropped coupling beyond the window is damped by at least (2-sqrt 3)^kHalo:
+// the matrix is symmetric and diagonally dominant by a factor 2 in every row,
+// so its Jacobi-scaled form has condition number at most 3 and an inverse
+// whose entries decay geometrically with that ratio.
+__device__ __forceinline__ void solve_chunk(const int16_t* __restrict__ kt,
+                                            const double* __restrict__ ky,
+                                            double* __restrict__ km, int n, int ch) {
+  const int s = 1 + ch * kChunk;
+  const int e = min(s + kChunk - 1, n - 2);
+  const int ws = max(1, s - kHalo);
+  const int we = min(n - 2, e + kHalo);
 
-    double tprev = (double)kt[ws - 1], t = (double)kt[ws];
-    double yprev = ky[ws - 1], y = ky[ws];
-    double sprev = (y - yprev) / (t - tprev);
-    double cp = 0.0, dp = 0.0;  // row ws-1 stands in for the dropped coupling
-    for (int j = ws; j < s; ++j) {
+  // forward sweep, positioned at row ws with row ws-1 standing in for the
+  // coupling it drops (cp = dp = 0)
+  double ftp = (double)kt[ws - 1], ft = (double)kt[ws];
+  double fy = ky[ws];
+  double fsp = (fy - ky[ws - 1]) * recip(ft - ftp);
+  double cp = 0.0, dp = 0.0;
+  // backward sweep, positioned at row we with row we+1 standing in likewise
+  double btn = (double)kt[we + 1], bt = (double)kt[we];
+  double by = ky[we];
+  double bsn = (ky[we + 1] - by) * recip(btn - bt);
+  double aa = 0.0, dd = 0.0;
+
+  const int nf = s - ws;                    // forward halo rows ws .. s-1
+  const int nb = (e < n - 2) ? we - e : 0;  // backward rows we .. e+1
+  const int steps = max(nf, nb);
+  for (int i = 0; i < steps; ++i) {
+    if (i < nf) {
+      const int j = ws + i;
       const double tn = (double)kt[j + 1], yn = ky[j + 1];
-      const double g0 = t - tprev, g1 = tn - t;
-      const double sn = (yn - y) / g1;
-      const double rhs = 6.0 * (sn - sprev);
-      const double den = 2.0 * (g0 + g1) - g0 * cp;
-      cp = g1 / den;
-      dp = (rhs - g0 * dp) / den;
-      tprev = t; t = tn; yprev = y; y = yn; sprev = sn;
+      const double g0 = ft - ftp, g1 = tn - ft;
+      const double sn = (yn - fy) * recip(g1);
+      const double rhs = 6.0 * (sn - fsp);
+      const double inv = recip(fma(-g0, cp, 2.0 * (g0 + g1)));
+      cp = g1 * inv;
+      dp = fma(-g0, dp, rhs) * inv;
+      ftp = ft; ft = tn; fy = yn; fsp = sn;
     }
-    double cpa[kChunk], dpa[kChunk];
-#pragma unroll
-    for (int q = 0; q < kChunk; ++q) {
-      cpa[q] = 0.0;
-      dpa[q] = 0.0;
-      if (s + q <= e) {
-        const int j = s + q;
-        const double tn = (double)kt[j + 1], yn = ky[j + 1];
-        const double g0 = t - tprev, g1 = tn - t;
-        const double sn = (yn - y) / g1;
-        const double rhs = 6.0 * (sn - sprev);
-        const double den = 2.0 * (g0 + g1) - g0 * cp;
-        cp = g1 / den;
-        dp = (rhs - g0 * dp) / den;
-        cpa[q] = cp;
-        dpa[q] = dp;
-        tprev = t; t = tn; yprev = y; y = yn; sprev = sn;
-      }
-    }
-    double Me;
-    if (e < n - 2) {
-      double tnx = (double)kt[we + 1], tt = (double)kt[we];
-      double ynx = ky[we + 1], yy = ky[we];
-      double snx = (ynx - yy) / (tnx - tt);
-      double aa = 0.0, dd = 0.0;  // row we+1 stands in for the dropped coupling
-      for (int j = we; j > e; --j) {
-        const double tp = (double)kt[j - 1], yp = ky[j - 1];
-        const double g1 = tnx - tt, g0 = tt - tp;
-        const double sp = (yy - yp) / g0;
-        const double rhs = 6.0 * (snx - sp);
-        const double den = 2.0 * (g0 + g1) - g1 * aa;
-        aa = g0 / den;
-        dd = (rhs - g1 * dd) / den;
-        tnx = tt; tt = tp; ynx = yy; yy = yp; snx = sp;
-      }
-      // M_e = dp - cp M_{e+1} and M_{e+1} = dd - aa M_e
-      Me = (dp - cp * dd) / (1.0 - cp * aa);
-    } else {
-      Me = dp;  // last row: M_{n-1} = 0
-    }
-    km[e] = Me;
-    double Mn = Me;
-#pragma unroll
-    for (int q = kChunk - 1; q >= 0; --q) {
-      if (s + q < e) {
-        Mn = dpa[q] - cpa[q] * Mn;
-        km[s + q] = Mn;
-      }
+    if (i < nb) {
+      const int j = we - i;
+      const double tp = (double)kt[j - 1], yp = ky[j - 1];
+      const double g1 = btn - bt, g0 = bt - tp;
+      const double sp = (by - yp) * recip(g0);
+      const double rhs = 6.0 * (bsn - sp);
+      const double inv = recip(fma(-g1, aa, 2.0 * (g0 + g1)));
+      aa = g0 * inv;
+      dd = fma(-g1, dd, rhs) * inv;
+      btn = bt; bt = tp; by = yp; bsn = sp;
     }
   }
-  if (tid == 0) {
-    km[0] = 0.0;
-    km[n - 1] = 0.0;
+  double cpa[kChunk], dpa[kChunk];
+#pragma unroll
+  for (int q = 0; q < kChunk; ++q) {
+    cpa[q] = 0.0;
+    dpa[q] = 0.0;
+    if (s + q <= e) {
+      const int j = s + q;
+      const double tn = (double)kt[j + 1], yn = ky[j + 1];
+      const double g0 = ft - ftp, g1 = tn - ft;
+      const double sn = (yn - fy) * recip(g1);
+      const double rhs = 6.0 * (sn - fsp);
+      const double inv = recip(fma(-g0, cp, 2.0 * (g0 + g1)));
+      cp = g1 * inv;
+      dp = fma(-g0, dp, rhs) * inv;
+      cpa[q] = cp;
+      dpa[q] = dp;
+      ftp = ft; ft = tn; fy = yn; fsp = sn;
+    }
+  }
+  // M_e = dp - cp M_{e+1} with M_{e+1} = dd - aa M_e from the right, or
+  // M_e = dp on the last row (M_{n-1} = 0)
+  const double Me = (e < n - 2) ? fma(-cp, dd, dp) * recip(fma(-cp, aa, 1.0)) : dp;
+  km[e] = Me;
+  double Mn = Me;
+#pragma unroll
+  for (int q = kChunk - 1; q >= 0; --q) {
+    if (s + q < e) {
+      Mn = fma(-cpa[q], Mn, dpa[q]);
+      km[s + q] = Mn;
+    }
   }
 }
 
-// Evaluate the spline at this thread's samples.  j0 is a knot index with
-// t_{j0} <= base; the walk advances j while t_{j+1} <= k (the last of the n
-// knots lies beyond the signal, so the walk never passes it).  UPDATE = false
-// stores the envelope in env; UPDATE = true finishes the sift:
-// h <- h - (env_upper + env_lower) / 2 with env holding the upper envelope.
-template <int C, bool UPDATE>
-__device__ __forceinline__ void eval_envelope(const int16_t* __restrict__ kt,
-                                              const double* __restrict__ ky,
-                                              const double* __restrict__ km, int n, int j0,
-                                              int base, int nv, double (&env)[C],
-                                              double (&h)[C]) {
-  if (nv <= 0) return;
-  int j = j0;
-  double t0 = (double)kt[j], y0 = ky[j], m0 = km[j];
-  double t1 = (double)kt[j + 1], y1 = ky[j + 1], m1 = km[j + 1];
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    if (c < nv) {
-      const double kk = (double)(base + c);
-      while (t1 <= kk && j + 2 < n) {
-        ++j;
-        t0 = t1; y0 = y1; m0 = m1;
-        t1 = (double)kt[j + 1]; y1 = ky[j + 1]; m1 = km[j + 1];
-      }
-      const double g = t1 - t0;
-      const double A = t1 - kk;
-      const double B = kk - t0;
-      const double A3 = A * A * A;
-      const double B3 = B * B * B;
-      const double g2 = g * g;
-      const double cub = (m0 * A3 + m1 * B3) / (6.0 * g);
-      const double lin = (y0 - m0 * g2 / 6.0) * A / g + (y1 - m1 * g2 / 6.0) * B / g;
-      const double v = cub + lin;
-      if (UPDATE) {
-        const double mean = 0.5 * (env[c] + v);
-        h[c] = h[c] - mean;
-      } else {
-        env[c] = v;
-      }
-    }
+// Second derivatives of up to two independent knot systems held in LDS: n1
+// knots at offset 0 and n2 knots at offset o2 (n = 0: no system).  Their
+// chunks are spread over the workgroup's threads.
+template <int NT>
+__device__ void spline_second_derivs(const int16_t* __restrict__ kt,
+                                     const double* __restrict__ ky, double* __restrict__ km,
+                                     int n1, int o2, int n2, int tid) {
+  const int c1 = n1 >= 3 ? (n1 - 2 + kChunk - 1) / kChunk : 0;
+  const int c2 = n2 >= 3 ? (n2 - 2 + kChunk - 1) / kChunk : 0;
+  for (int ch = tid; ch < c1 + c2; ch += NT) {
+    const bool second = ch >= c1;
+    const int o = second ? o2 : 0;
+    solve_chunk(kt + o, ky + o, km + o, second ? n2 : n1, second ? ch - c1 : ch);
   }
+  if (tid == 0) {
+    if (n1 >= 3) { km[0] = 0.0; km[n1 - 1] = 0.0; }
+    if (n2 >= 3) { km[o2] = 0.0; km[o2 + n2 - 1] = 0.0; }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Spline evaluation: one walker per envelope and thread
+// ---------------------------------------------------------------------------
+
+// The current segment [t0, t1) of a walker, in the form
+//   S(k) = a3 A^3 + b3 B^3 + p A + q B,  A = t1 - k,  B = k - t0,
+// with a3 = M_j/(6g), b3 = M_{j+1}/(6g), p = (y_j - M_j g^2/6)/g and
+// q = (y_{j+1} - M_{j+1} g^2/6)/g (g = t1 - t0): the textbook form of the
+// natural spline on a segment, with its divisions done once per segment.
+struct Seg {
+  int j;
+  double t0, t1;
+  double a3, b3, p, q;
+};
+
+__device__ __forceinline__ void seg_load(Seg& s, const int16_t* __restrict__ kt,
+                                         const double* __restrict__ ky,
+                                         const double* __restrict__ km, int j) {
+  s.j = j;
+  s.t0 = (double)kt[j];
+  s.t1 = (double)kt[j + 1];
+  const double y0 = ky[j], m0 = km[j], y1 = ky[j + 1], m1 = km[j + 1];
+  const double g = s.t1 - s.t0;
+  const double ig = recip(g);
+  const double ig6 = ig * (1.0 / 6.0);
+  const double g26 = g * g * (1.0 / 6.0);
+  s.a3 = m0 * ig6;
+  s.b3 = m1 * ig6;
+  s.p = fma(-m0, g26, y0) * ig;
+  s.q = fma(-m1, g26, y1) * ig;
+}
+
+// Value at sample k; advances while t_{j+1} <= k (the last of the n knots
+// lies beyond the signal, so the walk never passes it).
+__device__ __forceinline__ double seg_eval(Seg& s, const int16_t* __restrict__ kt,
+                                           const double* __restrict__ ky,
+                                           const double* __restrict__ km, int n, double k) {
+  while (s.t1 <= k && s.j + 2 < n) seg_load(s, kt, ky, km, s.j + 1);
+  const double A = s.t1 - k, B = k - s.t0;
+  const double A3 = A * A * A, B3 = B * B * B;
+  return fma(s.a3, A3, fma(s.b3, B3, fma(s.p, A, s.q * B)));
 }
 
 // ---------------------------------------------------------------------------
 // Resident Serial-EMD kernel: one workgroup per work item
 // ---------------------------------------------------------------------------
 
+// LDS: 256 B of wave totals, then one area (area_bytes) used in turn as
+//   - the staging buffer of the signal (L doubles) at load and IMF ends,
+//   - the published block ends of the extremum detection (20 B per thread),
+//   - the knot store: capk values, capk second derivatives, capk abscissae.
+// A sift keeps both envelopes' knots in the store when they fit together
+// (one solve, one fused evaluation and update); otherwise it builds them one
+// after the other, parking the upper envelope in global memory.
 template <int NT, int C>
 __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __restrict__ items,
-                                                          int K, int S) {
+                                                          int K, int S, int area_bytes) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NW = NT / kWave;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wid = tid / kWave;
   const WorkItem w = items[blockIdx.x];
+  // the resident path holds at most kResidentMaxL samples: 32-bit indices
   const int L = w.L;
-  const int64_t M = w.M, MN = w.M * w.N, R = w.M + w.D;
+  const int M = (int)w.M, MN = (int)(w.M * w.N), R = (int)(w.M + w.D);
   const int D = w.D;
 
   int* wagg = reinterpret_cast<int*>(smem);
   unsigned char* area = smem + kAggBytes;
-  const int cap = knot_cap(L);
+  const int capk = (area_bytes / (2 * (int)sizeof(double) + (int)sizeof(int16_t))) & ~7;
   double* stage = reinterpret_cast<double*>(area);
   double* ky = reinterpret_cast<double*>(area);
-  double* km = ky + cap;
-  int16_t* kt = reinterpret_cast<int16_t*>(km + cap);
+  double* km = ky + capk;
+  int16_t* kt = reinterpret_cast<int16_t*>(km + capk);
   double* pub_first = reinterpret_cast<double*>(area);
   double* pub_last = pub_first + NT;
   int* pub_key = reinterpret_cast<int*>(pub_last + NT);
@@ -374,8 +417,8 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
 
   // Load: serialize (Sec. 3.2), add the realization's noise (Sec. 2.2 Step 1)
   int bad = 0;
-  for (int64_t k = tid; k < L; k += NT) {
-    const int64_t i = k / R, m = k - i * R;
+  for (int k = tid; k < L; k += NT) {
+    const int i = k / R, m = k - i * R;
     double v = serial_at(w.X, M, D, i, m);
     if (w.flags & 1) v = __dadd_rn(v, __dmul_rn(w.beta, noise_at(w.key, k)));
     bad |= !isfinite(v);
@@ -392,6 +435,7 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
   for (int c = 0; c < C; ++c) h[c] = (c < nv) ? stage[base + c] : 0.0;
 
   int nimf = 0;
+  int64_t n_sifts = 0, n_knots = 0;
   while (nimf < K) {
     bool stop = false;
     for (int s = 0; s < S; ++s) {
@@ -408,22 +452,63 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
         break;
       }
       const int emax = excl >> 16, emin = excl & 0xffff;
-      double U[C];
-      // upper envelope through the maxima
-      emit_knots<C>(h, maxbits, carry, base, nv, L, emax, nmax, kt, ky);
-      __syncthreads();
-      const int pmax = nmax < 2 ? nmax : 2;
-      spline_second_derivs<NT>(kt, ky, km, nmax + 2 * pmax, tid);
-      __syncthreads();
-      eval_envelope<C, false>(kt, ky, km, nmax + 2 * pmax, pmax + emax - 1, base, nv, U, h);
-      __syncthreads();
-      // lower envelope through the minima, then mean removal
-      emit_knots<C>(h, minbits, carry, base, nv, L, emin, nmin, kt, ky);
-      __syncthreads();
-      const int pmin = nmin < 2 ? nmin : 2;
-      spline_second_derivs<NT>(kt, ky, km, nmin + 2 * pmin, tid);
-      __syncthreads();
-      eval_envelope<C, true>(kt, ky, km, nmin + 2 * pmin, pmin + emin - 1, base, nv, U, h);
+      const int pmax = nmax < 2 ? nmax : 2, pmin = nmin < 2 ? nmin : 2;
+      const int nkmax = nmax + 2 * pmax, nkmin = nmin + 2 * pmin;
+      ++n_sifts;
+      n_knots += nkmax + nkmin;
+      if (nkmax + nkmin <= capk) {
+        // both envelopes at once
+        emit_knots<C>(h, maxbits, carry, base, nv, L, emax, nmax, kt, ky);
+        emit_knots<C>(h, minbits, carry, base, nv, L, emin, nmin, kt + nkmax, ky + nkmax);
+        __syncthreads();
+        spline_second_derivs<NT>(kt, ky, km, nkmax, nkmax, nkmin, tid);
+        __syncthreads();
+        if (nv > 0) {
+          Seg su, sl;
+          seg_load(su, kt, ky, km, pmax + emax - 1);
+          seg_load(sl, kt + nkmax, ky + nkmax, km + nkmax, pmin + emin - 1);
+#pragma unroll 1
+          for (int c = 0; c < C; ++c) {
+            if (c < nv) {
+              const double kk = (double)(base + c);
+              const double up = seg_eval(su, kt, ky, km, nkmax, kk);
+              const double lo = seg_eval(sl, kt + nkmax, ky + nkmax, km + nkmax, nkmin, kk);
+              const double mean = 0.5 * (up + lo);
+              h[c] = h[c] - mean;
+            }
+          }
+        }
+      } else {
+        // one envelope at a time
+        emit_knots<C>(h, maxbits, carry, base, nv, L, emax, nmax, kt, ky);
+        __syncthreads();
+        spline_second_derivs<NT>(kt, ky, km, nkmax, 0, 0, tid);
+        __syncthreads();
+        if (nv > 0) {
+          Seg su;
+          seg_load(su, kt, ky, km, pmax + emax - 1);
+#pragma unroll 1
+          for (int c = 0; c < C; ++c)
+            if (c < nv) w.u[base + c] = seg_eval(su, kt, ky, km, nkmax, (double)(base + c));
+        }
+        __syncthreads();
+        emit_knots<C>(h, minbits, carry, base, nv, L, emin, nmin, kt, ky);
+        __syncthreads();
+        spline_second_derivs<NT>(kt, ky, km, nkmin, 0, 0, tid);
+        __syncthreads();
+        if (nv > 0) {
+          Seg sl;
+          seg_load(sl, kt, ky, km, pmin + emin - 1);
+#pragma unroll 1
+          for (int c = 0; c < C; ++c) {
+            if (c < nv) {
+              const double lo = seg_eval(sl, kt, ky, km, nkmin, (double)(base + c));
+              const double mean = 0.5 * (w.u[base + c] + lo);
+              h[c] = h[c] - mean;
+            }
+          }
+        }
+      }
     }
     if (stop) break;
     // IMF nimf = h (deserialized store, Sec. 3.3); residue r <- r - h
@@ -433,12 +518,12 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
       if (c < nv) stage[base + c] = h[c];
     __syncthreads();
     double* slot = w.out + (int64_t)nimf * MN;
-    for (int64_t k = tid; k < L; k += NT) {
+    for (int k = tid; k < L; k += NT) {
       const double hk = stage[k];
       const double nr = w.r[k] - hk;
       w.r[k] = nr;
       stage[k] = nr;
-      const int64_t i = k / R, m = k - i * R;
+      const int i = k / R, m = k - i * R;
       if (m < M) slot[i * M + m] = hk;
     }
     ++nimf;
@@ -448,16 +533,19 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
   }
   // residue into slot K, unused IMF slots zero (Sec. 4.3 zero fill)
   double* rslot = w.out + (int64_t)K * MN;
-  for (int64_t k = tid; k < L; k += NT) {
-    const int64_t i = k / R, m = k - i * R;
+  for (int k = tid; k < L; k += NT) {
+    const int i = k / R, m = k - i * R;
     if (m < M) rslot[i * M + m] = w.r[k];
   }
   for (int64_t o = (int64_t)nimf * MN + tid; o < (int64_t)K * MN; o += NT) w.out[o] = 0.0;
   if (tid == 0 && w.n_imfs) *w.n_imfs = nimf;
+  if (tid == 0 && w.stats) {
+    w.stats[0] = n_sifts;
+    w.stats[1] = n_knots;
+    w.stats[2] = n_sifts * (int64_t)L;
+  }
 }
 
-// Extrema of one 1D signal through the same detection code; indices are
-// written straight to global memory.
 template <int NT, int C>
 __global__ void __launch_bounds__(NT) extrema_kernel(const double* __restrict__ hin, int L,
                                                      int32_t* __restrict__ imax,
@@ -560,16 +648,25 @@ inline int grid_for(int64_t n, int threads) {
   return (int)g;
 }
 
-template <int NT>
-hipError_t launch_resident_nt(const WorkItem* d_items, int n, int maxL, int K, int S,
-                              hipStream_t stream) {
-  constexpr int C = 16;
-  const size_t lds = resident_lds_bytes(maxL, NT);
+template <int NT, int C>
+hipError_t launch_resident_cls(const WorkItem* d_items, int n, int maxL, int K, int S,
+                               hipStream_t stream) {
   auto kern = resident_emd_kernel<NT, C>;
+  // LDS per workgroup is 160 KiB, shared with the kernel's static LDS
+  static const int static_lds = [&] {
+    hipFuncAttributes a{};
+    return hipFuncGetAttributes(&a, reinterpret_cast<const void*>(kern)) == hipSuccess
+               ? (int)a.sharedSizeBytes
+               : 1024;
+  }();
+  const size_t limit = 160 * 1024 - (size_t)static_lds;
+  const size_t area = resident_area_bytes(maxL, NT, limit - kAggBytes);
+  const size_t lds = kAggBytes + area;
+  if (lds > limit) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(n), dim3(NT), lds, stream, d_items, K, S);
+  hipLaunchKernelGGL(kern, dim3(n), dim3(NT), lds, stream, d_items, K, S, (int)area);
   return hipGetLastError();
 }
 
@@ -579,29 +676,46 @@ hipError_t launch_resident_nt(const WorkItem* d_items, int n, int maxL, int K, i
 // Launchers
 // ---------------------------------------------------------------------------
 
-int resident_threads(int maxL) {
-  if (maxL <= 256 * 16) return 256;
-  if (maxL <= 512 * 16) return 512;
-  return 1024;
+// Threads and samples per thread for signals up to maxL samples.
+ResidentClass resident_class(int maxL) {
+  if (maxL <= 256 * 4) return {256, 4};
+  if (maxL <= 256 * 8) return {256, 8};
+  if (maxL <= 256 * 12) return {256, 12};
+  if (maxL <= 256 * 16) return {256, 16};
+  if (maxL <= 512 * 12) return {512, 12};
+  if (maxL <= 512 * 16) return {512, 16};
+  if (maxL <= 1024 * 12) return {1024, 12};
+  return {1024, 16};
 }
 
-size_t resident_lds_bytes(int maxL, int nt) {
-  const size_t cap = (size_t)knot_cap(maxL);
-  size_t area = align16(cap * (2 * sizeof(double) + sizeof(int16_t)));
-  const size_t stage = align16((size_t)maxL * sizeof(double));
-  const size_t pub = align16((size_t)nt * (2 * sizeof(double) + sizeof(int)));
-  if (stage > area) area = stage;
-  if (pub > area) area = pub;
-  return kAggBytes + area;
+size_t resident_area_bytes(int maxL, int nt, size_t max_area) {
+  const size_t per_knot = 2 * sizeof(double) + sizeof(int16_t);
+  const size_t stage = (size_t)maxL * sizeof(double);
+  const size_t pub = (size_t)nt * (2 * sizeof(double) + sizeof(int));
+  // one envelope at a time must always fit (at most (L-1)/2 + 4 knots each)
+  const size_t single = per_knot * ((size_t)knot_cap(maxL) + 8);
+  // both envelopes together (at most L + 6 knots) when the budget allows:
+  // 2 workgroups per CU below 1024 threads, one above
+  const size_t dual = per_knot * ((size_t)maxL + 16);
+  const size_t budget = std::min(max_area, nt >= 1024 ? max_area : max_area / 2 - 512);
+  size_t area = std::min(dual, budget);
+  area = std::max(area, std::max(stage, std::max(pub, single)));
+  return align16(area) <= max_area ? align16(area) : max_area & ~size_t(15);
 }
 
 hipError_t launch_resident(const WorkItem* d_items, int n, int maxL, int K, int S,
                            hipStream_t stream) {
   if (n <= 0) return hipSuccess;
-  switch (resident_threads(maxL)) {
-    case 256: return launch_resident_nt<256>(d_items, n, maxL, K, S, stream);
-    case 512: return launch_resident_nt<512>(d_items, n, maxL, K, S, stream);
-    default: return launch_resident_nt<1024>(d_items, n, maxL, K, S, stream);
+  const ResidentClass c = resident_class(maxL);
+  switch (c.nt * 100 + c.c) {
+    case 25604: return launch_resident_cls<256, 4>(d_items, n, maxL, K, S, stream);
+    case 25608: return launch_resident_cls<256, 8>(d_items, n, maxL, K, S, stream);
+    case 25612: return launch_resident_cls<256, 12>(d_items, n, maxL, K, S, stream);
+    case 25616: return launch_resident_cls<256, 16>(d_items, n, maxL, K, S, stream);
+    case 51212: return launch_resident_cls<512, 12>(d_items, n, maxL, K, S, stream);
+    case 51216: return launch_resident_cls<512, 16>(d_items, n, maxL, K, S, stream);
+    case 102412: return launch_resident_cls<1024, 12>(d_items, n, maxL, K, S, stream);
+    default: return launch_resident_cls<1024, 16>(d_items, n, maxL, K, S, stream);
   }
 }
 
