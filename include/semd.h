@@ -60,17 +60,23 @@ typedef enum {
 
 typedef enum { SEMD_BOUNDARY_MIRROR = 0 } semd_boundary;
 
+/* Execution path.  AUTO: one workgroup decomposes a signal on chip when its
+ * serialized length is at most semd_resident_max_length(), the streaming
+ * path (many workgroups per signal, state in device memory) otherwise.  The
+ * two paths compute the same decomposition within rounding. */
+typedef enum { SEMD_PATH_AUTO = 0, SEMD_PATH_ONCHIP = 1, SEMD_PATH_STREAM = 2 } semd_path;
+
 /* Method parameters.  transition_len is D of Sec. 3.2 (0 <= D <= M);
  * max_imfs is K >= 1; sift_iters is S >= 1; ensemble is the number NR >= 1 of
- * EEMD realizations (Sec. 2.2, used by semd_eemd_batch only); seed keys the
- * EEMD noise. */
+ * EEMD realizations (Sec. 2.2, used by semd_eemd_batch only); path is a
+ * semd_path; seed keys the EEMD noise. */
 typedef struct {
   int32_t transition_len;
   int32_t max_imfs;
   int32_t sift_iters;
   int32_t boundary_rule;
   int32_t ensemble;
-  int32_t reserved; /* must be 0 */
+  int32_t path;
   uint64_t seed;
 } semd_params;
 
@@ -107,7 +113,8 @@ const char* semd_last_error(void);
 int64_t semd_serial_length(int64_t M, int64_t N, int64_t D);
 
 /* Longest serialized signal the single-workgroup on-chip path takes (longer
- * signals go to the multi-workgroup streaming path). */
+ * signals go to the multi-workgroup streaming path).  Any path accepts
+ * serialized lengths up to 2^28; longer ones return SEMD_EUNSUPPORTED. */
 int64_t semd_resident_max_length(void);
 
 /* ---- the method --------------------------------------------------------- */

@@ -31,6 +31,9 @@ SEMD_EBUSY = 4
 SEMD_ENONFINITE = 5
 SEMD_EUNSUPPORTED = 6
 SEMD_BOUNDARY_MIRROR = 0
+SEMD_PATH_AUTO = 0
+SEMD_PATH_ONCHIP = 1
+SEMD_PATH_STREAM = 2
 
 
 class SemdError(RuntimeError):
@@ -42,7 +45,7 @@ class SemdError(RuntimeError):
 class semd_params(C.Structure):
     _fields_ = [("transition_len", C.c_int32), ("max_imfs", C.c_int32),
                 ("sift_iters", C.c_int32), ("boundary_rule", C.c_int32),
-                ("ensemble", C.c_int32), ("reserved", C.c_int32), ("seed", C.c_uint64)]
+                ("ensemble", C.c_int32), ("path", C.c_int32), ("seed", C.c_uint64)]
 
 
 class semd_item(C.Structure):
@@ -126,8 +129,8 @@ def _dims(dims: Sequence[int]):
 
 
 def _params(D: int, K: int, S: int, NR: int = 1, seed: int = 0,
-            boundary_rule: int = SEMD_BOUNDARY_MIRROR) -> semd_params:
-    return semd_params(int(D), int(K), int(S), int(boundary_rule), int(NR), 0,
+            boundary_rule: int = SEMD_BOUNDARY_MIRROR, path: int = SEMD_PATH_AUTO) -> semd_params:
+    return semd_params(int(D), int(K), int(S), int(boundary_rule), int(NR), int(path),
                        int(seed) & (2**64 - 1))
 
 
@@ -165,7 +168,8 @@ def semd_decompose(signal: torch.Tensor, dims: Sequence[int], max_imfs: int, sif
 
 def semd_decompose_ex(signal: torch.Tensor, dims: Sequence[int], D: int, max_imfs: int,
                       sift_iters: int, imfs_out: torch.Tensor | None = None,
-                      n_imfs_out: torch.Tensor | None = None, stream=None):
+                      n_imfs_out: torch.Tensor | None = None, stream=None,
+                      path: int = SEMD_PATH_AUTO):
     """Plain path: one signal per launch.  Returns (imfs_out, n_imfs_out)."""
     d, nd = _dims(dims)
     MN = 1
@@ -176,7 +180,7 @@ def semd_decompose_ex(signal: torch.Tensor, dims: Sequence[int], D: int, max_imf
         imfs_out = torch.empty((max_imfs + 1, MN), dtype=torch.float64, device=dev)
     if n_imfs_out is None:
         n_imfs_out = torch.empty(1, dtype=torch.int32, device=dev)
-    p = _params(D, max_imfs, sift_iters)
+    p = _params(D, max_imfs, sift_iters, path=path)
     _check(lib().semd_decompose_ex(_dev_f64(signal, "signal"), d, nd, C.byref(p),
                                    _dev_f64(imfs_out, "imfs_out"), n_imfs_out.data_ptr(),
                                    _stream(stream)), "semd_decompose_ex")
@@ -207,14 +211,14 @@ def _items(signals, dims_list, outs, counts, sigmas=None, item_ids=None, stats=N
 def semd_decompose_batch(signals: Sequence[torch.Tensor], dims_list: Sequence[Sequence[int]],
                          outs: Sequence[torch.Tensor], counts: torch.Tensor | None, D: int,
                          max_imfs: int, sift_iters: int, stats: torch.Tensor | None = None,
-                         stream=None) -> None:
+                         stream=None, path: int = SEMD_PATH_AUTO) -> None:
     """Batched path: every signal in one launch.  counts: int32 tensor of
     len(signals) entries (or None); stats: int64 tensor (len(signals), 3) of
     (sifts, knots, sample-sifts) per signal (or None)."""
     cviews = [counts[i:i + 1] for i in range(len(signals))] if counts is not None else None
     sviews = [stats[i] for i in range(len(signals))] if stats is not None else None
     arr, n = _items(signals, dims_list, outs, cviews, stats=sviews)
-    p = _params(D, max_imfs, sift_iters)
+    p = _params(D, max_imfs, sift_iters, path=path)
     _check(lib().semd_decompose_batch(arr, n, C.byref(p), _stream(stream)),
            "semd_decompose_batch")
 
@@ -223,11 +227,11 @@ def semd_eemd_batch(signals: Sequence[torch.Tensor], dims_list: Sequence[Sequenc
                     outs: Sequence[torch.Tensor], counts: torch.Tensor | None, D: int,
                     max_imfs: int, sift_iters: int, ensemble: int, seed: int,
                     noise_sigmas: Sequence[float], item_ids: Sequence[int] | None = None,
-                    stream=None) -> None:
+                    stream=None, path: int = SEMD_PATH_AUTO) -> None:
     """Serial-EEMD of every signal (NR = ensemble realizations each)."""
     cviews = [counts[i:i + 1] for i in range(len(signals))] if counts is not None else None
     arr, n = _items(signals, dims_list, outs, cviews, noise_sigmas, item_ids)
-    p = _params(D, max_imfs, sift_iters, ensemble, seed)
+    p = _params(D, max_imfs, sift_iters, ensemble, seed, path=path)
     _check(lib().semd_eemd_batch(arr, n, C.byref(p), _stream(stream)), "semd_eemd_batch")
 
 
@@ -281,18 +285,20 @@ def semd_noise(seed: int, item: int, m: int, L: int, w: torch.Tensor | None = No
 # conveniences
 # ---------------------------------------------------------------------------
 
-def decompose(X: torch.Tensor, M: int, N: int, D: int, K: int, S: int, stream=None):
+def decompose(X: torch.Tensor, M: int, N: int, D: int, K: int, S: int, stream=None,
+              path: int = SEMD_PATH_AUTO):
     """Serial-EMD of one column-major M x N signal set (plain path)."""
-    return semd_decompose_ex(X, [M, N], D, K, S, stream=stream)
+    return semd_decompose_ex(X, [M, N], D, K, S, stream=stream, path=path)
 
 
 def decompose_batch(Xs: Sequence[torch.Tensor], shapes: Sequence[tuple[int, int]], D: int, K: int,
-                    S: int, stream=None):
+                    S: int, stream=None, path: int = SEMD_PATH_AUTO):
     """Serial-EMD of many signal sets in one launch; returns (outs, counts)."""
     dev = Xs[0].device
     outs = [torch.empty((K + 1, M * N), dtype=torch.float64, device=dev) for (M, N) in shapes]
     counts = torch.empty(len(Xs), dtype=torch.int32, device=dev)
-    semd_decompose_batch(Xs, [list(s) for s in shapes], outs, counts, D, K, S, stream=stream)
+    semd_decompose_batch(Xs, [list(s) for s in shapes], outs, counts, D, K, S, stream=stream,
+                         path=path)
     return outs, counts
 
 
@@ -302,13 +308,14 @@ class PreparedBatch:
     repeatedly without rebuilding the descriptors."""
 
     def __init__(self, signals, dims_list, outs, counts=None, D=0, max_imfs=8, sift_iters=10,
-                 stats=None, ensemble=1, seed=0, noise_sigmas=None, item_ids=None):
+                 stats=None, ensemble=1, seed=0, noise_sigmas=None, item_ids=None,
+                 path=SEMD_PATH_AUTO):
         cviews = [counts[i:i + 1] for i in range(len(signals))] if counts is not None else None
         sviews = [stats[i] for i in range(len(signals))] if stats is not None else None
         self._keep = (list(signals), list(outs), counts, stats)
         self.items, self.n = _items(signals, dims_list, outs, cviews, noise_sigmas, item_ids,
                                     sviews)
-        self.params = _params(D, max_imfs, sift_iters, ensemble, seed)
+        self.params = _params(D, max_imfs, sift_iters, ensemble, seed, path=path)
         self.eemd = ensemble > 1 or noise_sigmas is not None
 
     def run(self, stream=None) -> None:

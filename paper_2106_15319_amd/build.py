@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libsemd.so")
-SOURCES = ["semd_kernels.hip", "semd_api.hip"]
+SOURCES = ["semd_kernels.hip", "semd_stream.hip", "semd_api.hip"]
 ARCH = os.environ.get("SEMD_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

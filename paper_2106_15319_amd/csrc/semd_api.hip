@@ -13,6 +13,7 @@
 
 #include "semd.h"
 #include "semd_internal.h"
+#include "semd_stream.h"
 
 namespace {
 
@@ -61,7 +62,8 @@ int check_params(const semd_params* p, bool ensemble) {
   if (p->boundary_rule != SEMD_BOUNDARY_MIRROR)
     return fail(SEMD_EINVAL, "unknown boundary_rule %d", p->boundary_rule);
   if (p->transition_len < 0) return fail(SEMD_EINVAL, "transition_len must be >= 0");
-  if (p->reserved != 0) return fail(SEMD_EINVAL, "params.reserved must be 0");
+  if (p->path < SEMD_PATH_AUTO || p->path > SEMD_PATH_STREAM)
+    return fail(SEMD_EINVAL, "unknown path %d", p->path);
   if (ensemble && p->ensemble < 1) return fail(SEMD_EINVAL, "ensemble must be >= 1");
   return SEMD_OK;
 }
@@ -119,23 +121,28 @@ int shape_of(const int64_t* dims, int ndim, int D, Shape* sh) {
   return SEMD_OK;
 }
 
-// Decompose `work` (host descriptors whose r fields hold offsets, in
-// doubles, into one workspace of ws_doubles) on the resident path.  Each item
-// owns 2 L doubles of it: the residue and a parking slot for an envelope.
-int run_resident(std::vector<semd::WorkItem>& work, int64_t ws_doubles, int K, int S,
-                 hipStream_t stream) {
+// Longest serialized signal: sample keys (4 * index + kind) are int32.
+constexpr int64_t kMaxL = int64_t(1) << 28;
+
+// Decompose `work` on the resident path: one workgroup per item, a workspace
+// of 2 L doubles per item (residue, parked envelope).
+int run_resident(std::vector<semd::WorkItem>& work, int K, int S, hipStream_t stream) {
   if (work.empty()) return SEMD_OK;
   // longest first, so the tail of each launch holds the short items
   std::stable_sort(work.begin(), work.end(),
                    [](const semd::WorkItem& a, const semd::WorkItem& b) { return a.L > b.L; });
+  int64_t ws_doubles = 0;
+  for (const auto& w : work) ws_doubles += 2 * (int64_t)w.L;
   double* ws = nullptr;
   hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&ws),
                                 sizeof(double) * (size_t)std::max<int64_t>(ws_doubles, 1), stream);
   if (e != hipSuccess)
     return fail(SEMD_ENOMEM, "workspace of %lld doubles", (long long)ws_doubles);
+  int64_t off = 0;
   for (auto& w : work) {
-    w.r = ws + reinterpret_cast<intptr_t>(w.r);
+    w.r = ws + off;
     w.u = w.r + w.L;
+    off += 2 * (int64_t)w.L;
   }
   void* d_items = nullptr;
   int rc = upload(work.data(), work.size() * sizeof(semd::WorkItem), stream, &d_items);
@@ -159,25 +166,149 @@ int run_resident(std::vector<semd::WorkItem>& work, int64_t ws_doubles, int K, i
   return rc;
 }
 
+// Device bytes the streaming path needs for one signal of L samples.
+size_t stream_bytes(int64_t L) {
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t cap = (size_t)((L - 1) / 2 + 12);
+  const size_t ntiles = (size_t)((L + semd::kTile - 1) / semd::kTile);
+  return 2 * al(sizeof(double) * (size_t)L) +
+         2 * (al(sizeof(int32_t) * cap) + 2 * al(sizeof(double) * cap)) +
+         al(sizeof(semd::TileInfo) * ntiles) + al(sizeof(semd::SigStatus));
+}
+
+// Decompose `work` on the streaming path: every sift of every signal as a
+// fixed sequence of tile / signal / knot-block launches over the batch.
+int run_stream(const std::vector<semd::WorkItem>& work, int K, int S, hipStream_t stream) {
+  const int n = (int)work.size();
+  if (n == 0) return SEMD_OK;
+  std::vector<semd::StreamSig> sigs(n);
+  std::vector<int2> tiles;
+  std::vector<int4> blocks;
+  size_t bytes = 0;
+  auto take = [&](size_t b) {
+    const size_t o = bytes;
+    bytes += (b + 255) & ~size_t(255);
+    return o;
+  };
+  // offsets into the arena first, pointers once it exists
+  std::vector<size_t> o_h(n), o_r(n), o_kt(2 * n), o_ky(2 * n), o_km(2 * n), o_ti(n), o_st(n);
+  for (int i = 0; i < n; ++i) {
+    const semd::WorkItem& w = work[i];
+    semd::StreamSig& g = sigs[i];
+    g = semd::StreamSig{};
+    g.X = w.X;
+    g.out = w.out;
+    g.n_imfs = w.n_imfs;
+    g.stats = w.stats;
+    g.M = w.M;
+    g.N = w.N;
+    g.D = w.D;
+    g.L = w.L;
+    g.beta = w.beta;
+    g.key = w.key;
+    g.flags = w.flags;
+    g.ntiles = (w.L + semd::kTile - 1) / semd::kTile;
+    g.cap = (w.L - 1) / 2 + 12;
+    o_h[i] = take(sizeof(double) * (size_t)w.L);
+    o_r[i] = take(sizeof(double) * (size_t)w.L);
+    for (int e = 0; e < 2; ++e) {
+      o_kt[2 * i + e] = take(sizeof(int32_t) * (size_t)g.cap);
+      o_ky[2 * i + e] = take(sizeof(double) * (size_t)g.cap);
+      o_km[2 * i + e] = take(sizeof(double) * (size_t)g.cap);
+    }
+    o_ti[i] = take(sizeof(semd::TileInfo) * (size_t)g.ntiles);
+    o_st[i] = take(sizeof(semd::SigStatus));
+    for (int t = 0; t < g.ntiles; ++t) tiles.push_back(make_int2(i, t));
+    const int nb = semd::stream_solve_blocks(g.cap);
+    for (int e = 0; e < 2; ++e)
+      for (int b = 0; b < nb; ++b) blocks.push_back(make_int4(i, e, b, 0));
+  }
+  unsigned char* arena = nullptr;
+  if (hipMallocAsync(reinterpret_cast<void**>(&arena), std::max<size_t>(bytes, 1), stream) !=
+      hipSuccess)
+    return fail(SEMD_ENOMEM, "streaming workspace of %zu bytes", bytes);
+  for (int i = 0; i < n; ++i) {
+    semd::StreamSig& g = sigs[i];
+    g.h = reinterpret_cast<double*>(arena + o_h[i]);
+    g.r = reinterpret_cast<double*>(arena + o_r[i]);
+    for (int e = 0; e < 2; ++e) {
+      g.kt[e] = reinterpret_cast<int32_t*>(arena + o_kt[2 * i + e]);
+      g.ky[e] = reinterpret_cast<double*>(arena + o_ky[2 * i + e]);
+      g.km[e] = reinterpret_cast<double*>(arena + o_km[2 * i + e]);
+    }
+    g.tinfo = reinterpret_cast<semd::TileInfo*>(arena + o_ti[i]);
+    g.st = reinterpret_cast<semd::SigStatus*>(arena + o_st[i]);
+  }
+  // one upload: signals, tiles, solve blocks
+  const size_t b_sig = sizeof(semd::StreamSig) * sigs.size();
+  const size_t b_til = sizeof(int2) * tiles.size();
+  const size_t b_blk = sizeof(int4) * blocks.size();
+  std::vector<unsigned char> pack(b_sig + b_til + b_blk);
+  std::memcpy(pack.data(), sigs.data(), b_sig);
+  std::memcpy(pack.data() + b_sig, tiles.data(), b_til);
+  std::memcpy(pack.data() + b_sig + b_til, blocks.data(), b_blk);
+  void* d_pack = nullptr;
+  int rc = upload(pack.data(), pack.size(), stream, &d_pack);
+  if (rc) { (void)hipFreeAsync(arena, stream); return rc; }
+  const auto* d_sigs = static_cast<const semd::StreamSig*>(d_pack);
+  const auto* d_tiles = reinterpret_cast<const int2*>(static_cast<unsigned char*>(d_pack) + b_sig);
+  const auto* d_blocks =
+      reinterpret_cast<const int4*>(static_cast<unsigned char*>(d_pack) + b_sig + b_til);
+  const int nt = (int)tiles.size(), nb = (int)blocks.size();
+  hipError_t e = semd::st_init(d_sigs, n, stream);
+  if (e == hipSuccess) e = semd::st_load(d_sigs, d_tiles, nt, stream);
+  for (int imf = 0; imf < K && e == hipSuccess; ++imf) {
+    for (int s = 0; s < S && e == hipSuccess; ++s)
+      e = semd::st_sift(d_sigs, n, d_tiles, nt, d_blocks, nb, s, stream);
+    if (e == hipSuccess) e = semd::st_imf_end(d_sigs, n, d_tiles, nt, stream);
+  }
+  if (e == hipSuccess) e = semd::st_final(d_sigs, d_tiles, nt, K, stream);
+  if (e != hipSuccess) rc = hip_fail(e, "streaming kernel launch");
+  (void)hipFreeAsync(d_pack, stream);
+  (void)hipFreeAsync(arena, stream);
+  return rc;
+}
+
+// Route every item to the on-chip path (one workgroup per signal) or the
+// streaming path, by `path` and length.
+int run_work(std::vector<semd::WorkItem>& work, int K, int S, int path, hipStream_t stream) {
+  std::vector<semd::WorkItem> onchip, streamed;
+  for (const auto& w : work) {
+    const bool fits = w.L <= semd::kResidentMaxL;
+    if (path == SEMD_PATH_STREAM || (path == SEMD_PATH_AUTO && !fits)) streamed.push_back(w);
+    else onchip.push_back(w);
+  }
+  int rc = run_resident(onchip, K, S, stream);
+  if (rc == SEMD_OK) rc = run_stream(streamed, K, S, stream);
+  return rc;
+}
+
 semd::WorkItem make_work(const double* X, double* out, int32_t* n_imfs, const Shape& sh, int D,
-                         int64_t r_offset, int64_t* stats = nullptr) {
+                         int64_t* stats = nullptr) {
   semd::WorkItem w{};
   w.X = X;
   w.out = out;
   w.n_imfs = n_imfs;
   w.stats = stats;
-  w.r = reinterpret_cast<double*>(static_cast<intptr_t>(r_offset));
   w.M = sh.M;
   w.N = sh.N;
   w.D = D;
   w.L = (int32_t)sh.L;
-  w.beta = 0.0;
-  w.key = 0;
-  w.flags = 0;
   return w;
 }
 
-int check_items(const semd_item* items, int n, int D, std::vector<Shape>& shapes) {
+int check_length(int64_t L, int path, int i) {
+  if (L > kMaxL)
+    return fail(SEMD_EUNSUPPORTED, "item %d: serialized length %lld exceeds %lld", i,
+                (long long)L, (long long)kMaxL);
+  if (path == SEMD_PATH_ONCHIP && L > semd::kResidentMaxL)
+    return fail(SEMD_EUNSUPPORTED,
+                "item %d: serialized length %lld exceeds the on-chip path limit %d", i,
+                (long long)L, semd::kResidentMaxL);
+  return SEMD_OK;
+}
+
+int check_items(const semd_item* items, int n, int D, int path, std::vector<Shape>& shapes) {
   if (n < 0) return fail(SEMD_EINVAL, "n must be >= 0");
   if (n > 0 && !items) return fail(SEMD_EINVAL, "items is NULL");
   shapes.resize(n);
@@ -191,10 +322,8 @@ int check_items(const semd_item* items, int n, int D, std::vector<Shape>& shapes
       std::snprintf(msg, sizeof(msg), "%s", g_err);
       return fail(rc, "item %d: %s", i, msg);
     }
-    if (shapes[i].L > semd::kResidentMaxL)
-      return fail(SEMD_EUNSUPPORTED,
-                  "item %d: serialized length %lld exceeds the on-chip path limit %d", i,
-                  (long long)shapes[i].L, semd::kResidentMaxL);
+    rc = check_length(shapes[i].L, path, i);
+    if (rc) return rc;
   }
   return SEMD_OK;
 }
@@ -223,12 +352,10 @@ int semd_decompose_ex(const double* signal, const int64_t* dims, int ndim, const
   Shape sh;
   rc = shape_of(dims, ndim, p->transition_len, &sh);
   if (rc) return rc;
-  if (sh.L > semd::kResidentMaxL)
-    return fail(SEMD_EUNSUPPORTED, "serialized length %lld exceeds the on-chip path limit %d",
-                (long long)sh.L, semd::kResidentMaxL);
-  std::vector<semd::WorkItem> work{
-      make_work(signal, imfs_out, n_imfs_out, sh, p->transition_len, 0)};
-  return run_resident(work, 2 * sh.L, p->max_imfs, p->sift_iters, stream);
+  rc = check_length(sh.L, p->path, 0);
+  if (rc) return rc;
+  std::vector<semd::WorkItem> work{make_work(signal, imfs_out, n_imfs_out, sh, p->transition_len)};
+  return run_work(work, p->max_imfs, p->sift_iters, p->path, stream);
 }
 
 int semd_decompose(const double* signal, const int64_t* dims, int ndim, int max_imfs,
@@ -252,17 +379,14 @@ int semd_decompose_batch(const semd_item* items, int n, const semd_params* p,
   int rc = check_params(p, false);
   if (rc) return rc;
   std::vector<Shape> shapes;
-  rc = check_items(items, n, p->transition_len, shapes);
+  rc = check_items(items, n, p->transition_len, p->path, shapes);
   if (rc) return rc;
   std::vector<semd::WorkItem> work;
   work.reserve(n);
-  int64_t off = 0;
-  for (int i = 0; i < n; ++i) {
+  for (int i = 0; i < n; ++i)
     work.push_back(make_work(items[i].signal, items[i].imfs_out, items[i].n_imfs_out, shapes[i],
-                             p->transition_len, off, items[i].stats_out));
-    off += 2 * shapes[i].L;
-  }
-  return run_resident(work, off, p->max_imfs, p->sift_iters, stream);
+                             p->transition_len, items[i].stats_out));
+  return run_work(work, p->max_imfs, p->sift_iters, p->path, stream);
 }
 
 int semd_eemd_batch(const semd_item* items, int n, const semd_params* p, hipStream_t stream) {
@@ -270,7 +394,7 @@ int semd_eemd_batch(const semd_item* items, int n, const semd_params* p, hipStre
   int rc = check_params(p, true);
   if (rc) return rc;
   std::vector<Shape> shapes;
-  rc = check_items(items, n, p->transition_len, shapes);
+  rc = check_items(items, n, p->transition_len, p->path, shapes);
   if (rc) return rc;
   for (int i = 0; i < n; ++i)
     if (!std::isfinite(items[i].noise_sigma) || items[i].noise_sigma < 0)
@@ -285,8 +409,8 @@ int semd_eemd_batch(const semd_item* items, int n, const semd_params* p, hipStre
     size_t bytes = 0;
     int i1 = i0;
     while (i1 < n) {
-      const size_t b = (size_t)NR * (sizeof(double) * ((size_t)(K + 1) * shapes[i1].M * shapes[i1].N +
-                                                       2 * shapes[i1].L) + sizeof(int32_t));
+      const size_t b = (size_t)NR * (sizeof(double) * (size_t)(K + 1) * shapes[i1].M * shapes[i1].N +
+                                     stream_bytes(shapes[i1].L) + sizeof(int32_t));
       if (i1 > i0 && bytes + b > budget) break;
       bytes += b;
       ++i1;
@@ -306,23 +430,21 @@ int semd_eemd_batch(const semd_item* items, int n, const semd_params* p, hipStre
     }
     std::vector<semd::WorkItem> work;
     work.reserve((size_t)NR * (i1 - i0));
-    int64_t off = 0;
     size_t so = 0;
     for (int i = i0; i < i1; ++i) {
       const size_t per = (size_t)(K + 1) * shapes[i].M * shapes[i].N;
       for (int m = 0; m < NR; ++m) {
         semd::WorkItem w = make_work(items[i].signal, buf + so + (size_t)m * per,
                                      cnt + (size_t)(i - i0) * NR + m, shapes[i],
-                                     p->transition_len, off);
+                                     p->transition_len);
         w.beta = items[i].noise_sigma;
         w.key = semd::noise_key(p->seed, items[i].item_id, (uint64_t)m);
         w.flags = 1;
         work.push_back(w);
-        off += 2 * shapes[i].L;
       }
       so += (size_t)NR * per;
     }
-    rc = run_resident(work, off, K, p->sift_iters, stream);
+    rc = run_work(work, K, p->sift_iters, p->path, stream);
     so = 0;
     for (int i = i0; i < i1 && rc == SEMD_OK; ++i) {
       const int64_t per = (int64_t)(K + 1) * shapes[i].M * shapes[i].N;

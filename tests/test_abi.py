@@ -44,7 +44,7 @@ def test_serial_length(M, N, D, want):
 
 def _p(**kw):
     p = semd.semd_params(kw.get("D", 0), kw.get("K", 6), kw.get("S", 10), kw.get("b", 0),
-                         kw.get("NR", 1), kw.get("res", 0), 0)
+                         kw.get("NR", 1), kw.get("path", 0), 0)
     return p
 
 
@@ -54,7 +54,8 @@ def _p(**kw):
     (dict(b=1), [100, 3], semd.SEMD_EINVAL),
     (dict(D=101), [100, 3], semd.SEMD_EINVAL),
     (dict(D=-1), [100, 3], semd.SEMD_EINVAL),
-    (dict(res=7), [100, 3], semd.SEMD_EINVAL),
+    (dict(path=7), [100, 3], semd.SEMD_EINVAL),
+    (dict(path=-1), [100, 3], semd.SEMD_EINVAL),
     (dict(), [0, 3], semd.SEMD_EINVAL),
     (dict(), [100, -2], semd.SEMD_EINVAL),
 ])
@@ -65,6 +66,17 @@ def test_decompose_ex_rejects_invalid_arguments(kw, dims, code):
     rc = L.semd_decompose_ex(BOGUS, d, len(dims), C.byref(p), BOGUS, None, None)
     assert rc == code
     assert L.semd_last_error().decode()
+
+
+def test_length_limits():
+    L = semd.lib()
+    d = (C.c_int64 * 2)(20000, 3)  # 60000 serialized samples: streaming only
+    p = _p(path=semd.SEMD_PATH_ONCHIP)
+    assert L.semd_decompose_ex(BOGUS, d, 2, C.byref(p), BOGUS, None, None) == \
+        semd.SEMD_EUNSUPPORTED
+    big = (C.c_int64 * 2)(1 << 20, 1 << 9)  # 2^29 samples: beyond any path
+    assert L.semd_decompose_ex(BOGUS, big, 2, C.byref(_p()), BOGUS, None, None) == \
+        semd.SEMD_EUNSUPPORTED
 
 
 def test_null_pointers_rejected():

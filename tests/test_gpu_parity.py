@@ -249,3 +249,117 @@ def test_eemd_zero_noise_single_realization_is_emd():
     semd.semd_eemd_batch([dev(it.X)], [[it.M, it.N]], [out], None, 20, 8, 10, 1, 0, [0.0])
     plain, _ = semd.semd_decompose_ex(dev(it.X), [it.M, it.N], 20, 8, 10)
     assert np.array_equal(host(out), host(plain))
+
+
+# --------------------------------------------------------------------------
+# streaming path (many workgroups per signal)
+# --------------------------------------------------------------------------
+
+STREAM = semd.SEMD_PATH_STREAM
+ONCHIP = semd.SEMD_PATH_ONCHIP
+
+
+def _series(cfg, k, M, N):
+    return workloads.series(workloads.rng_for(cfg, k), N, M)
+
+
+@pytest.mark.parametrize("M,N,D", [(3, 1, 0), (5, 1, 0), (100, 1, 0), (2047, 1, 0), (2048, 1, 0),
+                                   (2049, 1, 0), (1000, 3, 0), (1000, 3, 50), (1000, 5, 200)])
+def test_stream_small_matches_oracle(M, N, D):
+    X = _series(11, M * 10 + N, M, N)
+    out, n = semd.semd_decompose_ex(dev(X), [M, N], D, 6, 10, path=STREAM)
+    ties = []
+    _check_item(X, M, N, D, 6, 10, host(out), int(host(n)[0]), ties)
+
+
+def test_stream_faces_and_textures():
+    items = workloads.config2(4) + workloads.config1(2)
+    shapes = [(i.M, i.N) for i in items]
+    outs, counts = semd.decompose_batch([dev(i.X) for i in items], shapes, 0, 8, 10, path=STREAM)
+    counts = host(counts)
+    ties = []
+    for k, i in enumerate(items):
+        _check_item(i.X, i.M, i.N, 0, 8, 10, host(outs[k]), int(counts[k]), ties)
+    assert len(ties) <= 1
+
+
+def test_stream_equals_onchip():
+    items = workloads.config2(2) + [workloads.config0()]
+    for i in items:
+        a, na = semd.semd_decompose_ex(dev(i.X), [i.M, i.N], 7, 8, 10, path=ONCHIP)
+        b, nb = semd.semd_decompose_ex(dev(i.X), [i.M, i.N], 7, 8, 10, path=STREAM)
+        assert int(host(na)[0]) == int(host(nb)[0])
+        assert np.abs(host(a) - host(b)).max() <= TOL * np.abs(i.X).max()
+
+
+def test_stream_plateaus_across_tiles():
+    # equal-valued runs longer than a tile (2048 samples), entered and left
+    # in every direction, plus runs touching both ends
+    L = 20000
+    x = np.zeros(L)
+    x[:3000] = 2.0
+    x[3000:9000] = 5.0     # maximum plateau over ~3 tiles
+    x[9000:9500] = 1.0
+    x[9500:15000] = -3.0   # minimum plateau over ~3 tiles
+    x[15000:15100] = 0.5   # shoulder
+    x[15100:17000] = 0.7
+    x[17000:] = -1.0
+    x += 0.25 * np.sin(np.arange(L) / 900.0) * (np.arange(L) % 4096 < 100)
+    imax, imin = oracle.extrema(x)
+    out, n = semd.semd_decompose_ex(dev(x), [L, 1], 0, 4, 3, path=STREAM)
+    ref, nr = oracle.emd(x, 4, 3)
+    r = compare(host(out), int(host(n)[0]), ref, nr, np.abs(x).max())
+    assert r["ok"], r
+    assert len(imax) >= 1 and len(imin) >= 1
+
+
+@pytest.mark.parametrize("M,N,K,S", [(20000, 3, 6, 10), (500, 500, 6, 10), (1024, 1024, 3, 4)])
+def test_stream_long_signals(M, N, K, S):
+    if M == N:
+        X = workloads.texture(workloads.rng_for(12, M), M, N)
+    else:
+        X = _series(12, M, M, N)
+    out, n = semd.semd_decompose_ex(dev(X), [M, N], 0, K, S)  # auto: streaming by length
+    ties = []
+    _check_item(X, M, N, 0, K, S, host(out), int(host(n)[0]), ties)
+
+
+def test_auto_routes_mixed_batch():
+    shapes = [(100, 3), (30000, 2), (5000, 2), (11, 1), (40000, 1)]
+    Xs = [_series(13, k, M, N) for k, (M, N) in enumerate(shapes)]
+    outs, counts = semd.decompose_batch([dev(x) for x in Xs], shapes, 10, 6, 10)
+    counts = host(counts)
+    ties = []
+    for k, (M, N) in enumerate(shapes):
+        _check_item(Xs[k], M, N, 10, 6, 10, host(outs[k]), int(counts[k]), ties)
+
+
+@pytest.mark.parametrize("L", [1, 2, 3])
+def test_stream_tiny_signals(L):
+    x = np.array([1.0, -2.0, 0.5][:L])
+    out, n = semd.semd_decompose_ex(dev(x), [L, 1], 0, 4, 10, path=STREAM)
+    ref, nr = oracle.emd(x, 4, 10)
+    assert int(host(n)[0]) == nr == 0
+    assert np.array_equal(host(out), ref)
+
+
+def test_stream_non_finite_and_monotone():
+    x = np.ones(5000)
+    x[4000] = np.inf
+    out, n = semd.semd_decompose_ex(dev(x), [5000, 1], 0, 3, 10, path=STREAM)
+    assert int(host(n)[0]) == -semd.SEMD_ENONFINITE
+    assert np.all(host(out) == 0.0)
+    m = np.linspace(0.0, 1.0, 9000) ** 2
+    out, n = semd.semd_decompose_ex(dev(m), [9000, 1], 0, 3, 10, path=STREAM)
+    assert int(host(n)[0]) == 0 and np.array_equal(host(out)[3], m)
+
+
+def test_stream_eemd_long_signal():
+    M, N, D, K, S, NR, seed = 15000, 2, 50, 6, 10, 4, 99
+    X = _series(14, 0, M, N)
+    x = oracle.serialize(X, M, N, D)
+    beta = 0.2 * float(x.std())
+    out = torch.empty((K + 1, M * N), dtype=torch.float64, device=DEV)
+    semd.semd_eemd_batch([dev(X)], [[M, N]], [out], None, D, K, S, NR, seed, [beta], [3])
+    ref = oracle.eemd(X, M, N, D, K, S, NR, beta, seed, 3)
+    assert np.abs(host(out) - ref).max() <= TOL * np.abs(X).max()
