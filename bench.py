@@ -64,6 +64,8 @@ def main() -> int:
     ap.add_argument("--plain-items", type=int, default=256)
     ap.add_argument("--cpu-items", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--path", choices=["auto", "onchip", "stream"], default="auto",
+                    help="execution path of the batched decomposition")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the independent "
@@ -79,6 +81,8 @@ def main() -> int:
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     K, S, D = 8, 10, args.D
+    path = {"auto": semd.SEMD_PATH_AUTO, "onchip": semd.SEMD_PATH_ONCHIP,
+            "stream": semd.SEMD_PATH_STREAM}[args.path]
     items = workloads.config2(args.batch)
     M, N = items[0].M, items[0].N
     MN = M * N
@@ -93,7 +97,7 @@ def main() -> int:
 
     # work statistics of one decomposition of the batch (untimed)
     pb_stats = semd.PreparedBatch([X[i] for i in range(n)], shapes, [out[i] for i in range(n)],
-                                  counts, D, K, S, stats=stats)
+                                  counts, D, K, S, stats=stats, path=path)
     pb_stats.run()
     torch.cuda.synchronize()
     st = stats.sum(0).cpu().numpy()
@@ -101,7 +105,7 @@ def main() -> int:
     n_imfs = counts.cpu().numpy()
 
     pb = semd.PreparedBatch([X[i] for i in range(n)], shapes, [out[i] for i in range(n)],
-                            counts, D, K, S)
+                            counts, D, K, S, path=path)
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
         pb.run()
@@ -164,7 +168,7 @@ def main() -> int:
         "config": {"workload": f"face-like images 112x92 (uint8-valued) x {n}, serialized "
                                f"column-wise, D={D}, batched Serial-EMD",
                    "batch": n, "M": M, "N": N, "D": D, "L": L, "max_imfs": K,
-                   "sift_iters": S},
+                   "sift_iters": S, "path": args.path},
         "latency_ms": {"step_p50": pct(step_ms, 50), "step_p99": pct(step_ms, 99)},
         "plain": {"value": plain_value, "unit": "samples/s", "images": npl,
                   "image_p50_ms": pct(plain_ms, 50), "image_p99_ms": pct(plain_ms, 99),

@@ -169,6 +169,49 @@ int semd_extrema(const double* h, int64_t L, int32_t* imax, int32_t* imin, int32
 int semd_noise(uint64_t seed, uint64_t item, uint64_t m, int64_t L, double* w,
                hipStream_t stream);
 
+/* ---- serving: continuous batching -------------------------------------- */
+
+/* An engine keeps decompositions of independent requests resident on the
+ * device and advances all of them by one step per semd_engine_step: one
+ * sift (Sec. 2.1) for each, whatever IMF or sift it is at, or the IMF end /
+ * final output work a request reaches.  Requests join between steps when
+ * their device footprint fits the engine's memory budget.  Every request is
+ * decomposed exactly as semd_decompose_ex(path = SEMD_PATH_STREAM) would
+ * (bit-identical outputs): its arithmetic does not depend on the others.
+ * All engine calls on one engine must come from one host thread at a time
+ * and all steps must use one stream.  The engine owns its device memory
+ * (hbm_budget_bytes, allocated at creation); the caller owns every
+ * request's input and output buffers, which must stay valid until the
+ * request is reported done. */
+typedef struct semd_engine semd_engine;
+
+/* max_requests >= 1 resident requests at a time. */
+int semd_engine_create(size_t hbm_budget_bytes, int max_requests, semd_engine** out);
+
+/* Device bytes a request needs inside an engine. */
+int semd_engine_footprint(const semd_item* item, const semd_params* p, size_t* bytes);
+
+/* Admit one request (item: [host]; its signal, imfs_out and n_imfs_out as in
+ * semd_decompose_batch; noise fields ignored).  *ticket identifies it.
+ * SEMD_EBUSY: the footprint does not fit the free budget or all request
+ * slots are taken; retry after finished requests are polled. */
+int semd_engine_admit(semd_engine* e, const semd_item* item, const semd_params* p,
+                      int64_t* ticket);
+
+/* One step of every resident request, enqueued on `stream`. */
+int semd_engine_step(semd_engine* e, hipStream_t stream);
+
+/* Up to cap tickets ([host] done) of requests whose outputs are complete in
+ * stream order; n_done receives their number.  Does not wait for the device
+ * except for the step before the last one issued. */
+int semd_engine_poll(semd_engine* e, int64_t* done, int cap, int* n_done);
+
+/* Number of resident (admitted, not yet reported done) requests. */
+int semd_engine_resident(semd_engine* e, int* n);
+
+/* Waits for the engine's work and frees its device memory. */
+int semd_engine_destroy(semd_engine* e);
+
 #ifdef __cplusplus
 }
 #endif

@@ -77,6 +77,16 @@ _EXPORTS = {
                                C.c_void_p]),
     "semd_noise": (C.c_int, [C.c_uint64, C.c_uint64, C.c_uint64, C.c_int64, C.c_void_p,
                              C.c_void_p]),
+    "semd_engine_create": (C.c_int, [C.c_size_t, C.c_int, C.POINTER(C.c_void_p)]),
+    "semd_engine_footprint": (C.c_int, [C.POINTER(semd_item), C.POINTER(semd_params),
+                                        C.POINTER(C.c_size_t)]),
+    "semd_engine_admit": (C.c_int, [C.c_void_p, C.POINTER(semd_item), C.POINTER(semd_params),
+                                    C.POINTER(C.c_int64)]),
+    "semd_engine_step": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "semd_engine_poll": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_int,
+                                   C.POINTER(C.c_int)]),
+    "semd_engine_resident": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
+    "semd_engine_destroy": (C.c_int, [C.c_void_p]),
 }
 
 _lib = None
@@ -322,3 +332,77 @@ class PreparedBatch:
         fn = lib().semd_eemd_batch if self.eemd else lib().semd_decompose_batch
         _check(fn(self.items, self.n, C.byref(self.params), _stream(stream)),
                "semd_eemd_batch" if self.eemd else "semd_decompose_batch")
+
+
+# ---------------------------------------------------------------------------
+# serving engine (continuous batching)
+# ---------------------------------------------------------------------------
+
+class Engine:
+    """Continuous-batching engine (semd_engine_*): requests are admitted
+    between steps while their device footprint fits the budget; every step
+    advances all resident requests by one sift."""
+
+    def __init__(self, hbm_budget_bytes: int, max_requests: int):
+        h = C.c_void_p()
+        _check(lib().semd_engine_create(int(hbm_budget_bytes), int(max_requests), C.byref(h)),
+               "semd_engine_create")
+        self._h = h
+        self._keep: dict[int, tuple] = {}
+
+    @staticmethod
+    def footprint(dims: Sequence[int], D: int, K: int, S: int) -> int:
+        it = semd_item()
+        it.signal = 1
+        it.imfs_out = 1
+        for k, v in enumerate(dims):
+            it.dims[k] = int(v)
+        it.ndim = len(dims)
+        p = _params(D, K, S)
+        b = C.c_size_t()
+        _check(lib().semd_engine_footprint(C.byref(it), C.byref(p), C.byref(b)),
+               "semd_engine_footprint")
+        return int(b.value)
+
+    def admit(self, signal: torch.Tensor, dims: Sequence[int], out: torch.Tensor,
+              n_imfs: torch.Tensor | None, D: int, K: int, S: int) -> int | None:
+        """Ticket of the admitted request, or None when it does not fit now."""
+        arr, _ = _items([signal], [dims], [out],
+                        [n_imfs] if n_imfs is not None else None)
+        p = _params(D, K, S)
+        t = C.c_int64()
+        rc = lib().semd_engine_admit(self._h, arr, C.byref(p), C.byref(t))
+        if rc == SEMD_EBUSY:
+            return None
+        _check(rc, "semd_engine_admit")
+        self._keep[t.value] = (signal, out, n_imfs)
+        return int(t.value)
+
+    def step(self, stream=None) -> None:
+        _check(lib().semd_engine_step(self._h, _stream(stream)), "semd_engine_step")
+
+    def poll(self, cap: int = 4096) -> list[int]:
+        buf = (C.c_int64 * cap)()
+        n = C.c_int()
+        _check(lib().semd_engine_poll(self._h, buf, cap, C.byref(n)), "semd_engine_poll")
+        done = [int(buf[i]) for i in range(n.value)]
+        for t in done:
+            self._keep.pop(t, None)
+        return done
+
+    def resident(self) -> int:
+        n = C.c_int()
+        _check(lib().semd_engine_resident(self._h, C.byref(n)), "semd_engine_resident")
+        return int(n.value)
+
+    def close(self) -> None:
+        if self._h:
+            _check(lib().semd_engine_destroy(self._h), "semd_engine_destroy")
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -166,103 +166,116 @@ int run_resident(std::vector<semd::WorkItem>& work, int K, int S, hipStream_t st
   return rc;
 }
 
-// Device bytes the streaming path needs for one signal of L samples.
+// Device bytes the streaming path needs for one signal of L samples, and
+// the carving of such a region into the signal's buffers.
+size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+
 size_t stream_bytes(int64_t L) {
-  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   const size_t cap = (size_t)((L - 1) / 2 + 12);
   const size_t ntiles = (size_t)((L + semd::kTile - 1) / semd::kTile);
-  return 2 * al(sizeof(double) * (size_t)L) +
-         2 * (al(sizeof(int32_t) * cap) + 2 * al(sizeof(double) * cap)) +
-         al(sizeof(semd::TileInfo) * ntiles) + al(sizeof(semd::SigStatus));
+  return 2 * al256(sizeof(double) * (size_t)L) +
+         2 * (al256(sizeof(int32_t) * cap) + 2 * al256(sizeof(double) * cap)) +
+         al256(sizeof(semd::TileInfo) * ntiles) + al256(sizeof(semd::SigStatus));
 }
 
-// Decompose `work` on the streaming path: every sift of every signal as a
-// fixed sequence of tile / signal / knot-block launches over the batch.
+semd::StreamSig stream_sig(const semd::WorkItem& w, int K, int S, unsigned char* region) {
+  semd::StreamSig g{};
+  g.X = w.X;
+  g.out = w.out;
+  g.n_imfs = w.n_imfs;
+  g.stats = w.stats;
+  g.M = w.M;
+  g.N = w.N;
+  g.D = w.D;
+  g.L = w.L;
+  g.beta = w.beta;
+  g.key = w.key;
+  g.flags = w.flags;
+  g.ntiles = (w.L + semd::kTile - 1) / semd::kTile;
+  g.K = K;
+  g.S = S;
+  g.cap = (w.L - 1) / 2 + 12;
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    unsigned char* p = region + o;
+    o += al256(b);
+    return p;
+  };
+  g.h = reinterpret_cast<double*>(take(sizeof(double) * (size_t)w.L));
+  g.r = reinterpret_cast<double*>(take(sizeof(double) * (size_t)w.L));
+  for (int e = 0; e < 2; ++e) {
+    g.kt[e] = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (size_t)g.cap));
+    g.ky[e] = reinterpret_cast<double*>(take(sizeof(double) * (size_t)g.cap));
+    g.km[e] = reinterpret_cast<double*>(take(sizeof(double) * (size_t)g.cap));
+  }
+  g.tinfo = reinterpret_cast<semd::TileInfo*>(take(sizeof(semd::TileInfo) * (size_t)g.ntiles));
+  g.st = reinterpret_cast<semd::SigStatus*>(take(sizeof(semd::SigStatus)));
+  return g;
+}
+
+// Tile and solve-block tables of a list of streaming signals.
+void stream_tables(const std::vector<semd::StreamSig>& sigs, std::vector<int2>& tiles,
+                   std::vector<int4>& blocks) {
+  tiles.clear();
+  blocks.clear();
+  for (int i = 0; i < (int)sigs.size(); ++i) {
+    for (int t = 0; t < sigs[i].ntiles; ++t) tiles.push_back(make_int2(i, t));
+    const int nb = semd::stream_solve_blocks(sigs[i].cap);
+    for (int e = 0; e < 2; ++e)
+      for (int b = 0; b < nb; ++b) blocks.push_back(make_int4(i, e, b, 0));
+  }
+}
+
+// Signals, tiles and blocks packed for one upload; returns byte offsets.
+std::vector<unsigned char> pack_tables(const std::vector<semd::StreamSig>& sigs,
+                                       const std::vector<int2>& tiles,
+                                       const std::vector<int4>& blocks, size_t* o_til,
+                                       size_t* o_blk) {
+  const size_t b_sig = sizeof(semd::StreamSig) * sigs.size();
+  const size_t b_til = sizeof(int2) * tiles.size();
+  const size_t b_blk = sizeof(int4) * blocks.size();
+  std::vector<unsigned char> pack(std::max<size_t>(b_sig + b_til + b_blk, 16));
+  std::memcpy(pack.data(), sigs.data(), b_sig);
+  std::memcpy(pack.data() + b_sig, tiles.data(), b_til);
+  std::memcpy(pack.data() + b_sig + b_til, blocks.data(), b_blk);
+  *o_til = b_sig;
+  *o_blk = b_sig + b_til;
+  return pack;
+}
+
+// Decompose `work` on the streaming path: K*S steps of every signal.
 int run_stream(const std::vector<semd::WorkItem>& work, int K, int S, hipStream_t stream) {
   const int n = (int)work.size();
   if (n == 0) return SEMD_OK;
-  std::vector<semd::StreamSig> sigs(n);
-  std::vector<int2> tiles;
-  std::vector<int4> blocks;
   size_t bytes = 0;
-  auto take = [&](size_t b) {
-    const size_t o = bytes;
-    bytes += (b + 255) & ~size_t(255);
-    return o;
-  };
-  // offsets into the arena first, pointers once it exists
-  std::vector<size_t> o_h(n), o_r(n), o_kt(2 * n), o_ky(2 * n), o_km(2 * n), o_ti(n), o_st(n);
+  std::vector<size_t> offs(n);
   for (int i = 0; i < n; ++i) {
-    const semd::WorkItem& w = work[i];
-    semd::StreamSig& g = sigs[i];
-    g = semd::StreamSig{};
-    g.X = w.X;
-    g.out = w.out;
-    g.n_imfs = w.n_imfs;
-    g.stats = w.stats;
-    g.M = w.M;
-    g.N = w.N;
-    g.D = w.D;
-    g.L = w.L;
-    g.beta = w.beta;
-    g.key = w.key;
-    g.flags = w.flags;
-    g.ntiles = (w.L + semd::kTile - 1) / semd::kTile;
-    g.cap = (w.L - 1) / 2 + 12;
-    o_h[i] = take(sizeof(double) * (size_t)w.L);
-    o_r[i] = take(sizeof(double) * (size_t)w.L);
-    for (int e = 0; e < 2; ++e) {
-      o_kt[2 * i + e] = take(sizeof(int32_t) * (size_t)g.cap);
-      o_ky[2 * i + e] = take(sizeof(double) * (size_t)g.cap);
-      o_km[2 * i + e] = take(sizeof(double) * (size_t)g.cap);
-    }
-    o_ti[i] = take(sizeof(semd::TileInfo) * (size_t)g.ntiles);
-    o_st[i] = take(sizeof(semd::SigStatus));
-    for (int t = 0; t < g.ntiles; ++t) tiles.push_back(make_int2(i, t));
-    const int nb = semd::stream_solve_blocks(g.cap);
-    for (int e = 0; e < 2; ++e)
-      for (int b = 0; b < nb; ++b) blocks.push_back(make_int4(i, e, b, 0));
+    offs[i] = bytes;
+    bytes += al256(stream_bytes(work[i].L));
   }
   unsigned char* arena = nullptr;
   if (hipMallocAsync(reinterpret_cast<void**>(&arena), std::max<size_t>(bytes, 1), stream) !=
       hipSuccess)
     return fail(SEMD_ENOMEM, "streaming workspace of %zu bytes", bytes);
-  for (int i = 0; i < n; ++i) {
-    semd::StreamSig& g = sigs[i];
-    g.h = reinterpret_cast<double*>(arena + o_h[i]);
-    g.r = reinterpret_cast<double*>(arena + o_r[i]);
-    for (int e = 0; e < 2; ++e) {
-      g.kt[e] = reinterpret_cast<int32_t*>(arena + o_kt[2 * i + e]);
-      g.ky[e] = reinterpret_cast<double*>(arena + o_ky[2 * i + e]);
-      g.km[e] = reinterpret_cast<double*>(arena + o_km[2 * i + e]);
-    }
-    g.tinfo = reinterpret_cast<semd::TileInfo*>(arena + o_ti[i]);
-    g.st = reinterpret_cast<semd::SigStatus*>(arena + o_st[i]);
-  }
-  // one upload: signals, tiles, solve blocks
-  const size_t b_sig = sizeof(semd::StreamSig) * sigs.size();
-  const size_t b_til = sizeof(int2) * tiles.size();
-  const size_t b_blk = sizeof(int4) * blocks.size();
-  std::vector<unsigned char> pack(b_sig + b_til + b_blk);
-  std::memcpy(pack.data(), sigs.data(), b_sig);
-  std::memcpy(pack.data() + b_sig, tiles.data(), b_til);
-  std::memcpy(pack.data() + b_sig + b_til, blocks.data(), b_blk);
+  std::vector<semd::StreamSig> sigs(n);
+  for (int i = 0; i < n; ++i) sigs[i] = stream_sig(work[i], K, S, arena + offs[i]);
+  std::vector<int2> tiles;
+  std::vector<int4> blocks;
+  stream_tables(sigs, tiles, blocks);
+  size_t o_til, o_blk;
+  std::vector<unsigned char> pack = pack_tables(sigs, tiles, blocks, &o_til, &o_blk);
   void* d_pack = nullptr;
   int rc = upload(pack.data(), pack.size(), stream, &d_pack);
   if (rc) { (void)hipFreeAsync(arena, stream); return rc; }
-  const auto* d_sigs = static_cast<const semd::StreamSig*>(d_pack);
-  const auto* d_tiles = reinterpret_cast<const int2*>(static_cast<unsigned char*>(d_pack) + b_sig);
-  const auto* d_blocks =
-      reinterpret_cast<const int4*>(static_cast<unsigned char*>(d_pack) + b_sig + b_til);
+  unsigned char* dp = static_cast<unsigned char*>(d_pack);
+  const auto* d_sigs = reinterpret_cast<const semd::StreamSig*>(dp);
+  const auto* d_tiles = reinterpret_cast<const int2*>(dp + o_til);
+  const auto* d_blocks = reinterpret_cast<const int4*>(dp + o_blk);
   const int nt = (int)tiles.size(), nb = (int)blocks.size();
-  hipError_t e = semd::st_init(d_sigs, n, stream);
-  if (e == hipSuccess) e = semd::st_load(d_sigs, d_tiles, nt, stream);
-  for (int imf = 0; imf < K && e == hipSuccess; ++imf) {
-    for (int s = 0; s < S && e == hipSuccess; ++s)
-      e = semd::st_sift(d_sigs, n, d_tiles, nt, d_blocks, nb, s, stream);
-    if (e == hipSuccess) e = semd::st_imf_end(d_sigs, n, d_tiles, nt, stream);
-  }
-  if (e == hipSuccess) e = semd::st_final(d_sigs, d_tiles, nt, K, stream);
+  // every signal finishes within K*S steps (each step sifts it or ends an IMF)
+  hipError_t e = semd::st_load(d_sigs, d_tiles, nt, stream);
+  for (int step = 0; step < K * S && e == hipSuccess; ++step)
+    e = semd::st_step(d_sigs, n, d_tiles, nt, d_blocks, nb, stream);
   if (e != hipSuccess) rc = hip_fail(e, "streaming kernel launch");
   (void)hipFreeAsync(d_pack, stream);
   (void)hipFreeAsync(arena, stream);
@@ -504,6 +517,280 @@ int semd_noise(uint64_t seed, uint64_t item, uint64_t m, int64_t L, double* w,
   if (L == 0) return SEMD_OK;
   hipError_t e = semd::launch_noise(semd::noise_key(seed, item, m), L, w, stream);
   return e == hipSuccess ? SEMD_OK : hip_fail(e, "noise launch");
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Serving engine: continuous batching over the streaming kernels
+// ---------------------------------------------------------------------------
+
+#include <map>
+
+struct semd_engine {
+  struct Req {
+    int64_t ticket;
+    semd::StreamSig sig;
+    size_t off, bytes;
+    bool loaded;
+  };
+  size_t budget = 0;
+  int max_requests = 0;
+  unsigned char* arena = nullptr;
+  std::map<size_t, size_t> free_;  // offset -> bytes of free arena ranges
+  std::vector<Req> reqs;           // resident requests, in table order
+  bool dirty = true;               // tables differ from the requests
+  void* d_tables = nullptr;        // current device tables (signals, tiles, blocks)
+  int n_tiles = 0, n_blocks = 0, max_steps = 0;
+  size_t o_til = 0, o_blk = 0;
+  int32_t* d_done = nullptr;       // done flags of the last gathered step
+  int32_t* h_done = nullptr;       // pinned copy
+  int done_cap = 0;
+  hipEvent_t ev = nullptr;
+  bool pending = false;            // a gather awaits processing
+  std::vector<int64_t> pending_tickets;  // table order of that gather
+  std::vector<int64_t> finished;   // tickets ready for poll
+  int64_t next_ticket = 1;
+  hipStream_t last_stream = nullptr;
+
+  int alloc(size_t bytes, size_t* off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const size_t rest = it->second - bytes;
+        const size_t at = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[at] = rest;
+        return 0;
+      }
+    }
+    return -1;
+  }
+  void release(size_t off, size_t bytes) {
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  // Requests whose done flag was set in the last gathered step leave.
+  void process_gather() {
+    if (!pending) return;
+    pending = false;
+    for (size_t i = 0; i < pending_tickets.size(); ++i) {
+      if (!h_done[i]) continue;
+      const int64_t t = pending_tickets[i];
+      for (size_t j = 0; j < reqs.size(); ++j) {
+        if (reqs[j].ticket == t) {
+          release(reqs[j].off, reqs[j].bytes);
+          reqs.erase(reqs.begin() + (ptrdiff_t)j);
+          finished.push_back(t);
+          dirty = true;
+          break;
+        }
+      }
+    }
+  }
+};
+
+namespace {
+
+std::mutex g_engine_mu;
+
+int engine_check(const semd_item* it, const semd_params* p, Shape* sh) {
+  int rc = check_params(p, false);
+  if (rc) return rc;
+  if (!it) return fail(SEMD_EINVAL, "item is NULL");
+  std::vector<Shape> shapes;
+  rc = check_items(it, 1, p->transition_len, SEMD_PATH_STREAM, shapes);
+  if (rc) return rc;
+  *sh = shapes[0];
+  return SEMD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int semd_engine_create(size_t hbm_budget_bytes, int max_requests, semd_engine** out) {
+  g_err[0] = 0;
+  if (!out) return fail(SEMD_EINVAL, "out is NULL");
+  if (max_requests < 1) return fail(SEMD_EINVAL, "max_requests must be >= 1");
+  if (hbm_budget_bytes < (size_t(1) << 20)) return fail(SEMD_EINVAL, "budget below 1 MiB");
+  auto* e = new semd_engine();
+  e->budget = hbm_budget_bytes & ~size_t(255);
+  e->max_requests = max_requests;
+  if (hipMalloc(reinterpret_cast<void**>(&e->arena), e->budget) != hipSuccess) {
+    delete e;
+    return fail(SEMD_ENOMEM, "engine arena of %zu bytes", hbm_budget_bytes);
+  }
+  e->free_[0] = e->budget;
+  e->done_cap = max_requests;
+  if (hipMalloc(reinterpret_cast<void**>(&e->d_done), sizeof(int32_t) * max_requests) !=
+          hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&e->h_done), sizeof(int32_t) * max_requests,
+                    hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&e->ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipFree(e->arena);
+    if (e->d_done) (void)hipFree(e->d_done);
+    if (e->h_done) (void)hipHostFree(e->h_done);
+    delete e;
+    return fail(SEMD_ENOMEM, "engine flag buffers");
+  }
+  *out = e;
+  return SEMD_OK;
+}
+
+int semd_engine_footprint(const semd_item* item, const semd_params* p, size_t* bytes) {
+  g_err[0] = 0;
+  if (!bytes) return fail(SEMD_EINVAL, "bytes is NULL");
+  Shape sh;
+  const int rc = engine_check(item, p, &sh);
+  if (rc) return rc;
+  *bytes = al256(stream_bytes(sh.L));
+  return SEMD_OK;
+}
+
+int semd_engine_admit(semd_engine* e, const semd_item* item, const semd_params* p,
+                      int64_t* ticket) {
+  g_err[0] = 0;
+  if (!e || !ticket) return fail(SEMD_EINVAL, "NULL engine or ticket");
+  std::lock_guard<std::mutex> lock(g_engine_mu);
+  Shape sh;
+  int rc = engine_check(item, p, &sh);
+  if (rc) return rc;
+  if ((int)e->reqs.size() >= e->max_requests)
+    return fail(SEMD_EBUSY, "all %d request slots are taken", e->max_requests);
+  const size_t bytes = al256(stream_bytes(sh.L));
+  size_t off = 0;
+  if (e->alloc(bytes, &off))
+    return fail(SEMD_EBUSY, "request needs %zu bytes, not free in the engine budget", bytes);
+  semd::WorkItem w = make_work(item->signal, item->imfs_out, item->n_imfs_out, sh,
+                               p->transition_len, item->stats_out);
+  semd_engine::Req r{};
+  r.ticket = e->next_ticket++;
+  r.sig = stream_sig(w, p->max_imfs, p->sift_iters, e->arena + off);
+  r.off = off;
+  r.bytes = bytes;
+  r.loaded = false;
+  e->reqs.push_back(r);
+  e->dirty = true;
+  *ticket = r.ticket;
+  return SEMD_OK;
+}
+
+int semd_engine_step(semd_engine* e, hipStream_t stream) {
+  g_err[0] = 0;
+  if (!e) return fail(SEMD_EINVAL, "engine is NULL");
+  std::lock_guard<std::mutex> lock(g_engine_mu);
+  e->last_stream = stream;
+  const int n = (int)e->reqs.size();
+  hipError_t he = hipSuccess;
+  if (n > 0) {
+    if (e->dirty) {
+      std::vector<semd::StreamSig> sigs(n);
+      std::vector<int2> new_tiles;
+      for (int i = 0; i < n; ++i) {
+        sigs[i] = e->reqs[i].sig;
+        if (!e->reqs[i].loaded)
+          for (int t = 0; t < sigs[i].ntiles; ++t) new_tiles.push_back(make_int2(i, t));
+      }
+      std::vector<int2> tiles;
+      std::vector<int4> blocks;
+      stream_tables(sigs, tiles, blocks);
+      // new requests' tiles ride along after the blocks
+      const size_t b_new = sizeof(int2) * new_tiles.size();
+      size_t o_til, o_blk;
+      std::vector<unsigned char> pack = pack_tables(sigs, tiles, blocks, &o_til, &o_blk);
+      const size_t o_new = pack.size();
+      pack.resize(o_new + std::max<size_t>(b_new, 8));
+      std::memcpy(pack.data() + o_new, new_tiles.data(), b_new);
+      void* d = nullptr;
+      int rc = upload(pack.data(), pack.size(), stream, &d);
+      if (rc) return rc;
+      if (e->d_tables) (void)hipFreeAsync(e->d_tables, stream);
+      e->d_tables = d;
+      e->o_til = o_til;
+      e->o_blk = o_blk;
+      e->n_tiles = (int)tiles.size();
+      e->n_blocks = (int)blocks.size();
+      unsigned char* dp = static_cast<unsigned char*>(d);
+      he = semd::st_load(reinterpret_cast<const semd::StreamSig*>(dp),
+                         reinterpret_cast<const int2*>(dp + o_new), (int)new_tiles.size(), stream);
+      for (auto& r : e->reqs) r.loaded = true;
+      e->dirty = false;
+    }
+    // ticket order of the table this step runs on (retirements below change
+    // e->reqs, not the table)
+    std::vector<int64_t> table_tickets(n);
+    for (int i = 0; i < n; ++i) table_tickets[i] = e->reqs[i].ticket;
+    unsigned char* dp = static_cast<unsigned char*>(e->d_tables);
+    const auto* d_sigs = reinterpret_cast<const semd::StreamSig*>(dp);
+    if (he == hipSuccess)
+      he = semd::st_step(d_sigs, n, reinterpret_cast<const int2*>(dp + e->o_til), e->n_tiles,
+                         reinterpret_cast<const int4*>(dp + e->o_blk), e->n_blocks, stream);
+    // the previous step's flags: requests that finished then leave now
+    if (e->pending) {
+      if (hipEventSynchronize(e->ev) != hipSuccess) return fail(SEMD_EDEVICE, "event wait");
+      e->process_gather();
+    }
+    if (he == hipSuccess) he = semd::st_gather_done(d_sigs, n, e->d_done, stream);
+    if (he == hipSuccess)
+      he = hipMemcpyAsync(e->h_done, e->d_done, sizeof(int32_t) * n, hipMemcpyDeviceToHost,
+                          stream);
+    if (he == hipSuccess) he = hipEventRecord(e->ev, stream);
+    if (he == hipSuccess) {
+      e->pending = true;
+      e->pending_tickets = std::move(table_tickets);
+    }
+  }
+  if (he != hipSuccess) return hip_fail(he, "engine step");
+  return SEMD_OK;
+}
+
+int semd_engine_poll(semd_engine* e, int64_t* done, int cap, int* n_done) {
+  g_err[0] = 0;
+  if (!e || !n_done || (cap > 0 && !done)) return fail(SEMD_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lock(g_engine_mu);
+  if (e->pending && hipEventQuery(e->ev) == hipSuccess) e->process_gather();
+  const int k = std::min<int>(cap, (int)e->finished.size());
+  for (int i = 0; i < k; ++i) done[i] = e->finished[i];
+  e->finished.erase(e->finished.begin(), e->finished.begin() + k);
+  *n_done = k;
+  return SEMD_OK;
+}
+
+int semd_engine_resident(semd_engine* e, int* n) {
+  g_err[0] = 0;
+  if (!e || !n) return fail(SEMD_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lock(g_engine_mu);
+  *n = (int)e->reqs.size();
+  return SEMD_OK;
+}
+
+int semd_engine_destroy(semd_engine* e) {
+  g_err[0] = 0;
+  if (!e) return SEMD_OK;
+  std::lock_guard<std::mutex> lock(g_engine_mu);
+  if (e->last_stream) {
+    if (e->d_tables) (void)hipFreeAsync(e->d_tables, e->last_stream);
+    (void)hipStreamSynchronize(e->last_stream);
+  }
+  (void)hipDeviceSynchronize();
+  (void)hipFree(e->arena);
+  (void)hipFree(e->d_done);
+  (void)hipHostFree(e->h_done);
+  (void)hipEventDestroy(e->ev);
+  delete e;
+  return SEMD_OK;
 }
 
 }  // extern "C"

@@ -23,12 +23,26 @@ struct TileInfo {
   int32_t pad;
 };
 
+// What a step does to a signal (decided by the scan from the current
+// candidate's extrema).
+enum StepAction : int32_t {
+  kIdle = 0,      // finished: nothing
+  kSift = 1,      // one sift
+  kSiftLast = 2,  // one sift, then the IMF ends
+  kEndImf = 3,    // the candidate is not siftable: the IMF ends without a sift
+  kFinish = 4     // the residue is not siftable (or the input is bad): outputs final
+};
+
 // Dynamic state of one signal.
 struct SigStatus {
-  int32_t active;   // the decomposition goes on
-  int32_t skip;     // the current IMF's remaining sifts are skipped
-  int32_t nimf;     // IMFs written
+  int32_t active;   // final outputs not written yet
+  int32_t sift;     // sifts done in the current IMF
+  int32_t nimf;     // IMFs ended
   int32_t bad;      // input holds NaN/Inf
+  int32_t action;   // this step's StepAction
+  int32_t slot;     // output slot of the IMF ending this step
+  int32_t fin;      // this step writes the final outputs
+  int32_t done;     // final outputs written
   int32_t n[2];     // maxima / minima of the current sift
   int64_t n_sifts;  // sifts performed
   int64_t n_knots;  // knots used, mirrored ones included
@@ -46,6 +60,8 @@ struct StreamSig {
   uint64_t key;
   int32_t flags;    // bit 0: add beta * noise
   int32_t ntiles;
+  int32_t K;        // max IMFs
+  int32_t S;        // sifts per IMF
   double* h;        // candidate, L doubles
   double* r;        // residue, L doubles
   int32_t* kt[2];   // knot abscissae (maxima, minima), cap each
@@ -57,16 +73,15 @@ struct StreamSig {
   SigStatus* st;
 };
 
-hipError_t st_init(const StreamSig* sigs, int n, hipStream_t s);
+// h = r = serialized input (+ noise) and a fresh status, for the signals
+// whose tiles are listed.
 hipError_t st_load(const StreamSig* sigs, const int2* tiles, int ntiles, hipStream_t s);
-// One sift (detect, scan, compact, solve, eval) of every running signal; s is
-// the sift's index within its IMF.
-hipError_t st_sift(const StreamSig* sigs, int nsig, const int2* tiles, int ntiles,
-                   const int4* blocks, int nblocks, int s, hipStream_t st);
-hipError_t st_imf_end(const StreamSig* sigs, int nsig, const int2* tiles, int ntiles,
-                      hipStream_t s);
-hipError_t st_final(const StreamSig* sigs, const int2* tiles, int ntiles, int K,
-                    hipStream_t s);
+// One step of every listed signal: detect, scan (decides the step's action),
+// compact and solve (sifting signals), eval (sift, IMF end, final outputs).
+hipError_t st_step(const StreamSig* sigs, int nsig, const int2* tiles, int ntiles,
+                   const int4* blocks, int nblocks, hipStream_t s);
+// done[i] = status of signal i has its final outputs written.
+hipError_t st_gather_done(const StreamSig* sigs, int nsig, int32_t* done, hipStream_t s);
 // Solve blocks one envelope of `cap` knots needs.
 int stream_solve_blocks(int cap);
 

@@ -13,8 +13,11 @@
 //                       staged in LDS, windowed Thomas sweeps per chunk;
 //   eval     (tiles)    the tile's knots staged in LDS, both envelopes walked
 //                       per thread, mean removed from h.
-// Device flags (active, skip) make finished signals no-ops, so the host
-// issues one fixed launch sequence for the batch.
+// Every signal carries its own phase (sift index, IMFs ended); the scan
+// decides each step's action per signal, and the evaluation also performs
+// IMF ends and final outputs, so signals in different phases share one
+// step and finished ones are no-ops: a batch is K*S identical steps, and a
+// serving engine admits new signals between steps.
 #include <algorithm>
 
 #include "semd_device.h"
@@ -31,7 +34,9 @@ constexpr int kSB = kTT * kChunk;     // interior unknowns per solve block
 constexpr int kTKnots = kTile / 2 + 8;  // knots of one kind a tile window can hold
 constexpr int kNW = kTT / kWave;
 
-__device__ __forceinline__ bool running(const SigStatus& st) { return st.active && !st.skip; }
+__device__ __forceinline__ bool sifting(const SigStatus& st) {
+  return st.action == kSift || st.action == kSiftLast;
+}
 
 // Block-wide reductions / scans over kTT threads (one barrier each, plus one
 // on entry so the LDS scratch can be reused back to back).
@@ -107,21 +112,6 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ h, int a, 
 // Setup, load, detect, scan, compact
 // ---------------------------------------------------------------------------
 
-__global__ void st_init_kernel(const StreamSig* __restrict__ sigs, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
-    SigStatus* st = sigs[i].st;
-    st->active = 1;
-    st->skip = 0;
-    st->nimf = 0;
-    st->bad = 0;
-    st->n[0] = 0;
-    st->n[1] = 0;
-    st->n_sifts = 0;
-    st->n_knots = 0;
-  }
-}
-
 // Serialize (Sec. 3.2) and add the realization's noise (Sec. 2.2 Step 1):
 // h = r = x for the tile; a non-finite sample marks the tile.
 __global__ void __launch_bounds__(kTT) st_load_kernel(const StreamSig* __restrict__ sigs,
@@ -140,7 +130,24 @@ __global__ void __launch_bounds__(kTT) st_load_kernel(const StreamSig* __restric
     S.r[k] = v;
   }
   bad = __syncthreads_or(bad);
-  if (threadIdx.x == 0) S.tinfo[tv.y].bad = bad ? 1 : 0;
+  if (threadIdx.x == 0) {
+    S.tinfo[tv.y].bad = bad ? 1 : 0;
+    if (tv.y == 0) {
+      SigStatus* st = S.st;
+      st->active = 1;
+      st->sift = 0;
+      st->nimf = 0;
+      st->bad = 0;
+      st->action = kIdle;
+      st->slot = 0;
+      st->fin = 0;
+      st->done = 0;
+      st->n[0] = 0;
+      st->n[1] = 0;
+      st->n_sifts = 0;
+      st->n_knots = 0;
+    }
+  }
 }
 
 // Extremum counts of a tile whose first run may have started in an earlier
@@ -155,7 +162,7 @@ __global__ void __launch_bounds__(kTT) st_detect_kernel(const StreamSig* __restr
   __shared__ int cont_exit;
   const int2 tv = tiles[blockIdx.x];
   const StreamSig& S = sigs[tv.x];
-  if (!running(*S.st)) return;
+  if (!S.st->active) return;
   const int L = S.L;
   const int a = tv.y * kTile, n = min(kTile, L - a);
   double prev, next;
@@ -188,14 +195,21 @@ __global__ void __launch_bounds__(kTT) st_detect_kernel(const StreamSig* __restr
 }
 
 // One workgroup per signal: carries and ranks across its tiles, knot totals,
-// and the sift / decomposition stop decisions.
-__global__ void __launch_bounds__(kTT) st_scan_kernel(const StreamSig* __restrict__ sigs,
-                                                      int s) {
+// and the step's action (Sec. 2.1 Step 5 with a fixed sift count):
+//   siftable candidate, sift < S-1  -> kSift
+//   siftable candidate, sift = S-1  -> kSiftLast (the IMF ends after it)
+//   not siftable, sift > 0          -> kEndImf   (the candidate is the IMF)
+//   not siftable, sift = 0          -> kFinish   (the residue is final)
+// An IMF end that reaches K IMFs also finishes the decomposition.
+__global__ void __launch_bounds__(kTT) st_scan_kernel(const StreamSig* __restrict__ sigs) {
   __shared__ int64_t scratch64[kNW];
   __shared__ int scratch[kNW];
   const StreamSig& S = sigs[blockIdx.x];
   SigStatus* st = S.st;
-  if (!running(*st)) return;
+  if (!st->active) {
+    if (threadIdx.x == 0) st->action = kIdle;
+    return;
+  }
   const int nt = S.ntiles;
   // input with NaN/Inf: nothing is decomposed
   int bad = 0;
@@ -204,6 +218,8 @@ __global__ void __launch_bounds__(kTT) st_scan_kernel(const StreamSig* __restric
   if (bad) {
     if (threadIdx.x == 0) {
       st->bad = 1;
+      st->action = kFinish;
+      st->fin = 1;
       st->active = 0;
     }
     return;
@@ -242,15 +258,29 @@ __global__ void __launch_bounds__(kTT) st_scan_kernel(const StreamSig* __restric
   }
   if (threadIdx.x == 0) {
     const int nmax = (int)(off_run >> 32), nmin = (int)(off_run & 0xffffffff);
-    if (!(nmax >= 1 && nmin >= 1 && nmax + nmin >= 3)) {
-      if (s == 0) st->active = 0;  // the residue is not siftable: decomposition ends
-      else st->skip = 1;           // the candidate is not: the IMF ends here
-    } else {
+    int action, fin = 0;
+    if (nmax >= 1 && nmin >= 1 && nmax + nmin >= 3) {
       st->n[0] = nmax;
       st->n[1] = nmin;
       st->n_sifts += 1;
       st->n_knots += nmax + 2 * min(2, nmax) + nmin + 2 * min(2, nmin);
+      action = st->sift + 1 >= S.S ? kSiftLast : kSift;
+    } else {
+      action = st->sift == 0 ? kFinish : kEndImf;
     }
+    if (action == kSift) {
+      st->sift += 1;
+    } else if (action == kFinish) {
+      fin = 1;
+    } else {
+      st->slot = st->nimf;
+      st->nimf += 1;
+      st->sift = 0;
+      fin = st->nimf >= S.K;
+    }
+    st->action = action;
+    st->fin = fin;
+    if (fin) st->active = 0;
   }
 }
 
@@ -263,7 +293,7 @@ __global__ void __launch_bounds__(kTT) st_compact_kernel(const StreamSig* __rest
   __shared__ int64_t scratch64[kNW];
   const int2 tv = tiles[blockIdx.x];
   const StreamSig& S = sigs[tv.x];
-  if (!running(*S.st)) return;
+  if (!sifting(*S.st)) return;
   const int L = S.L;
   const int a = tv.y * kTile, n = min(kTile, L - a);
   const TileInfo ti = S.tinfo[tv.y];
@@ -308,7 +338,7 @@ __global__ void __launch_bounds__(kTT) st_solve_kernel(const StreamSig* __restri
   __shared__ double ly[kW];
   const int4 bv = blocks[blockIdx.x];  // (signal, envelope, block)
   const StreamSig& S = sigs[bv.x];
-  if (!running(*S.st)) return;
+  if (!sifting(*S.st)) return;
   const int env = bv.y;
   const int n = S.st->n[env];
   const int Pp = n < 2 ? n : 2;
@@ -336,9 +366,14 @@ __global__ void __launch_bounds__(kTT) st_solve_kernel(const StreamSig* __restri
 // Evaluate and update
 // ---------------------------------------------------------------------------
 
-// Envelope means removed from the tile (Sec. 2.1 Steps 2-4): the knots whose
-// segments cover the tile are staged in LDS; each thread walks them over its
-// samples for both envelopes.
+// One step's work on the tile's samples:
+//   kSift, kSiftLast  envelope means removed (Sec. 2.1 Steps 2-4): the knots
+//                     whose segments cover the tile are staged in LDS and
+//                     each thread walks them over its samples;
+//   kSiftLast, kEndImf  IMF end: the candidate is stored in its output slot
+//                     (deserialized, Sec. 3.3), r <- r - h, h <- r;
+//   final             residue into slot K, unused IMF slots zero (Sec. 4.3),
+//                     IMF count and statistics.
 __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restrict__ sigs,
                                                       const int2* __restrict__ tiles) {
   __shared__ double tbuf[kTile];
@@ -346,117 +381,102 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
   __shared__ double ly[2][kTKnots], lm[2][kTKnots];
   const int2 tv = tiles[blockIdx.x];
   const StreamSig& S = sigs[tv.x];
-  if (!running(*S.st)) return;
+  const SigStatus* st = S.st;
+  const int action = st->action;
+  if (action == kIdle) return;
   const int L = S.L;
   const int a = tv.y * kTile, n = min(kTile, L - a);
-  const TileInfo ti = S.tinfo[tv.y];
-  int cnt[2];
-#pragma unroll
-  for (int e = 0; e < 2; ++e) {
-    const int nk = S.st->n[e];
-    const int Pp = nk < 2 ? nk : 2;
-    const int n2 = nk + 2 * Pp;
-    // the last knot emitted before the tile sits before it; the one after
-    // the tile's first outside knot lies beyond the tile
-    const int j0 = Pp + ti.off[e] - 1;
-    const int j1 = min(n2 - 1, Pp + ti.off[e] + ti.tot[e] + 1);
-    cnt[e] = min(j1 - j0 + 1, kTKnots);  // j1 - j0 <= kTile / 2 + 2 by the counts
-    for (int i = threadIdx.x; i < cnt[e]; i += kTT) {
-      lt[e][i] = S.kt[e][j0 + i];
-      ly[e][i] = S.ky[e][j0 + i];
-      lm[e][i] = S.km[e][j0 + i];
-    }
-  }
   for (int i = threadIdx.x; i < n; i += kTT) tbuf[i] = S.h[a + i];
-  __syncthreads();
-  const int lb = threadIdx.x * kTC;
-  const int nv = max(0, min(kTC, n - lb));
-  if (nv > 0) {
-    const double k0 = (double)(a + lb);
-    Seg sg[2];
+  if (action == kSift || action == kSiftLast) {
+    const TileInfo ti = S.tinfo[tv.y];
+    int cnt[2];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      // last window knot at or before the thread's first sample
-      int lo = 0, hi = cnt[e] - 2;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if ((double)lt[e][mid] <= k0) lo = mid;
-        else hi = mid - 1;
+      const int nk = st->n[e];
+      const int Pp = nk < 2 ? nk : 2;
+      const int n2 = nk + 2 * Pp;
+      // the last knot emitted before the tile sits before it; the one after
+      // the tile's first outside knot lies beyond the tile
+      const int j0 = Pp + ti.off[e] - 1;
+      const int j1 = min(n2 - 1, Pp + ti.off[e] + ti.tot[e] + 1);
+      cnt[e] = min(j1 - j0 + 1, kTKnots);  // j1 - j0 <= kTile / 2 + 2 by the counts
+      for (int i = threadIdx.x; i < cnt[e]; i += kTT) {
+        lt[e][i] = S.kt[e][j0 + i];
+        ly[e][i] = S.ky[e][j0 + i];
+        lm[e][i] = S.km[e][j0 + i];
       }
-      seg_load(sg[e], lt[e], ly[e], lm[e], lo);
     }
+    __syncthreads();
+    const int lb = threadIdx.x * kTC;
+    const int nv = max(0, min(kTC, n - lb));
+    if (nv > 0) {
+      const double k0 = (double)(a + lb);
+      Seg sg[2];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        // last window knot at or before the thread's first sample
+        int lo = 0, hi = cnt[e] - 2;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if ((double)lt[e][mid] <= k0) lo = mid;
+          else hi = mid - 1;
+        }
+        seg_load(sg[e], lt[e], ly[e], lm[e], lo);
+      }
 #pragma unroll 1
-    for (int c = 0; c < nv; ++c) {
-      const double kk = k0 + c;
-      const double up = seg_eval(sg[0], lt[0], ly[0], lm[0], cnt[0], kk);
-      const double lo = seg_eval(sg[1], lt[1], ly[1], lm[1], cnt[1], kk);
-      const double mean = 0.5 * (up + lo);
-      tbuf[lb + c] = tbuf[lb + c] - mean;
+      for (int c = 0; c < nv; ++c) {
+        const double kk = k0 + c;
+        const double up = seg_eval(sg[0], lt[0], ly[0], lm[0], cnt[0], kk);
+        const double lo = seg_eval(sg[1], lt[1], ly[1], lm[1], cnt[1], kk);
+        const double mean = 0.5 * (up + lo);
+        tbuf[lb + c] = tbuf[lb + c] - mean;
+      }
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += kTT) S.h[a + i] = tbuf[i];
-}
-
-// ---------------------------------------------------------------------------
-// IMF ends and final outputs
-// ---------------------------------------------------------------------------
-
-// IMF nimf = h (deserialized store, Sec. 3.3); r <- r - h; h <- r.
-__global__ void __launch_bounds__(kTT) st_imf_end_kernel(const StreamSig* __restrict__ sigs,
-                                                         const int2* __restrict__ tiles) {
-  const int2 tv = tiles[blockIdx.x];
-  const StreamSig& S = sigs[tv.x];
-  if (!S.st->active) return;
-  const int a = tv.y * kTile, b = min(a + kTile, S.L);
-  const int64_t M = S.M, R = S.M + S.D;
-  double* slot = S.out + (int64_t)S.st->nimf * (S.M * S.N);
-  for (int k = a + threadIdx.x; k < b; k += kTT) {
-    const double hk = S.h[k];
-    const double nr = S.r[k] - hk;
-    S.r[k] = nr;
-    S.h[k] = nr;
-    const int64_t i = k / R, m = k - i * R;
-    if (m < M) slot[i * M + m] = hk;
-  }
-}
-
-__global__ void st_imf_commit_kernel(const StreamSig* __restrict__ sigs, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
-    SigStatus* st = sigs[i].st;
-    if (st->active) {
-      st->nimf += 1;
-      st->skip = 0;
-    }
-  }
-}
-
-// Residue (= h) into slot K, unused IMF slots zero (Sec. 4.3 zero fill).
-__global__ void __launch_bounds__(kTT) st_final_kernel(const StreamSig* __restrict__ sigs,
-                                                       const int2* __restrict__ tiles, int K) {
-  const int2 tv = tiles[blockIdx.x];
-  const StreamSig& S = sigs[tv.x];
-  const int a = tv.y * kTile, b = min(a + kTile, S.L);
   const int64_t M = S.M, R = S.M + S.D, MN = S.M * S.N;
-  const int bad = S.st->bad;
-  const int nimf = bad ? 0 : S.st->nimf;
-  for (int k = a + threadIdx.x; k < b; k += kTT) {
-    const int64_t i = k / R, m = k - i * R;
-    if (m < M) {
-      const int64_t o = i * M + m;
-      for (int s = nimf; s < K; ++s) S.out[s * MN + o] = 0.0;
-      S.out[(int64_t)K * MN + o] = bad ? 0.0 : S.h[k];
+  if (action == kSiftLast || action == kEndImf) {
+    double* slot = S.out + (int64_t)st->slot * MN;
+    for (int i = threadIdx.x; i < n; i += kTT) {
+      const int k = a + i;
+      const double hk = tbuf[i];
+      const double nr = S.r[k] - hk;
+      S.r[k] = nr;
+      tbuf[i] = nr;
+      const int64_t ii = k / R, m = k - ii * R;
+      if (m < M) slot[ii * M + m] = hk;
     }
   }
-  if (tv.y == 0 && threadIdx.x == 0) {
-    if (S.n_imfs) *S.n_imfs = bad ? -5 : nimf;
-    if (S.stats) {
-      S.stats[0] = S.st->n_sifts;
-      S.stats[1] = S.st->n_knots;
-      S.stats[2] = S.st->n_sifts * (int64_t)S.L;
+  if (st->fin) {
+    const int K = S.K, bad = st->bad;
+    const int nimf = bad ? 0 : st->nimf;
+    for (int i = threadIdx.x; i < n; i += kTT) {
+      const int k = a + i;
+      const int64_t ii = k / R, m = k - ii * R;
+      if (m < M) {
+        const int64_t o = ii * M + m;
+        for (int q = nimf; q < K; ++q) S.out[q * MN + o] = 0.0;
+        S.out[(int64_t)K * MN + o] = bad ? 0.0 : tbuf[i];
+      }
     }
+    if (tv.y == 0 && threadIdx.x == 0) {
+      if (S.n_imfs) *S.n_imfs = bad ? -5 : nimf;
+      if (S.stats) {
+        S.stats[0] = st->n_sifts;
+        S.stats[1] = st->n_knots;
+        S.stats[2] = st->n_sifts * (int64_t)S.L;
+      }
+      S.st->done = 1;
+    }
+  } else {
+    for (int i = threadIdx.x; i < n; i += kTT) S.h[a + i] = tbuf[i];
   }
+}
+
+__global__ void st_gather_done_kernel(const StreamSig* __restrict__ sigs, int n,
+                                      int32_t* __restrict__ done) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) done[i] = sigs[i].st->done;
 }
 
 inline dim3 per_signal(int n) { return dim3((n + 255) / 256); }
@@ -467,32 +487,24 @@ inline dim3 per_signal(int n) { return dim3((n + 255) / 256); }
 // Launchers
 // ---------------------------------------------------------------------------
 
-hipError_t st_init(const StreamSig* sigs, int n, hipStream_t s) {
-  hipLaunchKernelGGL(st_init_kernel, per_signal(n), dim3(256), 0, s, sigs, n);
-  return hipGetLastError();
-}
 hipError_t st_load(const StreamSig* sigs, const int2* tiles, int ntiles, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(st_load_kernel, dim3(ntiles), dim3(kTT), 0, s, sigs, tiles);
   return hipGetLastError();
 }
-hipError_t st_sift(const StreamSig* sigs, int nsig, const int2* tiles, int ntiles,
-                   const int4* blocks, int nblocks, int s, hipStream_t st) {
+hipError_t st_step(const StreamSig* sigs, int nsig, const int2* tiles, int ntiles,
+                   const int4* blocks, int nblocks, hipStream_t st) {
+  if (nsig <= 0) return hipSuccess;
   hipLaunchKernelGGL(st_detect_kernel, dim3(ntiles), dim3(kTT), 0, st, sigs, tiles);
-  hipLaunchKernelGGL(st_scan_kernel, dim3(nsig), dim3(kTT), 0, st, sigs, s);
+  hipLaunchKernelGGL(st_scan_kernel, dim3(nsig), dim3(kTT), 0, st, sigs);
   hipLaunchKernelGGL(st_compact_kernel, dim3(ntiles), dim3(kTT), 0, st, sigs, tiles);
   hipLaunchKernelGGL(st_solve_kernel, dim3(nblocks), dim3(kTT), 0, st, sigs, blocks);
   hipLaunchKernelGGL(st_eval_kernel, dim3(ntiles), dim3(kTT), 0, st, sigs, tiles);
   return hipGetLastError();
 }
-hipError_t st_imf_end(const StreamSig* sigs, int nsig, const int2* tiles, int ntiles,
-                      hipStream_t s) {
-  hipLaunchKernelGGL(st_imf_end_kernel, dim3(ntiles), dim3(kTT), 0, s, sigs, tiles);
-  hipLaunchKernelGGL(st_imf_commit_kernel, per_signal(nsig), dim3(256), 0, s, sigs, nsig);
-  return hipGetLastError();
-}
-hipError_t st_final(const StreamSig* sigs, const int2* tiles, int ntiles, int K,
-                    hipStream_t s) {
-  hipLaunchKernelGGL(st_final_kernel, dim3(ntiles), dim3(kTT), 0, s, sigs, tiles, K);
+hipError_t st_gather_done(const StreamSig* sigs, int nsig, int32_t* done, hipStream_t s) {
+  if (nsig <= 0) return hipSuccess;
+  hipLaunchKernelGGL(st_gather_done_kernel, per_signal(nsig), dim3(256), 0, s, sigs, nsig, done);
   return hipGetLastError();
 }
 

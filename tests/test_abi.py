@@ -116,3 +116,24 @@ def test_batch_validation():
     assert L.semd_eemd_batch(items, 2, C.byref(pe), None) == semd.SEMD_EINVAL
     assert L.semd_decompose_batch(items, -1, C.byref(p), None) == semd.SEMD_EINVAL
     assert L.semd_decompose_batch(None, 2, C.byref(p), None) == semd.SEMD_EINVAL
+
+
+def test_engine_validation_without_device():
+    L = semd.lib()
+    p = _p()
+    it = semd.semd_item()
+    it.signal = 0x1000
+    it.imfs_out = 0x2000
+    it.dims[0], it.dims[1] = 1000, 3
+    it.ndim = 2
+    b = C.c_size_t()
+    assert L.semd_engine_footprint(C.byref(it), C.byref(p), C.byref(b)) == semd.SEMD_OK
+    assert b.value >= 3000 * 16  # candidate and residue at least
+    it.ndim = 0
+    assert L.semd_engine_footprint(C.byref(it), C.byref(p), C.byref(b)) == semd.SEMD_EINVAL
+    t = C.c_int64()
+    assert L.semd_engine_admit(None, C.byref(it), C.byref(p), C.byref(t)) == semd.SEMD_EINVAL
+    assert L.semd_engine_step(None, None) == semd.SEMD_EINVAL
+    h = C.c_void_p()
+    assert L.semd_engine_create(1 << 30, 0, C.byref(h)) == semd.SEMD_EINVAL
+    assert L.semd_engine_create(10, 4, C.byref(h)) == semd.SEMD_EINVAL

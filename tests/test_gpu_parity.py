@@ -28,6 +28,16 @@ def host(t):
     return t.cpu().numpy()
 
 
+def assert_same(a, b, what=""):
+    """Bit-identical arrays (reported by their largest difference)."""
+    a, b = np.asarray(a), np.asarray(b)
+    assert a.shape == b.shape, (what, a.shape, b.shape)
+    if a.tobytes() != b.tobytes():
+        d = np.abs(a.astype(np.float64) - b.astype(np.float64))
+        raise AssertionError(f"{what}: not bit-identical, max |diff| = {np.nanmax(d):.3e}, "
+                             f"{int(np.count_nonzero(d))} of {d.size} differ")
+
+
 # --------------------------------------------------------------------------
 # single steps
 # --------------------------------------------------------------------------
@@ -39,16 +49,16 @@ def test_serialize_deserialize_bit_exact(M, N, D):
     X = rng.standard_normal(M * N) * 10.0 ** rng.integers(-5, 5, M * N)
     x = host(semd.semd_serialize(dev(X), [M, N], D))
     want = oracle.serialize(X, M, N, D)
-    assert x.tobytes() == want.tobytes()
+    assert_same(x, want, "serialize")
     y = rng.standard_normal(want.size)
     back = host(semd.semd_deserialize(dev(y), [M, N], D))
-    assert back.tobytes() == oracle.deserialize(y, M, N, D).tobytes()
+    assert_same(back, oracle.deserialize(y, M, N, D), "deserialize")
 
 
 def test_noise_bit_exact_million_draws():
     for (seed, item, m) in [(0, 0, 0), (2106_15319, 17, 63)]:
         w = host(semd.semd_noise(seed, item, m, 1_000_000))
-        assert w.tobytes() == oracle.noise(seed, item, m, 1_000_000).tobytes()
+        assert_same(w, oracle.noise(seed, item, m, 1_000_000), "noise")
 
 
 def _plateau_signal(rng, L):
@@ -147,7 +157,7 @@ def test_batch_equals_plain_bit_exact():
     outs, counts = semd.decompose_batch(Xs, shapes, 10, 8, 10)
     for k, i in enumerate(items):
         o, n = semd.semd_decompose_ex(Xs[k], [i.M, i.N], 10, 8, 10)
-        assert host(o).tobytes() == host(outs[k]).tobytes()
+        assert_same(host(o), host(outs[k]), "batch vs plain")
         assert int(host(n)[0]) == int(host(counts)[k])
 
 
@@ -168,7 +178,7 @@ def test_determinism():
     it = workloads.config2(1)[0]
     a, _ = semd.semd_decompose_ex(dev(it.X), [it.M, it.N], 20, 8, 10)
     b, _ = semd.semd_decompose_ex(dev(it.X), [it.M, it.N], 20, 8, 10)
-    assert host(a).tobytes() == host(b).tobytes()
+    assert_same(host(a), host(b), "determinism")
 
 
 # --------------------------------------------------------------------------
@@ -363,3 +373,81 @@ def test_stream_eemd_long_signal():
     semd.semd_eemd_batch([dev(X)], [[M, N]], [out], None, D, K, S, NR, seed, [beta], [3])
     ref = oracle.eemd(X, M, N, D, K, S, NR, beta, seed, 3)
     assert np.abs(host(out) - ref).max() <= TOL * np.abs(X).max()
+
+
+# --------------------------------------------------------------------------
+# serving engine
+# --------------------------------------------------------------------------
+
+def _engine_run(eng, reqs, K, S, D):
+    outs, tickets = [], {}
+    for k, (X, M, N) in enumerate(reqs):
+        out = torch.empty((K + 1, M * N), dtype=torch.float64, device=DEV)
+        cnt = torch.empty(1, dtype=torch.int32, device=DEV)
+        t = eng.admit(dev(X), (M, N), out, cnt, D, K, S)
+        assert t is not None
+        tickets[t] = k
+        outs.append((out, cnt))
+    done = set()
+    for _ in range(K * S + 4):
+        eng.step()
+        done.update(eng.poll())
+        if len(done) == len(reqs):
+            break
+    torch.cuda.synchronize()
+    done.update(eng.poll())
+    assert done == set(tickets)
+    return outs
+
+
+def test_engine_matches_stream_path_and_mix():
+    K, S, D = 6, 10, 10
+    reqs = [(_series(15, k, M, N), M, N) for k, (M, N) in
+            enumerate([(3000, 2), (500, 3), (12000, 4), (40, 1), (2049, 1)])]
+    eng = semd.Engine(1 << 30, 64)
+    mixed = _engine_run(eng, reqs, K, S, D)
+    for k, (X, M, N) in enumerate(reqs):
+        alone_eng = _engine_run(eng, [(X, M, N)], K, S, D)[0]
+        ref, nref = semd.semd_decompose_ex(dev(X), [M, N], D, K, S, path=STREAM)
+        # same arithmetic alone, in the mix and on the batch path: bit-identical
+        assert_same(host(mixed[k][0]), host(alone_eng[0]), "engine mix vs alone")
+        assert_same(host(mixed[k][0]), host(ref), "engine vs streaming batch path")
+        assert int(host(mixed[k][1])[0]) == int(host(nref)[0])
+        ties = []
+        _check_item(X, M, N, D, K, S, host(mixed[k][0]), int(host(mixed[k][1])[0]), ties)
+    eng.close()
+
+
+def test_engine_admission_budget_and_staggered_arrivals():
+    K, S, D = 4, 6, 0
+    M, N = 6000, 2
+    fp = semd.Engine.footprint([M, N], D, K, S)
+    eng = semd.Engine(int(fp * 2.5), 8)  # room for two requests at a time
+    Xs = [_series(16, k, M, N) for k in range(5)]
+    outs = [torch.empty((K + 1, M * N), dtype=torch.float64, device=DEV) for _ in Xs]
+    cnts = [torch.empty(1, dtype=torch.int32, device=DEV) for _ in Xs]
+    t0 = eng.admit(dev(Xs[0]), (M, N), outs[0], cnts[0], D, K, S)
+    for _ in range(3):
+        eng.step()  # the first request is already sifting when the next arrive
+    t1 = eng.admit(dev(Xs[1]), (M, N), outs[1], cnts[1], D, K, S)
+    assert t0 is not None and t1 is not None
+    assert eng.admit(dev(Xs[2]), (M, N), outs[2], cnts[2], D, K, S) is None  # over budget
+    pending = [2, 3, 4]
+    done = set()
+    owner = {t0: 0, t1: 1}
+    for _ in range(10 * K * S):
+        while pending:
+            t = eng.admit(dev(Xs[pending[0]]), (M, N), outs[pending[0]], cnts[pending[0]], D, K,
+                          S)
+            if t is None:
+                break
+            owner[t] = pending.pop(0)
+        eng.step()
+        done.update(eng.poll())
+        if len(done) == 5:
+            break
+    assert len(done) == 5 and not pending
+    for t, k in owner.items():
+        ties = []
+        _check_item(Xs[k], M, N, D, K, S, host(outs[k]), int(host(cnts[k])[0]), ties)
+    eng.close()
