@@ -27,13 +27,62 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# flops per sample per sift (extrema 2, two envelope evaluations 25 each,
-# mean and update 3) and per knot per sift (one Thomas row 16 + 2), as
-# written in the method; see the design notes
-FLOPS_PER_SAMPLE_SIFT = 55
-FLOPS_PER_KNOT = 18
+# algorithmic FP64 operations of the method: per sample per sift 4 compares
+# (extrema), 2 x 12 (one cubic piece of each envelope) and 3 (mean and
+# update); per knot per sift about 10 for its Thomas row plus 1 reciprocal
+FLOPS_PER_SAMPLE_SIFT = 30
+FLOPS_PER_KNOT = 11
 FP64_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBPS = 8000.0
+
+# HBM traffic of the resident kernel on this workload, read from FETCH_SIZE
+# and WRITE_SIZE counter runs and scaled by the same counters on a copy of
+# known size; valid only while the kernel sources are the ones it was taken on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "resident_emd_kernel_faces_112x92x1024_traffic.txt")
+KERNEL_SOURCES = ["semd_kernels.hip", "semd_device.h", "semd_internal.h"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2106_15319_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(n_images: int, D: int):
+    """Bytes per launch from the committed counter summary, or None when it
+    is absent, was taken on another workload, or the kernel changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.lstrip().startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        if kv["source_sha256"] != kernel_source_hash():
+            return None
+        if int(kv["images"]) != n_images or int(kv["D"]) != D:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe(mib: int, reps: int) -> int:
+    """A plain device-to-device copy of known size, for scaling the HBM
+    byte counters: prints the bytes read (= bytes written) per copy."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 8, "reps": reps}), flush=True)
+    return 0
 
 
 def pct(a, q):
@@ -66,11 +115,16 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--path", choices=["auto", "onchip", "stream"], default="auto",
                     help="execution path of the batched decomposition")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the independent "
               "signals of a batch would shard across GPUs with no exchange", file=sys.stderr)
         return 2
+
+    if args.copy_probe:
+        return copy_probe(args.copy_probe, max(1, args.steps))
 
     import torch
 
@@ -125,31 +179,40 @@ def main() -> int:
 
     # plain path: one launch per image, same images
     npl = min(args.plain_items, n)
-    outs1 = [torch.empty((K + 1, MN), dtype=torch.float64, device=dev) for _ in range(npl)]
-    cnt1 = torch.empty(npl, dtype=torch.int32, device=dev)
-    for i in range(min(4, npl)):
-        semd.semd_decompose_ex(X[i], [M, N], D, K, S, outs1[i], cnt1[i:i + 1])
-    torch.cuda.synchronize()
-    pev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(npl)]
-    t1 = time.perf_counter()
-    for i, (a, b) in enumerate(pev):
-        a.record(stream)
-        semd.semd_decompose_ex(X[i], [M, N], D, K, S, outs1[i], cnt1[i:i + 1])
-        b.record(stream)
-    torch.cuda.synchronize()
-    plain_wall = time.perf_counter() - t1
-    plain_ms = [a.elapsed_time(b) for a, b in pev]
-    plain_value = npl * MN / plain_wall
-    same = all(torch.equal(outs1[i], out[i]) for i in range(npl))
+    plain = None
+    if npl > 0:
+        outs1 = [torch.empty((K + 1, MN), dtype=torch.float64, device=dev) for _ in range(npl)]
+        cnt1 = torch.empty(npl, dtype=torch.int32, device=dev)
+        for i in range(min(4, npl)):
+            semd.semd_decompose_ex(X[i], [M, N], D, K, S, outs1[i], cnt1[i:i + 1])
+        torch.cuda.synchronize()
+        pev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(npl)]
+        t1 = time.perf_counter()
+        for i, (a, b) in enumerate(pev):
+            a.record(stream)
+            semd.semd_decompose_ex(X[i], [M, N], D, K, S, outs1[i], cnt1[i:i + 1])
+            b.record(stream)
+        torch.cuda.synchronize()
+        plain_wall = time.perf_counter() - t1
+        plain_ms = [a.elapsed_time(b) for a, b in pev]
+        plain_value = npl * MN / plain_wall
+        same = all(torch.equal(outs1[i], out[i]) for i in range(npl))
+        plain = {"value": plain_value, "unit": "samples/s", "images": npl,
+                 "image_p50_ms": pct(plain_ms, 50), "image_p99_ms": pct(plain_ms, 99),
+                 "batched_over_plain": value / plain_value, "outputs_identical": same}
 
-    # roofline of the dominant kernel (the resident decomposition kernel: one
-    # launch per step), algorithmic FP64 flops over its measured duration
+    # roofline of the dominant kernel: on the on-chip path the batch is one
+    # launch of the resident kernel per step (the events bracket that launch
+    # and its ~100 KB descriptor upload); on the streaming path the figure
+    # covers the whole step's kernel sequence
     kern_ms = float(np.mean(step_ms))
     flops = FLOPS_PER_SAMPLE_SIFT * sample_sifts + FLOPS_PER_KNOT * n_knots
     achieved = flops / (kern_ms / 1e3) / 1e12
     b_io = 8 * MN * n * (K + 2)
     b_stream = b_io + 16 * sample_sifts + 16 * L * int(n_imfs.sum())
+    onchip = args.path == "onchip" or (args.path == "auto" and L <= semd.semd_resident_max_length())
+    traffic = measured_traffic(n, D) if onchip else None
 
     res = {
         "metric": "samples decomposed/s/GPU (batched+served vs plain), p50/p99 latency, "
@@ -170,15 +233,13 @@ def main() -> int:
                    "batch": n, "M": M, "N": N, "D": D, "L": L, "max_imfs": K,
                    "sift_iters": S, "path": args.path},
         "latency_ms": {"step_p50": pct(step_ms, 50), "step_p99": pct(step_ms, 99)},
-        "plain": {"value": plain_value, "unit": "samples/s", "images": npl,
-                  "image_p50_ms": pct(plain_ms, 50), "image_p99_ms": pct(plain_ms, 99),
-                  "batched_over_plain": value / plain_value, "outputs_identical": same},
+        "plain": plain,
         "work": {"sifts": n_sifts, "knots": n_knots, "sample_sifts": sample_sifts,
                  "mean_imfs": float(n_imfs.mean())},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "resident_emd_kernel<1024,16>", "kernel_ms": kern_ms,
-                     "flops_per_launch": flops},
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
+                     "kernel": "resident_emd_kernel" if onchip else "streaming step",
+                     "kernel_ms": kern_ms, "flops_per_launch": flops},
         "hbm": {"algorithmic_io_bytes": b_io,
                 "io_GBps": b_io / (kern_ms / 1e3) / 1e9,
                 "io_frac_of_peak": b_io / (kern_ms / 1e3) / 1e9 / HBM_PEAK_GBPS,
