@@ -132,7 +132,7 @@ int run_resident(std::vector<semd::WorkItem>& work, int K, int S, hipStream_t st
   std::stable_sort(work.begin(), work.end(),
                    [](const semd::WorkItem& a, const semd::WorkItem& b) { return a.L > b.L; });
   int64_t ws_doubles = 0;
-  for (const auto& w : work) ws_doubles += 2 * (int64_t)w.L;
+  for (const auto& w : work) ws_doubles += semd::resident_ws_doubles(w.L);
   double* ws = nullptr;
   hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&ws),
                                 sizeof(double) * (size_t)std::max<int64_t>(ws_doubles, 1), stream);
@@ -142,7 +142,7 @@ int run_resident(std::vector<semd::WorkItem>& work, int K, int S, hipStream_t st
   for (auto& w : work) {
     w.r = ws + off;
     w.u = w.r + w.L;
-    off += 2 * (int64_t)w.L;
+    off += semd::resident_ws_doubles(w.L);
   }
   void* d_items = nullptr;
   int rc = upload(work.data(), work.size() * sizeof(semd::WorkItem), stream, &d_items);

@@ -15,7 +15,8 @@ struct WorkItem {
   int32_t* n_imfs;   // device, one int32 or nullptr
   int64_t* stats;    // device, 3 int64 (sifts, knots, sample-sifts) or nullptr
   double* r;         // device workspace, L doubles (residue, serialized)
-  double* u;         // device workspace, L doubles (upper envelope, when parked)
+  double* u;         // device workspace, resident_ws_doubles(L) - L doubles: the
+                     // parked upper envelope, or the global knot store
   int64_t M;         // fibre length (rows of X)
   int64_t N;         // number of fibres (columns of X)
   int32_t D;         // transition length
@@ -30,6 +31,17 @@ struct WorkItem {
 // per thread of its largest instance).
 constexpr int kResidentMaxL = 16384;
 
+// Knots the global knot store of one resident item holds: both envelopes of
+// any sift (at most L - 2 extrema plus 8 mirrored knots).
+__host__ __device__ constexpr int resident_gknot_cap(int L) { return L + 16; }
+
+// Workspace doubles of one resident item: the residue (L) and the region u,
+// which holds either the parked upper envelope (L doubles) or the global knot
+// store (4 doubles and one int16 per knot).
+__host__ __device__ constexpr int64_t resident_ws_doubles(int64_t L) {
+  return L + 4 * (L + 16) + ((L + 16) * 2 + 7) / 8 + 2;
+}
+
 // Launch shape of the resident kernel: threads per workgroup and samples per
 // thread, chosen from the longest signal of a launch.
 struct ResidentClass {
@@ -39,7 +51,8 @@ struct ResidentClass {
 ResidentClass resident_class(int maxL);
 
 // Bytes of the kernel's reusable LDS area for signals up to maxL samples,
-// at most max_area.
+// at most max_area (and at least what the block-end publication and the
+// staging window need).
 size_t resident_area_bytes(int maxL, int nt, size_t max_area);
 
 // Launch the resident kernel over `n` work items (device array), all with

@@ -28,62 +28,405 @@ using namespace dev;
 constexpr int kAggBytes = 256;
 
 // ---------------------------------------------------------------------------
+// Resident-path building blocks (blocked layout: thread t owns the C samples
+// [t*C, t*C + C) of the signal in registers h[])
+// ---------------------------------------------------------------------------
+
+// Knot store of the envelopes of one sift.  Knot j holds abscissa t_j, value
+// y_j and spline second derivative m_j; once the derivatives are known, q1_j
+// and q3_j hold the linear and cubic coefficients of segment [t_j, t_{j+1})
+// in the power form used by the walker (seg_coeffs).  34 bytes per knot.
+struct Knots {
+  double* y;
+  double* m;
+  double* q1;
+  double* q3;
+  int16_t* t;
+};
+
+constexpr int kKnotBytes = 4 * (int)sizeof(double) + (int)sizeof(int16_t);
+
+__device__ __forceinline__ Knots knots_in(unsigned char* p, int cap) {
+  Knots s;
+  s.y = reinterpret_cast<double*>(p);
+  s.m = s.y + cap;
+  s.q1 = s.m + cap;
+  s.q3 = s.q1 + cap;
+  s.t = reinterpret_cast<int16_t*>(s.q3 + cap);
+  return s;
+}
+
+__device__ __forceinline__ Knots knots_from(const Knots& a, int o) {
+  Knots s;
+  s.y = a.y + o;
+  s.m = a.m + o;
+  s.q1 = a.q1 + o;
+  s.q3 = a.q3 + o;
+  s.t = a.t + o;
+  return s;
+}
+
+// Extrema of the candidate (Sec. 2.1 Step 1) from per-thread step masks.
+// Bit b of R (F) is set when sample b of the thread is above (below) sample
+// b-1; bit 0 compares with the previous thread's last sample and bit C with
+// the next thread's first, so NE = R | F marks the starts of equal-valued
+// runs.  A sample c closes a run when step c -> c+1 is not flat; the run is a
+// maximum when it was entered rising and is left falling (minimum: the
+// reverse), and its knot sits at the floor-middle of the run.  A run that
+// starts in an earlier thread takes its entry kind from `carry` (key
+// 4*start + kind of the run holding the thread's first sample; kind 0 for the
+// run that starts at sample 0, which is never an extremum).  Contains one
+// barrier.
+template <int NT, int C>
+__device__ __forceinline__ void rd_detect(const double (&h)[C], int base, int nv, int L, int tid,
+                                          double* pub_first, double* pub_last, int* pub_key,
+                                          unsigned& R, unsigned& F, int& carry,
+                                          unsigned& maxbits, unsigned& minbits) {
+  R = 0u;
+  F = 0u;
+#pragma unroll
+  for (int b = 1; b < C; ++b) {
+    if (b < nv) {
+      R |= (h[b] > h[b - 1] ? 1u : 0u) << b;
+      F |= (h[b] < h[b - 1] ? 1u : 0u) << b;
+    }
+  }
+  if (nv > 0) {
+    const unsigned inner = R | F;
+    int key = -1;
+    if (inner) {
+      const int b = 31 - __clz(inner);
+      key = (base + b) * 4 + (((R >> b) & 1u) ? kRise : kFall);
+    }
+    double last = h[C - 1];
+    if (nv < C) {
+#pragma unroll
+      for (int c = 0; c < C - 1; ++c)
+        if (c == nv - 1) last = h[c];
+    }
+    pub_first[tid] = h[0];
+    pub_last[tid] = last;
+    pub_key[tid] = key;
+  }
+  __syncthreads();
+  carry = 0;
+  maxbits = 0u;
+  minbits = 0u;
+  if (nv <= 0) return;
+  if (tid > 0) {
+    const double prev = pub_last[tid - 1];
+    R |= h[0] > prev ? 1u : 0u;
+    F |= h[0] < prev ? 1u : 0u;
+    if (prev != h[0]) {
+      carry = base * 4 + step_kind(prev, h[0]);
+    } else {
+      // the run continues from an earlier thread: walk back to its start
+      int tau = tid - 1;
+      for (;;) {
+        const int kk = pub_key[tau];
+        if (kk >= 0) { carry = kk; break; }
+        if (tau == 0) { carry = 0; break; }
+        const double pl = pub_last[tau - 1], pf = pub_first[tau];
+        if (pl != pf) { carry = tau * C * 4 + step_kind(pl, pf); break; }
+        --tau;
+      }
+    }
+  }
+  if (nv == C && base + C < L) {
+    const double next = pub_first[tid + 1];
+    R |= (next > h[C - 1] ? 1u : 0u) << C;
+    F |= (next < h[C - 1] ? 1u : 0u) << C;
+  }
+  const unsigned NE = R | F;
+  const unsigned valid = (1u << nv) - 1u;
+  maxbits = R & (F >> 1) & valid;
+  minbits = F & (R >> 1) & valid;
+  // ends of runs longer than one sample (or holding the thread's first)
+  unsigned pe = (NE >> 1) & ~NE & valid;
+  while (pe) {
+    const int c = __ffs(pe) - 1;
+    pe &= pe - 1u;
+    const unsigned below = NE & ((1u << c) - 1u);
+    int kind;
+    if (below) {
+      const int b = 31 - __clz(below);
+      kind = ((R >> b) & 1u) ? kRise : kFall;
+    } else {
+      kind = carry & 3;
+    }
+    if (kind == kRise && ((F >> (c + 1)) & 1u)) maxbits |= 1u << c;
+    else if (kind == kFall && ((R >> (c + 1)) & 1u)) minbits |= 1u << c;
+  }
+}
+
+// Floor-middle of the equal-valued run that sample c of the thread closes.
+__device__ __forceinline__ int run_mid(unsigned NE, int carry, int base, int c) {
+  const unsigned below = NE & ((2u << c) - 1u);
+  const int start = below ? base + (31 - __clz(below)) : (carry >> 2);
+  return (start + base + c) >> 1;
+}
+
+// Write this thread's knots of one kind (bits) at ranks first.. among n,
+// plus the mirrored end knots (Sec. 2.1 Step 2 with the mirror boundary):
+//   [-k_P', ..., -k_1, k_1, ..., k_n, 2(L-1)-k_n, ..., 2(L-1)-k_{n-P'+1}],
+// P' = min(2, n), mirrored knots carrying their source's value.
+template <int C>
+__device__ __forceinline__ void rd_emit(const double (&h)[C], unsigned bits, unsigned NE,
+                                        int carry, int base, int L, int first, int n,
+                                        const Knots ks) {
+  const int Pp = n < 2 ? n : 2;
+  const int hi = 2 * (L - 1);
+#pragma unroll 1
+  for (int c = 0; c < C; ++c) {
+    if ((bits >> c) & 1u) {
+      const int g = first + __popc(bits & ((1u << c) - 1u));
+      const int mid = run_mid(NE, carry, base, c);
+      const double y = h[c];
+      ks.t[Pp + g] = (int16_t)mid;
+      ks.y[Pp + g] = y;
+      if (g < 2 || g >= n - 2) {
+        if (g == 0) { ks.t[Pp - 1] = (int16_t)(-mid); ks.y[Pp - 1] = y; }
+        if (g == 1 && Pp == 2) { ks.t[0] = (int16_t)(-mid); ks.y[0] = y; }
+        if (g == n - 1) { ks.t[Pp + n] = (int16_t)(hi - mid); ks.y[Pp + n] = y; }
+        if (g == n - 2 && Pp == 2) { ks.t[Pp + n + 1] = (int16_t)(hi - mid); ks.y[Pp + n + 1] = y; }
+      }
+    }
+  }
+}
+
+// Natural-spline second derivatives (Sec. 2.1 Step 2) of one chunk of
+// interior unknowns: rows s..e with s = 1 + ch*kChunk, by the windowed
+// Thomas sweeps of the streaming solver (forward from kHalo rows before the
+// chunk, backward from kHalo rows after it, joined at row e), except that the
+// forward factors of the chunk's rows wait in the knot store (c' in m, d' in
+// q1, both unused until the derivatives exist) instead of registers.
+__device__ __forceinline__ void rd_solve_chunk(const Knots ks, int n, int ch) {
+  const int s = 1 + ch * kChunk;
+  const int e = min(s + kChunk - 1, n - 2);
+  const int ws = max(1, s - kHalo);
+  const int we = min(n - 2, e + kHalo);
+  double ftp = (double)ks.t[ws - 1], ft = (double)ks.t[ws];
+  double fy = ks.y[ws];
+  double fsp = (fy - ks.y[ws - 1]) * recip(ft - ftp);
+  double cp = 0.0, dp = 0.0;
+  double btn = (double)ks.t[we + 1], bt = (double)ks.t[we];
+  double by = ks.y[we];
+  double bsn = (ks.y[we + 1] - by) * recip(btn - bt);
+  double aa = 0.0, dd = 0.0;
+  const int nf = e + 1 - ws;                // forward rows ws .. e
+  const int nb = (e < n - 2) ? we - e : 0;  // backward rows we .. e+1
+  const int steps = max(nf, nb);
+#pragma unroll 1
+  for (int i = 0; i < steps; ++i) {
+    if (i < nf) {
+      const int j = ws + i;
+      const double tn = (double)ks.t[j + 1], yn = ks.y[j + 1];
+      const double g0 = ft - ftp, g1 = tn - ft;
+      const double sn = (yn - fy) * recip(g1);
+      const double rhs = 6.0 * (sn - fsp);
+      const double inv = recip(fma(-g0, cp, 2.0 * (g0 + g1)));
+      cp = g1 * inv;
+      dp = fma(-g0, dp, rhs) * inv;
+      if (j >= s) {
+        ks.m[j] = cp;
+        ks.q1[j] = dp;
+      }
+      ftp = ft; ft = tn; fy = yn; fsp = sn;
+    }
+    if (i < nb) {
+      const int j = we - i;
+      const double tp = (double)ks.t[j - 1], yp = ks.y[j - 1];
+      const double g1 = btn - bt, g0 = bt - tp;
+      const double sp = (by - yp) * recip(g0);
+      const double rhs = 6.0 * (bsn - sp);
+      const double inv = recip(fma(-g1, aa, 2.0 * (g0 + g1)));
+      aa = g0 * inv;
+      dd = fma(-g1, dd, rhs) * inv;
+      btn = bt; bt = tp; by = yp; bsn = sp;
+    }
+  }
+  // M_e = d'_e - c'_e M_{e+1} with M_{e+1} = dd - aa M_e from the right, or
+  // M_e = d'_e on the last row (M_{n-1} = 0); then back-substitution
+  double Mn = (e < n - 2) ? fma(-cp, dd, dp) * recip(fma(-cp, aa, 1.0)) : dp;
+  ks.m[e] = Mn;
+#pragma unroll 1
+  for (int j = e - 1; j >= s; --j) {
+    Mn = fma(-ks.m[j], Mn, ks.q1[j]);
+    ks.m[j] = Mn;
+  }
+}
+
+// Second derivatives of up to two knot systems (n1 knots at offset 0, n2 at
+// offset o2; n = 0: none), their chunks spread over the workgroup.
+template <int NT>
+__device__ __forceinline__ void rd_solve(const Knots ks, int n1, int o2, int n2, int tid) {
+  const int c1 = n1 >= 3 ? (n1 - 2 + kChunk - 1) / kChunk : 0;
+  const int c2 = n2 >= 3 ? (n2 - 2 + kChunk - 1) / kChunk : 0;
+  for (int ch = tid; ch < c1 + c2; ch += NT) {
+    const bool second = ch >= c1;
+    rd_solve_chunk(second ? knots_from(ks, o2) : ks, second ? n2 : n1, second ? ch - c1 : ch);
+  }
+  if (tid == 0) {
+    if (n1 >= 3) { ks.m[0] = 0.0; ks.m[n1 - 1] = 0.0; }
+    if (n2 >= 3) { ks.m[o2] = 0.0; ks.m[o2 + n2 - 1] = 0.0; }
+  }
+}
+
+// Power-form coefficients of every segment of up to two knot systems (n1
+// knots at offset 0, n2 at offset o2).  On [t_j, t_{j+1}), with B = k - t_j
+// and g = t_{j+1} - t_j, the natural spline is
+//   y_j + b_j B + (m_j / 2) B^2 + ((m_{j+1} - m_j) / (6 g)) B^3,
+//   b_j = (y_{j+1} - y_j) / g - g (2 m_j + m_{j+1}) / 6;
+// the walker evaluates half of it (the envelope mean is the sum of the two
+// halves), so q1 = b_j / 2 and q3 = (m_{j+1} - m_j) / (12 g) are stored.
+template <int NT>
+__device__ __forceinline__ void seg_coeffs(const Knots ks, int n1, int o2, int n2, int tid) {
+  const int s1 = n1 - 1, s2 = n2 > 0 ? n2 - 1 : 0;
+  for (int i = tid; i < s1 + s2; i += NT) {
+    const int j = i < s1 ? i : o2 + (i - s1);
+    const double g = (double)((int)ks.t[j + 1] - (int)ks.t[j]);
+    const double ig = recip(g);
+    const double m0 = ks.m[j], m1 = ks.m[j + 1];
+    const double b = (ks.y[j + 1] - ks.y[j]) * ig - g * fma(2.0, m0, m1) * (1.0 / 6.0);
+    ks.q1[j] = 0.5 * b;
+    ks.q3[j] = (m1 - m0) * ig * (1.0 / 12.0);
+  }
+}
+
+// Walker over the segments of one envelope: the current segment [t0, t1),
+// its halved power-form coefficients and the local abscissa B = k - t0.
+struct Walk {
+  int j, t0, t1;
+  double B, q0, q1, q2, q3;
+};
+
+__device__ __forceinline__ void walk_load(Walk& w, const Knots& ks, int j) {
+  w.j = j;
+  w.t0 = ks.t[j];
+  w.t1 = ks.t[j + 1];
+  w.q0 = 0.5 * ks.y[j];
+  w.q1 = ks.q1[j];
+  w.q2 = 0.25 * ks.m[j];
+  w.q3 = ks.q3[j];
+}
+
+// Position at the segment holding sample k, starting from segment j (whose
+// left knot lies at or before k; the last knot lies beyond the signal).
+__device__ __forceinline__ void walk_init(Walk& w, const Knots& ks, int j, int k) {
+  walk_load(w, ks, j);
+  while (w.t1 <= k) walk_load(w, ks, w.j + 1);
+  w.B = (double)(k - w.t0);
+}
+
+// Half the envelope at sample k, the walker standing at k (knots are
+// distinct integers, so one step from k-1 crosses at most one of them).
+__device__ __forceinline__ double walk_at(Walk& w, const Knots& ks, int k) {
+  if (w.t1 <= k) {
+    walk_load(w, ks, w.j + 1);
+    w.B = (double)(k - w.t0);
+  }
+  return fma(fma(fma(w.q3, w.B, w.q2), w.B, w.q1), w.B, w.q0);
+}
+
+// One envelope pair (or one envelope) built and applied: knots emitted,
+// second derivatives solved, segment coefficients formed.  Barriers between
+// the phases; the caller evaluates.
+template <int NT, int C>
+__device__ __forceinline__ void build_envelopes(const double (&h)[C], unsigned bits1,
+                                                unsigned bits2, unsigned NE, int carry, int base,
+                                                int L, int first1, int n1, int first2, int n2,
+                                                const Knots ks, int nk1, int nk2, int tid) {
+  rd_emit<C>(h, bits1, NE, carry, base, L, first1, n1, ks);
+  if (n2 > 0) rd_emit<C>(h, bits2, NE, carry, base, L, first2, n2, knots_from(ks, nk1));
+  __syncthreads();
+  rd_solve<NT>(ks, nk1, nk1, nk2, tid);
+  __syncthreads();
+  seg_coeffs<NT>(ks, nk1, nk1, nk2, tid);
+  __syncthreads();
+}
+
+// Hides a value's origin from the optimizer (no instruction is emitted).
+__device__ __forceinline__ void opaque(int& v) { asm volatile("" : "+v"(v)); }
+
+// Samples of the chunk [c0, c1) of the signal that thread-owned slot c maps to.
+__device__ __forceinline__ bool in_chunk(int k, int c0, int c1) { return k >= c0 && k < c1; }
+
+// k / R and k % R for 0 <= k < 2^24 and R >= 1 from a float reciprocal,
+// corrected by one step either way.
+__device__ __forceinline__ void div_small(int k, int R, float invR, int& q, int& rem) {
+  q = (int)((float)k * invR);
+  rem = k - q * R;
+  if (rem < 0) { --q; rem += R; }
+  else if (rem >= R) { ++q; rem -= R; }
+}
+
+// ---------------------------------------------------------------------------
 // Resident Serial-EMD kernel: one workgroup per work item
 // ---------------------------------------------------------------------------
 
 // LDS: 256 B of wave totals, then one area (area_bytes) used in turn as
-//   - the staging buffer of the signal (L doubles) at load and IMF ends,
-//   - the published block ends of the extremum detection (20 B per thread),
-//   - the knot store: capk values, capk second derivatives, capk abscissae.
-// A sift keeps both envelopes' knots in the store when they fit together
-// (one solve, one fused evaluation and update); otherwise it builds them one
-// after the other, parking the upper envelope in global memory.
+//   - a staging window of the signal (a multiple of NT doubles) at load and
+//     IMF ends, so global reads and writes stay coalesced;
+//   - the published block ends of the extremum detection (20 B per thread);
+//   - the knot store (34 B per knot).
+// A sift keeps both envelopes' knots in LDS when they fit together (one
+// solve, one fused evaluation, mean and update); else one envelope at a time
+// when each fits (the upper envelope parked in global memory); else both in
+// the item's global knot store.
 template <int NT, int C>
 __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __restrict__ items,
                                                           int K, int S, int area_bytes) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NW = NT / kWave;
-  const int tid = threadIdx.x;
-  const int lane = tid & (kWave - 1);
-  const int wid = tid / kWave;
+  const int tid0 = threadIdx.x;
   const WorkItem w = items[blockIdx.x];
   // the resident path holds at most kResidentMaxL samples: 32-bit indices
   const int L = w.L;
   const int M = (int)w.M, MN = (int)(w.M * w.N), R = (int)(w.M + w.D);
   const int D = w.D;
+  const float invR = 1.0f / (float)R;
 
   int* wagg = reinterpret_cast<int*>(smem);
   unsigned char* area = smem + kAggBytes;
-  const int capk = (area_bytes / (2 * (int)sizeof(double) + (int)sizeof(int16_t))) & ~7;
+  const int capk = area_bytes / kKnotBytes;
+  const int scap = (area_bytes / (int)sizeof(double)) / NT * NT;
   double* stage = reinterpret_cast<double*>(area);
-  double* ky = reinterpret_cast<double*>(area);
-  double* km = ky + capk;
-  int16_t* kt = reinterpret_cast<int16_t*>(km + capk);
   double* pub_first = reinterpret_cast<double*>(area);
   double* pub_last = pub_first + NT;
   int* pub_key = reinterpret_cast<int*>(pub_last + NT);
+  const Knots lk = knots_in(area, capk);
+  const Knots gk = knots_in(reinterpret_cast<unsigned char*>(w.u), resident_gknot_cap(L));
 
-  const int base = tid * C;
-  const int nv = max(0, min(C, L - base));
+  const int base0 = tid0 * C;
+  const int nv0 = max(0, min(C, L - base0));
 
   // Load: serialize (Sec. 3.2), add the realization's noise (Sec. 2.2 Step 1)
-  int bad = 0;
-  for (int k = tid; k < L; k += NT) {
-    const int i = k / R, m = k - i * R;
-    double v = serial_at(w.X, M, D, i, m);
-    if (w.flags & 1) v = __dadd_rn(v, __dmul_rn(w.beta, noise_at(w.key, k)));
-    bad |= !isfinite(v);
-    stage[k] = v;
-    w.r[k] = v;
-  }
-  if (__syncthreads_or(bad)) {
-    for (int64_t o = tid; o < (int64_t)(K + 1) * MN; o += NT) w.out[o] = 0.0;
-    if (tid == 0 && w.n_imfs) *w.n_imfs = -5;
-    return;
-  }
   double h[C];
 #pragma unroll
-  for (int c = 0; c < C; ++c) h[c] = (c < nv) ? stage[base + c] : 0.0;
+  for (int c = 0; c < C; ++c) h[c] = 0.0;
+  int bad = 0;
+  for (int c0 = 0; c0 < L; c0 += scap) {
+    const int c1 = min(L, c0 + scap);
+    __syncthreads();
+    for (int k = c0 + tid0; k < c1; k += NT) {
+      int i, m;
+      div_small(k, R, invR, i, m);
+      double v = serial_at(w.X, M, D, i, m);
+      if (w.flags & 1) v = __dadd_rn(v, __dmul_rn(w.beta, noise_at(w.key, k)));
+      bad |= !isfinite(v);
+      stage[k - c0] = v;
+      w.r[k] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+      if (c < nv0 && in_chunk(base0 + c, c0, c1)) h[c] = stage[base0 + c - c0];
+  }
+  if (__syncthreads_or(bad)) {
+    for (int64_t o = tid0; o < (int64_t)(K + 1) * MN; o += NT) w.out[o] = 0.0;
+    if (tid0 == 0 && w.n_imfs) *w.n_imfs = -5;
+    return;
+  }
 
   int nimf = 0;
   int64_t n_sifts = 0, n_knots = 0;
@@ -91,113 +434,135 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
     bool stop = false;
     for (int s = 0; s < S; ++s) {
       __syncthreads();  // previous readers of the LDS area are done
-      int carry, cmax, cmin;
-      unsigned maxbits, minbits;
-      detect_extrema<NT, C>(h, 0, L, L, tid, 0, 0.0, pub_first, pub_last, pub_key, carry,
-                            maxbits, minbits, cmax, cmin, nullptr, nullptr);
+      // Values derived from the thread's position are recomputed every sift
+      // rather than hoisted out of the loop and held in registers throughout.
+      int tid = tid0, base = base0, nv = nv0;
+      opaque(tid);
+      opaque(base);
+      opaque(nv);
+      unsigned Rm, Fm, maxbits, minbits;
+      int carry;
+      rd_detect<NT, C>(h, base, nv, L, tid, pub_first, pub_last, pub_key, Rm, Fm, carry,
+                       maxbits, minbits);
       int tot;
-      const int excl = block_excl_sum<NW>((cmax << 16) | cmin, wagg, lane, wid, tot);
+      const int excl = block_excl_sum<NW>((__popc(maxbits) << 16) | __popc(minbits), wagg,
+                                          tid & (kWave - 1), tid / kWave, tot);
       const int nmax = tot >> 16, nmin = tot & 0xffff;
       if (!(nmax >= 1 && nmin >= 1 && nmax + nmin >= 3)) {
         stop = (s == 0);  // the residue itself is not siftable: decomposition ends
         break;
       }
+      const unsigned NE = Rm | Fm;
       const int emax = excl >> 16, emin = excl & 0xffff;
       const int pmax = nmax < 2 ? nmax : 2, pmin = nmin < 2 ? nmin : 2;
       const int nkmax = nmax + 2 * pmax, nkmin = nmin + 2 * pmin;
       ++n_sifts;
       n_knots += nkmax + nkmin;
-      if (nkmax + nkmin <= capk) {
-        // both envelopes at once
-        emit_knots<C>(h, maxbits, carry, base, nv, L, emax, nmax, kt, ky, nkmax);
-        emit_knots<C>(h, minbits, carry, base, nv, L, emin, nmin, kt + nkmax, ky + nkmax,
-                      nkmin);
-        __syncthreads();
-        spline_second_derivs<NT>(kt, ky, km, nkmax, nkmax, nkmin, tid);
-        __syncthreads();
+      const bool both_lds = nkmax + nkmin <= capk;
+      const bool single = !both_lds && nkmax <= capk && nkmin <= capk;
+      if (!single) {
+        // both envelopes at once, in LDS or in the global knot store
+        const Knots ks = both_lds ? lk : gk;
+        build_envelopes<NT, C>(h, maxbits, minbits, NE, carry, base, L, emax, nmax, emin, nmin,
+                               ks, nkmax, nkmin, tid);
         if (nv > 0) {
-          Seg su, sl;
-          seg_load(su, kt, ky, km, pmax + emax - 1);
-          seg_load(sl, kt + nkmax, ky + nkmax, km + nkmax, pmin + emin - 1);
-#pragma unroll 1
+          const Knots kl = knots_from(ks, nkmax);
+          Walk wu, wl;
+          walk_init(wu, ks, pmax + emax - 1, base);
+          walk_init(wl, kl, pmin + emin - 1, base);
+#pragma unroll
           for (int c = 0; c < C; ++c) {
             if (c < nv) {
-              const double kk = (double)(base + c);
-              const double up = seg_eval(su, kt, ky, km, nkmax, kk);
-              const double lo = seg_eval(sl, kt + nkmax, ky + nkmax, km + nkmax, nkmin, kk);
-              const double mean = 0.5 * (up + lo);
-              h[c] = h[c] - mean;
+              const int k = base + c;
+              const double up = walk_at(wu, ks, k);
+              const double lo = walk_at(wl, kl, k);
+              h[c] = h[c] - (up + lo);
+              wu.B += 1.0;
+              wl.B += 1.0;
             }
           }
         }
       } else {
-        // one envelope at a time
-        emit_knots<C>(h, maxbits, carry, base, nv, L, emax, nmax, kt, ky, nkmax);
-        __syncthreads();
-        spline_second_derivs<NT>(kt, ky, km, nkmax, 0, 0, tid);
-        __syncthreads();
+        // one envelope at a time: the upper one parked in global memory
+        build_envelopes<NT, C>(h, maxbits, 0u, NE, carry, base, L, emax, nmax, 0, 0, lk, nkmax,
+                               0, tid);
         if (nv > 0) {
-          Seg su;
-          seg_load(su, kt, ky, km, pmax + emax - 1);
-#pragma unroll 1
-          for (int c = 0; c < C; ++c)
-            if (c < nv) w.u[base + c] = seg_eval(su, kt, ky, km, nkmax, (double)(base + c));
-        }
-        __syncthreads();
-        emit_knots<C>(h, minbits, carry, base, nv, L, emin, nmin, kt, ky, nkmin);
-        __syncthreads();
-        spline_second_derivs<NT>(kt, ky, km, nkmin, 0, 0, tid);
-        __syncthreads();
-        if (nv > 0) {
-          Seg sl;
-          seg_load(sl, kt, ky, km, pmin + emin - 1);
-#pragma unroll 1
+          Walk wu;
+          walk_init(wu, lk, pmax + emax - 1, base);
+#pragma unroll
           for (int c = 0; c < C; ++c) {
             if (c < nv) {
-              const double lo = seg_eval(sl, kt, ky, km, nkmin, (double)(base + c));
-              const double mean = 0.5 * (w.u[base + c] + lo);
-              h[c] = h[c] - mean;
+              w.u[base + c] = walk_at(wu, lk, base + c);
+              wu.B += 1.0;
+            }
+          }
+        }
+        __syncthreads();
+        build_envelopes<NT, C>(h, minbits, 0u, NE, carry, base, L, emin, nmin, 0, 0, lk, nkmin,
+                               0, tid);
+        if (nv > 0) {
+          Walk wl;
+          walk_init(wl, lk, pmin + emin - 1, base);
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            if (c < nv) {
+              const double lo = walk_at(wl, lk, base + c);
+              h[c] = h[c] - (w.u[base + c] + lo);
+              wl.B += 1.0;
             }
           }
         }
       }
     }
     if (stop) break;
-    // IMF nimf = h (deserialized store, Sec. 3.3); residue r <- r - h
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < C; ++c)
-      if (c < nv) stage[base + c] = h[c];
-    __syncthreads();
+    // IMF nimf = h (deserialized store, Sec. 3.3); residue r <- r - h; h <- r
     double* slot = w.out + (int64_t)nimf * MN;
-    for (int k = tid; k < L; k += NT) {
-      const double hk = stage[k];
-      const double nr = w.r[k] - hk;
-      w.r[k] = nr;
-      stage[k] = nr;
-      const int i = k / R, m = k - i * R;
-      if (m < M) slot[i * M + m] = hk;
+    int tid = tid0, base = base0, nv = nv0;
+    opaque(tid);
+    opaque(base);
+    opaque(nv);
+    for (int c0 = 0; c0 < L; c0 += scap) {
+      const int c1 = min(L, c0 + scap);
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+        if (c < nv && in_chunk(base + c, c0, c1)) stage[base + c - c0] = h[c];
+      __syncthreads();
+      for (int k = c0 + tid; k < c1; k += NT) {
+        const double hk = stage[k - c0];
+        const double nr = w.r[k] - hk;
+        w.r[k] = nr;
+        stage[k - c0] = nr;
+        int i, m;
+        div_small(k, R, invR, i, m);
+        if (m < M) slot[i * M + m] = hk;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+        if (c < nv && in_chunk(base + c, c0, c1)) h[c] = stage[base + c - c0];
     }
     ++nimf;
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < C; ++c) h[c] = (c < nv) ? stage[base + c] : 0.0;
   }
-  // residue into slot K, unused IMF slots zero (Sec. 4.3 zero fill)
+  // residue into slot K (every r[k] was last written by this same thread),
+  // unused IMF slots zero (Sec. 4.3 zero fill)
   double* rslot = w.out + (int64_t)K * MN;
-  for (int k = tid; k < L; k += NT) {
-    const int i = k / R, m = k - i * R;
+  for (int k = tid0; k < L; k += NT) {
+    int i, m;
+    div_small(k, R, invR, i, m);
     if (m < M) rslot[i * M + m] = w.r[k];
   }
-  for (int64_t o = (int64_t)nimf * MN + tid; o < (int64_t)K * MN; o += NT) w.out[o] = 0.0;
-  if (tid == 0 && w.n_imfs) *w.n_imfs = nimf;
-  if (tid == 0 && w.stats) {
+  for (int64_t o = (int64_t)nimf * MN + tid0; o < (int64_t)K * MN; o += NT) w.out[o] = 0.0;
+  if (tid0 == 0 && w.n_imfs) *w.n_imfs = nimf;
+  if (tid0 == 0 && w.stats) {
     w.stats[0] = n_sifts;
     w.stats[1] = n_knots;
     w.stats[2] = n_sifts * (int64_t)L;
   }
 }
 
+// Extrema of one signal by the resident kernel's detection and ranking:
+// sorted maximum and minimum indices, and their counts.
 template <int NT, int C>
 __global__ void __launch_bounds__(NT) extrema_kernel(const double* __restrict__ hin, int L,
                                                      int32_t* __restrict__ imax,
@@ -215,23 +580,20 @@ __global__ void __launch_bounds__(NT) extrema_kernel(const double* __restrict__ 
   double h[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) h[c] = (c < nv) ? hin[base + c] : 0.0;
-  int carry, cmax, cmin;
-  unsigned maxbits, minbits;
-  detect_extrema<NT, C>(h, 0, L, L, tid, 0, 0.0, pub_first, pub_last, pub_key, carry, maxbits,
-                        minbits, cmax, cmin, nullptr, nullptr);
+  unsigned R, F, maxbits, minbits;
+  int carry;
+  rd_detect<NT, C>(h, base, nv, L, tid, pub_first, pub_last, pub_key, R, F, carry, maxbits,
+                   minbits);
   int tot;
-  const int excl = block_excl_sum<NW>((cmax << 16) | cmin, wagg, lane, wid, tot);
-  int gmax = excl >> 16, gmin = excl & 0xffff;
-  int start = carry >> 2;
+  const int excl = block_excl_sum<NW>((__popc(maxbits) << 16) | __popc(minbits), wagg, lane,
+                                      wid, tot);
+  const unsigned NE = R | F;
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    if (c < nv) {
-      const int k = base + c;
-      if (c > 0 && h[c - 1] != h[c]) start = k;
-      const int mid = (start + k) >> 1;
-      if ((maxbits >> c) & 1u) imax[gmax++] = mid;
-      if ((minbits >> c) & 1u) imin[gmin++] = mid;
-    }
+    if ((maxbits >> c) & 1u)
+      imax[(excl >> 16) + __popc(maxbits & ((1u << c) - 1u))] = run_mid(NE, carry, base, c);
+    if ((minbits >> c) & 1u)
+      imin[(excl & 0xffff) + __popc(minbits & ((1u << c) - 1u))] = run_mid(NE, carry, base, c);
   }
   if (tid == 0) {
     counts[0] = tot >> 16;
@@ -300,21 +662,43 @@ inline int grid_for(int64_t n, int threads) {
   return (int)g;
 }
 
+// Compute units of the current device (queried once).
+int device_cus() {
+  static const int cus = [] {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        v < 1)
+      v = 256;
+    return v;
+  }();
+  return cus;
+}
+
 template <int NT, int C>
 hipError_t launch_resident_cls(const WorkItem* d_items, int n, int maxL, int K, int S,
                                hipStream_t stream) {
   auto kern = resident_emd_kernel<NT, C>;
-  // LDS per workgroup is 160 KiB, shared with the kernel's static LDS
-  static const int static_lds = [&] {
+  static const hipFuncAttributes attr = [&] {
     hipFuncAttributes a{};
-    return hipFuncGetAttributes(&a, reinterpret_cast<const void*>(kern)) == hipSuccess
-               ? (int)a.sharedSizeBytes
-               : 1024;
+    if (hipFuncGetAttributes(&a, reinterpret_cast<const void*>(kern)) != hipSuccess) {
+      a.sharedSizeBytes = 1024;
+      a.numRegs = 256;
+    }
+    return a;
   }();
-  const size_t limit = 160 * 1024 - (size_t)static_lds;
+  // Workgroups a CU can hold by registers (512 VGPRs per SIMD lane, four
+  // SIMDs), and how many it will be given: the LDS is shared out among them.
+  constexpr size_t kLdsPerCU = 160 * 1024;
+  const int regs = std::max(8, (attr.numRegs + 7) / 8 * 8);
+  const int waves_simd = std::max(1, std::min(8, 512 / regs));
+  int wg_cu = std::max(1, waves_simd * 4 / (NT / kWave));
+  wg_cu = std::min(wg_cu, std::max(1, (n + device_cus() - 1) / device_cus()));
+  const size_t per_wg = (kLdsPerCU / (size_t)wg_cu) & ~size_t(511);
+  const size_t limit = std::min(per_wg, kLdsPerCU) - (size_t)attr.sharedSizeBytes;
   const size_t area = resident_area_bytes(maxL, NT, limit - kAggBytes);
   const size_t lds = kAggBytes + area;
-  if (lds > limit) return hipErrorInvalidValue;
+  if (lds > kLdsPerCU - (size_t)attr.sharedSizeBytes) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -341,18 +725,13 @@ ResidentClass resident_class(int maxL) {
 }
 
 size_t resident_area_bytes(int maxL, int nt, size_t max_area) {
-  const size_t per_knot = 2 * sizeof(double) + sizeof(int16_t);
-  const size_t stage = (size_t)maxL * sizeof(double);
   const size_t pub = (size_t)nt * (2 * sizeof(double) + sizeof(int));
-  // one envelope at a time must always fit (at most (L-1)/2 + 4 knots each)
-  const size_t single = per_knot * ((size_t)knot_cap(maxL) + 8);
-  // both envelopes together (at most L + 6 knots) when the budget allows:
-  // 2 workgroups per CU below 1024 threads, one above
-  const size_t dual = per_knot * ((size_t)maxL + 16);
-  const size_t budget = std::min(max_area, nt >= 1024 ? max_area : max_area / 2 - 512);
-  size_t area = std::min(dual, budget);
-  area = std::max(area, std::max(stage, std::max(pub, single)));
-  return align16(area) <= max_area ? align16(area) : max_area & ~size_t(15);
+  const size_t stage = (size_t)nt * sizeof(double);
+  // both envelopes of any sift (at most L + 6 knots) if the budget allows
+  const size_t dual = (size_t)kKnotBytes * ((size_t)maxL + 16);
+  size_t area = std::min(dual, max_area);
+  area = std::max(area, std::max(pub, stage));
+  return area & ~size_t(15);
 }
 
 hipError_t launch_resident(const WorkItem* d_items, int n, int maxL, int K, int S,
