@@ -42,10 +42,18 @@ struct Knots {
   double* q1;
   double* q3;
   int16_t* t;
+  double* trash_m;  // entries of m and q1 no knot uses: targets of discarded stores
+  double* trash_q;
 };
 
 constexpr int kKnotBytes = 4 * (int)sizeof(double) + (int)sizeof(int16_t);
 
+// Interior unknowns one thread solves in the resident kernel.  Odd, so that
+// the lanes of a wave, a chunk apart, spread over the LDS banks.
+constexpr int kRChunk = 7;
+
+// A store of cap knots in the region p; its last entry is reserved (the
+// discard target), so it holds systems of at most cap - 1 knots.
 __device__ __forceinline__ Knots knots_in(unsigned char* p, int cap) {
   Knots s;
   s.y = reinterpret_cast<double*>(p);
@@ -53,6 +61,8 @@ __device__ __forceinline__ Knots knots_in(unsigned char* p, int cap) {
   s.q1 = s.m + cap;
   s.q3 = s.q1 + cap;
   s.t = reinterpret_cast<int16_t*>(s.q3 + cap);
+  s.trash_m = s.m + (cap - 1);
+  s.trash_q = s.q1 + (cap - 1);
   return s;
 }
 
@@ -63,6 +73,8 @@ __device__ __forceinline__ Knots knots_from(const Knots& a, int o) {
   s.q1 = a.q1 + o;
   s.q3 = a.q3 + o;
   s.t = a.t + o;
+  s.trash_m = a.trash_m;
+  s.trash_q = a.trash_q;
   return s;
 }
 
@@ -194,57 +206,128 @@ __device__ __forceinline__ void rd_emit(const double (&h)[C], unsigned bits, uns
   }
 }
 
-// Natural-spline second derivatives (Sec. 2.1 Step 2) of one chunk of
-// interior unknowns: rows s..e with s = 1 + ch*kChunk, by the windowed
-// Thomas sweeps of the streaming solver (forward from kHalo rows before the
-// chunk, backward from kHalo rows after it, joined at row e), except that the
-// forward factors of the chunk's rows wait in the knot store (c' in m, d' in
-// q1, both unused until the derivatives exist) instead of registers.
+// Right-hand sides of the natural-spline equations (Sec. 2.1 Step 2) of up
+// to two knot systems (n1 knots at offset 0, n2 at offset o2): for every
+// interior row j,
+//   g_{j-1} m_{j-1} + 2 (g_{j-1} + g_j) m_j + g_j m_{j+1}
+//       = 6 ((y_{j+1} - y_j) / g_j - (y_j - y_{j-1}) / g_{j-1}),
+// stored in q3 (unused until the segment coefficients are formed), one row
+// per thread.
+template <int NT>
+__device__ __forceinline__ void rd_rhs(const Knots ks, int n1, int o2, int n2, int tid) {
+  const int r1 = n1 > 2 ? n1 - 2 : 0, r2 = n2 > 2 ? n2 - 2 : 0;
+  for (int i = tid; i < r1 + r2; i += NT) {
+    const int j = i < r1 ? 1 + i : o2 + 1 + (i - r1);
+    const int tm = ks.t[j - 1], t0 = ks.t[j], tp = ks.t[j + 1];
+    const double ym = ks.y[j - 1], y0 = ks.y[j], yp = ks.y[j + 1];
+    const double s0 = (y0 - ym) * recip((double)(t0 - tm));
+    const double s1 = (yp - y0) * recip((double)(tp - t0));
+    ks.q3[j] = 6.0 * (s1 - s0);
+  }
+}
+
+// One forward Thomas row j (eliminating the sub-diagonal): the row's knot
+// gaps from t_{j-1} < t_j < t_{j+1}, its right-hand side rj.
+__device__ __forceinline__ void thomas_fwd(int tm, int t0, int tp, double rj, double& cp,
+                                           double& dp) {
+  const double g0 = (double)(t0 - tm), g1 = (double)(tp - t0);
+  const double inv = recip(fma(-g0, cp, (double)(2 * (tp - tm))));
+  cp = g1 * inv;
+  dp = fma(-g0, dp, rj) * inv;
+}
+
+// One backward Thomas row j (eliminating the super-diagonal).
+__device__ __forceinline__ void thomas_bwd(int tm, int t0, int tp, double rj, double& aa,
+                                           double& dd) {
+  const double g0 = (double)(t0 - tm), g1 = (double)(tp - t0);
+  const double inv = recip(fma(-g1, aa, (double)(2 * (tp - tm))));
+  aa = g0 * inv;
+  dd = fma(-g1, dd, rj) * inv;
+}
+
+// Second derivatives of one chunk of interior unknowns, rows s..e with
+// s = 1 + ch*kRChunk: a forward Thomas sweep from kHalo rows before the chunk
+// and a backward sweep from kHalo rows after it (each started as if the row
+// beyond it did not exist), run side by side and joined at row e, then back-
+// substitution.  Windows that reach the ends of the system are exact; the
+// coupling a window drops is damped by at least (2 - sqrt 3)^kHalo, because
+// the matrix is symmetric with every diagonal twice its row's off-diagonal
+// sum, so the Jacobi-scaled matrix has condition number at most 3 and an
+// inverse whose entries decay geometrically at that rate.  The forward
+// factors of the chunk's rows wait in the knot store (c' in m, d' in q1).
 __device__ __forceinline__ void rd_solve_chunk(const Knots ks, int n, int ch) {
-  const int s = 1 + ch * kChunk;
-  const int e = min(s + kChunk - 1, n - 2);
+  const int s = 1 + ch * kRChunk;
+  const int e = min(s + kRChunk - 1, n - 2);
   const int ws = max(1, s - kHalo);
   const int we = min(n - 2, e + kHalo);
-  double ftp = (double)ks.t[ws - 1], ft = (double)ks.t[ws];
-  double fy = ks.y[ws];
-  double fsp = (fy - ks.y[ws - 1]) * recip(ft - ftp);
-  double cp = 0.0, dp = 0.0;
-  double btn = (double)ks.t[we + 1], bt = (double)ks.t[we];
-  double by = ks.y[we];
-  double bsn = (ks.y[we + 1] - by) * recip(btn - bt);
-  double aa = 0.0, dd = 0.0;
   const int nf = e + 1 - ws;                // forward rows ws .. e
   const int nb = (e < n - 2) ? we - e : 0;  // backward rows we .. e+1
-  const int steps = max(nf, nb);
+  double cp = 0.0, dp = 0.0, aa = 0.0, dd = 0.0;
+  // forward: row fj with knots ftm, ft0, ft1; backward: row bj with btm, bt0, btp
+  int fj = ws, ftm = ks.t[ws - 1], ft0 = ks.t[ws], ft1 = ks.t[ws + 1];
+  double fr = ks.q3[ws];
+  int bj = max(we, e + 1), btp = ks.t[min(bj + 1, n - 1)], bt0 = ks.t[min(bj, n - 1)];
+  int btm = ks.t[bj - 1];
+  double br = ks.q3[min(bj, n - 2)];
+  // The chunk's rows keep c' and d' (rows before it are another chunk's:
+  // their factors go to the discard slots, without a branch).
+#define SEMD_FWD_ROW()                                                  \
+  do {                                                                  \
+    const int fn = min(fj + 1, e);                                      \
+    const int ft2 = ks.t[fn + 1];                                       \
+    const double fr2 = ks.q3[fn];                                       \
+    thomas_fwd(ftm, ft0, ft1, fr, cp, dp);                              \
+    const bool keep = fj >= s;                                          \
+    *(keep ? ks.m + fj : ks.trash_m) = cp;                              \
+    *(keep ? ks.q1 + fj : ks.trash_q) = dp;                             \
+    ftm = ft0; ft0 = ft1; ft1 = ft2; fr = fr2; ++fj;                    \
+  } while (0)
+#define SEMD_BWD_ROW()                                                  \
+  do {                                                                  \
+    const int bn = max(bj - 1, e + 1);                                  \
+    const int btm2 = ks.t[bn - 1];                                      \
+    const double br2 = ks.q3[bn];                                       \
+    thomas_bwd(btm, bt0, btp, br, aa, dd);                              \
+    btp = bt0; bt0 = btm; btm = btm2; br = br2; --bj;                   \
+  } while (0)
+  // the longer sweep starts alone, then both run side by side to the join
+  int lead = nf - nb;
 #pragma unroll 1
-  for (int i = 0; i < steps; ++i) {
-    if (i < nf) {
-      const int j = ws + i;
-      const double tn = (double)ks.t[j + 1], yn = ks.y[j + 1];
-      const double g0 = ft - ftp, g1 = tn - ft;
-      const double sn = (yn - fy) * recip(g1);
-      const double rhs = 6.0 * (sn - fsp);
-      const double inv = recip(fma(-g0, cp, 2.0 * (g0 + g1)));
-      cp = g1 * inv;
-      dp = fma(-g0, dp, rhs) * inv;
-      if (j >= s) {
-        ks.m[j] = cp;
-        ks.q1[j] = dp;
-      }
-      ftp = ft; ft = tn; fy = yn; fsp = sn;
-    }
-    if (i < nb) {
-      const int j = we - i;
-      const double tp = (double)ks.t[j - 1], yp = ks.y[j - 1];
-      const double g1 = btn - bt, g0 = bt - tp;
-      const double sp = (by - yp) * recip(g0);
-      const double rhs = 6.0 * (bsn - sp);
-      const double inv = recip(fma(-g1, aa, 2.0 * (g0 + g1)));
-      aa = g0 * inv;
-      dd = fma(-g1, dd, rhs) * inv;
-      btn = bt; bt = tp; by = yp; bsn = sp;
-    }
+  for (; lead > 0; --lead) SEMD_FWD_ROW();
+#pragma unroll 1
+  for (; lead < 0; ++lead) SEMD_BWD_ROW();
+  const int both = min(nf, nb);
+#pragma unroll 1
+  for (int i = 0; i < both; ++i) {
+    // one forward and one backward row, their dependent chains interleaved
+    // operation by operation so that each hides the other's latency
+    const int fn = min(fj + 1, e), bn = max(bj - 1, e + 1);
+    const int ft2 = ks.t[fn + 1], btm2 = ks.t[bn - 1];
+    const double fr2 = ks.q3[fn], br2 = ks.q3[bn];
+    const double fg0 = (double)(ft0 - ftm), fg1 = (double)(ft1 - ft0);
+    const double bg0 = (double)(bt0 - btm), bg1 = (double)(btp - bt0);
+    const double fden = fma(-fg0, cp, (double)(2 * (ft1 - ftm)));
+    const double bden = fma(-bg1, aa, (double)(2 * (btp - btm)));
+    double fi = __builtin_amdgcn_rcp(fden), bi = __builtin_amdgcn_rcp(bden);
+    double fe = fma(-fden, fi, 1.0), be = fma(-bden, bi, 1.0);
+    fi = fma(fi, fe, fi);
+    bi = fma(bi, be, bi);
+    fe = fma(-fden, fi, 1.0);
+    be = fma(-bden, bi, 1.0);
+    fi = fma(fi, fe, fi);
+    bi = fma(bi, be, bi);
+    cp = fg1 * fi;
+    aa = bg0 * bi;
+    dp = fma(-fg0, dp, fr) * fi;
+    dd = fma(-bg1, dd, br) * bi;
+    const bool keep = fj >= s;
+    *(keep ? ks.m + fj : ks.trash_m) = cp;
+    *(keep ? ks.q1 + fj : ks.trash_q) = dp;
+    ftm = ft0; ft0 = ft1; ft1 = ft2; fr = fr2; ++fj;
+    btp = bt0; bt0 = btm; btm = btm2; br = br2; --bj;
   }
+#undef SEMD_FWD_ROW
+#undef SEMD_BWD_ROW
   // M_e = d'_e - c'_e M_{e+1} with M_{e+1} = dd - aa M_e from the right, or
   // M_e = d'_e on the last row (M_{n-1} = 0); then back-substitution
   double Mn = (e < n - 2) ? fma(-cp, dd, dp) * recip(fma(-cp, aa, 1.0)) : dp;
@@ -257,11 +340,12 @@ __device__ __forceinline__ void rd_solve_chunk(const Knots ks, int n, int ch) {
 }
 
 // Second derivatives of up to two knot systems (n1 knots at offset 0, n2 at
-// offset o2; n = 0: none), their chunks spread over the workgroup.
+// offset o2; n = 0: none), their chunks spread over the workgroup.  The
+// right-hand sides must be in q3.
 template <int NT>
 __device__ __forceinline__ void rd_solve(const Knots ks, int n1, int o2, int n2, int tid) {
-  const int c1 = n1 >= 3 ? (n1 - 2 + kChunk - 1) / kChunk : 0;
-  const int c2 = n2 >= 3 ? (n2 - 2 + kChunk - 1) / kChunk : 0;
+  const int c1 = n1 >= 3 ? (n1 - 2 + kRChunk - 1) / kRChunk : 0;
+  const int c2 = n2 >= 3 ? (n2 - 2 + kRChunk - 1) / kRChunk : 0;
   for (int ch = tid; ch < c1 + c2; ch += NT) {
     const bool second = ch >= c1;
     rd_solve_chunk(second ? knots_from(ks, o2) : ks, second ? n2 : n1, second ? ch - c1 : ch);
@@ -328,21 +412,96 @@ __device__ __forceinline__ double walk_at(Walk& w, const Knots& ks, int k) {
   return fma(fma(fma(w.q3, w.B, w.q2), w.B, w.q1), w.B, w.q0);
 }
 
-// One envelope pair (or one envelope) built and applied: knots emitted,
-// second derivatives solved, segment coefficients formed.  Barriers between
-// the phases; the caller evaluates.
-template <int NT, int C>
-__device__ __forceinline__ void build_envelopes(const double (&h)[C], unsigned bits1,
-                                                unsigned bits2, unsigned NE, int carry, int base,
-                                                int L, int first1, int n1, int first2, int n2,
-                                                const Knots ks, int nk1, int nk2, int tid) {
-  rd_emit<C>(h, bits1, NE, carry, base, L, first1, n1, ks);
-  if (n2 > 0) rd_emit<C>(h, bits2, NE, carry, base, L, first2, n2, knots_from(ks, nk1));
+// Both kinds of knots in one pass over the thread's samples: maxima go to
+// ku (first rank emax of nmax), minima to kl (first rank emin of nmin).
+template <int C>
+__device__ __forceinline__ void rd_emit_both(const double (&h)[C], unsigned maxbits,
+                                             unsigned minbits, unsigned NE, int carry, int base,
+                                             int L, int emax, int nmax, int emin, int nmin,
+                                             const Knots ku, const Knots kl) {
+  const unsigned any = maxbits | minbits;
+  // the sample slots holding a knot in any lane of the wave, one at a time
+  unsigned wave_any = any;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) wave_any |= __shfl_xor(wave_any, d, kWave);
+  wave_any = __builtin_amdgcn_readfirstlane(wave_any);
+  const int hi = 2 * (L - 1);
+  while (wave_any) {
+    const int c = __ffs(wave_any) - 1;
+    wave_any &= wave_any - 1u;
+    if ((any >> c) & 1u) {
+      const bool up = (maxbits >> c) & 1u;
+      const unsigned bits = up ? maxbits : minbits;
+      const int n = up ? nmax : nmin;
+      const Knots ks = up ? ku : kl;
+      const int Pp = n < 2 ? n : 2;
+      const int g = (up ? emax : emin) + __popc(bits & ((1u << c) - 1u));
+      const int mid = run_mid(NE, carry, base, c);
+      const double y = h[c];
+      ks.t[Pp + g] = (int16_t)mid;
+      ks.y[Pp + g] = y;
+      if (g < 2 || g >= n - 2) {
+        if (g == 0) { ks.t[Pp - 1] = (int16_t)(-mid); ks.y[Pp - 1] = y; }
+        if (g == 1 && Pp == 2) { ks.t[0] = (int16_t)(-mid); ks.y[0] = y; }
+        if (g == n - 1) { ks.t[Pp + n] = (int16_t)(hi - mid); ks.y[Pp + n] = y; }
+        if (g == n - 2 && Pp == 2) { ks.t[Pp + n + 1] = (int16_t)(hi - mid); ks.y[Pp + n + 1] = y; }
+      }
+    }
+  }
+}
+
+// Second derivatives and segment coefficients of the emitted knot systems
+// (n1 knots at offset 0, n2 at offset n1), with the barriers between the
+// phases; the knots must be complete (a barrier after emission).
+template <int NT>
+__device__ __forceinline__ void finish_envelopes(const Knots ks, int nk1, int nk2, int tid) {
+  rd_rhs<NT>(ks, nk1, nk1, nk2, tid);
   __syncthreads();
   rd_solve<NT>(ks, nk1, nk1, nk2, tid);
   __syncthreads();
   seg_coeffs<NT>(ks, nk1, nk1, nk2, tid);
   __syncthreads();
+}
+
+// One envelope (single-envelope mode): emitted, solved, coefficients formed.
+template <int NT, int C>
+__device__ __forceinline__ void build_envelope(const double (&h)[C], unsigned bits, unsigned NE,
+                                               int carry, int base, int L, int first, int n,
+                                               const Knots ks, int nk, int tid) {
+  rd_emit<C>(h, bits, NE, carry, base, L, first, n, ks);
+  __syncthreads();
+  finish_envelopes<NT>(ks, nk, 0, tid);
+}
+
+// One sift with both envelopes in one knot store: build, then evaluate both
+// walkers per sample and subtract the mean (Sec. 2.1 Steps 2-4).
+template <int NT, int C>
+__device__ __forceinline__ void sift_both(double (&h)[C], unsigned maxbits, unsigned minbits,
+                                          unsigned NE, int carry, int base, int nv, int L,
+                                          int emax, int nmax, int pmax, int emin, int nmin,
+                                          int pmin, const Knots ks, int nkmax, int nkmin,
+                                          int tid) {
+  rd_emit_both<C>(h, maxbits, minbits, NE, carry, base, L, emax, nmax, emin, nmin, ks,
+                  knots_from(ks, nkmax));
+  __syncthreads();
+  finish_envelopes<NT>(ks, nkmax, nkmin, tid);
+  if (nv > 0) {
+    const Knots kl = knots_from(ks, nkmax);
+    Walk wu, wl;
+    walk_init(wu, ks, pmax + emax - 1, base);
+    walk_init(wl, kl, pmin + emin - 1, base);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      if (c < nv) {
+        const int k = base + c;
+        const double up = walk_at(wu, ks, k);
+        const double lo = walk_at(wl, kl, k);
+        h[c] = h[c] - (up + lo);
+        wu.B += 1.0;
+        wl.B += 1.0;
+      }
+    }
+  }
 }
 
 // Hides a value's origin from the optimizer (no instruction is emitted).
@@ -388,7 +547,7 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
 
   int* wagg = reinterpret_cast<int*>(smem);
   unsigned char* area = smem + kAggBytes;
-  const int capk = area_bytes / kKnotBytes;
+  const int capk = area_bytes / kKnotBytes;  // knots the LDS store can take: capk - 1
   const int scap = (area_bytes / (int)sizeof(double)) / NT * NT;
   double* stage = reinterpret_cast<double*>(area);
   double* pub_first = reinterpret_cast<double*>(area);
@@ -458,34 +617,15 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
       const int nkmax = nmax + 2 * pmax, nkmin = nmin + 2 * pmin;
       ++n_sifts;
       n_knots += nkmax + nkmin;
-      const bool both_lds = nkmax + nkmin <= capk;
-      const bool single = !both_lds && nkmax <= capk && nkmin <= capk;
-      if (!single) {
-        // both envelopes at once, in LDS or in the global knot store
-        const Knots ks = both_lds ? lk : gk;
-        build_envelopes<NT, C>(h, maxbits, minbits, NE, carry, base, L, emax, nmax, emin, nmin,
-                               ks, nkmax, nkmin, tid);
-        if (nv > 0) {
-          const Knots kl = knots_from(ks, nkmax);
-          Walk wu, wl;
-          walk_init(wu, ks, pmax + emax - 1, base);
-          walk_init(wl, kl, pmin + emin - 1, base);
-#pragma unroll
-          for (int c = 0; c < C; ++c) {
-            if (c < nv) {
-              const int k = base + c;
-              const double up = walk_at(wu, ks, k);
-              const double lo = walk_at(wl, kl, k);
-              h[c] = h[c] - (up + lo);
-              wu.B += 1.0;
-              wl.B += 1.0;
-            }
-          }
-        }
-      } else {
-        // one envelope at a time: the upper one parked in global memory
-        build_envelopes<NT, C>(h, maxbits, 0u, NE, carry, base, L, emax, nmax, 0, 0, lk, nkmax,
-                               0, tid);
+      const bool both_lds = nkmax + nkmin <= capk - 1;
+      const bool single = !both_lds && nkmax <= capk - 1 && nkmin <= capk - 1;
+      if (both_lds) {
+        // both envelopes at once in LDS: one solve, fused evaluation and update
+        sift_both<NT, C>(h, maxbits, minbits, NE, carry, base, nv, L, emax, nmax, pmax, emin,
+                         nmin, pmin, lk, nkmax, nkmin, tid);
+      } else if (single) {
+        // one envelope at a time in LDS, the upper one parked in global memory
+        build_envelope<NT, C>(h, maxbits, NE, carry, base, L, emax, nmax, lk, nkmax, tid);
         if (nv > 0) {
           Walk wu;
           walk_init(wu, lk, pmax + emax - 1, base);
@@ -498,8 +638,7 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
           }
         }
         __syncthreads();
-        build_envelopes<NT, C>(h, minbits, 0u, NE, carry, base, L, emin, nmin, 0, 0, lk, nkmin,
-                               0, tid);
+        build_envelope<NT, C>(h, minbits, NE, carry, base, L, emin, nmin, lk, nkmin, tid);
         if (nv > 0) {
           Walk wl;
           walk_init(wl, lk, pmin + emin - 1, base);
@@ -512,6 +651,10 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
             }
           }
         }
+      } else {
+        // both envelopes in the item's global knot store
+        sift_both<NT, C>(h, maxbits, minbits, NE, carry, base, nv, L, emax, nmax, pmax, emin,
+                         nmin, pmin, gk, nkmax, nkmin, tid);
       }
     }
     if (stop) break;
@@ -528,14 +671,27 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
       for (int c = 0; c < C; ++c)
         if (c < nv && in_chunk(base + c, c0, c1)) stage[base + c - c0] = h[c];
       __syncthreads();
-      for (int k = c0 + tid; k < c1; k += NT) {
-        const double hk = stage[k - c0];
-        const double nr = w.r[k] - hk;
-        w.r[k] = nr;
-        stage[k - c0] = nr;
-        int i, m;
-        div_small(k, R, invR, i, m);
-        if (m < M) slot[i * M + m] = hk;
+      for (int k0 = c0 + tid; k0 < c1; k0 += 4 * NT) {
+        // four elements per pass, their residue loads issued together
+        double rk[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 + u * NT;
+          rk[u] = k < c1 ? w.r[k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 + u * NT;
+          if (k < c1) {
+            const double hk = stage[k - c0];
+            const double nr = rk[u] - hk;
+            w.r[k] = nr;
+            stage[k - c0] = nr;
+            int i, m;
+            div_small(k, R, invR, i, m);
+            if (m < M) slot[i * M + m] = hk;
+          }
+        }
       }
       __syncthreads();
 #pragma unroll
