@@ -174,8 +174,9 @@ size_t stream_bytes(int64_t L) {
   const size_t cap = (size_t)((L - 1) / 2 + 12);
   const size_t ntiles = (size_t)((L + semd::kTile - 1) / semd::kTile);
   return 2 * al256(sizeof(double) * (size_t)L) +
-         2 * (al256(sizeof(int32_t) * cap) + 2 * al256(sizeof(double) * cap)) +
-         al256(sizeof(semd::TileInfo) * ntiles) + al256(sizeof(semd::SigStatus));
+         2 * (al256(sizeof(int32_t) * cap) + 4 * al256(sizeof(double) * cap)) +
+         al256(sizeof(semd::TileInfo) * ntiles) + al256(sizeof(double) * 2 * ntiles) +
+         al256(sizeof(int32_t) * 2 * semd::kTileThreads * ntiles) + al256(sizeof(semd::SigStatus));
 }
 
 semd::StreamSig stream_sig(const semd::WorkItem& w, int K, int S, unsigned char* region) {
@@ -207,8 +208,13 @@ semd::StreamSig stream_sig(const semd::WorkItem& w, int K, int S, unsigned char*
     g.kt[e] = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (size_t)g.cap));
     g.ky[e] = reinterpret_cast<double*>(take(sizeof(double) * (size_t)g.cap));
     g.km[e] = reinterpret_cast<double*>(take(sizeof(double) * (size_t)g.cap));
+    g.kq1[e] = reinterpret_cast<double*>(take(sizeof(double) * (size_t)g.cap));
+    g.kq3[e] = reinterpret_cast<double*>(take(sizeof(double) * (size_t)g.cap));
   }
   g.tinfo = reinterpret_cast<semd::TileInfo*>(take(sizeof(semd::TileInfo) * (size_t)g.ntiles));
+  g.edge = reinterpret_cast<double*>(take(sizeof(double) * 2 * (size_t)g.ntiles));
+  g.trank = reinterpret_cast<int32_t*>(
+      take(sizeof(int32_t) * 2 * semd::kTileThreads * (size_t)g.ntiles));
   g.st = reinterpret_cast<semd::SigStatus*>(take(sizeof(semd::SigStatus)));
   return g;
 }

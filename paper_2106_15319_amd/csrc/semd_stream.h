@@ -7,8 +7,9 @@
 
 namespace semd {
 
-// Samples per tile (one workgroup of a tile kernel).
+// Samples per tile (one workgroup of a tile kernel) and threads per tile.
 constexpr int kTile = 2048;
+constexpr int kTileThreads = 256;
 
 // What the scan needs from, and gives back to, one tile.
 struct TileInfo {
@@ -67,9 +68,14 @@ struct StreamSig {
   int32_t* kt[2];   // knot abscissae (maxima, minima), cap each
   double* ky[2];    // knot values
   double* km[2];    // second derivatives
+  double* kq1[2];   // power-form linear coefficient of segment j (halved)
+  double* kq3[2];   // power-form cubic coefficient of segment j (halved)
   int32_t cap;      // knots per envelope
   int32_t pad;
   TileInfo* tinfo;  // ntiles
+  double* edge;     // ntiles x 2: a tile's first and last sample before the sift
+  int32_t* trank;   // ntiles x kTileThreads x 2: ranks of each tile thread's first
+                    // maximum and minimum knot (knots of earlier threads)
   SigStatus* st;
 };
 

@@ -28,10 +28,9 @@ namespace {
 
 using namespace dev;
 
-constexpr int kTT = 256;              // threads per tile workgroup
+constexpr int kTT = kTileThreads;     // threads per tile workgroup
 constexpr int kTC = kTile / kTT;      // samples per thread
 constexpr int kSB = kTT * kChunk;     // interior unknowns per solve block
-constexpr int kTKnots = kTile / 2 + 8;  // knots of one kind a tile window can hold
 constexpr int kNW = kTT / kWave;
 
 __device__ __forceinline__ bool sifting(const SigStatus& st) {
@@ -109,6 +108,146 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ h, int a, 
 }
 
 // ---------------------------------------------------------------------------
+// Extrema of a tile (Sec. 2.1 Step 1) from per-thread step masks
+// ---------------------------------------------------------------------------
+
+// What the detection of one thread's samples yields.
+struct TileDet {
+  unsigned maxbits, minbits;  // the thread's samples closing a maximum / minimum run
+  unsigned NE;                // bit b: sample b differs from sample b-1 (run starts)
+  int carry;                  // key of the run holding the thread's first sample
+  int last;                   // key of the run holding its last sample (-1: none)
+};
+
+// A tile holds samples a .. a+n-1 of a signal of length L; thread t owns the
+// C samples from a + t*C in h[].  first_key is the key (4*start + kind) of
+// the run holding sample a: 0 at the signal start (kind 0, never an
+// extremum), a*4 + kind when sample a differs from sample a-1, else the key
+// of a run that started before the tile, or kCont when that key is unknown
+// (its extremum, if any, is then left to the scan: the direction the run is
+// left in is written to *cont_exit).  next is sample a+n when a+n < L.
+// Bit b of the rise (fall) mask marks sample b above (below) sample b-1, bit
+// C the step to the next thread's first sample; a sample closes a run when
+// its next step is not flat, and the run is a maximum when entered rising
+// and left falling (minimum: the reverse).  Contains one barrier.
+template <int C>
+__device__ __forceinline__ void tile_detect(const double (&h)[C], int a, int n, int L, int tid,
+                                            int first_key, double next, double* pub_first,
+                                            double* pub_last, int* pub_key, int* cont_exit,
+                                            TileDet& d) {
+  const int lb = tid * C, base = a + lb;
+  const int nv = max(0, min(C, n - lb));
+  unsigned R = 0u, F = 0u;
+#pragma unroll
+  for (int b = 1; b < C; ++b) {
+    if (b < nv) {
+      R |= (h[b] > h[b - 1] ? 1u : 0u) << b;
+      F |= (h[b] < h[b - 1] ? 1u : 0u) << b;
+    }
+  }
+  if (nv > 0) {
+    const unsigned inner = R | F;
+    int key = -1;
+    if (inner) {
+      const int b = 31 - __clz(inner);
+      key = (base + b) * 4 + (((R >> b) & 1u) ? kRise : kFall);
+    }
+    double last = h[C - 1];
+    if (nv < C) {
+#pragma unroll
+      for (int c = 0; c < C - 1; ++c)
+        if (c == nv - 1) last = h[c];
+    }
+    pub_first[tid] = h[0];
+    pub_last[tid] = last;
+    pub_key[tid] = key;
+  }
+  __syncthreads();
+  d.maxbits = 0u;
+  d.minbits = 0u;
+  d.NE = 0u;
+  d.carry = first_key;
+  d.last = -1;
+  if (nv <= 0) return;
+  int carry = first_key;
+  if (tid > 0) {
+    const double prev = pub_last[tid - 1];
+    R |= h[0] > prev ? 1u : 0u;
+    F |= h[0] < prev ? 1u : 0u;
+    if (prev != h[0]) {
+      carry = base * 4 + step_kind(prev, h[0]);
+    } else {
+      // the run continues from an earlier thread: walk back to its start
+      int tau = tid - 1;
+      for (;;) {
+        const int kk = pub_key[tau];
+        if (kk >= 0) { carry = kk; break; }
+        if (tau == 0) { carry = first_key; break; }
+        const double pl = pub_last[tau - 1], pf = pub_first[tau];
+        if (pl != pf) { carry = (a + tau * C) * 4 + step_kind(pl, pf); break; }
+        --tau;
+      }
+    }
+  } else if (a > 0 && (first_key >> 2) == a) {
+    // sample a starts a run: the step into it
+    R |= (first_key & 3) == kRise ? 1u : 0u;
+    F |= (first_key & 3) == kFall ? 1u : 0u;
+  }
+  if (nv == C && base + C < L) {
+    const double nx = (lb + C < n) ? pub_first[tid + 1] : next;
+    R |= (nx > h[C - 1] ? 1u : 0u) << C;
+    F |= (nx < h[C - 1] ? 1u : 0u) << C;
+  }
+  const unsigned NE = R | F;
+  const unsigned valid = (1u << nv) - 1u;
+  unsigned maxbits = R & (F >> 1) & valid;
+  unsigned minbits = F & (R >> 1) & valid;
+  unsigned pe = (NE >> 1) & ~NE & valid;
+  while (pe) {
+    const int c = __ffs(pe) - 1;
+    pe &= pe - 1u;
+    const unsigned below = NE & ((1u << c) - 1u);
+    int kind;
+    if (below) {
+      const int b = 31 - __clz(below);
+      kind = ((R >> b) & 1u) ? kRise : kFall;
+    } else {
+      kind = carry & 3;
+    }
+    if (kind == kRise && ((F >> (c + 1)) & 1u)) maxbits |= 1u << c;
+    else if (kind == kFall && ((R >> (c + 1)) & 1u)) minbits |= 1u << c;
+    else if (kind == kCont && cont_exit) *cont_exit = ((F >> (c + 1)) & 1u) ? kFall : kRise;
+  }
+  const unsigned top = NE & valid;
+  if (top) {
+    const int b = 31 - __clz(top);
+    d.last = (base + b) * 4 + (((R >> b) & 1u) ? kRise : kFall);
+  } else {
+    d.last = carry;
+  }
+  d.maxbits = maxbits;
+  d.minbits = minbits;
+  d.NE = NE;
+  d.carry = carry;
+}
+
+// Counts and run keys of a detected tile into its TileInfo (thread 0).
+__device__ __forceinline__ void publish_tile(const TileDet& d, int first_key, int cont_exit,
+                                             TileInfo& t, int64_t* scratch64, int* scratch) {
+  int64_t tot;
+  block_excl_sum64(((int64_t)__popc(d.maxbits) << 32) | (uint32_t)__popc(d.minbits), scratch64,
+                   tot);
+  const int lastkey = block_max(d.last, scratch);
+  if (threadIdx.x == 0) {
+    t.cnt[0] = (int)(tot >> 32);
+    t.cnt[1] = (int)(tot & 0xffffffff);
+    t.lastkey = (lastkey & 3) == kCont ? -1 : lastkey;
+    t.cont = first_key == kCont;
+    t.cont_exit = cont_exit;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Setup, load, detect, scan, compact
 // ---------------------------------------------------------------------------
 
@@ -150,8 +289,10 @@ __global__ void __launch_bounds__(kTT) st_load_kernel(const StreamSig* __restric
   }
 }
 
-// Extremum counts of a tile whose first run may have started in an earlier
-// tile (kind kCont); that run's extremum, if any, is resolved by the scan.
+// Extremum counts of a tile whose candidate the previous step did not
+// detect (a fresh signal, or a new IMF's first candidate h = r; a sift step
+// detects its result itself).  The tile's first run may have started in an
+// earlier tile (kind kCont); its extremum, if any, is resolved by the scan.
 __global__ void __launch_bounds__(kTT) st_detect_kernel(const StreamSig* __restrict__ sigs,
                                                         const int2* __restrict__ tiles) {
   __shared__ double tbuf[kTile];
@@ -162,7 +303,7 @@ __global__ void __launch_bounds__(kTT) st_detect_kernel(const StreamSig* __restr
   __shared__ int cont_exit;
   const int2 tv = tiles[blockIdx.x];
   const StreamSig& S = sigs[tv.x];
-  if (!S.st->active) return;
+  if (!S.st->active || S.st->action == kSift) return;
   const int L = S.L;
   const int a = tv.y * kTile, n = min(kTile, L - a);
   double prev, next;
@@ -177,21 +318,11 @@ __global__ void __launch_bounds__(kTT) st_detect_kernel(const StreamSig* __restr
     const int i = threadIdx.x * kTC + c;
     h[c] = i < n ? tbuf[i] : 0.0;
   }
-  int carry, cmax, cmin, last;
-  unsigned maxbits, minbits;
-  detect_extrema<kTT, kTC>(h, a, n, L, threadIdx.x, first_key, next, pub_first, pub_last,
-                           pub_key, carry, maxbits, minbits, cmax, cmin, &cont_exit, &last);
-  int64_t tot;
-  block_excl_sum64(((int64_t)cmax << 32) | (uint32_t)cmin, scratch64, tot);
-  const int lastkey = block_max(last, scratch);
-  if (threadIdx.x == 0) {
-    TileInfo& t = S.tinfo[tv.y];
-    t.cnt[0] = (int)(tot >> 32);
-    t.cnt[1] = (int)(tot & 0xffffffff);
-    t.lastkey = (lastkey & 3) == kCont ? -1 : lastkey;
-    t.cont = first_key == kCont;
-    t.cont_exit = cont_exit;
-  }
+  TileDet d;
+  tile_detect<kTC>(h, a, n, L, threadIdx.x, first_key, next, pub_first, pub_last, pub_key,
+                   &cont_exit, d);
+  __syncthreads();
+  publish_tile(d, first_key, cont_exit, S.tinfo[tv.y], scratch64, scratch);
 }
 
 // One workgroup per signal: carries and ranks across its tiles, knot totals,
@@ -308,16 +439,27 @@ __global__ void __launch_bounds__(kTT) st_compact_kernel(const StreamSig* __rest
     const int i = threadIdx.x * kTC + c;
     h[c] = i < n ? tbuf[i] : 0.0;
   }
-  int carry, cmax, cmin, last;
-  unsigned maxbits, minbits;
-  detect_extrema<kTT, kTC>(h, a, n, L, threadIdx.x, first_key, next, pub_first, pub_last,
-                           pub_key, carry, maxbits, minbits, cmax, cmin, nullptr, &last);
+  // the tile's edge samples as they are before this sift, for the
+  // evaluation of the neighbouring tiles
+  if (threadIdx.x == 0) {
+    S.edge[2 * tv.y] = tbuf[0];
+    S.edge[2 * tv.y + 1] = tbuf[n - 1];
+  }
+  TileDet d;
+  tile_detect<kTC>(h, a, n, L, threadIdx.x, first_key, next, pub_first, pub_last, pub_key,
+                   nullptr, d);
+  const int carry = d.carry;
+  const unsigned maxbits = d.maxbits, minbits = d.minbits;
   int64_t tot;
   const int64_t ex =
-      block_excl_sum64(((int64_t)cmax << 32) | (uint32_t)cmin, scratch64, tot);
+      block_excl_sum64(((int64_t)__popc(maxbits) << 32) | (uint32_t)__popc(minbits), scratch64, tot);
   const int nmax = S.st->n[0], nmin = S.st->n[1];
   const int base = a + threadIdx.x * kTC;
   const int nv = max(0, min(kTC, n - threadIdx.x * kTC));
+  const int rmax = ti.off[0] + (int)(ex >> 32), rmin = ti.off[1] + (int)(ex & 0xffffffff);
+  int32_t* tr = S.trank + 2 * ((int64_t)tv.y * kTT + threadIdx.x);
+  tr[0] = rmax;
+  tr[1] = rmin;
   emit_knots<kTC>(h, maxbits, carry, base, nv, L, ti.off[0] + (int)(ex >> 32), nmax, S.kt[0],
                   S.ky[0], S.cap);
   emit_knots<kTC>(h, minbits, carry, base, nv, L, ti.off[1] + (int)(ex & 0xffffffff), nmin,
@@ -328,9 +470,122 @@ __global__ void __launch_bounds__(kTT) st_compact_kernel(const StreamSig* __rest
 // Solve
 // ---------------------------------------------------------------------------
 
+// Second derivatives of interior rows s..e (s = 1 + ch*kChunk) of one knot
+// system of n knots staged in LDS (element j at j - w0), by windowed Thomas
+// sweeps: forward from kHalo rows before the chunk, backward from kHalo rows
+// after it, joined at row e, then back-substitution (the damping argument is
+// the resident solver's).  The backward factors at row e+1 also give
+// m_{e+1}, so the chunk writes the power-form coefficients of its segments
+// s..e (and segment 0 when it holds row 1): on [t_j, t_{j+1}), B = k - t_j,
+// g = t_{j+1} - t_j, the spline is
+//   y_j + b_j B + (m_j / 2) B^2 + ((m_{j+1} - m_j) / (6 g)) B^3,
+//   b_j = (y_{j+1} - y_j) / g - g (2 m_j + m_{j+1}) / 6,
+// stored halved (the envelope mean is the sum of two halves): q1 = b_j / 2,
+// q3 = (m_{j+1} - m_j) / (12 g).
+__device__ __forceinline__ void st_solve_chunk(const int32_t* __restrict__ lt,
+                                               const double* __restrict__ ly, int w0, int n,
+                                               int ch, double* __restrict__ km,
+                                               double* __restrict__ kq1,
+                                               double* __restrict__ kq3) {
+  const int s = 1 + ch * kChunk;
+  const int e = min(s + kChunk - 1, n - 2);
+  const int ws = max(1, s - kHalo);
+  const int we = min(n - 2, e + kHalo);
+#define T(j) ((double)lt[(j) - w0])
+#define Y(j) (ly[(j) - w0])
+  double ftp = T(ws - 1), ft = T(ws), fy = Y(ws);
+  double fsp = (fy - Y(ws - 1)) * recip(ft - ftp);
+  double cp = 0.0, dp = 0.0;
+  double btn = T(we + 1), bt = T(we), by = Y(we);
+  double bsn = (Y(we + 1) - by) * recip(btn - bt);
+  double aa = 0.0, dd = 0.0;
+  const int nf = s - ws;                    // forward halo rows ws .. s-1
+  const int nb = (e < n - 2) ? we - e : 0;  // backward rows we .. e+1
+  const int steps = max(nf, nb);
+#pragma unroll 1
+  for (int i = 0; i < steps; ++i) {
+    if (i < nf) {
+      const double tn = T(ws + i + 1), yn = Y(ws + i + 1);
+      const double g0 = ft - ftp, g1 = tn - ft;
+      const double sn = (yn - fy) * recip(g1);
+      const double inv = recip(fma(-g0, cp, 2.0 * (g0 + g1)));
+      cp = g1 * inv;
+      dp = fma(-g0, dp, 6.0 * (sn - fsp)) * inv;
+      ftp = ft; ft = tn; fy = yn; fsp = sn;
+    }
+    if (i < nb) {
+      const int j = we - i;
+      const double tp = T(j - 1), yp = Y(j - 1);
+      const double g1 = btn - bt, g0 = bt - tp;
+      const double sp = (by - yp) * recip(g0);
+      const double inv = recip(fma(-g1, aa, 2.0 * (g0 + g1)));
+      aa = g0 * inv;
+      dd = fma(-g1, dd, 6.0 * (bsn - sp)) * inv;
+      btn = bt; bt = tp; by = yp; bsn = sp;
+    }
+  }
+  double cpa[kChunk], dpa[kChunk];
+#pragma unroll
+  for (int q = 0; q < kChunk; ++q) {
+    cpa[q] = 0.0;
+    dpa[q] = 0.0;
+    if (s + q <= e) {
+      const double tn = T(s + q + 1), yn = Y(s + q + 1);
+      const double g0 = ft - ftp, g1 = tn - ft;
+      const double sn = (yn - fy) * recip(g1);
+      const double inv = recip(fma(-g0, cp, 2.0 * (g0 + g1)));
+      cp = g1 * inv;
+      dp = fma(-g0, dp, 6.0 * (sn - fsp)) * inv;
+      cpa[q] = cp;
+      dpa[q] = dp;
+      ftp = ft; ft = tn; fy = yn; fsp = sn;
+    }
+  }
+  // M_e = d'_e - c'_e M_{e+1} with M_{e+1} = dd - aa M_e from the right, or
+  // M_e = d'_e on the last row (M_{n-1} = 0)
+  double Ms[kChunk + 1];
+  const double Me = (e < n - 2) ? fma(-cp, dd, dp) * recip(fma(-cp, aa, 1.0)) : dp;
+#pragma unroll
+  for (int q = 0; q <= kChunk; ++q) Ms[q] = 0.0;
+  double Mn = Me;
+#pragma unroll
+  for (int q = kChunk - 1; q >= 0; --q) {
+    if (s + q == e) Ms[q] = Me;
+    if (s + q < e) {
+      Mn = fma(-cpa[q], Mn, dpa[q]);
+      Ms[q] = Mn;
+    }
+  }
+  const double Mafter = (e < n - 2) ? fma(-aa, Me, dd) : 0.0;  // m_{e+1}
+#pragma unroll
+  for (int q = 0; q < kChunk; ++q) {
+    const int j = s + q;
+    if (j <= e) {
+      km[j] = Ms[q];
+      const double m0 = Ms[q], m1 = (j < e) ? Ms[q + 1] : Mafter;
+      const double g = T(j + 1) - T(j);
+      const double ig = recip(g);
+      const double b = (Y(j + 1) - Y(j)) * ig - g * fma(2.0, m0, m1) * (1.0 / 6.0);
+      kq1[j] = 0.5 * b;
+      kq3[j] = (m1 - m0) * ig * (1.0 / 12.0);
+    }
+  }
+  if (s == 1) {  // segment 0, with m_0 = 0
+    const double m1 = Ms[0];
+    const double g = T(1) - T(0);
+    const double ig = recip(g);
+    const double b = (Y(1) - Y(0)) * ig - g * m1 * (1.0 / 6.0);
+    kq1[0] = 0.5 * b;
+    kq3[0] = m1 * ig * (1.0 / 12.0);
+  }
+#undef T
+#undef Y
+}
+
 // One block per (signal, envelope, kSB interior unknowns): the knots the
 // block's chunks read (their rows plus kHalo+1 on each side) are staged in
-// LDS, each thread solves one chunk and writes its second derivatives.
+// LDS, each thread solves one chunk and writes its second derivatives and
+// segment coefficients.
 __global__ void __launch_bounds__(kTT) st_solve_kernel(const StreamSig* __restrict__ sigs,
                                                        const int4* __restrict__ blocks) {
   constexpr int kW = kSB + 2 * kHalo + 4;
@@ -355,11 +610,47 @@ __global__ void __launch_bounds__(kTT) st_solve_kernel(const StreamSig* __restri
   }
   __syncthreads();
   const int ch = (r0 - 1) / kChunk + threadIdx.x;
-  if (1 + ch * kChunk < r1) solve_chunk(lt, ly, w0, S.km[env], n2, ch);
+  if (1 + ch * kChunk < r1)
+    st_solve_chunk(lt, ly, w0, n2, ch, S.km[env], S.kq1[env], S.kq3[env]);
   if (bv.z == 0 && threadIdx.x == 0) {
     S.km[env][0] = 0.0;
     S.km[env][n2 - 1] = 0.0;
   }
+}
+
+// Walker over the segments of one envelope of a streaming signal, reading
+// the knot store in global memory: the current segment [t0, t1), its halved
+// power-form coefficients and B = k - t0.
+struct StWalk {
+  int j, t0, t1;
+  double B, q0, q1, q2, q3;
+};
+
+__device__ __forceinline__ void st_walk_load(StWalk& w, const StreamSig& S, int e, int j) {
+  w.j = j;
+  w.t0 = S.kt[e][j];
+  w.t1 = S.kt[e][j + 1];
+  w.q0 = 0.5 * S.ky[e][j];
+  w.q1 = S.kq1[e][j];
+  w.q2 = 0.25 * S.km[e][j];
+  w.q3 = S.kq3[e][j];
+}
+
+// Position at the segment holding sample k from segment j (whose left knot
+// lies at or before k; the last knot lies beyond the signal).
+__device__ __forceinline__ void st_walk_init(StWalk& w, const StreamSig& S, int e, int j, int k) {
+  st_walk_load(w, S, e, j);
+  while (w.t1 <= k) st_walk_load(w, S, e, w.j + 1);
+  w.B = (double)(k - w.t0);
+}
+
+// Half the envelope at sample k (one step from k-1 crosses at most one knot).
+__device__ __forceinline__ double st_walk_at(StWalk& w, const StreamSig& S, int e, int k) {
+  if (w.t1 <= k) {
+    st_walk_load(w, S, e, w.j + 1);
+    w.B = (double)(k - w.t0);
+  }
+  return fma(fma(fma(w.q3, w.B, w.q2), w.B, w.q1), w.B, w.q0);
 }
 
 // ---------------------------------------------------------------------------
@@ -377,8 +668,12 @@ __global__ void __launch_bounds__(kTT) st_solve_kernel(const StreamSig* __restri
 __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restrict__ sigs,
                                                       const int2* __restrict__ tiles) {
   __shared__ double tbuf[kTile];
-  __shared__ int32_t lt[2][kTKnots];
-  __shared__ double ly[2][kTKnots], lm[2][kTKnots];
+  __shared__ double pub_first[kTT], pub_last[kTT];
+  __shared__ int pub_key[kTT];
+  __shared__ int scratch[kNW];
+  __shared__ int64_t scratch64[kNW];
+  __shared__ double halo[2];  // the neighbours' edge samples after the sift
+  __shared__ int cont_exit;
   const int2 tv = tiles[blockIdx.x];
   const StreamSig& S = sigs[tv.x];
   const SigStatus* st = S.st;
@@ -388,49 +683,70 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
   const int a = tv.y * kTile, n = min(kTile, L - a);
   for (int i = threadIdx.x; i < n; i += kTT) tbuf[i] = S.h[a + i];
   if (action == kSift || action == kSiftLast) {
-    const TileInfo ti = S.tinfo[tv.y];
-    int cnt[2];
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int nk = st->n[e];
-      const int Pp = nk < 2 ? nk : 2;
-      const int n2 = nk + 2 * Pp;
-      // the last knot emitted before the tile sits before it; the one after
-      // the tile's first outside knot lies beyond the tile
-      const int j0 = Pp + ti.off[e] - 1;
-      const int j1 = min(n2 - 1, Pp + ti.off[e] + ti.tot[e] + 1);
-      cnt[e] = min(j1 - j0 + 1, kTKnots);  // j1 - j0 <= kTile / 2 + 2 by the counts
-      for (int i = threadIdx.x; i < cnt[e]; i += kTT) {
-        lt[e][i] = S.kt[e][j0 + i];
-        ly[e][i] = S.ky[e][j0 + i];
-        lm[e][i] = S.km[e][j0 + i];
-      }
-    }
-    __syncthreads();
     const int lb = threadIdx.x * kTC;
     const int nv = max(0, min(kTC, n - lb));
+    const int k0 = a + lb;
+    // thread 0 starts one sample early for the previous tile's last sample
+    const int ks = (threadIdx.x == 0 && a > 0) ? k0 - 1 : k0;
+    StWalk wk[2];
     if (nv > 0) {
-      const double k0 = (double)(a + lb);
-      Seg sg[2];
+      const int32_t* tr = S.trank + 2 * ((int64_t)tv.y * kTT + threadIdx.x);
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
-        // last window knot at or before the thread's first sample
-        int lo = 0, hi = cnt[e] - 2;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if ((double)lt[e][mid] <= k0) lo = mid;
-          else hi = mid - 1;
+        const int nk = st->n[e];
+        const int Pp = nk < 2 ? nk : 2;
+        // the last knot of earlier threads lies before the thread's first
+        // sample (and before sample a-1 for thread 0: it lies in an earlier
+        // tile or is a mirrored knot)
+        st_walk_init(wk[e], S, e, Pp + tr[e] - 1, ks);
+      }
+      if (ks < k0) {
+        const double up = st_walk_at(wk[0], S, 0, ks);
+        const double lo = st_walk_at(wk[1], S, 1, ks);
+        halo[0] = S.edge[2 * tv.y - 1] - (up + lo);
+        wk[0].B += 1.0;
+        wk[1].B += 1.0;
+      }
+    }
+    if (threadIdx.x == 0) cont_exit = 0;
+    __syncthreads();
+    if (nv > 0) {
+#pragma unroll
+      for (int c = 0; c < kTC; ++c) {
+        if (c < nv) {
+          const int k = k0 + c;
+          const double up = st_walk_at(wk[0], S, 0, k);
+          const double lo = st_walk_at(wk[1], S, 1, k);
+          tbuf[lb + c] = tbuf[lb + c] - (up + lo);
+          wk[0].B += 1.0;
+          wk[1].B += 1.0;
         }
-        seg_load(sg[e], lt[e], ly[e], lm[e], lo);
       }
-#pragma unroll 1
-      for (int c = 0; c < nv; ++c) {
-        const double kk = k0 + c;
-        const double up = seg_eval(sg[0], lt[0], ly[0], lm[0], cnt[0], kk);
-        const double lo = seg_eval(sg[1], lt[1], ly[1], lm[1], cnt[1], kk);
-        const double mean = 0.5 * (up + lo);
-        tbuf[lb + c] = tbuf[lb + c] - mean;
+      // the thread holding the tile's last sample continues to the next
+      // tile's first sample
+      if (lb + nv == n && a + n < L) {
+        const int k = a + n;
+        const double up = st_walk_at(wk[0], S, 0, k);
+        const double lo = st_walk_at(wk[1], S, 1, k);
+        halo[1] = S.edge[2 * tv.y + 2] - (up + lo);
       }
+    }
+    if (action == kSift) {
+      // the sifted candidate stays the candidate: its extrema now, while
+      // it is on chip (the next step's detection is skipped)
+      __syncthreads();
+      const double prev = a > 0 ? halo[0] : 0.0;
+      const double next = a + n < L ? halo[1] : 0.0;
+      const int first_key =
+          a == 0 ? 0 : (prev != tbuf[0] ? a * 4 + step_kind(prev, tbuf[0]) : kCont);
+      double h[kTC];
+#pragma unroll
+      for (int c = 0; c < kTC; ++c) h[c] = lb + c < n ? tbuf[lb + c] : 0.0;
+      TileDet d;
+      tile_detect<kTC>(h, a, n, L, threadIdx.x, first_key, next, pub_first, pub_last, pub_key,
+                       &cont_exit, d);
+      __syncthreads();
+      publish_tile(d, first_key, cont_exit, S.tinfo[tv.y], scratch64, scratch);
     }
   }
   __syncthreads();
