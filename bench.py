@@ -1,16 +1,24 @@
 #!/usr/bin/env python3
 """Serial-EMD throughput on one MI355X.
 
-Workload (one step): the 1,024 face-like 112 x 92 images (uint8-valued, as
-float64) serialized column by column to 10,304-sample signals (D = 0), each
-decomposed into up to 8 IMFs with 10 sifts per IMF, all in one batched
-launch.  Inputs and outputs stay resident in HBM; the timed region holds K
-such steps between two synchronizations.
+Default workload (one step): the 1,024 face-like 112 x 92 images
+(uint8-valued, as float64) serialized column by column to 10,304-sample
+signals (D = 0), each decomposed into up to 8 IMFs with 10 sifts per IMF, all
+in one batched launch.  Inputs and outputs stay resident in HBM; the timed
+region holds K such steps between two synchronizations.
 
 Reported beside the batched throughput: the plain path (one launch per
 image, same images, same parameters), per-step and per-image latency
 percentiles, the roofline position of the dominant kernel, and the CPU
 oracle timed on the host over the same images.
+
+Other workloads (--workload), each printing one line of the same shape:
+  series    one 3 x 1000 multivariate series, plain path, latency over repeats
+  textures  64 texture images 128 x 128, one launch per image (and batched)
+  eemd      a seeded subset of the uneven multivariate batch as an EEMD
+            ensemble of 64 realizations per series (streaming path)
+  serving   the serving mix with Poisson arrivals: continuous-batching
+            engine against plain per-request decompositions
 
 Prints one JSON line.
 """
@@ -35,9 +43,10 @@ FLOPS_PER_KNOT = 11
 FP64_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBPS = 8000.0
 
-# HBM traffic of the resident kernel on this workload, read from FETCH_SIZE
-# and WRITE_SIZE counter runs and scaled by the same counters on a copy of
-# known size; valid only while the kernel sources are the ones it was taken on
+# HBM traffic of the resident kernel on the face workload, read from
+# FETCH_SIZE and WRITE_SIZE counter runs and scaled by the same counters on a
+# copy of known size; valid only while the kernel sources are the ones it was
+# taken on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "resident_emd_kernel_faces_112x92x1024_traffic.txt")
 KERNEL_SOURCES = ["semd_kernels.hip", "semd_device.h", "semd_internal.h"]
 
@@ -89,8 +98,44 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a), q))
 
 
-def cpu_baseline(items, D, K, S, threads):
-    """The oracle over the same images on the host, one image per task."""
+def base_record(args, metric_value, ms_per_step, dtype="f64"):
+    return {
+        "metric": "samples decomposed/s/GPU (batched+served vs plain), p50/p99 latency, "
+                  "%HBM peak",
+        "value": metric_value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+    }
+
+
+def roofline_alu(flops, kern_ms, kernel, traffic=None):
+    achieved = flops / (kern_ms / 1e3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic, "kernel": kernel,
+            "kernel_ms": kern_ms, "flops_per_launch": flops}
+
+
+def work_stats(stats, counts):
+    st = stats.sum(0).cpu().numpy()
+    n_imfs = counts.cpu().numpy()
+    return {"sifts": int(st[0]), "knots": int(st[1]), "sample_sifts": int(st[2]),
+            "mean_imfs": float(np.maximum(n_imfs, 0).mean())}
+
+
+def cpu_threads():
+    return min(16, os.cpu_count() or 1)
+
+
+def cpu_decompose_rate(items, D, K, S, threads):
+    """The oracle over the given items on the host, one item per task."""
     import oracle
     from concurrent.futures import ThreadPoolExecutor
 
@@ -103,37 +148,12 @@ def cpu_baseline(items, D, K, S, threads):
     return samples / dt, dt, samples
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--batch", type=int, default=1024)
-    ap.add_argument("--D", type=int, default=0)
-    ap.add_argument("--plain-items", type=int, default=256)
-    ap.add_argument("--cpu-items", type=int, default=1024)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--path", choices=["auto", "onchip", "stream"], default="auto",
-                    help="execution path of the batched decomposition")
-    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
-                    help="only run a device copy of MIB MiB (counter calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the independent "
-              "signals of a batch would shard across GPUs with no exchange", file=sys.stderr)
-        return 2
+# ---------------------------------------------------------------------------
+# workloads
+# ---------------------------------------------------------------------------
 
-    if args.copy_probe:
-        return copy_probe(args.copy_probe, max(1, args.steps))
-
-    import torch
-
-    import paper_2106_15319_amd as semd
-    import workloads
-
-    assert torch.cuda.is_available(), "bench.py needs the HIP device"
+def run_faces(args, semd, torch, workloads):
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     K, S, D = 8, 10, args.D
     path = {"auto": semd.SEMD_PATH_AUTO, "onchip": semd.SEMD_PATH_ONCHIP,
             "stream": semd.SEMD_PATH_STREAM}[args.path]
@@ -150,13 +170,10 @@ def main() -> int:
     shapes = [[M, N]] * n
 
     # work statistics of one decomposition of the batch (untimed)
-    pb_stats = semd.PreparedBatch([X[i] for i in range(n)], shapes, [out[i] for i in range(n)],
-                                  counts, D, K, S, stats=stats, path=path)
-    pb_stats.run()
+    semd.PreparedBatch([X[i] for i in range(n)], shapes, [out[i] for i in range(n)], counts, D,
+                       K, S, stats=stats, path=path).run()
     torch.cuda.synchronize()
-    st = stats.sum(0).cpu().numpy()
-    n_sifts, n_knots, sample_sifts = int(st[0]), int(st[1]), int(st[2])
-    n_imfs = counts.cpu().numpy()
+    work = work_stats(stats, counts)
 
     pb = semd.PreparedBatch([X[i] for i in range(n)], shapes, [out[i] for i in range(n)],
                             counts, D, K, S, path=path)
@@ -207,52 +224,305 @@ def main() -> int:
     # and its ~100 KB descriptor upload); on the streaming path the figure
     # covers the whole step's kernel sequence
     kern_ms = float(np.mean(step_ms))
-    flops = FLOPS_PER_SAMPLE_SIFT * sample_sifts + FLOPS_PER_KNOT * n_knots
-    achieved = flops / (kern_ms / 1e3) / 1e12
-    b_io = 8 * MN * n * (K + 2)
-    b_stream = b_io + 16 * sample_sifts + 16 * L * int(n_imfs.sum())
+    flops = FLOPS_PER_SAMPLE_SIFT * work["sample_sifts"] + FLOPS_PER_KNOT * work["knots"]
     onchip = args.path == "onchip" or (args.path == "auto" and L <= semd.semd_resident_max_length())
     traffic = measured_traffic(n, D) if onchip else None
+    b_io = 8 * MN * n * (K + 2)
+    b_stream = b_io + 16 * work["sample_sifts"] + 16 * L * int(round(work["mean_imfs"] * n))
 
-    res = {
-        "metric": "samples decomposed/s/GPU (batched+served vs plain), p50/p99 latency, "
-                  "%HBM peak",
-        "value": value,
-        "unit": "samples/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"face-like images 112x92 (uint8-valued) x {n}, serialized "
-                               f"column-wise, D={D}, batched Serial-EMD",
-                   "batch": n, "M": M, "N": N, "D": D, "L": L, "max_imfs": K,
-                   "sift_iters": S, "path": args.path},
-        "latency_ms": {"step_p50": pct(step_ms, 50), "step_p99": pct(step_ms, 99)},
-        "plain": plain,
-        "work": {"sifts": n_sifts, "knots": n_knots, "sample_sifts": sample_sifts,
-                 "mean_imfs": float(n_imfs.mean())},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
-                     "kernel": "resident_emd_kernel" if onchip else "streaming step",
-                     "kernel_ms": kern_ms, "flops_per_launch": flops},
-        "hbm": {"algorithmic_io_bytes": b_io,
-                "io_GBps": b_io / (kern_ms / 1e3) / 1e9,
-                "io_frac_of_peak": b_io / (kern_ms / 1e3) / 1e9 / HBM_PEAK_GBPS,
-                "stream_equivalent_GBps": b_stream / (kern_ms / 1e3) / 1e9},
-    }
+    res = base_record(args, value, ms_per_step)
+    res["config"] = {"workload": f"face-like images 112x92 (uint8-valued) x {n}, serialized "
+                                 f"column-wise, D={D}, batched Serial-EMD",
+                     "batch": n, "M": M, "N": N, "D": D, "L": L, "max_imfs": K,
+                     "sift_iters": S, "path": args.path}
+    res["latency_ms"] = {"step_p50": pct(step_ms, 50), "step_p99": pct(step_ms, 99)}
+    res["plain"] = plain
+    res["work"] = work
+    res["roofline"] = roofline_alu(flops, kern_ms,
+                                   "resident_emd_kernel" if onchip else "streaming step", traffic)
+    res["hbm"] = {"algorithmic_io_bytes": b_io,
+                  "io_GBps": b_io / (kern_ms / 1e3) / 1e9,
+                  "io_frac_of_peak": b_io / (kern_ms / 1e3) / 1e9 / HBM_PEAK_GBPS,
+                  "stream_equivalent_GBps": b_stream / (kern_ms / 1e3) / 1e9}
     if not args.no_cpu:
-        threads = min(16, os.cpu_count() or 1)
+        threads = cpu_threads()
         ncpu = min(args.cpu_items, n)
-        rate, dt, samples = cpu_baseline(items[:ncpu], D, K, S, threads)
+        rate, dt, samples = cpu_decompose_rate(items[:ncpu], D, K, S, threads)
         res["cpu_baseline"] = {"value": rate, "unit": "samples/s", "cores": threads,
                                "kind": "oracle",
                                "sample": f"{ncpu} of the {n} images, {samples} input samples, "
                                          f"{dt:.1f} s wall on {threads} threads"}
+    return res
+
+
+def run_series(args, semd, torch, workloads):
+    """One 3 x 1000 series per launch (plain path), repeated."""
+    dev = torch.device("cuda:0")
+    K, S, D = 6, 10, args.D
+    it = workloads.config0()
+    M, N = it.M, it.N
+    X = torch.from_numpy(it.X).to(dev)
+    out = torch.empty((K + 1, M * N), dtype=torch.float64, device=dev)
+    cnt = torch.empty(1, dtype=torch.int32, device=dev)
+    st = torch.zeros((1, 3), dtype=torch.int64, device=dev)
+    semd.PreparedBatch([X], [[M, N]], [out], cnt, D, K, S, stats=st).run()
+    torch.cuda.synchronize()
+    work = work_stats(st, cnt)
+    reps = max(args.steps, 1)
+    stream = torch.cuda.current_stream()
+    for _ in range(max(args.warmup, 1)):
+        semd.semd_decompose_ex(X, [M, N], D, K, S, out, cnt)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        semd.semd_decompose_ex(X, [M, N], D, K, S, out, cnt)
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = [a.elapsed_time(b) for a, b in ev]
+    ms = wall * 1e3 / reps
+    res = base_record(args, M * N / (ms / 1e3), ms)
+    L = M * N + D * N - D
+    res["config"] = {"workload": f"3-channel series x 1000 samples, D={D}, plain path, one "
+                                 f"signal per launch", "M": M, "N": N, "D": D, "L": L,
+                     "max_imfs": K, "sift_iters": S, "repeats": reps}
+    res["latency_ms"] = {"p50": pct(lat, 50), "p99": pct(lat, 99)}
+    res["work"] = work
+    flops = FLOPS_PER_SAMPLE_SIFT * work["sample_sifts"] + FLOPS_PER_KNOT * work["knots"]
+    res["roofline"] = roofline_alu(flops, float(np.mean(lat)),
+                                   "resident_emd_kernel (1 workgroup)")
+    if not args.no_cpu:
+        import oracle
+        oracle.lib()
+        nrep = 50
+        t1 = time.perf_counter()
+        for _ in range(nrep):
+            oracle.decompose(it.X, M, N, D, K, S)
+        dt = time.perf_counter() - t1
+        res["cpu_baseline"] = {"value": nrep * M * N / dt, "unit": "samples/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"{nrep} decompositions of the series, {dt:.2f} s on "
+                                         f"one thread ({1e3 * dt / nrep:.2f} ms each)"}
+    return res
+
+
+def run_textures(args, semd, torch, workloads):
+    """64 texture images 128 x 128, one launch per image; batched alongside."""
+    dev = torch.device("cuda:0")
+    K, S, D = 8, 10, args.D
+    items = workloads.config1(64, 128)
+    n = len(items)
+    M, N = items[0].M, items[0].N
+    MN = M * N
+    X = torch.from_numpy(np.stack([i.X for i in items])).to(dev)
+    outs = [torch.empty((K + 1, MN), dtype=torch.float64, device=dev) for _ in range(n)]
+    cnt = torch.empty(n, dtype=torch.int32, device=dev)
+    st = torch.zeros((n, 3), dtype=torch.int64, device=dev)
+    semd.PreparedBatch([X[i] for i in range(n)], [[M, N]] * n, outs, cnt, D, K, S,
+                       stats=st).run()
+    torch.cuda.synchronize()
+    work = work_stats(st, cnt)
+    stream = torch.cuda.current_stream()
+    for i in range(2):
+        semd.semd_decompose_ex(X[i], [M, N], D, K, S, outs[i], cnt[i:i + 1])
+    torch.cuda.synchronize()
+    steps = max(args.steps // 10, 1)
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(n)]
+        for i, (a, b) in enumerate(ev):
+            a.record(stream)
+            semd.semd_decompose_ex(X[i], [M, N], D, K, S, outs[i], cnt[i:i + 1])
+            b.record(stream)
+        torch.cuda.synchronize()
+        lat += [a.elapsed_time(b) for a, b in ev]
+    wall = time.perf_counter() - t0
+    ms = wall * 1e3 / steps
+    res = base_record(args, n * MN / (ms / 1e3), ms)
+    res["steps"] = steps
+    L = M * N + D * N - D
+    res["config"] = {"workload": f"texture images 128x128 x {n}, D={D}, plain path (one launch "
+                                 f"per image)", "images": n, "M": M, "N": N, "D": D, "L": L,
+                     "max_imfs": K, "sift_iters": S}
+    res["latency_ms"] = {"image_p50": pct(lat, 50), "image_p99": pct(lat, 99)}
+    pb = semd.PreparedBatch([X[i] for i in range(n)], [[M, N]] * n, outs, cnt, D, K, S)
+    pb.run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        pb.run()
+    torch.cuda.synchronize()
+    bms = (time.perf_counter() - t1) * 1e3 / steps
+    res["batched"] = {"value": n * MN / (bms / 1e3), "ms_per_step": bms,
+                      "batched_over_plain": ms / bms}
+    res["work"] = work
+    flops = FLOPS_PER_SAMPLE_SIFT * work["sample_sifts"] + FLOPS_PER_KNOT * work["knots"]
+    res["roofline"] = roofline_alu(flops / n, float(np.mean(lat)),
+                                   "resident_emd_kernel (1 workgroup per launch)")
+    if not args.no_cpu:
+        threads = cpu_threads()
+        rate, dt, samples = cpu_decompose_rate(items, D, K, S, threads)
+        res["cpu_baseline"] = {"value": rate, "unit": "samples/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"all {n} images, {dt:.1f} s wall on {threads} threads"}
+    return res
+
+
+def run_eemd(args, semd, torch, workloads):
+    """A seeded subset of the uneven multivariate batch, EEMD with 64
+    realizations per series, all series in one semd_eemd_batch call."""
+    dev = torch.device("cuda:0")
+    K, S, D, NR = 6, 10, args.D, 64
+    shapes = workloads.config3_shapes(4096)
+    pick = list(range(args.series))
+    items = [workloads.config3_item(i, shapes[i]) for i in pick]
+    Xs = [torch.from_numpy(it.X).to(dev) for it in items]
+    outs = [torch.empty((K + 1, it.M * it.N), dtype=torch.float64, device=dev) for it in items]
+    cnt = torch.empty(len(items), dtype=torch.int32, device=dev)
+    # beta = 0.2 std of the serialized signal (D = 0: the samples themselves)
+    sig = []
+    for it, x in zip(items, Xs):
+        if D == 0:
+            sig.append(0.2 * float(np.std(it.X)))
+        else:
+            xs = semd.semd_serialize(x, [it.M, it.N], D)
+            sig.append(0.2 * float(xs.std(unbiased=False).item()))
+    ids = [int(i) for i in pick]
+    pb = semd.PreparedBatch(Xs, [[it.M, it.N] for it in items], outs, cnt, D, K, S,
+                            ensemble=NR, seed=2106, noise_sigmas=sig, item_ids=ids)
+    for _ in range(max(args.warmup, 1)):
+        pb.run()
+    torch.cuda.synchronize()
+    steps = max(min(args.steps, 3), 1)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pb.run()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    samples = sum(it.M * it.N for it in items)
+    res = base_record(args, samples / (ms / 1e3), ms)
+    res["steps"] = steps
+    res["config"] = {"workload": f"uneven multivariate series (2-16 channels x 1e3-6.5e4 "
+                                 f"samples), first {len(items)} of the 4,096-series batch, EEMD "
+                                 f"with {NR} realizations each, D={D}",
+                     "series": len(items), "input_samples": samples, "realizations": NR,
+                     "max_imfs": K, "sift_iters": S, "D": D}
+    res["realization_samples_per_s"] = samples * NR / (ms / 1e3)
+    res["roofline"] = None
+    if not args.no_cpu:
+        import oracle
+        from concurrent.futures import ThreadPoolExecutor
+        oracle.lib()
+        threads = cpu_threads()
+        # a bounded sample: the shortest series of the subset, all realizations
+        order = sorted(range(len(items)), key=lambda i: items[i].M * items[i].N)[:threads]
+        t1 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(lambda i: oracle.eemd(items[i].X, items[i].M, items[i].N, D, K, S, NR,
+                                              sig[i], 2106, ids[i]), order))
+        dt = time.perf_counter() - t1
+        cs = sum(items[i].M * items[i].N for i in order)
+        res["cpu_baseline"] = {"value": cs / dt, "unit": "samples/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"{len(order)} shortest series of the subset ({cs} input "
+                                         f"samples) x {NR} realizations, {dt:.1f} s wall"}
+    return res
+
+
+def run_serving(args, semd, torch, workloads):
+    """Poisson arrivals of the serving mix: engine against plain."""
+    from paper_2106_15319_amd import serving
+
+    dev = torch.device("cuda:0")
+    S, D = 10, 0
+    nreq = args.requests
+    reqs, kinds = [], []
+    for i in range(nreq):
+        kind, it = workloads.serving_request(i)
+        K = 6 if kind == "series" else 8
+        x = torch.from_numpy(it.X).to(dev)
+        out = torch.empty((K + 1, it.M * it.N), dtype=torch.float64, device=dev)
+        cnt = torch.empty(1, dtype=torch.int32, device=dev)
+        reqs.append(serving.Request(x, (it.M, it.N), out, cnt, D, K, S))
+        kinds.append(kind)
+    samples = sum(r.dims[0] * r.dims[1] for r in reqs)
+    rng = np.random.default_rng(2106_15319 + 4)
+    if args.qps > 0:
+        arrivals = np.cumsum(rng.exponential(1.0 / args.qps, size=nreq)).tolist()
+    else:  # saturation: every request queued at the start
+        arrivals = [0.0] * nreq
+    # warm both paths on the first requests
+    serving.serve_plain(reqs[:2], [0.0, 0.0], semd.SEMD_PATH_AUTO)
+    serving.serve_engine(reqs[:2], [0.0, 0.0], args.budget_gib << 30, 256)
+    eng = serving.serve_engine(reqs, arrivals, args.budget_gib << 30, 256)
+    plain = serving.serve_plain(reqs, arrivals, semd.SEMD_PATH_AUTO)
+    res = base_record(args, samples / eng["wall"], eng["wall"] * 1e3)
+    res["steps"] = eng["steps"]
+    res["warmup"] = 0
+    res["config"] = {"workload": f"serving mix (60% textures 64-512 px, 30% series 2-16 x "
+                                 f"1e3-65536, 10% 1024x1024), {nreq} requests, "
+                                 + (f"Poisson arrivals at {args.qps} req/s" if args.qps > 0
+                                    else "all queued at the start"), "requests": nreq,
+                     "qps": args.qps, "input_samples": samples,
+                     "mix": {k: kinds.count(k) for k in sorted(set(kinds))}}
+    res["latency_ms"] = {"p50": 1e3 * pct(eng["latency"], 50),
+                         "p99": 1e3 * pct(eng["latency"], 99)}
+    res["served"] = {"value": samples / eng["wall"], "wall_s": eng["wall"],
+                     "engine_steps": eng["steps"], "max_resident": eng["max_resident"]}
+    res["plain"] = {"value": samples / plain["wall"], "wall_s": plain["wall"],
+                    "p50_ms": 1e3 * pct(plain["latency"], 50),
+                    "p99_ms": 1e3 * pct(plain["latency"], 99),
+                    "served_over_plain": plain["wall"] / eng["wall"]}
+    res["roofline"] = None
+    return res
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=["faces", "series", "textures", "eemd", "serving"],
+                    default="faces")
+    ap.add_argument("--batch", type=int, default=1024, help="faces: images per step")
+    ap.add_argument("--D", type=int, default=0, help="transition length")
+    ap.add_argument("--plain-items", type=int, default=256,
+                    help="faces: images timed on the plain path")
+    ap.add_argument("--cpu-items", type=int, default=1024,
+                    help="faces: images timed with the oracle")
+    ap.add_argument("--series", type=int, default=32, help="eemd: series of the subset")
+    ap.add_argument("--requests", type=int, default=120, help="serving: requests")
+    ap.add_argument("--qps", type=float, default=40.0,
+                    help="serving: arrival rate (0: all requests queued at the start)")
+    ap.add_argument("--budget-gib", type=int, default=32, help="serving: engine HBM budget")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--path", choices=["auto", "onchip", "stream"], default="auto",
+                    help="faces: execution path of the batched decomposition")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a device copy of MIB MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the independent "
+              "signals of a batch would shard across GPUs with no exchange", file=sys.stderr)
+        return 2
+    if args.copy_probe:
+        return copy_probe(args.copy_probe, max(1, args.steps))
+
+    import torch
+
+    import paper_2106_15319_amd as semd
+    import workloads
+
+    assert torch.cuda.is_available(), "bench.py needs the HIP device"
+    torch.cuda.set_device(0)
+    run = {"faces": run_faces, "series": run_series, "textures": run_textures,
+           "eemd": run_eemd, "serving": run_serving}[args.workload]
+    res = run(args, semd, torch, workloads)
     print(json.dumps(res), flush=True)
     return 0
 
