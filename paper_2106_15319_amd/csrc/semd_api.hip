@@ -68,6 +68,127 @@ int check_params(const semd_params* p, bool ensemble) {
   return SEMD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Graph replay of the streaming step
+// ---------------------------------------------------------------------------
+
+// A stream that can be captured: the caller's, or, for the null stream, a
+// stream of this thread's own (default priority) joined to the caller's by
+// events before and after the work.
+struct CaptureStream {
+  hipStream_t caller = nullptr, s = nullptr;
+  hipEvent_t in = nullptr, out = nullptr;
+  bool side = false;
+
+  hipError_t open(hipStream_t c) {
+    caller = c;
+    if (c != nullptr) {
+      s = c;
+      return hipSuccess;
+    }
+    thread_local hipStream_t own = nullptr;
+    thread_local hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    if (!own) {
+      hipError_t e = hipStreamCreateWithFlags(&own, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_in, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_out, hipEventDisableTiming);
+      if (e != hipSuccess) return e;
+    }
+    s = own;
+    in = ev_in;
+    out = ev_out;
+    side = true;
+    hipError_t e = hipEventRecord(in, caller);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, in, 0);
+    return e;
+  }
+  // the caller's stream waits for everything enqueued on s so far
+  hipError_t join() {
+    if (!side) return hipSuccess;
+    hipError_t e = hipEventRecord(out, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(caller, out, 0);
+    return e;
+  }
+};
+
+// Executable graphs whose launches may still be in flight, each with an
+// event recorded after its last launch; destroyed once the event completes.
+struct RetiredGraph {
+  hipGraphExec_t exec;
+  hipGraph_t graph;
+  hipEvent_t ev;
+};
+std::mutex g_retire_mu;
+std::vector<RetiredGraph> g_retired;
+
+void sweep_retired_graphs() {
+  std::lock_guard<std::mutex> lock(g_retire_mu);
+  for (size_t i = 0; i < g_retired.size();) {
+    RetiredGraph& r = g_retired[i];
+    if (hipEventQuery(r.ev) == hipSuccess) {
+      (void)hipGraphExecDestroy(r.exec);
+      (void)hipGraphDestroy(r.graph);
+      (void)hipEventDestroy(r.ev);
+      g_retired[i] = g_retired.back();
+      g_retired.pop_back();
+    } else {
+      ++i;
+    }
+  }
+}
+
+// The kernels one streaming step launches, captured once as a graph and
+// replayed once per step.  retire() hands the graph over for destruction
+// after the work already enqueued on a stream.
+struct StepGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+
+  StepGraph() = default;
+  StepGraph(const StepGraph&) = delete;
+  StepGraph& operator=(const StepGraph&) = delete;
+  ~StepGraph() { retire(nullptr); }
+
+  // s: the stream its launches went to (nullptr: none are pending)
+  void retire(hipStream_t s) {
+    if (!exec && !graph) return;
+    hipEvent_t ev = nullptr;
+    if (s != nullptr || exec) {
+      if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+          hipEventRecord(ev, s) != hipSuccess) {
+        if (ev) (void)hipEventDestroy(ev);
+        ev = nullptr;
+        (void)hipDeviceSynchronize();
+      }
+    }
+    if (ev) {
+      std::lock_guard<std::mutex> lock(g_retire_mu);
+      g_retired.push_back({exec, graph, ev});
+    } else {
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (graph) (void)hipGraphDestroy(graph);
+    }
+    exec = nullptr;
+    graph = nullptr;
+  }
+  template <typename F>
+  hipError_t capture(hipStream_t s, F&& launches) {
+    retire(s);
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const hipError_t le = launches(s);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s, &g);
+    if (le != hipSuccess || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return le != hipSuccess ? le : e;
+    }
+    graph = g;
+    return hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  }
+  hipError_t launch(hipStream_t s) const { return hipGraphLaunch(exec, s); }
+};
+
 // Pinned staging blocks for host -> device descriptor uploads; a block is
 // reused once the copy recorded on it has completed.
 struct PinnedBlock {
@@ -278,10 +399,22 @@ int run_stream(const std::vector<semd::WorkItem>& work, int K, int S, hipStream_
   const auto* d_tiles = reinterpret_cast<const int2*>(dp + o_til);
   const auto* d_blocks = reinterpret_cast<const int4*>(dp + o_blk);
   const int nt = (int)tiles.size(), nb = (int)blocks.size();
-  // every signal finishes within K*S steps (each step sifts it or ends an IMF)
-  hipError_t e = semd::st_load(d_sigs, d_tiles, nt, stream);
-  for (int step = 0; step < K * S && e == hipSuccess; ++step)
-    e = semd::st_step(d_sigs, n, d_tiles, nt, d_blocks, nb, stream);
+  // every signal finishes within K*S steps (each step sifts it or ends an
+  // IMF): the step is captured once and replayed K*S times
+  sweep_retired_graphs();
+  CaptureStream cs;
+  hipError_t e = cs.open(stream);
+  if (e == hipSuccess) e = semd::st_load(d_sigs, d_tiles, nt, cs.s);
+  {
+    StepGraph g;
+    if (e == hipSuccess)
+      e = g.capture(cs.s, [&](hipStream_t s) {
+        return semd::st_step(d_sigs, n, d_tiles, nt, d_blocks, nb, s);
+      });
+    for (int step = 0; step < K * S && e == hipSuccess; ++step) e = g.launch(cs.s);
+    g.retire(cs.s);
+    if (e == hipSuccess) e = cs.join();
+  }
   if (e != hipSuccess) rc = hip_fail(e, "streaming kernel launch");
   (void)hipFreeAsync(d_pack, stream);
   (void)hipFreeAsync(arena, stream);
@@ -558,6 +691,8 @@ struct semd_engine {
   std::vector<int64_t> finished;   // tickets ready for poll
   int64_t next_ticket = 1;
   hipStream_t last_stream = nullptr;
+  StepGraph graph;                 // the step on the current tables
+  bool graph_ok = false;
 
   int alloc(size_t bytes, size_t* off) {
     for (auto it = free_.begin(); it != free_.end(); ++it) {
@@ -733,6 +868,7 @@ int semd_engine_step(semd_engine* e, hipStream_t stream) {
                          reinterpret_cast<const int2*>(dp + o_new), (int)new_tiles.size(), stream);
       for (auto& r : e->reqs) r.loaded = true;
       e->dirty = false;
+      e->graph_ok = false;
     }
     // ticket order of the table this step runs on (retirements below change
     // e->reqs, not the table)
@@ -740,15 +876,29 @@ int semd_engine_step(semd_engine* e, hipStream_t stream) {
     for (int i = 0; i < n; ++i) table_tickets[i] = e->reqs[i].ticket;
     unsigned char* dp = static_cast<unsigned char*>(e->d_tables);
     const auto* d_sigs = reinterpret_cast<const semd::StreamSig*>(dp);
-    if (he == hipSuccess)
-      he = semd::st_step(d_sigs, n, reinterpret_cast<const int2*>(dp + e->o_til), e->n_tiles,
-                         reinterpret_cast<const int4*>(dp + e->o_blk), e->n_blocks, stream);
+    // one sift of every resident request and the gather of their done
+    // flags, captured once per table version and replayed every step
+    sweep_retired_graphs();
+    CaptureStream cs;
+    if (he == hipSuccess) he = cs.open(stream);
+    if (he == hipSuccess && !e->graph_ok) {
+      const int nt = e->n_tiles, nb = e->n_blocks;
+      int32_t* d_done = e->d_done;
+      he = e->graph.capture(cs.s, [&](hipStream_t s) {
+        hipError_t le = semd::st_step(d_sigs, n, reinterpret_cast<const int2*>(dp + e->o_til),
+                                      nt, reinterpret_cast<const int4*>(dp + e->o_blk), nb, s);
+        if (le == hipSuccess) le = semd::st_gather_done(d_sigs, n, d_done, s);
+        return le;
+      });
+      e->graph_ok = he == hipSuccess;
+    }
+    if (he == hipSuccess) he = e->graph.launch(cs.s);
+    if (he == hipSuccess) he = cs.join();
     // the previous step's flags: requests that finished then leave now
     if (e->pending) {
       if (hipEventSynchronize(e->ev) != hipSuccess) return fail(SEMD_EDEVICE, "event wait");
       e->process_gather();
     }
-    if (he == hipSuccess) he = semd::st_gather_done(d_sigs, n, e->d_done, stream);
     if (he == hipSuccess)
       he = hipMemcpyAsync(e->h_done, e->d_done, sizeof(int32_t) * n, hipMemcpyDeviceToHost,
                           stream);
@@ -791,6 +941,8 @@ int semd_engine_destroy(semd_engine* e) {
     (void)hipStreamSynchronize(e->last_stream);
   }
   (void)hipDeviceSynchronize();
+  e->graph.retire(nullptr);
+  sweep_retired_graphs();
   (void)hipFree(e->arena);
   (void)hipFree(e->d_done);
   (void)hipHostFree(e->h_done);

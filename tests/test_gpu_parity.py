@@ -364,6 +364,27 @@ def test_stream_non_finite_and_monotone():
     assert int(host(n)[0]) == 0 and np.array_equal(host(out)[3], m)
 
 
+def test_stream_graph_replays_repeat():
+    # every streaming decomposition replays one captured step graph K*S
+    # times; repeated calls, with unrelated eager work and synchronizations
+    # in between, give bit-identical results that match the oracle
+    it = workloads.config3_item(5, (6000, 3))
+    x = dev(it.X)
+    runs = []
+    for r in range(3):
+        out, n = semd.semd_decompose_ex(x, [it.M, it.N], 0, 6, 10, path=STREAM)
+        junk = torch.randn(1 << 20, dtype=torch.float64, device="cuda").cumsum(0)
+        torch.cuda.synchronize()
+        runs.append((host(out), int(host(n)[0]), float(junk[-1])))
+    for o, nn, _ in runs[1:]:
+        assert nn == runs[0][1]
+        assert_same(o, runs[0][0], "graph replay")
+    ref, nr, st = oracle.decompose(it.X, it.M, it.N, 0, 6, 10, with_stats=True)
+    r = compare(runs[0][0], runs[0][1], ref.reshape(runs[0][0].shape), nr, np.abs(it.X).max(),
+                st["min_gap"])
+    assert_parity(r, "graph replay vs oracle")
+
+
 def test_stream_eemd_long_signal():
     M, N, D, K, S, NR, seed = 15000, 2, 50, 6, 10, 4, 99
     X = _series(14, 0, M, N)
