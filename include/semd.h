@@ -117,6 +117,39 @@ int64_t semd_serial_length(int64_t M, int64_t N, int64_t D);
  * serialized lengths up to 2^28; longer ones return SEMD_EUNSUPPORTED. */
 int64_t semd_resident_max_length(void);
 
+/* ---- launch-shape tuning (on-chip path) -------------------------------- */
+
+/* The on-chip kernel runs one workgroup per signal in one of several compiled
+ * launch shapes (threads per workgroup x samples per thread); the shape
+ * changes speed only, never results.  A process-wide table chooses the shape
+ * per signal-length bucket (upper bounds 1024, 2048, 3072, 4096, 6144, 8192,
+ * 12288, 16384) and per regime: "latency" for launches with fewer signals
+ * than the device has compute units, "throughput" otherwise.  Buckets absent
+ * from the table use built-in defaults.  These calls are not meant to run
+ * concurrently with decompositions on other host threads. */
+
+/* Times every eligible shape for each bucket up to max_length (in [3,
+ * 16384]) on synthetic signals -- one signal for the latency regime, `batch`
+ * (at least the compute-unit count) for the throughput regime, 6 IMFs x 10
+ * sifts -- and records the fastest in the table.  Blocks until done; uses
+ * `stream` and temporary device memory. */
+int semd_autotune(int64_t max_length, int batch, hipStream_t stream);
+
+/* The table as text ([host] buf of cap bytes, NUL-terminated; *needed [host]
+ * receives the size it needs).  First line "semd-tune <abi> <gfx arch>", then
+ * one line "latency|throughput <bucket bound> <threads> <samples>" per entry.
+ * Returns SEMD_EINVAL (with *needed set) when cap is too small. */
+int semd_tune_get(char* buf, size_t cap, size_t* needed);
+
+/* Replaces the table with one in the text form above ([host] NUL-terminated).
+ * SEMD_EINVAL if it was made for another ABI version or GPU architecture, or
+ * names a shape that is not compiled or too small for its bucket; the table
+ * is then unchanged. */
+int semd_tune_set(const char* text);
+
+/* Empties the table (built-in defaults everywhere). */
+int semd_tune_reset(void);
+
 /* ---- the method --------------------------------------------------------- */
 
 /* Serial-EMD of one signal (Sec. 3): serialize, EMD, deserialize.  D is the

@@ -60,6 +60,10 @@ _EXPORTS = {
     "semd_last_error": (C.c_char_p, []),
     "semd_serial_length": (C.c_int64, [C.c_int64, C.c_int64, C.c_int64]),
     "semd_resident_max_length": (C.c_int64, []),
+    "semd_autotune": (C.c_int, [C.c_int64, C.c_int, C.c_void_p]),
+    "semd_tune_get": (C.c_int, [C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
+    "semd_tune_set": (C.c_int, [C.c_char_p]),
+    "semd_tune_reset": (C.c_int, []),
     "semd_decompose": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_int, C.c_int, C.c_int,
                                  C.c_int, C.c_void_p, C.c_void_p]),
     "semd_decompose_ex": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_int,
@@ -158,6 +162,46 @@ def semd_serial_length(M: int, N: int, D: int) -> int:
 
 def semd_resident_max_length() -> int:
     return int(lib().semd_resident_max_length())
+
+
+def semd_autotune(max_length: int = 16384, batch: int = 512, stream=None) -> None:
+    """Time the on-chip launch shapes per length bucket and keep the fastest."""
+    _check(lib().semd_autotune(int(max_length), int(batch), _stream(stream)), "semd_autotune")
+
+
+def semd_tune_get() -> str:
+    """The launch-shape table in its text form."""
+    need = C.c_size_t()
+    lib().semd_tune_get(None, 0, C.byref(need))
+    buf = C.create_string_buffer(int(need.value))
+    _check(lib().semd_tune_get(buf, need.value, C.byref(need)), "semd_tune_get")
+    return buf.value.decode()
+
+
+def semd_tune_set(text: str) -> None:
+    _check(lib().semd_tune_set(text.encode()), "semd_tune_set")
+
+
+def semd_tune_reset() -> None:
+    _check(lib().semd_tune_reset(), "semd_tune_reset")
+
+
+def autotune(max_length: int = 16384, batch: int = 512, cache: str | None = None,
+             stream=None) -> str:
+    """Load the launch-shape table from `cache` when it was made for this
+    library and GPU; otherwise tune now (about a second) and write it there.
+    Returns the table's text."""
+    if cache and os.path.exists(cache):
+        text = open(cache).read()
+        if lib().semd_tune_set(text.encode()) == SEMD_OK:
+            return text
+    semd_autotune(max_length, batch, stream)
+    text = semd_tune_get()
+    if cache:
+        os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+        with open(cache, "w") as fh:
+            fh.write(text)
+    return text
 
 
 def semd_decompose(signal: torch.Tensor, dims: Sequence[int], max_imfs: int, sift_iters: int,

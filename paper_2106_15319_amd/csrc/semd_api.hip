@@ -9,6 +9,7 @@
 #include <cstring>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "semd.h"
@@ -245,9 +246,60 @@ int shape_of(const int64_t* dims, int ndim, int D, Shape* sh) {
 // Longest serialized signal: sample keys (4 * index + kind) are int32.
 constexpr int64_t kMaxL = int64_t(1) << 28;
 
+// ---------------------------------------------------------------------------
+// Launch shapes of the resident kernel: defaults and the tuned table
+// ---------------------------------------------------------------------------
+
+// Length buckets (upper bounds) of the table, and its two regimes: launches
+// with fewer items than the device has compute units (latency: a workgroup
+// has a CU to itself) and launches with at least as many (throughput).
+constexpr int kBuckets[] = {1024, 2048, 3072, 4096, 6144, 8192, 12288, 16384};
+constexpr int kNBuckets = (int)(sizeof(kBuckets) / sizeof(kBuckets[0]));
+static_assert(kBuckets[kNBuckets - 1] == semd::kResidentMaxL, "buckets cover the resident path");
+
+struct TuneTable {
+  semd::ResidentClass cls[2][kNBuckets];
+  bool set[2][kNBuckets];
+};
+std::mutex g_tune_mu;
+TuneTable g_tune{};
+
+int device_compute_units() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v < 1)
+    return 256;
+  return v;
+}
+
+int bucket_of(int L) {
+  for (int b = 0; b < kNBuckets; ++b)
+    if (L <= kBuckets[b]) return b;
+  return kNBuckets - 1;
+}
+
+semd::ResidentClass class_for(int L, int regime) {
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const int b = bucket_of(L);
+    if (g_tune.set[regime][b]) return g_tune.cls[regime][b];
+  }
+  return semd::resident_class(L);
+}
+
+bool class_compiled(semd::ResidentClass c) {
+  semd::ResidentClass all[32];
+  const int n = semd::resident_classes(all, 32);
+  for (int i = 0; i < n; ++i)
+    if (all[i].nt == c.nt && all[i].c == c.c) return true;
+  return false;
+}
+
 // Decompose `work` on the resident path: one workgroup per item, a workspace
-// of 2 L doubles per item (residue, parked envelope).
-int run_resident(std::vector<semd::WorkItem>& work, int K, int S, hipStream_t stream) {
+// of resident_ws_doubles(L) per item (residue, parked envelope or knot
+// store).  force: a launch shape for every item (else the table's choice).
+int run_resident(std::vector<semd::WorkItem>& work, int K, int S, hipStream_t stream,
+                 const semd::ResidentClass* force = nullptr) {
   if (work.empty()) return SEMD_OK;
   // longest first, so the tail of each launch holds the short items
   std::stable_sort(work.begin(), work.end(),
@@ -272,13 +324,15 @@ int run_resident(std::vector<semd::WorkItem>& work, int K, int S, hipStream_t st
   auto same = [](const semd::ResidentClass& a, const semd::ResidentClass& b) {
     return a.nt == b.nt && a.c == b.c;
   };
+  const int regime = (int)work.size() >= device_compute_units() ? 1 : 0;
+  auto shape = [&](int L) { return force ? *force : class_for(L, regime); };
   size_t i0 = 0;
   while (i0 < work.size() && rc == SEMD_OK) {
-    const semd::ResidentClass cls = semd::resident_class(work[i0].L);
+    const semd::ResidentClass cls = shape(work[i0].L);
     size_t i1 = i0;
-    while (i1 < work.size() && same(semd::resident_class(work[i1].L), cls)) ++i1;
+    while (i1 < work.size() && same(shape(work[i1].L), cls)) ++i1;
     const auto* d = static_cast<const semd::WorkItem*>(d_items) + i0;
-    e = semd::launch_resident(d, (int)(i1 - i0), work[i0].L, K, S, stream);
+    e = semd::launch_resident(d, (int)(i1 - i0), work[i0].L, cls, K, S, stream);
     if (e != hipSuccess) rc = hip_fail(e, "resident kernel launch");
     i0 = i1;
   }
@@ -494,6 +548,165 @@ int64_t semd_serial_length(int64_t M, int64_t N, int64_t D) {
 }
 
 int64_t semd_resident_max_length(void) { return semd::kResidentMaxL; }
+
+int semd_autotune(int64_t max_length, int batch, hipStream_t stream) {
+  g_err[0] = 0;
+  if (max_length < 3 || max_length > semd::kResidentMaxL)
+    return fail(SEMD_EINVAL, "max_length must be in [3, %d]", semd::kResidentMaxL);
+  if (batch < 1 || batch > 65536) return fail(SEMD_EINVAL, "batch must be in [1, 65536]");
+  const int K = 6, S = 10;
+  const int cus = device_compute_units();
+  semd::ResidentClass all[32];
+  const int nall = semd::resident_classes(all, 32);
+  TuneTable t;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    t = g_tune;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(SEMD_EDEVICE, "event creation failed");
+  }
+  int rc = SEMD_OK;
+  for (int regime = 0; regime < 2 && rc == SEMD_OK; ++regime) {
+    const int n = regime == 0 ? 1 : std::max(batch, cus);
+    for (int b = 0; b < kNBuckets && rc == SEMD_OK; ++b) {
+      const int lo = b == 0 ? 3 : kBuckets[b - 1] + 1;
+      if (lo > max_length) break;
+      const int64_t L = kBuckets[b];  // the bucket's longest signal
+      double *X = nullptr, *out = nullptr;
+      if (hipMalloc(reinterpret_cast<void**>(&X), sizeof(double) * L * n) != hipSuccess ||
+          hipMalloc(reinterpret_cast<void**>(&out), sizeof(double) * L * (K + 1) * n) !=
+              hipSuccess) {
+        if (X) (void)hipFree(X);
+        rc = fail(SEMD_ENOMEM, "tuning buffers for %d signals of %lld samples", n, (long long)L);
+        break;
+      }
+      std::vector<semd::WorkItem> work;
+      Shape sh{L, 1, L};
+      for (int i = 0; i < n; ++i)
+        work.push_back(make_work(X + i * L, out + i * L * (K + 1), nullptr, sh, 0));
+      hipError_t he = semd::launch_synth(X, L, n, 2106, stream);
+      float best_ms = 0.0f;
+      semd::ResidentClass best{0, 0};
+      for (int ci = 0; ci < nall && he == hipSuccess && rc == SEMD_OK; ++ci) {
+        const semd::ResidentClass c = all[ci];
+        if (c.nt * c.c < L || c.nt * c.c > 4 * L) continue;
+        std::vector<semd::WorkItem> w = work;
+        rc = run_resident(w, K, S, stream, &c);  // warm-up
+        if (rc == SEMD_OK) he = hipEventRecord(e0, stream);
+        for (int r = 0; r < 2 && rc == SEMD_OK && he == hipSuccess; ++r) {
+          w = work;
+          rc = run_resident(w, K, S, stream, &c);
+        }
+        if (rc == SEMD_OK && he == hipSuccess) he = hipEventRecord(e1, stream);
+        if (rc == SEMD_OK && he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (rc == SEMD_OK && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (rc == SEMD_OK && he == hipSuccess && (best.nt == 0 || ms < best_ms)) {
+          best = c;
+          best_ms = ms;
+        }
+      }
+      if (he != hipSuccess && rc == SEMD_OK) rc = hip_fail(he, "tuning run");
+      (void)hipStreamSynchronize(stream);
+      (void)hipFree(X);
+      (void)hipFree(out);
+      if (rc == SEMD_OK && best.nt > 0) {
+        t.cls[regime][b] = best;
+        t.set[regime][b] = true;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc == SEMD_OK) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune = t;
+  }
+  return rc;
+}
+
+// Text form of the table:
+//   semd-tune <abi> <gfx arch>
+//   latency|throughput <bucket bound> <threads> <samples per thread>
+int semd_tune_get(char* buf, size_t cap, size_t* needed) {
+  g_err[0] = 0;
+  if (!needed) return fail(SEMD_EINVAL, "needed is NULL");
+  hipDeviceProp_t prop{};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return fail(SEMD_EDEVICE, "no device");
+  std::string text = "semd-tune " + std::to_string(SEMD_ABI_VERSION) + " " + prop.gcnArchName +
+                     "\n";
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    for (int r = 0; r < 2; ++r)
+      for (int b = 0; b < kNBuckets; ++b)
+        if (g_tune.set[r][b])
+          text += std::string(r == 0 ? "latency " : "throughput ") +
+                  std::to_string(kBuckets[b]) + " " + std::to_string(g_tune.cls[r][b].nt) + " " +
+                  std::to_string(g_tune.cls[r][b].c) + "\n";
+  }
+  *needed = text.size() + 1;
+  if (buf && cap > 0) {
+    const size_t k = std::min(cap - 1, text.size());
+    std::memcpy(buf, text.data(), k);
+    buf[k] = 0;
+    if (cap < text.size() + 1) return fail(SEMD_EINVAL, "buffer of %zu bytes is short", cap);
+  }
+  return SEMD_OK;
+}
+
+int semd_tune_set(const char* text) {
+  g_err[0] = 0;
+  if (!text) return fail(SEMD_EINVAL, "text is NULL");
+  hipDeviceProp_t prop{};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return fail(SEMD_EDEVICE, "no device");
+  TuneTable t{};
+  const char* p = text;
+  int abi = 0;
+  char arch[96] = "";
+  int used = 0;
+  if (std::sscanf(p, "semd-tune %d %95s%n", &abi, arch, &used) != 2)
+    return fail(SEMD_EINVAL, "not a tuning table");
+  if (abi != SEMD_ABI_VERSION || std::strcmp(arch, prop.gcnArchName) != 0)
+    return fail(SEMD_EINVAL, "tuning table is for abi %d on %s, not abi %d on %s", abi, arch,
+                SEMD_ABI_VERSION, prop.gcnArchName);
+  p += used;
+  for (;;) {
+    char word[16] = "";
+    int bound = 0, nt = 0, c = 0;
+    const int got = std::sscanf(p, "%15s %d %d %d%n", word, &bound, &nt, &c, &used);
+    if (got == EOF || got <= 0) break;
+    if (got != 4) return fail(SEMD_EINVAL, "malformed tuning entry");
+    p += used;
+    const int r = std::strcmp(word, "latency") == 0 ? 0
+                  : std::strcmp(word, "throughput") == 0 ? 1
+                                                          : -1;
+    int b = -1;
+    for (int i = 0; i < kNBuckets; ++i)
+      if (kBuckets[i] == bound) b = i;
+    const semd::ResidentClass cls{nt, c};
+    if (r < 0 || b < 0 || !class_compiled(cls) || nt * c < bound)
+      return fail(SEMD_EINVAL, "invalid tuning entry %s %d %d %d", word, bound, nt, c);
+    t.cls[r][b] = cls;
+    t.set[r][b] = true;
+  }
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune = t;
+  return SEMD_OK;
+}
+
+int semd_tune_reset(void) {
+  g_err[0] = 0;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune = TuneTable{};
+  return SEMD_OK;
+}
 
 int semd_decompose_ex(const double* signal, const int64_t* dims, int ndim, const semd_params* p,
                       double* imfs_out, int32_t* n_imfs_out, hipStream_t stream) {

@@ -43,7 +43,8 @@ __host__ __device__ constexpr int64_t resident_ws_doubles(int64_t L) {
 }
 
 // Launch shape of the resident kernel: threads per workgroup and samples per
-// thread, chosen from the longest signal of a launch.
+// thread.  resident_class() is the default choice for the longest signal of a
+// launch (a tuned table may choose another).
 struct ResidentClass {
   int nt;
   int c;
@@ -55,10 +56,15 @@ ResidentClass resident_class(int maxL);
 // staging window need).
 size_t resident_area_bytes(int maxL, int nt, size_t max_area);
 
-// Launch the resident kernel over `n` work items (device array), all with
-// L <= maxL.  Returns hipSuccess or the launch error.
-hipError_t launch_resident(const WorkItem* d_items, int n, int maxL, int K, int S,
-                           hipStream_t stream);
+// The compiled launch shapes: up to cap of them into out; returns how many
+// exist.
+int resident_classes(ResidentClass* out, int cap);
+
+// Launch the resident kernel with shape c (c.nt * c.c >= maxL) over `n` work
+// items (device array), all with L <= maxL.  Returns hipSuccess or the
+// launch error (hipErrorInvalidValue for a shape that is not compiled).
+hipError_t launch_resident(const WorkItem* d_items, int n, int maxL, ResidentClass c, int K,
+                           int S, hipStream_t stream);
 
 // Extrema of one 1D signal (3 <= L <= kResidentMaxL) through the resident
 // detection/compaction code: indices to imax/imin, counts[0..1].
@@ -70,6 +76,8 @@ hipError_t launch_serialize(const double* X, int64_t M, int64_t N, int D, double
 hipError_t launch_deserialize(const double* y, int64_t M, int64_t N, int D, double* out,
                               hipStream_t stream);
 hipError_t launch_noise(uint64_t key, int64_t L, double* w, hipStream_t stream);
+// Synthetic tuning signals: n x L doubles at x (two sinusoids and noise).
+hipError_t launch_synth(double* x, int64_t L, int n, uint64_t seed, hipStream_t stream);
 
 // Slot-wise mean over NR realization buffers: src holds NR consecutive blocks
 // of `count` doubles; dst[i] = (sum_m src[m*count + i]) / NR, summed in m order.

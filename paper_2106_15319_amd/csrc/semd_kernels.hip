@@ -787,6 +787,20 @@ __global__ void noise_kernel(uint64_t key, int64_t L, double* __restrict__ w) {
     w[k] = noise_at(key, k);
 }
 
+// Tuning input: n signals of L samples, signal i at x + i*L: two sinusoids
+// and white noise, x[k] = sin(2 pi k / 37.3) + 0.6 sin(2 pi k / 9.7 + i)
+// + 0.25 w_i[k].
+__global__ void synth_kernel(double* __restrict__ x, int64_t L, int n, uint64_t seed) {
+  const int64_t total = L * n;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = q / L, k = q - i * L;
+    const double t = (double)k;
+    x[q] = sin(2.0 * M_PI * t / 37.3) + 0.6 * sin(2.0 * M_PI * t / 9.7 + (double)i) +
+           0.25 * noise_at(noise_key(seed, (uint64_t)i, 0), k);
+  }
+}
+
 __global__ void ensemble_mean_kernel(const double* __restrict__ src, int NR, int64_t count,
                                      double* __restrict__ dst) {
   const double den = (double)NR;
@@ -869,13 +883,13 @@ hipError_t launch_resident_cls(const WorkItem* d_items, int n, int maxL, int K, 
 // ---------------------------------------------------------------------------
 
 // Threads and samples per thread for signals up to maxL samples.
+// Defaults: the shapes the tuner picks on MI355X (more threads per signal
+// beat more signals per CU: the sift phases are bound by latency).
 ResidentClass resident_class(int maxL) {
   if (maxL <= 256 * 4) return {256, 4};
-  if (maxL <= 256 * 8) return {256, 8};
-  if (maxL <= 256 * 12) return {256, 12};
-  if (maxL <= 256 * 16) return {256, 16};
-  if (maxL <= 512 * 12) return {512, 12};
-  if (maxL <= 512 * 16) return {512, 16};
+  if (maxL <= 1024 * 4 && maxL <= 2048) return {1024, 4};
+  if (maxL <= 512 * 8) return {512, 8};
+  if (maxL <= 1024 * 8) return {1024, 8};
   if (maxL <= 1024 * 12) return {1024, 12};
   return {1024, 16};
 }
@@ -890,19 +904,34 @@ size_t resident_area_bytes(int maxL, int nt, size_t max_area) {
   return area & ~size_t(15);
 }
 
-hipError_t launch_resident(const WorkItem* d_items, int n, int maxL, int K, int S,
-                           hipStream_t stream) {
+// The compiled launch shapes (threads, samples per thread).
+static const ResidentClass kClasses[] = {{256, 4},   {256, 8},   {256, 12},  {256, 16},
+                                         {512, 8},   {512, 12},  {512, 16},  {1024, 4},
+                                         {1024, 8},  {1024, 12}, {1024, 16}};
+
+int resident_classes(ResidentClass* out, int cap) {
+  const int n = (int)(sizeof(kClasses) / sizeof(kClasses[0]));
+  for (int i = 0; i < n && i < cap; ++i) out[i] = kClasses[i];
+  return n;
+}
+
+hipError_t launch_resident(const WorkItem* d_items, int n, int maxL, ResidentClass c, int K,
+                           int S, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
-  const ResidentClass c = resident_class(maxL);
+  if (c.nt * c.c < maxL) return hipErrorInvalidValue;
   switch (c.nt * 100 + c.c) {
     case 25604: return launch_resident_cls<256, 4>(d_items, n, maxL, K, S, stream);
     case 25608: return launch_resident_cls<256, 8>(d_items, n, maxL, K, S, stream);
     case 25612: return launch_resident_cls<256, 12>(d_items, n, maxL, K, S, stream);
     case 25616: return launch_resident_cls<256, 16>(d_items, n, maxL, K, S, stream);
+    case 51208: return launch_resident_cls<512, 8>(d_items, n, maxL, K, S, stream);
     case 51212: return launch_resident_cls<512, 12>(d_items, n, maxL, K, S, stream);
     case 51216: return launch_resident_cls<512, 16>(d_items, n, maxL, K, S, stream);
+    case 102404: return launch_resident_cls<1024, 4>(d_items, n, maxL, K, S, stream);
+    case 102408: return launch_resident_cls<1024, 8>(d_items, n, maxL, K, S, stream);
     case 102412: return launch_resident_cls<1024, 12>(d_items, n, maxL, K, S, stream);
-    default: return launch_resident_cls<1024, 16>(d_items, n, maxL, K, S, stream);
+    case 102416: return launch_resident_cls<1024, 16>(d_items, n, maxL, K, S, stream);
+    default: return hipErrorInvalidValue;
   }
 }
 
@@ -927,6 +956,12 @@ hipError_t launch_deserialize(const double* y, int64_t M, int64_t N, int D, doub
                               hipStream_t stream) {
   hipLaunchKernelGGL(deserialize_kernel, dim3(grid_for(M * N, 256)), dim3(256), 0, stream, y,
                      M, N, D, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_synth(double* x, int64_t L, int n, uint64_t seed, hipStream_t stream) {
+  hipLaunchKernelGGL(synth_kernel, dim3(grid_for(L * n, 256)), dim3(256), 0, stream, x, L, n,
+                     seed);
   return hipGetLastError();
 }
 

@@ -137,3 +137,13 @@ def test_engine_validation_without_device():
     h = C.c_void_p()
     assert L.semd_engine_create(1 << 30, 0, C.byref(h)) == semd.SEMD_EINVAL
     assert L.semd_engine_create(10, 4, C.byref(h)) == semd.SEMD_EINVAL
+
+
+def test_tuning_validation_without_device():
+    L = semd.lib()
+    assert L.semd_autotune(2, 64, None) == semd.SEMD_EINVAL
+    assert L.semd_autotune(1 << 20, 64, None) == semd.SEMD_EINVAL
+    assert L.semd_autotune(4096, 0, None) == semd.SEMD_EINVAL
+    assert L.semd_tune_get(None, 0, None) == semd.SEMD_EINVAL
+    assert L.semd_tune_set(None) == semd.SEMD_EINVAL
+    assert L.semd_tune_reset() == semd.SEMD_OK

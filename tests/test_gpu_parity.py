@@ -472,3 +472,61 @@ def test_engine_admission_budget_and_staggered_arrivals():
         ties = []
         _check_item(Xs[k], M, N, D, K, S, host(outs[k]), int(host(cnts[k])[0]), ties)
     eng.close()
+
+
+# --------------------------------------------------------------------------
+# launch-shape tuning
+# --------------------------------------------------------------------------
+
+def test_every_launch_shape_gives_identical_results():
+    # the shape table changes speed only: a face image (bucket 12288) and a
+    # 3000-sample series (bucket 3072) under every compiled shape that fits
+    arch = semd.semd_tune_get().splitlines()[0]
+    cases = [(workloads.config2(1)[0], 12288, 8), (workloads.config0(), 3072, 6)]
+    shapes = [(256, 4), (256, 8), (256, 12), (256, 16), (512, 8), (512, 12), (512, 16),
+              (1024, 4), (1024, 8), (1024, 12), (1024, 16)]
+    try:
+        for it, bound, K in cases:
+            x = dev(it.X)
+            ref = None
+            for nt, c in shapes:
+                if nt * c < bound:
+                    continue
+                semd.semd_tune_set(f"{arch}\nlatency {bound} {nt} {c}\n")
+                out, n = semd.semd_decompose_ex(x, [it.M, it.N], 0, K, 10, path=ONCHIP)
+                got = (host(out), int(host(n)[0]))
+                if ref is None:
+                    ref = got
+                else:
+                    assert got[1] == ref[1]
+                    assert_same(got[0], ref[0], f"shape {nt}x{c}")
+    finally:
+        semd.semd_tune_reset()
+
+
+def test_autotune_round_trip():
+    try:
+        semd.semd_autotune(4096, 256)
+        text = semd.semd_tune_get()
+        lines = text.splitlines()
+        assert lines[0].startswith("semd-tune 1 gfx")
+        entries = [l.split() for l in lines[1:]]
+        assert {e[0] for e in entries} == {"latency", "throughput"}
+        assert {int(e[1]) for e in entries} == {1024, 2048, 3072, 4096}
+        for e in entries:
+            assert int(e[2]) * int(e[3]) >= int(e[1])
+        semd.semd_tune_reset()
+        assert semd.semd_tune_get().splitlines()[1:] == []
+        semd.semd_tune_set(text)
+        assert semd.semd_tune_get() == text
+        with pytest.raises(semd.SemdError):
+            semd.semd_tune_set(text.replace("gfx", "gfy", 1))
+        with pytest.raises(semd.SemdError):
+            semd.semd_tune_set(lines[0] + "\nlatency 4096 256 4\n")  # too small a shape
+        assert semd.semd_tune_get() == text  # unchanged by the rejected tables
+        # decompositions under the tuned table still match the oracle
+        it = workloads.config0()
+        out, n = semd.semd_decompose_ex(dev(it.X), [it.M, it.N], 0, 6, 10)
+        _check_item(it.X, it.M, it.N, 0, 6, 10, host(out), int(host(n)[0]), [])
+    finally:
+        semd.semd_tune_reset()
