@@ -10,18 +10,30 @@ namespace semd {
 // Samples per tile (one workgroup of a tile kernel) and threads per tile.
 constexpr int kTile = 2048;
 constexpr int kTileThreads = 256;
+// Knots of one kind a tile can hold (a strict extremum needs two steps).
+constexpr int kTileKnots = kTile / 2 + 8;
+
+// One spline segment as the evaluation reads it: its knots and the halved
+// power-form coefficients, S(k)/2 = ((q3 B + q2) B + q1) B + q0, B = k - t0.
+struct alignas(16) SegRec {
+  double t0, t1;
+  double q0, q1, q2, q3;
+};
 
 // What the scan needs from, and gives back to, one tile.
 struct TileInfo {
-  int32_t cnt[2];     // extrema found by detect, continuation run excluded
-  int32_t tot[2];     // extrema of the tile, continuation run resolved
+  int32_t cnt[2];     // extrema found by detection, the continued run excluded
+  int32_t tot[2];     // extrema of the tile, the continued run resolved
   int32_t off[2];     // rank of the tile's first knot of each kind
   int32_t lastkey;    // 4*index + step kind of the tile's last run start, -1 if none
   int32_t carry;      // key of the run holding the tile's first sample
   int32_t cont;       // that run started before the tile
   int32_t cont_exit;  // direction the run is left in inside the tile, 0 if not
   int32_t bad;        // the tile holds NaN/Inf input
+  int32_t cont_pos;   // sample where that run ends (its extremum's sample), -1 if none
+  int32_t cont_knot;  // bit e: the continued run is an extremum of kind e (scan)
   int32_t pad;
+  double cont_y;      // the continued run's value
 };
 
 // What a step does to a signal (decided by the scan from the current
@@ -67,15 +79,15 @@ struct StreamSig {
   double* r;        // residue, L doubles
   int32_t* kt[2];   // knot abscissae (maxima, minima), cap each
   double* ky[2];    // knot values
-  double* km[2];    // second derivatives
-  double* kq1[2];   // power-form linear coefficient of segment j (halved)
-  double* kq3[2];   // power-form cubic coefficient of segment j (halved)
+  SegRec* seg[2];   // segment j = [t_j, t_{j+1}) of each envelope, for evaluation
   int32_t cap;      // knots per envelope
   int32_t pad;
   TileInfo* tinfo;  // ntiles
   double* edge;     // ntiles x 2: a tile's first and last sample before the sift
-  int32_t* trank;   // ntiles x kTileThreads x 2: ranks of each tile thread's first
-                    // maximum and minimum knot (knots of earlier threads)
+  int32_t* trank;   // ntiles x kTileThreads x 2: knots of each kind the tile's
+                    // earlier threads hold (ranks within the tile)
+  int32_t* lpos[2]; // ntiles x kTileKnots: the tile's knots at tile-local ranks
+  double* lval[2];  //   (positions and values), written by detection
   SigStatus* st;
 };
 

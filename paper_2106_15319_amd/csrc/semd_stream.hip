@@ -125,7 +125,8 @@ struct TileDet {
 // extremum), a*4 + kind when sample a differs from sample a-1, else the key
 // of a run that started before the tile, or kCont when that key is unknown
 // (its extremum, if any, is then left to the scan: the direction the run is
-// left in is written to *cont_exit).  next is sample a+n when a+n < L.
+// left in is written to *cont_exit, the sample it ends at to *cont_pos and
+// its value to *cont_y).  next is sample a+n when a+n < L.
 // Bit b of the rise (fall) mask marks sample b above (below) sample b-1, bit
 // C the step to the next thread's first sample; a sample closes a run when
 // its next step is not flat, and the run is a maximum when entered rising
@@ -134,7 +135,7 @@ template <int C>
 __device__ __forceinline__ void tile_detect(const double (&h)[C], int a, int n, int L, int tid,
                                             int first_key, double next, double* pub_first,
                                             double* pub_last, int* pub_key, int* cont_exit,
-                                            TileDet& d) {
+                                            int* cont_pos, double* cont_y, TileDet& d) {
   const int lb = tid * C, base = a + lb;
   const int nv = max(0, min(C, n - lb));
   unsigned R = 0u, F = 0u;
@@ -216,7 +217,11 @@ __device__ __forceinline__ void tile_detect(const double (&h)[C], int a, int n, 
     }
     if (kind == kRise && ((F >> (c + 1)) & 1u)) maxbits |= 1u << c;
     else if (kind == kFall && ((R >> (c + 1)) & 1u)) minbits |= 1u << c;
-    else if (kind == kCont && cont_exit) *cont_exit = ((F >> (c + 1)) & 1u) ? kFall : kRise;
+    else if (kind == kCont && cont_exit) {
+      *cont_exit = ((F >> (c + 1)) & 1u) ? kFall : kRise;
+      *cont_pos = base + c;
+      *cont_y = h[c];
+    }
   }
   const unsigned top = NE & valid;
   if (top) {
@@ -231,19 +236,50 @@ __device__ __forceinline__ void tile_detect(const double (&h)[C], int a, int n, 
   d.carry = carry;
 }
 
-// Counts and run keys of a detected tile into its TileInfo (thread 0).
-__device__ __forceinline__ void publish_tile(const TileDet& d, int first_key, int cont_exit,
-                                             TileInfo& t, int64_t* scratch64, int* scratch) {
+// Floor-middle of the equal-valued run that sample c of a thread closes
+// (NE and carry as in TileDet; base is the thread's first sample).
+__device__ __forceinline__ int run_mid(unsigned NE, int carry, int base, int c) {
+  const unsigned below = NE & ((2u << c) - 1u);
+  const int start = below ? base + (31 - __clz(below)) : (carry >> 2);
+  return (start + base + c) >> 1;
+}
+
+// What detection leaves for the scan, compaction and evaluation: each
+// thread's knots at tile-local ranks (positions and values), the knots each
+// thread's predecessors in the tile hold, the tile's counts and run keys, and
+// the continued run's end (its extremum is decided by the scan).
+__device__ __forceinline__ void record_tile(const TileDet& d, const double (&h)[kTC], int a,
+                                            int first_key, int cont_exit, int cont_pos,
+                                            double cont_y, const StreamSig& S, int tile,
+                                            int64_t* scratch64, int* scratch) {
   int64_t tot;
-  block_excl_sum64(((int64_t)__popc(d.maxbits) << 32) | (uint32_t)__popc(d.minbits), scratch64,
-                   tot);
+  const int64_t ex = block_excl_sum64(
+      ((int64_t)__popc(d.maxbits) << 32) | (uint32_t)__popc(d.minbits), scratch64, tot);
+  int g[2] = {(int)(ex >> 32), (int)(ex & 0xffffffff)};
+  int32_t* tr = S.trank + 2 * ((int64_t)tile * kTT + threadIdx.x);
+  tr[0] = g[0];
+  tr[1] = g[1];
+  const int base = a + threadIdx.x * kTC;
+  const int64_t lo = (int64_t)tile * kTileKnots;
+#pragma unroll
+  for (int c = 0; c < kTC; ++c) {
+    if (((d.maxbits | d.minbits) >> c) & 1u) {
+      const int e = ((d.maxbits >> c) & 1u) ? 0 : 1;
+      S.lpos[e][lo + g[e]] = run_mid(d.NE, d.carry, base, c);
+      S.lval[e][lo + g[e]] = h[c];
+      ++g[e];
+    }
+  }
   const int lastkey = block_max(d.last, scratch);
   if (threadIdx.x == 0) {
+    TileInfo& t = S.tinfo[tile];
     t.cnt[0] = (int)(tot >> 32);
     t.cnt[1] = (int)(tot & 0xffffffff);
     t.lastkey = (lastkey & 3) == kCont ? -1 : lastkey;
     t.cont = first_key == kCont;
     t.cont_exit = cont_exit;
+    t.cont_pos = cont_exit ? cont_pos : -1;
+    t.cont_y = cont_y;
   }
 }
 
@@ -300,7 +336,8 @@ __global__ void __launch_bounds__(kTT) st_detect_kernel(const StreamSig* __restr
   __shared__ int pub_key[kTT];
   __shared__ int scratch[kNW];
   __shared__ int64_t scratch64[kNW];
-  __shared__ int cont_exit;
+  __shared__ int cont_exit, cont_pos;
+  __shared__ double cont_y;
   const int2 tv = tiles[blockIdx.x];
   const StreamSig& S = sigs[tv.x];
   if (!S.st->active || S.st->action == kSift) return;
@@ -320,9 +357,9 @@ __global__ void __launch_bounds__(kTT) st_detect_kernel(const StreamSig* __restr
   }
   TileDet d;
   tile_detect<kTC>(h, a, n, L, threadIdx.x, first_key, next, pub_first, pub_last, pub_key,
-                   &cont_exit, d);
+                   &cont_exit, &cont_pos, &cont_y, d);
   __syncthreads();
-  publish_tile(d, first_key, cont_exit, S.tinfo[tv.y], scratch64, scratch);
+  record_tile(d, h, a, first_key, cont_exit, cont_pos, cont_y, S, tv.y, scratch64, scratch);
 }
 
 // One workgroup per signal: carries and ranks across its tiles, knot totals,
@@ -378,6 +415,7 @@ __global__ void __launch_bounds__(kTT) st_scan_kernel(const StreamSig* __restric
     if (valid) {
       TileInfo& o = S.tinfo[t];
       o.carry = carry_in;
+      o.cont_knot = dmax | (dmin << 1);
       o.tot[0] = tmax;
       o.tot[1] = tmin;
       const int64_t off = off_run + ex_off;
@@ -415,55 +453,51 @@ __global__ void __launch_bounds__(kTT) st_scan_kernel(const StreamSig* __restric
   }
 }
 
-// Knots of the tile at their ranks (Sec. 2.1 Step 1 -> Step 2).
+// One knot and its mirrored copies (Sec. 2.1 Step 2 with the mirror
+// boundary): the knot list of one envelope is
+//   [-k_P', ..., -k_1, k_1, ..., k_n, 2(L-1)-k_n, ..., 2(L-1)-k_{n-P'+1}],
+// P' = min(2, n), mirrored knots carrying their source's value.
+__device__ __forceinline__ void put_knot(int32_t* kt, double* ky, int g, int n, int L, int pos,
+                                         double y) {
+  const int Pp = n < 2 ? n : 2;
+  kt[Pp + g] = pos;
+  ky[Pp + g] = y;
+  if (g < 2 || g >= n - 2) {
+    const int hi = 2 * (L - 1);
+    if (g == 0) { kt[Pp - 1] = -pos; ky[Pp - 1] = y; }
+    if (g == 1 && Pp == 2) { kt[0] = -pos; ky[0] = y; }
+    if (g == n - 1) { kt[Pp + n] = hi - pos; ky[Pp + n] = y; }
+    if (g == n - 2 && Pp == 2) { kt[Pp + n + 1] = hi - pos; ky[Pp + n + 1] = y; }
+  }
+}
+
+// The knots of the tile at their ranks (Sec. 2.1 Step 1 -> Step 2): the
+// continued run's extremum, when the scan found one, then the tile's own
+// knots as detection listed them.  Also the tile's edge samples before this
+// sift, for the evaluation of the neighbouring tiles.
 __global__ void __launch_bounds__(kTT) st_compact_kernel(const StreamSig* __restrict__ sigs,
                                                          const int2* __restrict__ tiles) {
-  __shared__ double tbuf[kTile];
-  __shared__ double pub_first[kTT], pub_last[kTT];
-  __shared__ int pub_key[kTT];
-  __shared__ int64_t scratch64[kNW];
   const int2 tv = tiles[blockIdx.x];
   const StreamSig& S = sigs[tv.x];
   if (!sifting(*S.st)) return;
   const int L = S.L;
   const int a = tv.y * kTile, n = min(kTile, L - a);
   const TileInfo ti = S.tinfo[tv.y];
-  double prev, next;
-  stage_tile(S.h, a, n, L, tbuf, prev, next);
-  __syncthreads();
-  const int first_key =
-      a == 0 ? 0 : (prev != tbuf[0] ? a * 4 + step_kind(prev, tbuf[0]) : ti.carry);
-  double h[kTC];
-#pragma unroll
-  for (int c = 0; c < kTC; ++c) {
-    const int i = threadIdx.x * kTC + c;
-    h[c] = i < n ? tbuf[i] : 0.0;
-  }
-  // the tile's edge samples as they are before this sift, for the
-  // evaluation of the neighbouring tiles
   if (threadIdx.x == 0) {
-    S.edge[2 * tv.y] = tbuf[0];
-    S.edge[2 * tv.y + 1] = tbuf[n - 1];
+    S.edge[2 * tv.y] = S.h[a];
+    S.edge[2 * tv.y + 1] = S.h[a + n - 1];
   }
-  TileDet d;
-  tile_detect<kTC>(h, a, n, L, threadIdx.x, first_key, next, pub_first, pub_last, pub_key,
-                   nullptr, d);
-  const int carry = d.carry;
-  const unsigned maxbits = d.maxbits, minbits = d.minbits;
-  int64_t tot;
-  const int64_t ex =
-      block_excl_sum64(((int64_t)__popc(maxbits) << 32) | (uint32_t)__popc(minbits), scratch64, tot);
-  const int nmax = S.st->n[0], nmin = S.st->n[1];
-  const int base = a + threadIdx.x * kTC;
-  const int nv = max(0, min(kTC, n - threadIdx.x * kTC));
-  const int rmax = ti.off[0] + (int)(ex >> 32), rmin = ti.off[1] + (int)(ex & 0xffffffff);
-  int32_t* tr = S.trank + 2 * ((int64_t)tv.y * kTT + threadIdx.x);
-  tr[0] = rmax;
-  tr[1] = rmin;
-  emit_knots<kTC>(h, maxbits, carry, base, nv, L, ti.off[0] + (int)(ex >> 32), nmax, S.kt[0],
-                  S.ky[0], S.cap);
-  emit_knots<kTC>(h, minbits, carry, base, nv, L, ti.off[1] + (int)(ex & 0xffffffff), nmin,
-                  S.kt[1], S.ky[1], S.cap);
+  const int64_t lo = (int64_t)tv.y * kTileKnots;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int nk = S.st->n[e];
+    const int ck = (ti.cont_knot >> e) & 1;
+    if (ck && threadIdx.x == 0)
+      put_knot(S.kt[e], S.ky[e], ti.off[e], nk, L, ((ti.carry >> 2) + ti.cont_pos) >> 1,
+               ti.cont_y);
+    for (int i = threadIdx.x; i < ti.cnt[e]; i += kTT)
+      put_knot(S.kt[e], S.ky[e], ti.off[e] + ck + i, nk, L, S.lpos[e][lo + i], S.lval[e][lo + i]);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -484,9 +518,7 @@ __global__ void __launch_bounds__(kTT) st_compact_kernel(const StreamSig* __rest
 // q3 = (m_{j+1} - m_j) / (12 g).
 __device__ __forceinline__ void st_solve_chunk(const int32_t* __restrict__ lt,
                                                const double* __restrict__ ly, int w0, int n,
-                                               int ch, double* __restrict__ km,
-                                               double* __restrict__ kq1,
-                                               double* __restrict__ kq3) {
+                                               int ch, SegRec* __restrict__ seg) {
   const int s = 1 + ch * kChunk;
   const int e = min(s + kChunk - 1, n - 2);
   const int ws = max(1, s - kHalo);
@@ -561,22 +593,21 @@ __device__ __forceinline__ void st_solve_chunk(const int32_t* __restrict__ lt,
   for (int q = 0; q < kChunk; ++q) {
     const int j = s + q;
     if (j <= e) {
-      km[j] = Ms[q];
       const double m0 = Ms[q], m1 = (j < e) ? Ms[q + 1] : Mafter;
-      const double g = T(j + 1) - T(j);
+      const double t0 = T(j), t1 = T(j + 1), y0 = Y(j);
+      const double g = t1 - t0;
       const double ig = recip(g);
-      const double b = (Y(j + 1) - Y(j)) * ig - g * fma(2.0, m0, m1) * (1.0 / 6.0);
-      kq1[j] = 0.5 * b;
-      kq3[j] = (m1 - m0) * ig * (1.0 / 12.0);
+      const double b = (Y(j + 1) - y0) * ig - g * fma(2.0, m0, m1) * (1.0 / 6.0);
+      seg[j] = SegRec{t0, t1, 0.5 * y0, 0.5 * b, 0.25 * m0, (m1 - m0) * ig * (1.0 / 12.0)};
     }
   }
   if (s == 1) {  // segment 0, with m_0 = 0
     const double m1 = Ms[0];
-    const double g = T(1) - T(0);
+    const double t0 = T(0), t1 = T(1), y0 = Y(0);
+    const double g = t1 - t0;
     const double ig = recip(g);
-    const double b = (Y(1) - Y(0)) * ig - g * m1 * (1.0 / 6.0);
-    kq1[0] = 0.5 * b;
-    kq3[0] = m1 * ig * (1.0 / 12.0);
+    const double b = (Y(1) - y0) * ig - g * m1 * (1.0 / 6.0);
+    seg[0] = SegRec{t0, t1, 0.5 * y0, 0.5 * b, 0.0, m1 * ig * (1.0 / 12.0)};
   }
 #undef T
 #undef Y
@@ -611,46 +642,35 @@ __global__ void __launch_bounds__(kTT) st_solve_kernel(const StreamSig* __restri
   __syncthreads();
   const int ch = (r0 - 1) / kChunk + threadIdx.x;
   if (1 + ch * kChunk < r1)
-    st_solve_chunk(lt, ly, w0, n2, ch, S.km[env], S.kq1[env], S.kq3[env]);
-  if (bv.z == 0 && threadIdx.x == 0) {
-    S.km[env][0] = 0.0;
-    S.km[env][n2 - 1] = 0.0;
-  }
+    st_solve_chunk(lt, ly, w0, n2, ch, S.seg[env]);
 }
 
 // Walker over the segments of one envelope of a streaming signal, reading
-// the knot store in global memory: the current segment [t0, t1), its halved
-// power-form coefficients and B = k - t0.
+// the segment records in global memory: the current segment [t0, t1), its
+// halved power-form coefficients and B = k - t0.
 struct StWalk {
-  int j, t0, t1;
-  double B, q0, q1, q2, q3;
+  int j;
+  SegRec cur;
+  double B;
 };
-
-__device__ __forceinline__ void st_walk_load(StWalk& w, const StreamSig& S, int e, int j) {
-  w.j = j;
-  w.t0 = S.kt[e][j];
-  w.t1 = S.kt[e][j + 1];
-  w.q0 = 0.5 * S.ky[e][j];
-  w.q1 = S.kq1[e][j];
-  w.q2 = 0.25 * S.km[e][j];
-  w.q3 = S.kq3[e][j];
-}
 
 // Position at the segment holding sample k from segment j (whose left knot
 // lies at or before k; the last knot lies beyond the signal).
 __device__ __forceinline__ void st_walk_init(StWalk& w, const StreamSig& S, int e, int j, int k) {
-  st_walk_load(w, S, e, j);
-  while (w.t1 <= k) st_walk_load(w, S, e, w.j + 1);
-  w.B = (double)(k - w.t0);
+  const SegRec* seg = S.seg[e];
+  w.j = j;
+  w.cur = seg[j];
+  while (w.cur.t1 <= (double)k) w.cur = seg[++w.j];
+  w.B = (double)k - w.cur.t0;
 }
 
 // Half the envelope at sample k (one step from k-1 crosses at most one knot).
 __device__ __forceinline__ double st_walk_at(StWalk& w, const StreamSig& S, int e, int k) {
-  if (w.t1 <= k) {
-    st_walk_load(w, S, e, w.j + 1);
-    w.B = (double)(k - w.t0);
+  if (w.cur.t1 <= (double)k) {
+    w.cur = S.seg[e][++w.j];
+    w.B = (double)k - w.cur.t0;
   }
-  return fma(fma(fma(w.q3, w.B, w.q2), w.B, w.q1), w.B, w.q0);
+  return fma(fma(fma(w.cur.q3, w.B, w.cur.q2), w.B, w.cur.q1), w.B, w.cur.q0);
 }
 
 // ---------------------------------------------------------------------------
@@ -673,7 +693,8 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
   __shared__ int scratch[kNW];
   __shared__ int64_t scratch64[kNW];
   __shared__ double halo[2];  // the neighbours' edge samples after the sift
-  __shared__ int cont_exit;
+  __shared__ int cont_exit, cont_pos;
+  __shared__ double cont_y;
   const int2 tv = tiles[blockIdx.x];
   const StreamSig& S = sigs[tv.x];
   const SigStatus* st = S.st;
@@ -691,14 +712,19 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
     StWalk wk[2];
     if (nv > 0) {
       const int32_t* tr = S.trank + 2 * ((int64_t)tv.y * kTT + threadIdx.x);
+      const TileInfo& ti = S.tinfo[tv.y];
+      // the continued run's extremum precedes this thread's knots when the
+      // run ends in an earlier thread of the tile
+      const bool cont_before = ti.cont_pos >= 0 && ti.cont_pos < k0;
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         const int nk = st->n[e];
         const int Pp = nk < 2 ? nk : 2;
+        const int rank = ti.off[e] + (cont_before ? ((ti.cont_knot >> e) & 1) : 0) + tr[e];
         // the last knot of earlier threads lies before the thread's first
         // sample (and before sample a-1 for thread 0: it lies in an earlier
         // tile or is a mirrored knot)
-        st_walk_init(wk[e], S, e, Pp + tr[e] - 1, ks);
+        st_walk_init(wk[e], S, e, Pp + rank - 1, ks);
       }
       if (ks < k0) {
         const double up = st_walk_at(wk[0], S, 0, ks);
@@ -744,9 +770,9 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
       for (int c = 0; c < kTC; ++c) h[c] = lb + c < n ? tbuf[lb + c] : 0.0;
       TileDet d;
       tile_detect<kTC>(h, a, n, L, threadIdx.x, first_key, next, pub_first, pub_last, pub_key,
-                       &cont_exit, d);
+                       &cont_exit, &cont_pos, &cont_y, d);
       __syncthreads();
-      publish_tile(d, first_key, cont_exit, S.tinfo[tv.y], scratch64, scratch);
+      record_tile(d, h, a, first_key, cont_exit, cont_pos, cont_y, S, tv.y, scratch64, scratch);
     }
   }
   __syncthreads();
