@@ -290,6 +290,21 @@ def run_series(args, semd, torch, workloads):
                                  f"signal per launch", "M": M, "N": N, "D": D, "L": L,
                      "max_imfs": K, "sift_iters": S, "repeats": reps}
     res["latency_ms"] = {"p50": pct(lat, 50), "p99": pct(lat, 99)}
+    # the standard (slice-wise) EMD of the same channels, for comparison
+    so = torch.empty((K + 1, M * N), dtype=torch.float64, device=dev)
+    sn = torch.empty(N, dtype=torch.int32, device=dev)
+    semd.semd_decompose_slices(X, [M, N], K, S, so, sn)
+    torch.cuda.synchronize()
+    sev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    for a, b in sev:
+        a.record(stream)
+        semd.semd_decompose_slices(X, [M, N], K, S, so, sn)
+        b.record(stream)
+    torch.cuda.synchronize()
+    slat = [a.elapsed_time(b) for a, b in sev]
+    res["slices"] = {"p50_ms": pct(slat, 50), "p99_ms": pct(slat, 99),
+                     "channels": N, "imfs_per_channel": [int(v) for v in sn.cpu().tolist()]}
     res["work"] = work
     flops = FLOPS_PER_SAMPLE_SIFT * work["sample_sifts"] + FLOPS_PER_KNOT * work["knots"]
     res["roofline"] = roofline_alu(flops, float(np.mean(lat)),

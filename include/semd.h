@@ -165,6 +165,17 @@ int semd_decompose_ex(const double* signal, const int64_t* dims, int ndim,
                       const semd_params* p, double* imfs_out, int32_t* n_imfs_out,
                       hipStream_t stream);
 
+/* Standard (slice-wise) EMD, the baseline Serial-EMD is compared with (Sec. 4):
+ * each of the N columns of X (length M each, dims as above) is decomposed by
+ * the 1D EMD of Sec. 2.1 on its own, with no serialization.  p->transition_len
+ * must be 0; p->ensemble is ignored.  imfs_out: (K+1)*M*N doubles in the same
+ * slot-major layout as semd_decompose_ex (column i of every slot is column
+ * i's mode); n_imfs_out: N int32 (IMFs of each column) or NULL.  Signals longer
+ * than semd_resident_max_length() take the streaming path. */
+int semd_decompose_slices(const double* signal, const int64_t* dims, int ndim,
+                          const semd_params* p, double* imfs_out, int32_t* n_imfs_out,
+                          hipStream_t stream);
+
 /* Serial-EMD of n independent signals of any shapes in one batched launch
  * (p->ensemble ignored).  items, p: [host]; the items array may be reused as
  * soon as the call returns. */

@@ -71,6 +71,9 @@ _EXPORTS = {
                                     C.c_void_p]),
     "semd_decompose_batch": (C.c_int, [C.POINTER(semd_item), C.c_int, C.POINTER(semd_params),
                                        C.c_void_p]),
+    "semd_decompose_slices": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_int,
+                                        C.POINTER(semd_params), C.c_void_p, C.c_void_p,
+                                        C.c_void_p]),
     "semd_eemd_batch": (C.c_int, [C.POINTER(semd_item), C.c_int, C.POINTER(semd_params),
                                   C.c_void_p]),
     "semd_serialize": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_int, C.c_int,
@@ -238,6 +241,29 @@ def semd_decompose_ex(signal: torch.Tensor, dims: Sequence[int], D: int, max_imf
     _check(lib().semd_decompose_ex(_dev_f64(signal, "signal"), d, nd, C.byref(p),
                                    _dev_f64(imfs_out, "imfs_out"), n_imfs_out.data_ptr(),
                                    _stream(stream)), "semd_decompose_ex")
+    return imfs_out, n_imfs_out
+
+
+def semd_decompose_slices(signal: torch.Tensor, dims: Sequence[int], max_imfs: int,
+                          sift_iters: int, imfs_out: torch.Tensor | None = None,
+                          n_imfs_out: torch.Tensor | None = None, stream=None,
+                          path: int = SEMD_PATH_AUTO):
+    """Standard (slice-wise) EMD: every column decomposed on its own.
+    Returns (imfs_out (K+1, M*N), n_imfs_out (N,))."""
+    d, nd = _dims(dims)
+    M = int(dims[0])
+    N = 1
+    for v in dims[1:]:
+        N *= int(v)
+    dev = signal.device
+    if imfs_out is None:
+        imfs_out = torch.empty((max_imfs + 1, M * N), dtype=torch.float64, device=dev)
+    if n_imfs_out is None:
+        n_imfs_out = torch.empty(N, dtype=torch.int32, device=dev)
+    p = _params(0, max_imfs, sift_iters, path=path)
+    _check(lib().semd_decompose_slices(_dev_f64(signal, "signal"), d, nd, C.byref(p),
+                                       _dev_f64(imfs_out, "imfs_out"), n_imfs_out.data_ptr(),
+                                       _stream(stream)), "semd_decompose_slices")
     return imfs_out, n_imfs_out
 
 

@@ -371,6 +371,7 @@ semd::StreamSig stream_sig(const semd::WorkItem& w, int K, int S, unsigned char*
   g.beta = w.beta;
   g.key = w.key;
   g.flags = w.flags;
+  g.slot_stride = w.slot_stride;
   g.ntiles = (w.L + semd::kTile - 1) / semd::kTile;
   g.K = K;
   g.S = S;
@@ -508,6 +509,7 @@ semd::WorkItem make_work(const double* X, double* out, int32_t* n_imfs, const Sh
   w.N = sh.N;
   w.D = D;
   w.L = (int32_t)sh.L;
+  w.slot_stride = sh.M * sh.N;
   return w;
 }
 
@@ -728,6 +730,35 @@ int semd_decompose_ex(const double* signal, const int64_t* dims, int ndim, const
   rc = check_length(sh.L, p->path, 0);
   if (rc) return rc;
   std::vector<semd::WorkItem> work{make_work(signal, imfs_out, n_imfs_out, sh, p->transition_len)};
+  return run_work(work, p->max_imfs, p->sift_iters, p->path, stream);
+}
+
+int semd_decompose_slices(const double* signal, const int64_t* dims, int ndim,
+                          const semd_params* p, double* imfs_out, int32_t* n_imfs_out,
+                          hipStream_t stream) {
+  g_err[0] = 0;
+  int rc = check_params(p, false);
+  if (rc) return rc;
+  if (p->transition_len != 0)
+    return fail(SEMD_EINVAL, "transition_len must be 0: slices are not serialized");
+  if (!signal || !imfs_out) return fail(SEMD_EINVAL, "NULL signal or output");
+  int64_t M, N;
+  rc = parse_dims(dims, ndim, &M, &N);
+  if (rc) return rc;
+  if (N > (int64_t(1) << 24)) return fail(SEMD_EUNSUPPORTED, "%lld slices", (long long)N);
+  rc = check_length(M, p->path, 0);
+  if (rc) return rc;
+  // column i is a signal of its own, writing its slots at column i of the
+  // shared slot-major output
+  const Shape col{M, 1, M};
+  std::vector<semd::WorkItem> work;
+  work.reserve((size_t)N);
+  for (int64_t i = 0; i < N; ++i) {
+    semd::WorkItem w = make_work(signal + i * M, imfs_out + i * M,
+                                 n_imfs_out ? n_imfs_out + i : nullptr, col, 0);
+    w.slot_stride = M * N;
+    work.push_back(w);
+  }
   return run_work(work, p->max_imfs, p->sift_iters, p->path, stream);
 }
 

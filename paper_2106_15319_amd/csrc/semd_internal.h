@@ -25,6 +25,7 @@ struct WorkItem {
   uint64_t key;      // SplitMix64 stream key of this realization
   int32_t flags;     // bit 0: add beta * noise to the serialized signal
   int32_t pad;
+  int64_t slot_stride;  // doubles from one output slot to the next (M*N when contiguous)
 };
 
 // Longest serialized signal the resident kernel handles (threads x samples

@@ -581,8 +581,10 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
     for (int c = 0; c < C; ++c)
       if (c < nv0 && in_chunk(base0 + c, c0, c1)) h[c] = stage[base0 + c - c0];
   }
+  const int64_t SS = w.slot_stride;
   if (__syncthreads_or(bad)) {
-    for (int64_t o = tid0; o < (int64_t)(K + 1) * MN; o += NT) w.out[o] = 0.0;
+    for (int q = 0; q <= K; ++q)
+      for (int o = tid0; o < MN; o += NT) w.out[q * SS + o] = 0.0;
     if (tid0 == 0 && w.n_imfs) *w.n_imfs = -5;
     return;
   }
@@ -659,7 +661,7 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
     }
     if (stop) break;
     // IMF nimf = h (deserialized store, Sec. 3.3); residue r <- r - h; h <- r
-    double* slot = w.out + (int64_t)nimf * MN;
+    double* slot = w.out + (int64_t)nimf * SS;
     int tid = tid0, base = base0, nv = nv0;
     opaque(tid);
     opaque(base);
@@ -702,13 +704,14 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
   }
   // residue into slot K (every r[k] was last written by this same thread),
   // unused IMF slots zero (Sec. 4.3 zero fill)
-  double* rslot = w.out + (int64_t)K * MN;
+  double* rslot = w.out + (int64_t)K * SS;
   for (int k = tid0; k < L; k += NT) {
     int i, m;
     div_small(k, R, invR, i, m);
     if (m < M) rslot[i * M + m] = w.r[k];
   }
-  for (int64_t o = (int64_t)nimf * MN + tid0; o < (int64_t)K * MN; o += NT) w.out[o] = 0.0;
+  for (int q = nimf; q < K; ++q)
+    for (int o = tid0; o < MN; o += NT) w.out[q * SS + o] = 0.0;
   if (tid0 == 0 && w.n_imfs) *w.n_imfs = nimf;
   if (tid0 == 0 && w.stats) {
     w.stats[0] = n_sifts;

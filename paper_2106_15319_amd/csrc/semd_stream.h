@@ -71,6 +71,7 @@ struct StreamSig {
   int32_t D, L;
   double beta;
   uint64_t key;
+  int64_t slot_stride;  // doubles from one output slot to the next
   int32_t flags;    // bit 0: add beta * noise
   int32_t ntiles;
   int32_t K;        // max IMFs

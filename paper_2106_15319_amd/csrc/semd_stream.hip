@@ -776,9 +776,9 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
     }
   }
   __syncthreads();
-  const int64_t M = S.M, R = S.M + S.D, MN = S.M * S.N;
+  const int64_t M = S.M, R = S.M + S.D;
   if (action == kSiftLast || action == kEndImf) {
-    double* slot = S.out + (int64_t)st->slot * MN;
+    double* slot = S.out + (int64_t)st->slot * S.slot_stride;
     for (int i = threadIdx.x; i < n; i += kTT) {
       const int k = a + i;
       const double hk = tbuf[i];
@@ -797,8 +797,8 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
       const int64_t ii = k / R, m = k - ii * R;
       if (m < M) {
         const int64_t o = ii * M + m;
-        for (int q = nimf; q < K; ++q) S.out[q * MN + o] = 0.0;
-        S.out[(int64_t)K * MN + o] = bad ? 0.0 : tbuf[i];
+        for (int q = nimf; q < K; ++q) S.out[q * S.slot_stride + o] = 0.0;
+        S.out[(int64_t)K * S.slot_stride + o] = bad ? 0.0 : tbuf[i];
       }
     }
     if (tv.y == 0 && threadIdx.x == 0) {

@@ -147,3 +147,15 @@ def test_tuning_validation_without_device():
     assert L.semd_tune_get(None, 0, None) == semd.SEMD_EINVAL
     assert L.semd_tune_set(None) == semd.SEMD_EINVAL
     assert L.semd_tune_reset() == semd.SEMD_OK
+
+
+def test_slices_validation():
+    L = semd.lib()
+    d = (C.c_int64 * 2)(100, 3)
+    assert L.semd_decompose_slices(BOGUS, d, 2, C.byref(_p(D=5)), BOGUS, None, None) == \
+        semd.SEMD_EINVAL  # slices are not serialized
+    assert L.semd_decompose_slices(None, d, 2, C.byref(_p()), BOGUS, None, None) == \
+        semd.SEMD_EINVAL
+    big = (C.c_int64 * 2)(20000, 2)
+    assert L.semd_decompose_slices(BOGUS, big, 2, C.byref(_p(path=semd.SEMD_PATH_ONCHIP)),
+                                   BOGUS, None, None) == semd.SEMD_EUNSUPPORTED

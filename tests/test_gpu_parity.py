@@ -530,3 +530,33 @@ def test_autotune_round_trip():
         _check_item(it.X, it.M, it.N, 0, 6, 10, host(out), int(host(n)[0]), [])
     finally:
         semd.semd_tune_reset()
+
+
+# --------------------------------------------------------------------------
+# standard (slice-wise) EMD
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind", ["series", "texture", "long"])
+def test_slices_match_oracle(kind):
+    if kind == "series":
+        it = workloads.config0()
+    elif kind == "texture":
+        it = workloads.config1(1, 64)[0]
+    else:  # columns longer than the on-chip limit: streaming path
+        it = workloads.config3_item(7, (20000, 2))
+    K, S = 6, 10
+    out, n = semd.semd_decompose_slices(dev(it.X), [it.M, it.N], K, S)
+    out, n = host(out), host(n)
+    ref, nref = oracle.decompose_slices(it.X, it.M, it.N, K, S)
+    assert list(n) == list(nref)
+    xmax = np.abs(it.X).max()
+    assert np.abs(out - ref.reshape(out.shape)).max() <= TOL * xmax
+
+
+def test_slices_equal_single_column_serial():
+    # one column: slice-wise and serial decompositions are the same EMD
+    it = workloads.config3_item(3, (3000, 1))
+    a, na = semd.semd_decompose_slices(dev(it.X), [it.M, 1], 6, 10)
+    b, nb = semd.semd_decompose_ex(dev(it.X), [it.M, 1], 0, 6, 10)
+    assert int(host(na)[0]) == int(host(nb)[0])
+    assert_same(host(a), host(b), "slices vs serial")
