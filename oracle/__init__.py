@@ -58,6 +58,10 @@ def lib():
         L.semd_ref_spline_eval.argtypes = [_d, _d, _d, C.c_int64, C.c_int64, _d]
         L.semd_ref_envelope.argtypes = [_d, C.c_int64, _i64, C.c_int64, _d]
         L.semd_ref_emd.argtypes = [_d, C.c_int64, C.c_int, C.c_int, _d, _int, C.POINTER(Stats)]
+        L.semd_ref_emd_sd.argtypes = [_d, C.c_int64, C.c_int, C.c_int, C.c_double, _d, _int,
+                                      C.POINTER(Stats)]
+        L.semd_ref_decompose_sd.argtypes = [_d, C.c_int64, C.c_int64, C.c_int64, C.c_int,
+                                            C.c_int, C.c_double, _d, _int, C.POINTER(Stats)]
         L.semd_ref_decompose.argtypes = [_d, C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_int,
                                          _d, _int, C.POINTER(Stats)]
         L.semd_ref_decompose_slices.argtypes = [_d, C.c_int64, C.c_int64, C.c_int, C.c_int,
@@ -70,6 +74,7 @@ def lib():
         for name in ("semd_ref_serialize", "semd_ref_deserialize", "semd_ref_extrema",
                      "semd_ref_spline_solve", "semd_ref_spline_eval", "semd_ref_envelope",
                      "semd_ref_emd", "semd_ref_decompose", "semd_ref_decompose_slices",
+                     "semd_ref_emd_sd", "semd_ref_decompose_sd",
                      "semd_ref_noise", "semd_ref_eemd"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -145,28 +150,31 @@ def envelope(h, idx) -> np.ndarray:
     return env
 
 
-def emd(x, K: int, S: int, with_stats: bool = False):
-    """Sec. 2.1: (K+1, L) slots (IMFs, zero fill, residue in slot K) and n_imfs."""
+def emd(x, K: int, S: int, with_stats: bool = False, sd: float = 0.0):
+    """Sec. 2.1: (K+1, L) slots (IMFs, zero fill, residue in slot K) and n_imfs.
+    sd > 0: an IMF also ends once a sift's SD falls below sd (at most S sifts)."""
     x = _f64(x)
     L = x.size
     out = np.empty((K + 1) * L)
     n = C.c_int()
     st = Stats()
-    _check(lib().semd_ref_emd(_p(x), L, K, S, _p(out), C.byref(n), C.byref(st)), "emd")
+    _check(lib().semd_ref_emd_sd(_p(x), L, K, S, float(sd), _p(out), C.byref(n), C.byref(st)),
+           "emd")
     res = (out.reshape(K + 1, L), n.value)
     if with_stats:
         return res + ({"min_gap": st.min_gap, "n_sifts": st.n_sifts, "n_equal": st.n_equal},)
     return res
 
 
-def decompose(Xcol, M: int, N: int, D: int, K: int, S: int, with_stats: bool = False):
-    """Serial-EMD (Sec. 3): (K+1, M*N) column-major slots and n_imfs."""
+def decompose(Xcol, M: int, N: int, D: int, K: int, S: int, with_stats: bool = False,
+              sd: float = 0.0):
+    """Serial-EMD (Sec. 3): (K+1, M*N) column-major slots and n_imfs (sd as in emd)."""
     X = _f64(Xcol)
     out = np.empty((K + 1) * M * N)
     n = C.c_int()
     st = Stats()
-    _check(lib().semd_ref_decompose(_p(X), M, N, D, K, S, _p(out), C.byref(n), C.byref(st)),
-           "decompose")
+    _check(lib().semd_ref_decompose_sd(_p(X), M, N, D, K, S, float(sd), _p(out), C.byref(n),
+                                       C.byref(st)), "decompose")
     res = (out.reshape(K + 1, M * N), n.value)
     if with_stats:
         return res + ({"min_gap": st.min_gap, "n_sifts": st.n_sifts, "n_equal": st.n_equal},)

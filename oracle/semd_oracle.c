@@ -232,7 +232,12 @@ static void note_gaps(const double* h, int64_t L, semd_ref_stats* st) {
 
 int semd_ref_emd(const double* x, int64_t L, int K, int S, double* imfs, int* n_imfs,
                  semd_ref_stats* stats) {
-  if (!x || !imfs || !n_imfs || L < 1 || K < 1 || S < 1) return -1;
+  return semd_ref_emd_sd(x, L, K, S, 0.0, imfs, n_imfs, stats);
+}
+
+int semd_ref_emd_sd(const double* x, int64_t L, int K, int S, double sd_threshold,
+                    double* imfs, int* n_imfs, semd_ref_stats* stats) {
+  if (!x || !imfs || !n_imfs || L < 1 || K < 1 || S < 1 || !(sd_threshold >= 0.0)) return -1;
   for (int64_t k = 0; k < L; ++k)
     if (!isfinite(x[k])) return -3;
   semd_ref_stats st;
@@ -274,12 +279,18 @@ int semd_ref_emd(const double* x, int64_t L, int K, int S, double* imfs, int* n_
       rc = semd_ref_envelope(h, L, imax, na, up);
       if (rc == 0) rc = semd_ref_envelope(h, L, imin, ni, lo);
       if (rc != 0) goto done;
+      /* the change of this sift is the mean m itself: SD = sum m^2 / sum h^2
+         over the candidate before the sift (Huang et al. 1998) */
+      double num = 0.0, den = 0.0;
       for (int64_t k = 0; k < L; ++k) {
         double m = 0.5 * (up[k] + lo[k]);
+        num += m * m;
+        den += h[k] * h[k];
         h[k] = h[k] - m;
       }
       pristine = 0;
       st.n_sifts += 1;
+      if (sd_threshold > 0.0 && num < sd_threshold * den) break;
     }
     /* Step 5 (fixed-count criterion): c_i = h; residue r = r - c_i. */
     memcpy(imfs + (size_t)nimf * (size_t)L, h, nb);
@@ -296,13 +307,18 @@ done:
 
 int semd_ref_decompose(const double* X, int64_t M, int64_t N, int64_t D, int K, int S,
                        double* out, int* n_imfs, semd_ref_stats* stats) {
+  return semd_ref_decompose_sd(X, M, N, D, K, S, 0.0, out, n_imfs, stats);
+}
+
+int semd_ref_decompose_sd(const double* X, int64_t M, int64_t N, int64_t D, int K, int S,
+                          double sd_threshold, double* out, int* n_imfs, semd_ref_stats* stats) {
   if (!X || !out || !n_imfs || M < 1 || N < 1 || D < 0 || D > M || K < 1 || S < 1) return -1;
   const int64_t L = semd_ref_serial_length(M, N, D);
   double* x = (double*)malloc(sizeof(double) * (size_t)L);
   double* R = (double*)malloc(sizeof(double) * (size_t)L * (size_t)(K + 1));
   if (!x || !R) { free(x); free(R); return -2; }
   int rc = semd_ref_serialize(X, M, N, D, x);
-  if (rc == 0) rc = semd_ref_emd(x, L, K, S, R, n_imfs, stats);
+  if (rc == 0) rc = semd_ref_emd_sd(x, L, K, S, sd_threshold, R, n_imfs, stats);
   if (rc == 0)
     for (int k = 0; k <= K; ++k)
       semd_ref_deserialize(R + (size_t)k * (size_t)L, M, N, D, out + (size_t)k * (size_t)(M * N));

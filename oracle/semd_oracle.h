@@ -67,10 +67,23 @@ typedef struct {
 int semd_ref_emd(const double* x, int64_t L, int K, int S, double* imfs, int* n_imfs,
                  semd_ref_stats* stats);
 
+/* Sec. 2.1 with a data-dependent stop (Step 5 leaves the criterion open): as
+ * semd_ref_emd, but an IMF also ends after the sift whose mean m satisfies
+ * sum_k m[k]^2 < sd_threshold * sum_k h[k]^2, h the candidate before that
+ * sift (the SD criterion of Huang et al. 1998; both sums taken in k order),
+ * with at most S sifts.  sd_threshold = 0 is the fixed-count rule. */
+int semd_ref_emd_sd(const double* x, int64_t L, int K, int S, double sd_threshold,
+                    double* imfs, int* n_imfs, semd_ref_stats* stats);
+
 /* Serial-EMD: serialize (Sec. 3.2), EMD (Sec. 2.1), deserialize (Sec. 3.3).
  * out: (K+1)*M*N doubles in the same slot convention. */
 int semd_ref_decompose(const double* X, int64_t M, int64_t N, int64_t D, int K, int S,
                        double* out, int* n_imfs, semd_ref_stats* stats);
+
+/* semd_ref_decompose with the SD stopping rule of semd_ref_emd_sd. */
+int semd_ref_decompose_sd(const double* X, int64_t M, int64_t N, int64_t D, int K, int S,
+                          double sd_threshold, double* out, int* n_imfs,
+                          semd_ref_stats* stats);
 
 /* Standard-version (slice-wise) EMD: every column of X decomposed on its own,
  * no serialization (Sec. 4 opening).  out: (K+1)*M*N; n_imfs: N ints. */

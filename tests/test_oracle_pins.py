@@ -21,6 +21,7 @@ from scipy.interpolate import CubicSpline
 from scipy.signal import find_peaks
 
 import oracle
+import workloads
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -427,3 +428,43 @@ def test_noise_stream_definition():
         acc = sum(sm(s2, 12 * k + j + 1) >> 11 for j in range(12))
         want.append(float(acc - 6 * 2**53) * 2.0**-53)
     assert list(oracle.noise(seed, item, m, 4)) == want
+
+
+# ---------------------------------------------------------------------------
+# SD stopping rule (Step 5 criterion left open by Sec. 2.1; Huang et al. 1998)
+# ---------------------------------------------------------------------------
+
+def _one_sift(h):
+    """One sift by the pinned envelope routine: (new candidate, m)."""
+    imax, imin = oracle.extrema(h)
+    m = 0.5 * (oracle.envelope(h, imax) + oracle.envelope(h, imin))
+    return h - m, m
+
+
+def test_sd_rule_limits_reduce_to_fixed_counts():
+    x = workloads.config0().X[:1000]
+    fixed, nf = oracle.emd(x, 6, 10)
+    tiny, nt = oracle.emd(x, 6, 10, sd=1e-300)   # never below: all S sifts
+    assert nt == nf and tiny.tobytes() == fixed.tobytes()
+    one, n1 = oracle.emd(x, 6, 1)
+    huge, nh = oracle.emd(x, 6, 10, sd=1e300)    # always below: one sift per IMF
+    assert nh == n1 and huge.tobytes() == one.tobytes()
+
+
+def test_sd_rule_stops_at_the_first_sift_below_the_threshold():
+    # SD of each sift of the first IMF computed here with numpy; thresholds
+    # placed between consecutive SD values stop the IMF after that sift
+    x = workloads.config0().X[:1000]
+    h = x.copy()
+    sds, hs = [], []
+    for _ in range(6):
+        h_new, m = _one_sift(h)
+        sds.append(float(np.sum(m * m) / np.sum(h * h)))
+        h = h_new
+        hs.append(h.copy())
+    assert all(sds[i] > sds[i + 1] for i in range(5))  # this signal converges monotonically
+    for stop in range(1, 5):
+        thr = 0.5 * (sds[stop - 1] + sds[stop])       # sift stop+1 is the first below
+        out, n = oracle.emd(x, 1, 10, sd=thr)
+        assert n == 1
+        np.testing.assert_allclose(out[0], hs[stop], rtol=0, atol=1e-12 * np.abs(x).max())
