@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define SEMD_ABI_VERSION 1
+#define SEMD_ABI_VERSION 2
 
 typedef enum {
   SEMD_OK = 0,
@@ -66,10 +66,19 @@ typedef enum { SEMD_BOUNDARY_MIRROR = 0 } semd_boundary;
  * two paths compute the same decomposition within rounding. */
 typedef enum { SEMD_PATH_AUTO = 0, SEMD_PATH_ONCHIP = 1, SEMD_PATH_STREAM = 2 } semd_path;
 
+/* When an IMF's sifting stops (Sec. 2.1 Step 5 leaves the criterion open).
+ * FIXED: after sift_iters sifts.  SD: also after the first sift whose mean
+ * envelope m satisfies sum m^2 < sd_threshold * sum h^2, h the candidate
+ * before that sift (the SD criterion of Huang et al. 1998), still at most
+ * sift_iters sifts.  Either way an IMF ends early when its candidate has too
+ * few extrema to sift. */
+typedef enum { SEMD_STOP_FIXED = 0, SEMD_STOP_SD = 1 } semd_stop;
+
 /* Method parameters.  transition_len is D of Sec. 3.2 (0 <= D <= M);
  * max_imfs is K >= 1; sift_iters is S >= 1; ensemble is the number NR >= 1 of
  * EEMD realizations (Sec. 2.2, used by semd_eemd_batch only); path is a
- * semd_path; seed keys the EEMD noise. */
+ * semd_path; seed keys the EEMD noise; stop_rule is a semd_stop and
+ * sd_threshold (> 0, finite) its threshold under SEMD_STOP_SD. */
 typedef struct {
   int32_t transition_len;
   int32_t max_imfs;
@@ -78,6 +87,9 @@ typedef struct {
   int32_t ensemble;
   int32_t path;
   uint64_t seed;
+  int32_t stop_rule;
+  int32_t reserved; /* must be 0 */
+  double sd_threshold;
 } semd_params;
 
 /* One signal of a batch.  signal: device, M*N doubles (M = dims[0], N =

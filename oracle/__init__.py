@@ -27,7 +27,8 @@ _int = C.POINTER(C.c_int)
 
 
 class Stats(C.Structure):
-    _fields_ = [("min_gap", C.c_double), ("n_sifts", C.c_int64), ("n_equal", C.c_int64)]
+    _fields_ = [("min_gap", C.c_double), ("n_sifts", C.c_int64), ("n_equal", C.c_int64),
+                ("sd_margin", C.c_double)]
 
 
 def build(force: bool = True) -> str:
@@ -66,16 +67,22 @@ def lib():
                                          _d, _int, C.POINTER(Stats)]
         L.semd_ref_decompose_slices.argtypes = [_d, C.c_int64, C.c_int64, C.c_int, C.c_int,
                                                 _d, _int]
+        L.semd_ref_decompose_slices_sd.argtypes = [_d, C.c_int64, C.c_int64, C.c_int, C.c_int,
+                                                   C.c_double, _d, _int]
         L.semd_ref_splitmix64.restype = C.c_uint64
         L.semd_ref_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
         L.semd_ref_noise.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.c_int64, _d]
         L.semd_ref_eemd.argtypes = [_d, C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_int,
                                     C.c_int, C.c_double, C.c_uint64, C.c_uint64, _d]
+        L.semd_ref_eemd_sd.argtypes = [_d, C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_int,
+                                       C.c_int, C.c_double, C.c_uint64, C.c_uint64, C.c_double,
+                                       _d]
         for name in ("semd_ref_serialize", "semd_ref_deserialize", "semd_ref_extrema",
                      "semd_ref_spline_solve", "semd_ref_spline_eval", "semd_ref_envelope",
                      "semd_ref_emd", "semd_ref_decompose", "semd_ref_decompose_slices",
                      "semd_ref_emd_sd", "semd_ref_decompose_sd",
-                     "semd_ref_noise", "semd_ref_eemd"):
+                     "semd_ref_decompose_slices_sd", "semd_ref_noise", "semd_ref_eemd",
+                     "semd_ref_eemd_sd"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -150,6 +157,11 @@ def envelope(h, idx) -> np.ndarray:
     return env
 
 
+def _stats(st) -> dict:
+    return {"min_gap": st.min_gap, "n_sifts": st.n_sifts, "n_equal": st.n_equal,
+            "sd_margin": st.sd_margin}
+
+
 def emd(x, K: int, S: int, with_stats: bool = False, sd: float = 0.0):
     """Sec. 2.1: (K+1, L) slots (IMFs, zero fill, residue in slot K) and n_imfs.
     sd > 0: an IMF also ends once a sift's SD falls below sd (at most S sifts)."""
@@ -162,7 +174,7 @@ def emd(x, K: int, S: int, with_stats: bool = False, sd: float = 0.0):
            "emd")
     res = (out.reshape(K + 1, L), n.value)
     if with_stats:
-        return res + ({"min_gap": st.min_gap, "n_sifts": st.n_sifts, "n_equal": st.n_equal},)
+        return res + (_stats(st),)
     return res
 
 
@@ -177,17 +189,17 @@ def decompose(Xcol, M: int, N: int, D: int, K: int, S: int, with_stats: bool = F
                                        C.byref(st)), "decompose")
     res = (out.reshape(K + 1, M * N), n.value)
     if with_stats:
-        return res + ({"min_gap": st.min_gap, "n_sifts": st.n_sifts, "n_equal": st.n_equal},)
+        return res + (_stats(st),)
     return res
 
 
-def decompose_slices(Xcol, M: int, N: int, K: int, S: int):
+def decompose_slices(Xcol, M: int, N: int, K: int, S: int, sd: float = 0.0):
     """Standard-version EMD: each column on its own.  ((K+1, M*N), n_imfs[N])."""
     X = _f64(Xcol)
     out = np.empty((K + 1) * M * N)
     n = np.empty(N, dtype=np.int32)
-    _check(lib().semd_ref_decompose_slices(_p(X), M, N, K, S, _p(out),
-                                           n.ctypes.data_as(_int)), "decompose_slices")
+    _check(lib().semd_ref_decompose_slices_sd(_p(X), M, N, K, S, float(sd), _p(out),
+                                              n.ctypes.data_as(_int)), "decompose_slices")
     return out.reshape(K + 1, M * N), n
 
 
@@ -202,10 +214,10 @@ def noise(seed: int, item: int, m: int, L: int) -> np.ndarray:
 
 
 def eemd(Xcol, M: int, N: int, D: int, K: int, S: int, NR: int, beta: float, seed: int,
-         item: int = 0) -> np.ndarray:
+         item: int = 0, sd: float = 0.0) -> np.ndarray:
     """Sec. 2.2 EEMD of the serialized signal: (K+1, M*N) mean slots."""
     X = _f64(Xcol)
     out = np.empty((K + 1) * M * N)
-    _check(lib().semd_ref_eemd(_p(X), M, N, D, K, S, NR, float(beta), seed, item, _p(out)),
-           "eemd")
+    _check(lib().semd_ref_eemd_sd(_p(X), M, N, D, K, S, NR, float(beta), seed, item, float(sd),
+                                  _p(out)), "eemd")
     return out.reshape(K + 1, M * N)

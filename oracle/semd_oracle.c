@@ -244,6 +244,7 @@ int semd_ref_emd_sd(const double* x, int64_t L, int K, int S, double sd_threshol
   st.min_gap = INFINITY;
   st.n_sifts = 0;
   st.n_equal = 0;
+  st.sd_margin = INFINITY;
 
   const size_t nb = sizeof(double) * (size_t)L;
   double* r = (double*)malloc(nb);
@@ -290,7 +291,14 @@ int semd_ref_emd_sd(const double* x, int64_t L, int K, int S, double sd_threshol
       }
       pristine = 0;
       st.n_sifts += 1;
-      if (sd_threshold > 0.0 && num < sd_threshold * den) break;
+      if (sd_threshold > 0.0 && s + 1 < S) {
+        const double lim = sd_threshold * den;
+        if (lim > 0.0) {
+          const double margin = fabs(num - lim) / lim;
+          if (margin < st.sd_margin) st.sd_margin = margin;
+        }
+        if (num < lim) break;
+      }
     }
     /* Step 5 (fixed-count criterion): c_i = h; residue r = r - c_i. */
     memcpy(imfs + (size_t)nimf * (size_t)L, h, nb);
@@ -328,12 +336,17 @@ int semd_ref_decompose_sd(const double* X, int64_t M, int64_t N, int64_t D, int 
 
 int semd_ref_decompose_slices(const double* X, int64_t M, int64_t N, int K, int S,
                               double* out, int* n_imfs) {
+  return semd_ref_decompose_slices_sd(X, M, N, K, S, 0.0, out, n_imfs);
+}
+
+int semd_ref_decompose_slices_sd(const double* X, int64_t M, int64_t N, int K, int S,
+                                 double sd_threshold, double* out, int* n_imfs) {
   if (!X || !out || !n_imfs || M < 1 || N < 1 || K < 1 || S < 1) return -1;
   double* R = (double*)malloc(sizeof(double) * (size_t)M * (size_t)(K + 1));
   if (!R) return -2;
   int rc = 0;
   for (int64_t c = 0; c < N && rc == 0; ++c) {
-    rc = semd_ref_emd(X + c * M, M, K, S, R, &n_imfs[c], NULL);
+    rc = semd_ref_emd_sd(X + c * M, M, K, S, sd_threshold, R, &n_imfs[c], NULL);
     for (int k = 0; k <= K && rc == 0; ++k)
       memcpy(out + (size_t)k * (size_t)(M * N) + (size_t)(c * M), R + (size_t)k * (size_t)M,
              sizeof(double) * (size_t)M);
@@ -373,6 +386,12 @@ int semd_ref_noise(uint64_t seed, uint64_t item, uint64_t m, int64_t L, double* 
 
 int semd_ref_eemd(const double* X, int64_t M, int64_t N, int64_t D, int K, int S, int NR,
                   double beta, uint64_t seed, uint64_t item, double* out) {
+  return semd_ref_eemd_sd(X, M, N, D, K, S, NR, beta, seed, item, 0.0, out);
+}
+
+int semd_ref_eemd_sd(const double* X, int64_t M, int64_t N, int64_t D, int K, int S, int NR,
+                     double beta, uint64_t seed, uint64_t item, double sd_threshold,
+                     double* out) {
   if (!X || !out || M < 1 || N < 1 || D < 0 || D > M || K < 1 || S < 1 || NR < 1) return -1;
   if (!isfinite(beta)) return -1;
   const int64_t L = semd_ref_serial_length(M, N, D);
@@ -396,7 +415,7 @@ int semd_ref_eemd(const double* X, int64_t M, int64_t N, int64_t D, int K, int S
     }
     /* Step 2: decompose each x_m completely by EMD */
     int nimf = 0;
-    rc = semd_ref_emd(xm, L, K, S, R, &nimf, NULL);
+    rc = semd_ref_emd_sd(xm, L, K, S, sd_threshold, R, &nimf, NULL);
     /* Step 3 (accumulate in realization order, zero slots included) */
     for (size_t i = 0; rc == 0 && i < slot * (size_t)(K + 1); ++i) acc[i] = acc[i] + R[i];
   }

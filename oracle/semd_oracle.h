@@ -59,6 +59,8 @@ typedef struct {
                        /* seen by an extremum test after the very first one   */
   int64_t n_sifts;     /* sifts performed                                      */
   int64_t n_equal;     /* adjacent equal pairs seen after the first test       */
+  double sd_margin;    /* min |num - thr*den| / (thr*den) over the SD tests    */
+                       /* that could end an IMF early (INFINITY if none)      */
 } semd_ref_stats;
 
 /* Sec. 2.1 Steps 1-5 with a fixed number S of sifts per IMF and at most K IMFs.
@@ -89,6 +91,9 @@ int semd_ref_decompose_sd(const double* X, int64_t M, int64_t N, int64_t D, int 
  * no serialization (Sec. 4 opening).  out: (K+1)*M*N; n_imfs: N ints. */
 int semd_ref_decompose_slices(const double* X, int64_t M, int64_t N, int K, int S,
                               double* out, int* n_imfs);
+/* The same with the SD stopping rule of semd_ref_emd_sd. */
+int semd_ref_decompose_slices_sd(const double* X, int64_t M, int64_t N, int K, int S,
+                                 double sd_threshold, double* out, int* n_imfs);
 
 /* SplitMix64 (Steele, Lea & Flood 2014): the n-th output (n >= 1) of the
  * generator whose state starts at `state`. */
@@ -103,6 +108,10 @@ int semd_ref_noise(uint64_t seed, uint64_t item, uint64_t m, int64_t L, double* 
  * out: (K+1)*M*N doubles (mean IMFs, mean residue in slot K). */
 int semd_ref_eemd(const double* X, int64_t M, int64_t N, int64_t D, int K, int S, int NR,
                   double beta, uint64_t seed, uint64_t item, double* out);
+/* The same with the SD stopping rule of semd_ref_emd_sd in every realization. */
+int semd_ref_eemd_sd(const double* X, int64_t M, int64_t N, int64_t D, int K, int S, int NR,
+                     double beta, uint64_t seed, uint64_t item, double sd_threshold,
+                     double* out);
 
 #ifdef __cplusplus
 }

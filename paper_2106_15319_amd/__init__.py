@@ -34,6 +34,8 @@ SEMD_BOUNDARY_MIRROR = 0
 SEMD_PATH_AUTO = 0
 SEMD_PATH_ONCHIP = 1
 SEMD_PATH_STREAM = 2
+SEMD_STOP_FIXED = 0
+SEMD_STOP_SD = 1
 
 
 class SemdError(RuntimeError):
@@ -45,7 +47,8 @@ class SemdError(RuntimeError):
 class semd_params(C.Structure):
     _fields_ = [("transition_len", C.c_int32), ("max_imfs", C.c_int32),
                 ("sift_iters", C.c_int32), ("boundary_rule", C.c_int32),
-                ("ensemble", C.c_int32), ("path", C.c_int32), ("seed", C.c_uint64)]
+                ("ensemble", C.c_int32), ("path", C.c_int32), ("seed", C.c_uint64),
+                ("stop_rule", C.c_int32), ("reserved", C.c_int32), ("sd_threshold", C.c_double)]
 
 
 class semd_item(C.Structure):
@@ -146,9 +149,13 @@ def _dims(dims: Sequence[int]):
 
 
 def _params(D: int, K: int, S: int, NR: int = 1, seed: int = 0,
-            boundary_rule: int = SEMD_BOUNDARY_MIRROR, path: int = SEMD_PATH_AUTO) -> semd_params:
+            boundary_rule: int = SEMD_BOUNDARY_MIRROR, path: int = SEMD_PATH_AUTO,
+            sd: float = 0.0) -> semd_params:
+    """sd > 0 selects the SD stopping rule with that threshold; 0 the fixed
+    sift count."""
+    rule = SEMD_STOP_SD if sd > 0 else SEMD_STOP_FIXED
     return semd_params(int(D), int(K), int(S), int(boundary_rule), int(NR), int(path),
-                       int(seed) & (2**64 - 1))
+                       int(seed) & (2**64 - 1), rule, 0, float(sd))
 
 
 # ---------------------------------------------------------------------------
@@ -226,8 +233,9 @@ def semd_decompose(signal: torch.Tensor, dims: Sequence[int], max_imfs: int, sif
 def semd_decompose_ex(signal: torch.Tensor, dims: Sequence[int], D: int, max_imfs: int,
                       sift_iters: int, imfs_out: torch.Tensor | None = None,
                       n_imfs_out: torch.Tensor | None = None, stream=None,
-                      path: int = SEMD_PATH_AUTO):
-    """Plain path: one signal per launch.  Returns (imfs_out, n_imfs_out)."""
+                      path: int = SEMD_PATH_AUTO, sd: float = 0.0):
+    """Plain path: one signal per launch.  Returns (imfs_out, n_imfs_out).
+    sd > 0: SD stopping rule with that threshold."""
     d, nd = _dims(dims)
     MN = 1
     for v in dims:
@@ -237,7 +245,7 @@ def semd_decompose_ex(signal: torch.Tensor, dims: Sequence[int], D: int, max_imf
         imfs_out = torch.empty((max_imfs + 1, MN), dtype=torch.float64, device=dev)
     if n_imfs_out is None:
         n_imfs_out = torch.empty(1, dtype=torch.int32, device=dev)
-    p = _params(D, max_imfs, sift_iters, path=path)
+    p = _params(D, max_imfs, sift_iters, path=path, sd=sd)
     _check(lib().semd_decompose_ex(_dev_f64(signal, "signal"), d, nd, C.byref(p),
                                    _dev_f64(imfs_out, "imfs_out"), n_imfs_out.data_ptr(),
                                    _stream(stream)), "semd_decompose_ex")
@@ -247,7 +255,7 @@ def semd_decompose_ex(signal: torch.Tensor, dims: Sequence[int], D: int, max_imf
 def semd_decompose_slices(signal: torch.Tensor, dims: Sequence[int], max_imfs: int,
                           sift_iters: int, imfs_out: torch.Tensor | None = None,
                           n_imfs_out: torch.Tensor | None = None, stream=None,
-                          path: int = SEMD_PATH_AUTO):
+                          path: int = SEMD_PATH_AUTO, sd: float = 0.0):
     """Standard (slice-wise) EMD: every column decomposed on its own.
     Returns (imfs_out (K+1, M*N), n_imfs_out (N,))."""
     d, nd = _dims(dims)
@@ -260,7 +268,7 @@ def semd_decompose_slices(signal: torch.Tensor, dims: Sequence[int], max_imfs: i
         imfs_out = torch.empty((max_imfs + 1, M * N), dtype=torch.float64, device=dev)
     if n_imfs_out is None:
         n_imfs_out = torch.empty(N, dtype=torch.int32, device=dev)
-    p = _params(0, max_imfs, sift_iters, path=path)
+    p = _params(0, max_imfs, sift_iters, path=path, sd=sd)
     _check(lib().semd_decompose_slices(_dev_f64(signal, "signal"), d, nd, C.byref(p),
                                        _dev_f64(imfs_out, "imfs_out"), n_imfs_out.data_ptr(),
                                        _stream(stream)), "semd_decompose_slices")
@@ -291,14 +299,14 @@ def _items(signals, dims_list, outs, counts, sigmas=None, item_ids=None, stats=N
 def semd_decompose_batch(signals: Sequence[torch.Tensor], dims_list: Sequence[Sequence[int]],
                          outs: Sequence[torch.Tensor], counts: torch.Tensor | None, D: int,
                          max_imfs: int, sift_iters: int, stats: torch.Tensor | None = None,
-                         stream=None, path: int = SEMD_PATH_AUTO) -> None:
+                         stream=None, path: int = SEMD_PATH_AUTO, sd: float = 0.0) -> None:
     """Batched path: every signal in one launch.  counts: int32 tensor of
     len(signals) entries (or None); stats: int64 tensor (len(signals), 3) of
     (sifts, knots, sample-sifts) per signal (or None)."""
     cviews = [counts[i:i + 1] for i in range(len(signals))] if counts is not None else None
     sviews = [stats[i] for i in range(len(signals))] if stats is not None else None
     arr, n = _items(signals, dims_list, outs, cviews, stats=sviews)
-    p = _params(D, max_imfs, sift_iters, path=path)
+    p = _params(D, max_imfs, sift_iters, path=path, sd=sd)
     _check(lib().semd_decompose_batch(arr, n, C.byref(p), _stream(stream)),
            "semd_decompose_batch")
 
@@ -307,11 +315,11 @@ def semd_eemd_batch(signals: Sequence[torch.Tensor], dims_list: Sequence[Sequenc
                     outs: Sequence[torch.Tensor], counts: torch.Tensor | None, D: int,
                     max_imfs: int, sift_iters: int, ensemble: int, seed: int,
                     noise_sigmas: Sequence[float], item_ids: Sequence[int] | None = None,
-                    stream=None, path: int = SEMD_PATH_AUTO) -> None:
+                    stream=None, path: int = SEMD_PATH_AUTO, sd: float = 0.0) -> None:
     """Serial-EEMD of every signal (NR = ensemble realizations each)."""
     cviews = [counts[i:i + 1] for i in range(len(signals))] if counts is not None else None
     arr, n = _items(signals, dims_list, outs, cviews, noise_sigmas, item_ids)
-    p = _params(D, max_imfs, sift_iters, ensemble, seed, path=path)
+    p = _params(D, max_imfs, sift_iters, ensemble, seed, path=path, sd=sd)
     _check(lib().semd_eemd_batch(arr, n, C.byref(p), _stream(stream)), "semd_eemd_batch")
 
 
@@ -366,19 +374,19 @@ def semd_noise(seed: int, item: int, m: int, L: int, w: torch.Tensor | None = No
 # ---------------------------------------------------------------------------
 
 def decompose(X: torch.Tensor, M: int, N: int, D: int, K: int, S: int, stream=None,
-              path: int = SEMD_PATH_AUTO):
+              path: int = SEMD_PATH_AUTO, sd: float = 0.0):
     """Serial-EMD of one column-major M x N signal set (plain path)."""
-    return semd_decompose_ex(X, [M, N], D, K, S, stream=stream, path=path)
+    return semd_decompose_ex(X, [M, N], D, K, S, stream=stream, path=path, sd=sd)
 
 
 def decompose_batch(Xs: Sequence[torch.Tensor], shapes: Sequence[tuple[int, int]], D: int, K: int,
-                    S: int, stream=None, path: int = SEMD_PATH_AUTO):
+                    S: int, stream=None, path: int = SEMD_PATH_AUTO, sd: float = 0.0):
     """Serial-EMD of many signal sets in one launch; returns (outs, counts)."""
     dev = Xs[0].device
     outs = [torch.empty((K + 1, M * N), dtype=torch.float64, device=dev) for (M, N) in shapes]
     counts = torch.empty(len(Xs), dtype=torch.int32, device=dev)
     semd_decompose_batch(Xs, [list(s) for s in shapes], outs, counts, D, K, S, stream=stream,
-                         path=path)
+                         path=path, sd=sd)
     return outs, counts
 
 
@@ -389,13 +397,13 @@ class PreparedBatch:
 
     def __init__(self, signals, dims_list, outs, counts=None, D=0, max_imfs=8, sift_iters=10,
                  stats=None, ensemble=1, seed=0, noise_sigmas=None, item_ids=None,
-                 path=SEMD_PATH_AUTO):
+                 path=SEMD_PATH_AUTO, sd=0.0):
         cviews = [counts[i:i + 1] for i in range(len(signals))] if counts is not None else None
         sviews = [stats[i] for i in range(len(signals))] if stats is not None else None
         self._keep = (list(signals), list(outs), counts, stats)
         self.items, self.n = _items(signals, dims_list, outs, cviews, noise_sigmas, item_ids,
                                     sviews)
-        self.params = _params(D, max_imfs, sift_iters, ensemble, seed, path=path)
+        self.params = _params(D, max_imfs, sift_iters, ensemble, seed, path=path, sd=sd)
         self.eemd = ensemble > 1 or noise_sigmas is not None
 
     def run(self, stream=None) -> None:
@@ -435,11 +443,12 @@ class Engine:
         return int(b.value)
 
     def admit(self, signal: torch.Tensor, dims: Sequence[int], out: torch.Tensor,
-              n_imfs: torch.Tensor | None, D: int, K: int, S: int) -> int | None:
+              n_imfs: torch.Tensor | None, D: int, K: int, S: int,
+              sd: float = 0.0) -> int | None:
         """Ticket of the admitted request, or None when it does not fit now."""
         arr, _ = _items([signal], [dims], [out],
                         [n_imfs] if n_imfs is not None else None)
-        p = _params(D, K, S)
+        p = _params(D, K, S, sd=sd)
         t = C.c_int64()
         rc = lib().semd_engine_admit(self._h, arr, C.byref(p), C.byref(t))
         if rc == SEMD_EBUSY:

@@ -66,7 +66,17 @@ int check_params(const semd_params* p, bool ensemble) {
   if (p->path < SEMD_PATH_AUTO || p->path > SEMD_PATH_STREAM)
     return fail(SEMD_EINVAL, "unknown path %d", p->path);
   if (ensemble && p->ensemble < 1) return fail(SEMD_EINVAL, "ensemble must be >= 1");
+  if (p->stop_rule != SEMD_STOP_FIXED && p->stop_rule != SEMD_STOP_SD)
+    return fail(SEMD_EINVAL, "unknown stop_rule %d", p->stop_rule);
+  if (p->stop_rule == SEMD_STOP_SD && !(p->sd_threshold > 0.0 && std::isfinite(p->sd_threshold)))
+    return fail(SEMD_EINVAL, "sd_threshold must be positive and finite");
+  if (p->reserved != 0) return fail(SEMD_EINVAL, "params.reserved must be 0");
   return SEMD_OK;
+}
+
+// The SD threshold a validated params set asks for (0: fixed sift count).
+double sd_of(const semd_params* p) {
+  return p->stop_rule == SEMD_STOP_SD ? p->sd_threshold : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -372,6 +382,7 @@ semd::StreamSig stream_sig(const semd::WorkItem& w, int K, int S, unsigned char*
   g.key = w.key;
   g.flags = w.flags;
   g.slot_stride = w.slot_stride;
+  g.sd = w.sd;
   g.ntiles = (w.L + semd::kTile - 1) / semd::kTile;
   g.K = K;
   g.S = S;
@@ -499,7 +510,7 @@ int run_work(std::vector<semd::WorkItem>& work, int K, int S, int path, hipStrea
 }
 
 semd::WorkItem make_work(const double* X, double* out, int32_t* n_imfs, const Shape& sh, int D,
-                         int64_t* stats = nullptr) {
+                         double sd, int64_t* stats = nullptr) {
   semd::WorkItem w{};
   w.X = X;
   w.out = out;
@@ -510,6 +521,7 @@ semd::WorkItem make_work(const double* X, double* out, int32_t* n_imfs, const Sh
   w.D = D;
   w.L = (int32_t)sh.L;
   w.slot_stride = sh.M * sh.N;
+  w.sd = sd;
   return w;
 }
 
@@ -596,7 +608,7 @@ int semd_autotune(int64_t max_length, int batch, hipStream_t stream) {
       std::vector<semd::WorkItem> work;
       Shape sh{L, 1, L};
       for (int i = 0; i < n; ++i)
-        work.push_back(make_work(X + i * L, out + i * L * (K + 1), nullptr, sh, 0));
+        work.push_back(make_work(X + i * L, out + i * L * (K + 1), nullptr, sh, 0, 0.0));
       hipError_t he = semd::launch_synth(X, L, n, 2106, stream);
       float best_ms = 0.0f;
       semd::ResidentClass best{0, 0};
@@ -729,7 +741,8 @@ int semd_decompose_ex(const double* signal, const int64_t* dims, int ndim, const
   if (rc) return rc;
   rc = check_length(sh.L, p->path, 0);
   if (rc) return rc;
-  std::vector<semd::WorkItem> work{make_work(signal, imfs_out, n_imfs_out, sh, p->transition_len)};
+  std::vector<semd::WorkItem> work{make_work(signal, imfs_out, n_imfs_out, sh, p->transition_len,
+                                               sd_of(p))};
   return run_work(work, p->max_imfs, p->sift_iters, p->path, stream);
 }
 
@@ -755,7 +768,7 @@ int semd_decompose_slices(const double* signal, const int64_t* dims, int ndim,
   work.reserve((size_t)N);
   for (int64_t i = 0; i < N; ++i) {
     semd::WorkItem w = make_work(signal + i * M, imfs_out + i * M,
-                                 n_imfs_out ? n_imfs_out + i : nullptr, col, 0);
+                                 n_imfs_out ? n_imfs_out + i : nullptr, col, 0, sd_of(p));
     w.slot_stride = M * N;
     work.push_back(w);
   }
@@ -789,7 +802,7 @@ int semd_decompose_batch(const semd_item* items, int n, const semd_params* p,
   work.reserve(n);
   for (int i = 0; i < n; ++i)
     work.push_back(make_work(items[i].signal, items[i].imfs_out, items[i].n_imfs_out, shapes[i],
-                             p->transition_len, items[i].stats_out));
+                             p->transition_len, sd_of(p), items[i].stats_out));
   return run_work(work, p->max_imfs, p->sift_iters, p->path, stream);
 }
 
@@ -840,7 +853,7 @@ int semd_eemd_batch(const semd_item* items, int n, const semd_params* p, hipStre
       for (int m = 0; m < NR; ++m) {
         semd::WorkItem w = make_work(items[i].signal, buf + so + (size_t)m * per,
                                      cnt + (size_t)(i - i0) * NR + m, shapes[i],
-                                     p->transition_len);
+                                     p->transition_len, sd_of(p));
         w.beta = items[i].noise_sigma;
         w.key = semd::noise_key(p->seed, items[i].item_id, (uint64_t)m);
         w.flags = 1;
@@ -1067,7 +1080,7 @@ int semd_engine_admit(semd_engine* e, const semd_item* item, const semd_params* 
   if (e->alloc(bytes, &off))
     return fail(SEMD_EBUSY, "request needs %zu bytes, not free in the engine budget", bytes);
   semd::WorkItem w = make_work(item->signal, item->imfs_out, item->n_imfs_out, sh,
-                               p->transition_len, item->stats_out);
+                               p->transition_len, sd_of(p), item->stats_out);
   semd_engine::Req r{};
   r.ticket = e->next_ticket++;
   r.sig = stream_sig(w, p->max_imfs, p->sift_iters, e->arena + off);

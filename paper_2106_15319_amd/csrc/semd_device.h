@@ -84,6 +84,32 @@ __device__ __forceinline__ int block_excl_sum(int v, int* wagg, int lane, int wi
   return before + inc - v;
 }
 
+// Block-wide sums of two doubles per thread (wave shuffles, then the wave
+// sums through LDS, 2*NW doubles, added in wave order so every thread gets
+// the same totals).  Contains one barrier; wsum must not be in use.
+template <int NW>
+__device__ __forceinline__ void block_sum2(double a, double b, double* wsum, int lane, int wid,
+                                           double& ta, double& tb) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    a += __shfl_xor(a, d, kWave);
+    b += __shfl_xor(b, d, kWave);
+  }
+  if (lane == 0) {
+    wsum[2 * wid] = a;
+    wsum[2 * wid + 1] = b;
+  }
+  __syncthreads();
+  double sa = 0.0, sb = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    sa += wsum[2 * w];
+    sb += wsum[2 * w + 1];
+  }
+  ta = sa;
+  tb = sb;
+}
+
 // 1/x for positive normal x: the hardware reciprocal estimate refined by two
 // Newton-Raphson steps r <- r + r (1 - x r); within an ulp of 1/x.
 __device__ __forceinline__ double recip(double x) {

@@ -26,6 +26,7 @@ struct WorkItem {
   int32_t flags;     // bit 0: add beta * noise to the serialized signal
   int32_t pad;
   int64_t slot_stride;  // doubles from one output slot to the next (M*N when contiguous)
+  double sd;         // SD stopping threshold; 0: fixed sift count
 };
 
 // Longest serialized signal the resident kernel handles (threads x samples

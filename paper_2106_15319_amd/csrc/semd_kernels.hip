@@ -474,13 +474,14 @@ __device__ __forceinline__ void build_envelope(const double (&h)[C], unsigned bi
 }
 
 // One sift with both envelopes in one knot store: build, then evaluate both
-// walkers per sample and subtract the mean (Sec. 2.1 Steps 2-4).
+// walkers per sample and subtract the mean (Sec. 2.1 Steps 2-4).  Adds the
+// thread's sums of m^2 and of the candidate's h^2 before the sift to num, den.
 template <int NT, int C>
 __device__ __forceinline__ void sift_both(double (&h)[C], unsigned maxbits, unsigned minbits,
                                           unsigned NE, int carry, int base, int nv, int L,
                                           int emax, int nmax, int pmax, int emin, int nmin,
                                           int pmin, const Knots ks, int nkmax, int nkmin,
-                                          int tid) {
+                                          int tid, double& num, double& den) {
   rd_emit_both<C>(h, maxbits, minbits, NE, carry, base, L, emax, nmax, emin, nmin, ks,
                   knots_from(ks, nkmax));
   __syncthreads();
@@ -496,7 +497,10 @@ __device__ __forceinline__ void sift_both(double (&h)[C], unsigned maxbits, unsi
         const int k = base + c;
         const double up = walk_at(wu, ks, k);
         const double lo = walk_at(wl, kl, k);
-        h[c] = h[c] - (up + lo);
+        const double m = up + lo;
+        num = fma(m, m, num);
+        den = fma(h[c], h[c], den);
+        h[c] = h[c] - m;
         wu.B += 1.0;
         wl.B += 1.0;
       }
@@ -537,6 +541,7 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
                                                           int K, int S, int area_bytes) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NW = NT / kWave;
+  static_assert(2 * NW * sizeof(double) <= kAggBytes, "wave sums exceed the LDS head");
   const int tid0 = threadIdx.x;
   const WorkItem w = items[blockIdx.x];
   // the resident path holds at most kResidentMaxL samples: 32-bit indices
@@ -621,10 +626,11 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
       n_knots += nkmax + nkmin;
       const bool both_lds = nkmax + nkmin <= capk - 1;
       const bool single = !both_lds && nkmax <= capk - 1 && nkmin <= capk - 1;
+      double num = 0.0, den = 0.0;
       if (both_lds) {
         // both envelopes at once in LDS: one solve, fused evaluation and update
         sift_both<NT, C>(h, maxbits, minbits, NE, carry, base, nv, L, emax, nmax, pmax, emin,
-                         nmin, pmin, lk, nkmax, nkmin, tid);
+                         nmin, pmin, lk, nkmax, nkmin, tid, num, den);
       } else if (single) {
         // one envelope at a time in LDS, the upper one parked in global memory
         build_envelope<NT, C>(h, maxbits, NE, carry, base, L, emax, nmax, lk, nkmax, tid);
@@ -648,7 +654,10 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
           for (int c = 0; c < C; ++c) {
             if (c < nv) {
               const double lo = walk_at(wl, lk, base + c);
-              h[c] = h[c] - (w.u[base + c] + lo);
+              const double m = w.u[base + c] + lo;
+              num = fma(m, m, num);
+              den = fma(h[c], h[c], den);
+              h[c] = h[c] - m;
               wl.B += 1.0;
             }
           }
@@ -656,7 +665,15 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
       } else {
         // both envelopes in the item's global knot store
         sift_both<NT, C>(h, maxbits, minbits, NE, carry, base, nv, L, emax, nmax, pmax, emin,
-                         nmin, pmin, gk, nkmax, nkmin, tid);
+                         nmin, pmin, gk, nkmax, nkmin, tid, num, den);
+      }
+      // SD criterion: the IMF ends after a sift whose mean is small against
+      // the candidate it was removed from (every thread sees the same sums)
+      if (w.sd > 0.0) {
+        double tnum, tden;
+        block_sum2<NW>(num, den, reinterpret_cast<double*>(wagg), tid & (kWave - 1),
+                       tid / kWave, tnum, tden);
+        if (tnum < w.sd * tden) break;
       }
     }
     if (stop) break;

@@ -34,6 +34,8 @@ struct TileInfo {
   int32_t cont_knot;  // bit e: the continued run is an extremum of kind e (scan)
   int32_t pad;
   double cont_y;      // the continued run's value
+  double sd_num;      // sums over the tile's samples of a sift step: m^2
+  double sd_den;      //   and h^2 of the candidate before the sift
 };
 
 // What a step does to a signal (decided by the scan from the current
@@ -42,7 +44,8 @@ enum StepAction : int32_t {
   kIdle = 0,      // finished: nothing
   kSift = 1,      // one sift
   kSiftLast = 2,  // one sift, then the IMF ends
-  kEndImf = 3,    // the candidate is not siftable: the IMF ends without a sift
+  kEndImf = 3,    // the candidate is not siftable, or the last sift met the SD
+                  // criterion: the IMF ends without a sift
   kFinish = 4     // the residue is not siftable (or the input is bad): outputs final
 };
 
@@ -72,6 +75,7 @@ struct StreamSig {
   double beta;
   uint64_t key;
   int64_t slot_stride;  // doubles from one output slot to the next
+  double sd;        // SD stopping threshold; 0: fixed sift count
   int32_t flags;    // bit 0: add beta * noise
   int32_t ntiles;
   int32_t K;        // max IMFs

@@ -362,8 +362,20 @@ __global__ void __launch_bounds__(kTT) st_detect_kernel(const StreamSig* __restr
   record_tile(d, h, a, first_key, cont_exit, cont_pos, cont_y, S, tv.y, scratch64, scratch);
 }
 
+// Ends the current IMF (its candidate is stored by the evaluation); reaching
+// K IMFs finishes the decomposition.
+__device__ __forceinline__ void end_imf(SigStatus* st, int K) {
+  st->slot = st->nimf;
+  st->nimf += 1;
+  st->sift = 0;
+  st->fin = st->nimf >= K;
+  st->action = kEndImf;
+  if (st->fin) st->active = 0;
+}
+
 // One workgroup per signal: carries and ranks across its tiles, knot totals,
-// and the step's action (Sec. 2.1 Step 5 with a fixed sift count):
+// and the step's action (Sec. 2.1 Step 5):
+//   last step's sift met the SD criterion  -> kEndImf
 //   siftable candidate, sift < S-1  -> kSift
 //   siftable candidate, sift = S-1  -> kSiftLast (the IMF ends after it)
 //   not siftable, sift > 0          -> kEndImf   (the candidate is the IMF)
@@ -372,6 +384,7 @@ __global__ void __launch_bounds__(kTT) st_detect_kernel(const StreamSig* __restr
 __global__ void __launch_bounds__(kTT) st_scan_kernel(const StreamSig* __restrict__ sigs) {
   __shared__ int64_t scratch64[kNW];
   __shared__ int scratch[kNW];
+  __shared__ double wsum[2 * kNW];
   const StreamSig& S = sigs[blockIdx.x];
   SigStatus* st = S.st;
   if (!st->active) {
@@ -379,6 +392,20 @@ __global__ void __launch_bounds__(kTT) st_scan_kernel(const StreamSig* __restric
     return;
   }
   const int nt = S.ntiles;
+  if (S.sd > 0.0 && st->action == kSift) {
+    // SD criterion over the whole signal: the tiles' sums of the last sift
+    double num = 0.0, den = 0.0;
+    for (int t = threadIdx.x; t < nt; t += kTT) {
+      num += S.tinfo[t].sd_num;
+      den += S.tinfo[t].sd_den;
+    }
+    double tnum, tden;
+    block_sum2<kNW>(num, den, wsum, threadIdx.x & (kWave - 1), threadIdx.x / kWave, tnum, tden);
+    if (tnum < S.sd * tden) {
+      if (threadIdx.x == 0) end_imf(st, S.K);
+      return;
+    }
+  }
   // input with NaN/Inf: nothing is decomposed
   int bad = 0;
   for (int t = threadIdx.x; t < nt; t += kTT) bad |= S.tinfo[t].bad;
@@ -437,16 +464,13 @@ __global__ void __launch_bounds__(kTT) st_scan_kernel(const StreamSig* __restric
     } else {
       action = st->sift == 0 ? kFinish : kEndImf;
     }
-    if (action == kSift) {
-      st->sift += 1;
-    } else if (action == kFinish) {
-      fin = 1;
-    } else {
-      st->slot = st->nimf;
-      st->nimf += 1;
-      st->sift = 0;
-      fin = st->nimf >= S.K;
+    if (action == kSiftLast || action == kEndImf) {
+      end_imf(st, S.K);
+      st->action = action;
+      return;
     }
+    if (action == kSift) st->sift += 1;
+    else fin = 1;  // kFinish
     st->action = action;
     st->fin = fin;
     if (fin) st->active = 0;
@@ -693,6 +717,7 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
   __shared__ int scratch[kNW];
   __shared__ int64_t scratch64[kNW];
   __shared__ double halo[2];  // the neighbours' edge samples after the sift
+  __shared__ double wsum[2 * kNW];
   __shared__ int cont_exit, cont_pos;
   __shared__ double cont_y;
   const int2 tv = tiles[blockIdx.x];
@@ -736,6 +761,7 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
     }
     if (threadIdx.x == 0) cont_exit = 0;
     __syncthreads();
+    double num = 0.0, den = 0.0;  // the tile's sums for the SD criterion
     if (nv > 0) {
 #pragma unroll
       for (int c = 0; c < kTC; ++c) {
@@ -743,7 +769,10 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
           const int k = k0 + c;
           const double up = st_walk_at(wk[0], S, 0, k);
           const double lo = st_walk_at(wk[1], S, 1, k);
-          tbuf[lb + c] = tbuf[lb + c] - (up + lo);
+          const double m = up + lo, hk = tbuf[lb + c];
+          num = fma(m, m, num);
+          den = fma(hk, hk, den);
+          tbuf[lb + c] = hk - m;
           wk[0].B += 1.0;
           wk[1].B += 1.0;
         }
@@ -758,6 +787,15 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
       }
     }
     if (action == kSift) {
+      if (S.sd > 0.0) {
+        double tnum, tden;
+        block_sum2<kNW>(num, den, wsum, threadIdx.x & (kWave - 1), threadIdx.x / kWave, tnum,
+                        tden);
+        if (threadIdx.x == 0) {
+          S.tinfo[tv.y].sd_num = tnum;
+          S.tinfo[tv.y].sd_den = tden;
+        }
+      }
       // the sifted candidate stays the candidate: its extrema now, while
       // it is on chip (the next step's detection is skipped)
       __syncthreads();

@@ -31,7 +31,7 @@ def test_library_loads_and_exports_every_declared_symbol():
 
 
 def test_abi_version_and_limits():
-    assert semd.semd_abi_version() == 1
+    assert semd.semd_abi_version() == 2
     assert semd.semd_resident_max_length() >= 16384
 
 
@@ -44,7 +44,8 @@ def test_serial_length(M, N, D, want):
 
 def _p(**kw):
     p = semd.semd_params(kw.get("D", 0), kw.get("K", 6), kw.get("S", 10), kw.get("b", 0),
-                         kw.get("NR", 1), kw.get("path", 0), 0)
+                         kw.get("NR", 1), kw.get("path", 0), 0, kw.get("stop", 0),
+                         kw.get("res", 0), kw.get("sd", 0.0))
     return p
 
 
@@ -56,6 +57,12 @@ def _p(**kw):
     (dict(D=-1), [100, 3], semd.SEMD_EINVAL),
     (dict(path=7), [100, 3], semd.SEMD_EINVAL),
     (dict(path=-1), [100, 3], semd.SEMD_EINVAL),
+    (dict(stop=2), [100, 3], semd.SEMD_EINVAL),
+    (dict(stop=semd.SEMD_STOP_SD, sd=0.0), [100, 3], semd.SEMD_EINVAL),
+    (dict(stop=semd.SEMD_STOP_SD, sd=-0.2), [100, 3], semd.SEMD_EINVAL),
+    (dict(stop=semd.SEMD_STOP_SD, sd=float("inf")), [100, 3], semd.SEMD_EINVAL),
+    (dict(stop=semd.SEMD_STOP_SD, sd=float("nan")), [100, 3], semd.SEMD_EINVAL),
+    (dict(res=1), [100, 3], semd.SEMD_EINVAL),
     (dict(), [0, 3], semd.SEMD_EINVAL),
     (dict(), [100, -2], semd.SEMD_EINVAL),
 ])

@@ -400,12 +400,12 @@ def test_stream_eemd_long_signal():
 # serving engine
 # --------------------------------------------------------------------------
 
-def _engine_run(eng, reqs, K, S, D):
+def _engine_run(eng, reqs, K, S, D, sd=0.0):
     outs, tickets = [], {}
     for k, (X, M, N) in enumerate(reqs):
         out = torch.empty((K + 1, M * N), dtype=torch.float64, device=DEV)
         cnt = torch.empty(1, dtype=torch.int32, device=DEV)
-        t = eng.admit(dev(X), (M, N), out, cnt, D, K, S)
+        t = eng.admit(dev(X), (M, N), out, cnt, D, K, S, sd=sd)
         assert t is not None
         tickets[t] = k
         outs.append((out, cnt))
@@ -509,7 +509,7 @@ def test_autotune_round_trip():
         semd.semd_autotune(4096, 256)
         text = semd.semd_tune_get()
         lines = text.splitlines()
-        assert lines[0].startswith("semd-tune 1 gfx")
+        assert lines[0].startswith(f"semd-tune {semd.semd_abi_version()} gfx")
         entries = [l.split() for l in lines[1:]]
         assert {e[0] for e in entries} == {"latency", "throughput"}
         assert {int(e[1]) for e in entries} == {1024, 2048, 3072, 4096}
@@ -560,3 +560,101 @@ def test_slices_equal_single_column_serial():
     b, nb = semd.semd_decompose_ex(dev(it.X), [it.M, 1], 0, 6, 10)
     assert int(host(na)[0]) == int(host(nb)[0])
     assert_same(host(a), host(b), "slices vs serial")
+
+
+# --------------------------------------------------------------------------
+# SD stopping rule
+# --------------------------------------------------------------------------
+
+# An SD test whose ratio lies this close (relative) to the threshold may be
+# decided either way under a different summation order.
+SD_TIE = 1e-9
+
+
+def _check_sd(X, M, N, D, K, S, thr, out, n, ties, stats=None):
+    ref, nr, st = oracle.decompose(X, M, N, D, K, S, with_stats=True, sd=thr)
+    r = compare(out, n, ref, nr, np.abs(X).max(), st["min_gap"])
+    r["tie"] = r["tie"] or st["sd_margin"] < SD_TIE
+    if r["tie"]:
+        ties.append(r)
+    assert_parity(r, f"M={M} N={N} D={D} sd={thr}")
+    if stats is not None and r["ok"]:
+        assert int(stats[0]) == st["n_sifts"]
+    return r, st
+
+
+@pytest.mark.parametrize("path", [ONCHIP, STREAM])
+@pytest.mark.parametrize("thr", [0.3, 0.05, 1e-3])
+def test_sd_rule_matches_oracle(path, thr):
+    items = [workloads.config0()] + workloads.config2(3) + workloads.config1(1, size=64)
+    K, S, D = 8, 30, 20
+    shapes = [(i.M, i.N) for i in items]
+    outs = [torch.empty((K + 1, M * N), dtype=torch.float64, device=DEV) for M, N in shapes]
+    counts = torch.empty(len(items), dtype=torch.int32, device=DEV)
+    stats = torch.empty((len(items), 3), dtype=torch.int64, device=DEV)
+    semd.semd_decompose_batch([dev(i.X) for i in items], [list(s) for s in shapes], outs, counts,
+                              D, K, S, stats=stats, path=path, sd=thr)
+    counts, stats = host(counts), host(stats)
+    ties, early = [], 0
+    for k, i in enumerate(items):
+        r, st = _check_sd(i.X, i.M, i.N, D, K, S, thr, host(outs[k]), int(counts[k]), ties,
+                          stats[k])
+        early += st["n_sifts"] < r["n_gpu"] * S
+    assert len(ties) <= 1
+    assert early >= 1  # the rule ended IMFs before the sift limit
+
+
+def test_sd_rule_stream_equals_onchip_and_engine():
+    K, S, D, thr = 8, 30, 10, 0.05
+    reqs = [(workloads.config2(1)[0].X, 112, 92), (_series(21, 0, 3000, 2), 3000, 2)]
+    eng = semd.Engine(1 << 30, 16)
+    served = _engine_run(eng, reqs, K, S, D, sd=thr)
+    eng.close()
+    for k, (X, M, N) in enumerate(reqs):
+        a, na = semd.semd_decompose_ex(dev(X), [M, N], D, K, S, path=ONCHIP, sd=thr)
+        b, nb = semd.semd_decompose_ex(dev(X), [M, N], D, K, S, path=STREAM, sd=thr)
+        # the engine runs the streaming kernels: the same sums, the same bits
+        assert_same(host(served[k][0]), host(b), "engine vs streaming path")
+        _, st = _check_sd(X, M, N, D, K, S, thr, host(a), int(host(na)[0]), [])
+        if st["sd_margin"] >= SD_TIE:
+            # the two paths solve in different chunkings: equal within rounding
+            assert int(host(na)[0]) == int(host(nb)[0])
+            assert np.abs(host(a) - host(b)).max() <= TOL * np.abs(X).max()
+
+
+@pytest.mark.parametrize("kind", ["white", "alternating"])
+def test_sd_rule_dense_knot_stores(kind):
+    # the densest knot sets: the sift runs from the global knot store
+    L = semd.semd_resident_max_length()
+    k = np.arange(L)
+    if kind == "white":
+        x = np.random.default_rng(78).standard_normal(L)
+    else:
+        x = np.where(k % 2 == 0, 1.0, -1.0) * (1.0 + 0.001 * np.sin(k / 50.0))
+    thr = 0.1
+    for path in (ONCHIP, STREAM):
+        out, n = semd.semd_decompose_ex(dev(x), [L, 1], 0, 3, 8, path=path, sd=thr)
+        _check_sd(x, L, 1, 0, 3, 8, thr, host(out), int(host(n)[0]), [])
+
+
+def test_sd_rule_long_signal_stream():
+    it = workloads.config3_item(5, (20000, 3))
+    K, S, D, thr = 6, 20, 40, 0.2
+    out, n = semd.semd_decompose_ex(dev(it.X), [it.M, it.N], D, K, S, sd=thr)
+    _check_sd(it.X, it.M, it.N, D, K, S, thr, host(out), int(host(n)[0]), [])
+
+
+def test_sd_rule_slices_and_eemd():
+    it = workloads.config0()
+    M, N, K, S, thr = it.M, it.N, 6, 20, 0.2
+    out, n = semd.semd_decompose_slices(dev(it.X), [M, N], K, S, sd=thr)
+    ref, nref = oracle.decompose_slices(it.X, M, N, K, S, sd=thr)
+    assert list(host(n)) == list(nref)
+    assert np.abs(host(out) - ref).max() <= TOL * np.abs(it.X).max()
+    D, NR, seed = 50, 4, 99
+    beta = 0.2 * float(oracle.serialize(it.X, M, N, D).std())
+    eo = torch.empty((K + 1, M * N), dtype=torch.float64, device=DEV)
+    semd.semd_eemd_batch([dev(it.X)], [[M, N]], [eo], None, D, K, S, NR, seed, [beta], [3],
+                         sd=thr)
+    eref = oracle.eemd(it.X, M, N, D, K, S, NR, beta, seed, 3, sd=thr)
+    assert np.abs(host(eo) - eref).max() <= TOL * np.abs(it.X).max()

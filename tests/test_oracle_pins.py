@@ -468,3 +468,40 @@ def test_sd_rule_stops_at_the_first_sift_below_the_threshold():
         out, n = oracle.emd(x, 1, 10, sd=thr)
         assert n == 1
         np.testing.assert_allclose(out[0], hs[stop], rtol=0, atol=1e-12 * np.abs(x).max())
+
+
+def test_sd_margin_reports_the_closest_decision():
+    # the margin of the stopping tests: infinite without the SD rule; with a
+    # threshold placed between two consecutive SD values, the distance of
+    # the nearer one relative to the threshold
+    x = workloads.config0().X[:1000]
+    _, _, st = oracle.emd(x, 1, 10, with_stats=True)
+    assert st["sd_margin"] == float("inf")
+    h = x.copy()
+    sds = []
+    for _ in range(3):
+        h_new, m = _one_sift(h)
+        sds.append(float(np.sum(m * m) / np.sum(h * h)))
+        h = h_new
+    thr = 0.5 * (sds[1] + sds[2])  # the IMF ends after its third sift
+    _, n, st = oracle.emd(x, 1, 10, with_stats=True, sd=thr)
+    assert n == 1 and st["n_sifts"] == 3
+    want = min(abs(s - thr) / thr for s in sds)
+    assert abs(st["sd_margin"] - want) <= 1e-9 * want
+
+
+def test_sd_rule_in_slices_and_ensemble():
+    # slice-wise EMD with the SD rule is the SD-rule EMD of each column; an
+    # ensemble of one noiseless realization is the plain SD-rule decomposition
+    it = workloads.config0()
+    M, N, K, S, thr = it.M, it.N, 6, 10, 0.2
+    out, n = oracle.decompose_slices(it.X, M, N, K, S, sd=thr)
+    for c in range(N):
+        col, nc = oracle.emd(it.X[c * M:(c + 1) * M], K, S, sd=thr)
+        assert n[c] == nc
+        assert out[:, c * M:(c + 1) * M].tobytes() == col.tobytes()
+    ens = oracle.eemd(it.X, M, N, 20, K, S, 1, 0.0, 7, sd=thr)
+    plain, _ = oracle.decompose(it.X, M, N, 20, K, S, sd=thr)
+    assert ens.tobytes() == plain.tobytes()
+    fixed, _ = oracle.decompose(it.X, M, N, 20, K, S)
+    assert plain.tobytes() != fixed.tobytes()  # the rule does stop early here
