@@ -19,6 +19,8 @@ Other workloads (--workload), each printing one line of the same shape:
             ensemble of 64 realizations per series (streaming path)
   serving   the serving mix with Poisson arrivals: continuous-batching
             engine against plain per-request decompositions
+  dsweep    the transition-length sweep of Sec. 4.1 (D = 1..500) on the
+            six-variate pick-up-mask series, fixed and SD stopping rules
 
 Prints one JSON line.
 """
@@ -324,6 +326,99 @@ def run_series(args, semd, torch, workloads):
     return res
 
 
+def run_dsweep(args, semd, torch, workloads):
+    """Transition-length sweep of Sec. 4.1: the six-variate pick-up-mask series
+    (6 x 1000 samples) decomposed on the plain path for D = 1..500 under the
+    fixed sift count (S = 10) and the SD rule (at most 100 sifts per IMF).
+    Per D and rule: latency percentiles over the repeats, the work done, the
+    oracle's time on one host thread, and how far the first two serial IMFs
+    of each variate lie from its slice-wise (standard EMD) IMFs."""
+    dev = torch.device("cuda:0")
+    it = workloads.config5()
+    M, N, K = it.M, it.N, 8
+    X = torch.from_numpy(it.X).to(dev)
+    rules = [("fixed", 10, 0.0), ("sd", 100, args.sd)]
+    Ds = [1, 2, 5, 10, 20, 50, 100, 200, 300, 400, 500]
+    reps = max(args.steps, 1)
+    stream = torch.cuda.current_stream()
+    slices = {}
+    for name, S, sd in rules:
+        so, sn = semd.semd_decompose_slices(X, [M, N], K, S, sd=sd)
+        slices[name] = (so.cpu().numpy(), sn.cpu().numpy())
+    cpu_reps = 0 if args.no_cpu else 10
+    if cpu_reps:
+        import oracle
+        oracle.lib()
+    rows = []
+    for D in Ds:
+        for name, S, sd in rules:
+            out = torch.empty((K + 1, M * N), dtype=torch.float64, device=dev)
+            cnt = torch.empty(1, dtype=torch.int32, device=dev)
+            st = torch.zeros((1, 3), dtype=torch.int64, device=dev)
+            semd.PreparedBatch([X], [[M, N]], [out], cnt, D, K, S, stats=st, sd=sd).run()
+            torch.cuda.synchronize()
+            work = work_stats(st, cnt)
+            for _ in range(max(args.warmup, 1)):
+                semd.semd_decompose_ex(X, [M, N], D, K, S, out, cnt, sd=sd)
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(reps)]
+            for a, b in ev:
+                a.record(stream)
+                semd.semd_decompose_ex(X, [M, N], D, K, S, out, cnt, sd=sd)
+                b.record(stream)
+            torch.cuda.synchronize()
+            lat = [a.elapsed_time(b) for a, b in ev]
+            o = out.cpu().numpy()
+            so = slices[name][0]
+            diffs = []
+            for q in range(2):
+                d = [float(np.linalg.norm(o[q, c * M:(c + 1) * M] - so[q, c * M:(c + 1) * M]) /
+                           max(np.linalg.norm(so[q, c * M:(c + 1) * M]), 1e-300))
+                     for c in range(N)]
+                diffs.append(float(np.mean(d)))
+            row = {"D": D, "rule": name, "L": M * N + D * N - D, "p50_ms": pct(lat, 50),
+                   "p10_ms": pct(lat, 10), "p90_ms": pct(lat, 90), "sifts": work["sifts"],
+                   "n_imfs": int(cnt.cpu()[0]), "imf12_rel_diff_vs_slices": diffs}
+            if cpu_reps:
+                ct = []
+                for _ in range(cpu_reps):
+                    t1 = time.perf_counter()
+                    oracle.decompose(it.X, M, N, D, K, S, sd=sd)
+                    ct.append(1e3 * (time.perf_counter() - t1))
+                row["cpu_ms"] = pct(ct, 50)
+            rows.append(row)
+    head = next(r for r in rows if r["D"] == 200 and r["rule"] == "sd")
+    ms = head["p50_ms"]
+    res = base_record(args, M * N / (ms / 1e3), ms)
+    res["config"] = {"workload": "six-variate pick-up-mask series 6 x 1000 (Sec. 4.1), "
+                                 "transition-length sweep, plain path; value at D=200 "
+                                 "(20 % of the length) under the SD rule",
+                     "M": M, "N": N, "max_imfs": K, "D_values": Ds,
+                     "rules": {"fixed": "S=10 sifts per IMF",
+                               "sd": f"SD < {args.sd}, at most 100 sifts per IMF"},
+                     "repeats": reps}
+    res["sweep"] = rows
+    res["slices"] = {name: [int(v) for v in slices[name][1]] for name, _, _ in rules}
+    # the D=200 SD-rule decomposition on the roofline
+    out = torch.empty((K + 1, M * N), dtype=torch.float64, device=dev)
+    cnt = torch.empty(1, dtype=torch.int32, device=dev)
+    st = torch.zeros((1, 3), dtype=torch.int64, device=dev)
+    semd.PreparedBatch([X], [[M, N]], [out], cnt, 200, K, 100, stats=st, sd=args.sd).run()
+    torch.cuda.synchronize()
+    work = work_stats(st, cnt)
+    res["work"] = work
+    flops = FLOPS_PER_SAMPLE_SIFT * work["sample_sifts"] + FLOPS_PER_KNOT * work["knots"]
+    res["roofline"] = roofline_alu(flops, ms, "resident_emd_kernel (1 workgroup)")
+    res["paper_context"] = {"serial_emd_ms_at_D50": 10.96, "hardware": "i7-6700HQ laptop",
+                            "note": "the paper's stopping rule is not stated"}
+    if cpu_reps:
+        res["cpu_baseline"] = {"value": M * N / (head["cpu_ms"] / 1e3), "unit": "samples/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"median of {cpu_reps} oracle decompositions per "
+                                         "sweep row on one thread; value at D=200, SD rule"}
+    return res
+
+
 def run_textures(args, semd, torch, workloads):
     """64 texture images 128 x 128, one launch per image; batched alongside."""
     dev = torch.device("cuda:0")
@@ -502,8 +597,10 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["faces", "series", "textures", "eemd", "serving"],
+    ap.add_argument("--workload",
+                    choices=["faces", "series", "textures", "eemd", "serving", "dsweep"],
                     default="faces")
+    ap.add_argument("--sd", type=float, default=0.05, help="dsweep: SD stopping threshold")
     ap.add_argument("--batch", type=int, default=1024, help="faces: images per step")
     ap.add_argument("--D", type=int, default=0, help="transition length")
     ap.add_argument("--plain-items", type=int, default=256,
@@ -536,7 +633,7 @@ def main() -> int:
     assert torch.cuda.is_available(), "bench.py needs the HIP device"
     torch.cuda.set_device(0)
     run = {"faces": run_faces, "series": run_series, "textures": run_textures,
-           "eemd": run_eemd, "serving": run_serving}[args.workload]
+           "eemd": run_eemd, "serving": run_serving, "dsweep": run_dsweep}[args.workload]
     res = run(args, semd, torch, workloads)
     print(json.dumps(res), flush=True)
     return 0

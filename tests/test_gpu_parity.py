@@ -658,3 +658,16 @@ def test_sd_rule_slices_and_eemd():
                          sd=thr)
     eref = oracle.eemd(it.X, M, N, D, K, S, NR, beta, seed, 3, sd=thr)
     assert np.abs(host(eo) - eref).max() <= TOL * np.abs(it.X).max()
+
+
+# --------------------------------------------------------------------------
+# transition-length sweep input (Sec. 4.1)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("D", [1, 2, 50, 200, 500, 1000])
+@pytest.mark.parametrize("rule", ["fixed", "sd"])
+def test_mask_series_sweep_matches_oracle(D, rule):
+    it = workloads.config5()
+    K, S, sd = (8, 10, 0.0) if rule == "fixed" else (8, 100, 0.05)
+    out, n = semd.semd_decompose_ex(dev(it.X), [it.M, it.N], D, K, S, sd=sd)
+    _check_sd(it.X, it.M, it.N, D, K, S, sd, host(out), int(host(n)[0]), [])

@@ -16,6 +16,9 @@ Recipes (stand-ins; the paper's own data are not available):
   * texture   -- sum of 3 oriented unit-amplitude gratings with periods 4, 16
                  and 64 px, orientation U[0, pi), phase U[0, 2pi), plus
                  N(0, 0.05^2) (artificial texture images of Sec. 4.2).
+  * mask      -- the six-variate signal of Sec. 4.1: four unit sinusoids
+                 (32, 16, 8, 2 Hz at 1 kHz, zero phase) picked per variate by
+                 the paper's pick-up mask; no noise (the D sweep's input).
   * face-like -- 112 x 92 grey image: 4..8 Gaussian blobs (sigma U[8, 30] px,
                  amplitude U[40, 200]) plus gratings of period 6 and 24 px at
                  12 grey levels each, clipped to [0, 255] and rounded to uint8
@@ -85,6 +88,31 @@ def face_like(rng: np.random.Generator, H: int = 112, W: int = 92) -> np.ndarray
     return np.asfortranarray(img).ravel(order="F")
 
 
+# Which of the four sinusoids (rows: 32, 16, 8, 2 Hz) each of the six variates
+# U..Z holds: the pick-up mask of Sec. 4.1 (8 Hz is common to all).
+PICKUP_MASK = np.array([[1, 1, 0, 1, 0, 0],
+                        [1, 1, 1, 0, 1, 0],
+                        [1, 1, 1, 1, 1, 1],
+                        [1, 0, 1, 1, 0, 1]])
+PICKUP_FREQS_HZ = (32.0, 16.0, 8.0, 2.0)
+
+
+def mask_series(M: int = 1000, fs: float = 1000.0) -> np.ndarray:
+    """The six-variate signal of Sec. 4.1: variate j is the sum of the unit
+    sinusoids sin(2 pi f_i k / fs), k = 0..M-1, over the rows i of column j of
+    the pick-up mask.  M x 6, column-major flat.  (The sampling rate, the
+    amplitudes and the phases are not given in the paper: 1 s at 1 kHz, unit
+    amplitude and zero phase are this recipe's choice.)"""
+    k = np.arange(M, dtype=np.float64)
+    X = np.zeros((M, PICKUP_MASK.shape[1]), dtype=np.float64, order="F")
+    for i, f in enumerate(PICKUP_FREQS_HZ):
+        wave = np.sin(2 * math.pi * f * k / fs)
+        for j in range(PICKUP_MASK.shape[1]):
+            if PICKUP_MASK[i, j]:
+                X[:, j] += wave
+    return X.ravel(order="F")
+
+
 @dataclass
 class Item:
     X: np.ndarray  # column-major flat M*N float64
@@ -95,6 +123,12 @@ class Item:
 def config0() -> Item:
     """One 3-channel series, 1000 samples per channel."""
     return Item(series(rng_for(0), 3, 1000), 1000, 3)
+
+
+def config5() -> Item:
+    """The six-variate pick-up-mask series of Sec. 4.1 (1000 samples each),
+    the input of the transition-length sweep."""
+    return Item(mask_series(1000), 1000, 6)
 
 
 def config1(n: int = 64, size: int = 128) -> list[Item]:
