@@ -25,7 +25,6 @@ namespace {
 
 using namespace dev;
 
-constexpr int kAggBytes = 256;
 
 // ---------------------------------------------------------------------------
 // Resident-path building blocks (blocked layout: thread t owns the C samples
@@ -35,25 +34,18 @@ constexpr int kAggBytes = 256;
 // Knot store of the envelopes of one sift.  Knot j holds abscissa t_j, value
 // y_j and spline second derivative m_j; once the derivatives are known, q1_j
 // and q3_j hold the linear and cubic coefficients of segment [t_j, t_{j+1})
-// in the power form used by the walker (seg_coeffs).  34 bytes per knot.
+// in the power form used by the walker (solve_envelopes).  34 bytes per knot.
 struct Knots {
   double* y;
   double* m;
   double* q1;
   double* q3;
   int16_t* t;
-  double* trash_m;  // entries of m and q1 no knot uses: targets of discarded stores
-  double* trash_q;
 };
 
 constexpr int kKnotBytes = 4 * (int)sizeof(double) + (int)sizeof(int16_t);
 
-// Interior unknowns one thread solves in the resident kernel.  Odd, so that
-// the lanes of a wave, a chunk apart, spread over the LDS banks.
-constexpr int kRChunk = 7;
-
-// A store of cap knots in the region p; its last entry is reserved (the
-// discard target), so it holds systems of at most cap - 1 knots.
+// A store of cap knots in the region p.
 __device__ __forceinline__ Knots knots_in(unsigned char* p, int cap) {
   Knots s;
   s.y = reinterpret_cast<double*>(p);
@@ -61,8 +53,6 @@ __device__ __forceinline__ Knots knots_in(unsigned char* p, int cap) {
   s.q1 = s.m + cap;
   s.q3 = s.q1 + cap;
   s.t = reinterpret_cast<int16_t*>(s.q3 + cap);
-  s.trash_m = s.m + (cap - 1);
-  s.trash_q = s.q1 + (cap - 1);
   return s;
 }
 
@@ -73,8 +63,6 @@ __device__ __forceinline__ Knots knots_from(const Knots& a, int o) {
   s.q1 = a.q1 + o;
   s.q3 = a.q3 + o;
   s.t = a.t + o;
-  s.trash_m = a.trash_m;
-  s.trash_q = a.trash_q;
   return s;
 }
 
@@ -206,175 +194,256 @@ __device__ __forceinline__ void rd_emit(const double (&h)[C], unsigned bits, uns
   }
 }
 
-// Right-hand sides of the natural-spline equations (Sec. 2.1 Step 2) of up
-// to two knot systems (n1 knots at offset 0, n2 at offset o2): for every
-// interior row j,
-//   g_{j-1} m_{j-1} + 2 (g_{j-1} + g_j) m_j + g_j m_{j+1}
-//       = 6 ((y_{j+1} - y_j) / g_j - (y_j - y_{j-1}) / g_{j-1}),
-// stored in q3 (unused until the segment coefficients are formed), one row
-// per thread.
-template <int NT>
-__device__ __forceinline__ void rd_rhs(const Knots ks, int n1, int o2, int n2, int tid) {
-  const int r1 = n1 > 2 ? n1 - 2 : 0, r2 = n2 > 2 ? n2 - 2 : 0;
-  for (int i = tid; i < r1 + r2; i += NT) {
-    const int j = i < r1 ? 1 + i : o2 + 1 + (i - r1);
-    const int tm = ks.t[j - 1], t0 = ks.t[j], tp = ks.t[j + 1];
-    const double ym = ks.y[j - 1], y0 = ks.y[j], yp = ks.y[j + 1];
-    const double s0 = (y0 - ym) * recip((double)(t0 - tm));
-    const double s1 = (yp - y0) * recip((double)(tp - t0));
-    ks.q3[j] = 6.0 * (s1 - s0);
+// ---------------------------------------------------------------------------
+// Natural-spline second derivatives and segment coefficients (Sec. 2.1
+// Step 2) by two block-wide scans
+// ---------------------------------------------------------------------------
+//
+// The knots of the sift's systems are taken as one sequence of rows k.  The
+// first and last knot of each system read M_k = 0 (the natural end
+// conditions); every other row reads
+//   a M_{k-1} + b M_k + c M_{k+1} = r,
+//   a = t_k - t_{k-1}, c = t_{k+1} - t_k, b = 2 (a + c),
+//   r = 6 ((y_{k+1} - y_k) / c - (y_k - y_{k-1}) / a).
+// Forward elimination leaves row k as M_k + c'_k M_{k+1} = d'_k.  In
+// homogeneous form (c'_k = P_k / Q_k, d'_k = D_k / Q_k) one row is the
+// linear map
+//   Q' = b Q - a P,  P' = c Q,  D' = r Q - a D,
+// and a end row the map (Q, 0, 0), which forgets the system before it.  The
+// maps of consecutive rows compose associatively, so the forward
+// elimination of all rows is a block-wide scan of 3x3 maps of the shape
+// [[A, 0], [v^T, s]] (A 2x2), applied to (1, 0, 0).  Back-substitution,
+// M_k = d'_k - c'_k M_{k+1}, is a scan of affine maps run from the end.  The
+// result is the exact tridiagonal solution (no truncated coupling); scaling
+// the homogeneous quantities by powers of two changes no ratio, so they are
+// renormalized exactly wherever they could leave the exponent range.
+
+// One forward map, x -> (a00 Q + a01 P, a10 Q + a11 P, v0 Q + v1 P + s D).
+struct FwdMap {
+  double a00, a01, a10, a11, v0, v1, s;
+};
+
+__device__ __forceinline__ FwdMap fwd_identity() { return {1.0, 0.0, 0.0, 1.0, 0.0, 0.0, 1.0}; }
+
+// X after Y.
+__device__ __forceinline__ FwdMap fwd_compose(const FwdMap& X, const FwdMap& Y) {
+  FwdMap Z;
+  Z.a00 = fma(X.a00, Y.a00, X.a01 * Y.a10);
+  Z.a01 = fma(X.a00, Y.a01, X.a01 * Y.a11);
+  Z.a10 = fma(X.a10, Y.a00, X.a11 * Y.a10);
+  Z.a11 = fma(X.a10, Y.a01, X.a11 * Y.a11);
+  Z.v0 = fma(X.v0, Y.a00, fma(X.v1, Y.a10, X.s * Y.v0));
+  Z.v1 = fma(X.v0, Y.a01, fma(X.v1, Y.a11, X.s * Y.v1));
+  Z.s = X.s * Y.s;
+  return Z;
+}
+
+// Row k's map after X: a cheaper compose for the sparse row map.
+__device__ __forceinline__ FwdMap fwd_row_after(double a, double b, double c, double r,
+                                                const FwdMap& X) {
+  FwdMap Z;
+  Z.a00 = fma(b, X.a00, -a * X.a10);
+  Z.a01 = fma(b, X.a01, -a * X.a11);
+  Z.a10 = c * X.a00;
+  Z.a11 = c * X.a01;
+  Z.v0 = fma(r, X.a00, -a * X.v0);
+  Z.v1 = fma(r, X.a01, -a * X.v1);
+  Z.s = -a * X.s;
+  return Z;
+}
+
+// Exact rescaling by a power of two bringing |A| near 1.
+__device__ __forceinline__ void fwd_normalize(FwdMap& X) {
+  const int ex = __builtin_amdgcn_frexp_exp(fabs(X.a00) + fabs(X.a01) + fabs(X.a10) +
+                                            fabs(X.a11));
+  X.a00 = __builtin_amdgcn_ldexp(X.a00, -ex);
+  X.a01 = __builtin_amdgcn_ldexp(X.a01, -ex);
+  X.a10 = __builtin_amdgcn_ldexp(X.a10, -ex);
+  X.a11 = __builtin_amdgcn_ldexp(X.a11, -ex);
+  X.v0 = __builtin_amdgcn_ldexp(X.v0, -ex);
+  X.v1 = __builtin_amdgcn_ldexp(X.v1, -ex);
+  X.s = __builtin_amdgcn_ldexp(X.s, -ex);
+}
+
+__device__ __forceinline__ void fwd_apply(const FwdMap& X, double& Q, double& P, double& D) {
+  const double q = fma(X.a00, Q, X.a01 * P);
+  const double p = fma(X.a10, Q, X.a11 * P);
+  D = fma(X.v0, Q, fma(X.v1, P, X.s * D));
+  Q = q;
+  P = p;
+}
+
+__device__ __forceinline__ void vec_normalize(double& Q, double& P, double& D) {
+  const int ex = __builtin_amdgcn_frexp_exp(Q);  // Q > 0
+  Q = __builtin_amdgcn_ldexp(Q, -ex);
+  P = __builtin_amdgcn_ldexp(P, -ex);
+  D = __builtin_amdgcn_ldexp(D, -ex);
+}
+
+__device__ __forceinline__ FwdMap fwd_shfl_up(const FwdMap& X, int d) {
+  FwdMap Y;
+  Y.a00 = __shfl_up(X.a00, d, kWave);
+  Y.a01 = __shfl_up(X.a01, d, kWave);
+  Y.a10 = __shfl_up(X.a10, d, kWave);
+  Y.a11 = __shfl_up(X.a11, d, kWave);
+  Y.v0 = __shfl_up(X.v0, d, kWave);
+  Y.v1 = __shfl_up(X.v1, d, kWave);
+  Y.s = __shfl_up(X.s, d, kWave);
+  return Y;
+}
+
+// The equation of row k (0 <= k < n1 + n2; the systems are knots [0, n1)
+// and [n1, n1 + n2)): coefficients a, b, c, r, and the slope of segment k
+// (unused on a system's last knot).
+__device__ __forceinline__ void spline_row(const Knots ks, int n1, int n2, int k, double& a,
+                                           double& b, double& c, double& r, double& slope) {
+  const bool first = k == 0 || k == n1;
+  const bool last = k == n1 - 1 || k == n1 + n2 - 1;
+  const int t0 = ks.t[k];
+  const double y0 = ks.y[k];
+  double s0 = 0.0, s1 = 0.0, g0 = 0.0, g1 = 0.0;
+  if (!last) {
+    const int tp = ks.t[k + 1];
+    g1 = (double)(tp - t0);
+    s1 = (ks.y[k + 1] - y0) * recip(g1);
+  }
+  if (!first) {
+    const int tm = ks.t[k - 1];
+    g0 = (double)(t0 - tm);
+    s0 = (y0 - ks.y[k - 1]) * recip(g0);
+  }
+  slope = s1;
+  if (first || last) {
+    a = 0.0; b = 1.0; c = 0.0; r = 0.0;
+  } else {
+    a = g0; c = g1; b = 2.0 * (g0 + g1); r = 6.0 * (s1 - s0);
   }
 }
 
-// One forward Thomas row j (eliminating the sub-diagonal): the row's knot
-// gaps from t_{j-1} < t_j < t_{j+1}, its right-hand side rj.
-__device__ __forceinline__ void thomas_fwd(int tm, int t0, int tp, double rj, double& cp,
-                                           double& dp) {
-  const double g0 = (double)(t0 - tm), g1 = (double)(tp - t0);
-  const double inv = recip(fma(-g0, cp, (double)(2 * (tp - tm))));
-  cp = g1 * inv;
-  dp = fma(-g0, dp, rj) * inv;
-}
+// LDS head layout: block-scan ints and the SD sums (256 B), the forward
+// wave aggregates (7 doubles per wave), the backward ones (2 per wave).
+constexpr int kWaggBytes = 256;
+constexpr int kScanFwdBytes = 7 * 16 * (int)sizeof(double);
+constexpr int kScanBwdBytes = 2 * 16 * (int)sizeof(double);
+constexpr int kAggBytes = kWaggBytes + kScanFwdBytes + kScanBwdBytes;
 
-// One backward Thomas row j (eliminating the super-diagonal).
-__device__ __forceinline__ void thomas_bwd(int tm, int t0, int tp, double rj, double& aa,
-                                           double& dd) {
-  const double g0 = (double)(t0 - tm), g1 = (double)(tp - t0);
-  const double inv = recip(fma(-g1, aa, (double)(2 * (tp - tm))));
-  aa = g0 * inv;
-  dd = fma(-g1, dd, rj) * inv;
-}
-
-// Second derivatives of one chunk of interior unknowns, rows s..e with
-// s = 1 + ch*kRChunk: a forward Thomas sweep from kHalo rows before the chunk
-// and a backward sweep from kHalo rows after it (each started as if the row
-// beyond it did not exist), run side by side and joined at row e, then back-
-// substitution.  Windows that reach the ends of the system are exact; the
-// coupling a window drops is damped by at least (2 - sqrt 3)^kHalo, because
-// the matrix is symmetric with every diagonal twice its row's off-diagonal
-// sum, so the Jacobi-scaled matrix has condition number at most 3 and an
-// inverse whose entries decay geometrically at that rate.  The forward
-// factors of the chunk's rows wait in the knot store (c' in m, d' in q1).
-__device__ __forceinline__ void rd_solve_chunk(const Knots ks, int n, int ch) {
-  const int s = 1 + ch * kRChunk;
-  const int e = min(s + kRChunk - 1, n - 2);
-  const int ws = max(1, s - kHalo);
-  const int we = min(n - 2, e + kHalo);
-  const int nf = e + 1 - ws;                // forward rows ws .. e
-  const int nb = (e < n - 2) ? we - e : 0;  // backward rows we .. e+1
-  double cp = 0.0, dp = 0.0, aa = 0.0, dd = 0.0;
-  // forward: row fj with knots ftm, ft0, ft1; backward: row bj with btm, bt0, btp
-  int fj = ws, ftm = ks.t[ws - 1], ft0 = ks.t[ws], ft1 = ks.t[ws + 1];
-  double fr = ks.q3[ws];
-  int bj = max(we, e + 1), btp = ks.t[min(bj + 1, n - 1)], bt0 = ks.t[min(bj, n - 1)];
-  int btm = ks.t[bj - 1];
-  double br = ks.q3[min(bj, n - 2)];
-  // The chunk's rows keep c' and d' (rows before it are another chunk's:
-  // their factors go to the discard slots, without a branch).
-#define SEMD_FWD_ROW()                                                  \
-  do {                                                                  \
-    const int fn = min(fj + 1, e);                                      \
-    const int ft2 = ks.t[fn + 1];                                       \
-    const double fr2 = ks.q3[fn];                                       \
-    thomas_fwd(ftm, ft0, ft1, fr, cp, dp);                              \
-    const bool keep = fj >= s;                                          \
-    *(keep ? ks.m + fj : ks.trash_m) = cp;                              \
-    *(keep ? ks.q1 + fj : ks.trash_q) = dp;                             \
-    ftm = ft0; ft0 = ft1; ft1 = ft2; fr = fr2; ++fj;                    \
-  } while (0)
-#define SEMD_BWD_ROW()                                                  \
-  do {                                                                  \
-    const int bn = max(bj - 1, e + 1);                                  \
-    const int btm2 = ks.t[bn - 1];                                      \
-    const double br2 = ks.q3[bn];                                       \
-    thomas_bwd(btm, bt0, btp, br, aa, dd);                              \
-    btp = bt0; bt0 = btm; btm = btm2; br = br2; --bj;                   \
-  } while (0)
-  // the longer sweep starts alone, then both run side by side to the join
-  int lead = nf - nb;
-#pragma unroll 1
-  for (; lead > 0; --lead) SEMD_FWD_ROW();
-#pragma unroll 1
-  for (; lead < 0; ++lead) SEMD_BWD_ROW();
-  const int both = min(nf, nb);
-#pragma unroll 1
-  for (int i = 0; i < both; ++i) {
-    // one forward and one backward row, their dependent chains interleaved
-    // operation by operation so that each hides the other's latency
-    const int fn = min(fj + 1, e), bn = max(bj - 1, e + 1);
-    const int ft2 = ks.t[fn + 1], btm2 = ks.t[bn - 1];
-    const double fr2 = ks.q3[fn], br2 = ks.q3[bn];
-    const double fg0 = (double)(ft0 - ftm), fg1 = (double)(ft1 - ft0);
-    const double bg0 = (double)(bt0 - btm), bg1 = (double)(btp - bt0);
-    const double fden = fma(-fg0, cp, (double)(2 * (ft1 - ftm)));
-    const double bden = fma(-bg1, aa, (double)(2 * (btp - btm)));
-    double fi = __builtin_amdgcn_rcp(fden), bi = __builtin_amdgcn_rcp(bden);
-    double fe = fma(-fden, fi, 1.0), be = fma(-bden, bi, 1.0);
-    fi = fma(fi, fe, fi);
-    bi = fma(bi, be, bi);
-    fe = fma(-fden, fi, 1.0);
-    be = fma(-bden, bi, 1.0);
-    fi = fma(fi, fe, fi);
-    bi = fma(bi, be, bi);
-    cp = fg1 * fi;
-    aa = bg0 * bi;
-    dp = fma(-fg0, dp, fr) * fi;
-    dd = fma(-bg1, dd, br) * bi;
-    const bool keep = fj >= s;
-    *(keep ? ks.m + fj : ks.trash_m) = cp;
-    *(keep ? ks.q1 + fj : ks.trash_q) = dp;
-    ftm = ft0; ft0 = ft1; ft1 = ft2; fr = fr2; ++fj;
-    btp = bt0; bt0 = btm; btm = btm2; br = br2; --bj;
-  }
-#undef SEMD_FWD_ROW
-#undef SEMD_BWD_ROW
-  // M_e = d'_e - c'_e M_{e+1} with M_{e+1} = dd - aa M_e from the right, or
-  // M_e = d'_e on the last row (M_{n-1} = 0); then back-substitution
-  double Mn = (e < n - 2) ? fma(-cp, dd, dp) * recip(fma(-cp, aa, 1.0)) : dp;
-  ks.m[e] = Mn;
-#pragma unroll 1
-  for (int j = e - 1; j >= s; --j) {
-    Mn = fma(-ks.m[j], Mn, ks.q1[j]);
-    ks.m[j] = Mn;
-  }
-}
-
-// Second derivatives of up to two knot systems (n1 knots at offset 0, n2 at
-// offset o2; n = 0: none), their chunks spread over the workgroup.  The
-// right-hand sides must be in q3.
-template <int NT>
-__device__ __forceinline__ void rd_solve(const Knots ks, int n1, int o2, int n2, int tid) {
-  const int c1 = n1 >= 3 ? (n1 - 2 + kRChunk - 1) / kRChunk : 0;
-  const int c2 = n2 >= 3 ? (n2 - 2 + kRChunk - 1) / kRChunk : 0;
-  for (int ch = tid; ch < c1 + c2; ch += NT) {
-    const bool second = ch >= c1;
-    rd_solve_chunk(second ? knots_from(ks, o2) : ks, second ? n2 : n1, second ? ch - c1 : ch);
-  }
-  if (tid == 0) {
-    if (n1 >= 3) { ks.m[0] = 0.0; ks.m[n1 - 1] = 0.0; }
-    if (n2 >= 3) { ks.m[o2] = 0.0; ks.m[o2 + n2 - 1] = 0.0; }
-  }
-}
-
-// Power-form coefficients of every segment of up to two knot systems (n1
-// knots at offset 0, n2 at offset o2).  On [t_j, t_{j+1}), with B = k - t_j
-// and g = t_{j+1} - t_j, the natural spline is
-//   y_j + b_j B + (m_j / 2) B^2 + ((m_{j+1} - m_j) / (6 g)) B^3,
-//   b_j = (y_{j+1} - y_j) / g - g (2 m_j + m_{j+1}) / 6;
+// Second derivatives m and segment coefficients q1, q3 of the knot systems
+// [0, n1) and [n1, n1 + n2) (n2 = 0: one system).  On [t_k, t_{k+1}), with
+// B = k' - t_k and g = t_{k+1} - t_k, the natural spline is
+//   y_k + b_k B + (m_k / 2) B^2 + ((m_{k+1} - m_k) / (6 g)) B^3,
+//   b_k = (y_{k+1} - y_k) / g - g (2 m_k + m_{k+1}) / 6;
 // the walker evaluates half of it (the envelope mean is the sum of the two
-// halves), so q1 = b_j / 2 and q3 = (m_{j+1} - m_j) / (12 g) are stored.
+// halves), so q1 = b_k / 2 and q3 = (m_{k+1} - m_k) / (12 g) are stored.
+// Rows go to the threads in blocks of R, over enough waves to keep every
+// SIMD busy.  Contains two barriers and ends with a third.
 template <int NT>
-__device__ __forceinline__ void seg_coeffs(const Knots ks, int n1, int o2, int n2, int tid) {
-  const int s1 = n1 - 1, s2 = n2 > 0 ? n2 - 1 : 0;
-  for (int i = tid; i < s1 + s2; i += NT) {
-    const int j = i < s1 ? i : o2 + (i - s1);
-    const double g = (double)((int)ks.t[j + 1] - (int)ks.t[j]);
-    const double ig = recip(g);
-    const double m0 = ks.m[j], m1 = ks.m[j + 1];
-    const double b = (ks.y[j + 1] - ks.y[j]) * ig - g * fma(2.0, m0, m1) * (1.0 / 6.0);
-    ks.q1[j] = 0.5 * b;
-    ks.q3[j] = (m1 - m0) * ig * (1.0 / 12.0);
+__device__ __forceinline__ void solve_envelopes(const Knots ks, int n1, int n2, int tid,
+                                                double* fwd_lds, double* bwd_lds) {
+  constexpr int NW = NT / kWave;
+  static_assert(NW <= 16, "wave aggregates sized for 16 waves");
+  const int rows = n1 + n2;
+  const int wact = min(NW, max(min(4, NW), (rows + 4 * kWave - 1) / (4 * kWave)));
+  const int R = (rows + wact * kWave - 1) / (wact * kWave);
+  const int lane = tid & (kWave - 1), wid = tid / kWave;
+  const int k0 = tid * R, k1 = min(rows, k0 + R);
+  const bool wave_active = wid < wact;
+
+  // forward: the thread's aggregate, then the in-wave inclusive scan
+  FwdMap G = fwd_identity();
+  if (wave_active) {
+    for (int k = k0; k < k1; ++k) {
+      double a, b, c, r, sl;
+      spline_row(ks, n1, n2, k, a, b, c, r, sl);
+      G = fwd_row_after(a, b, c, r, G);
+      if (((k - k0) & 3) == 3) fwd_normalize(G);
+    }
+    fwd_normalize(G);
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const FwdMap Y = fwd_shfl_up(G, d);
+      if (lane >= d) G = fwd_compose(G, Y);
+    }
+    if (lane == kWave - 1) {
+      double* o = fwd_lds + 7 * wid;
+      o[0] = G.a00; o[1] = G.a01; o[2] = G.a10; o[3] = G.a11;
+      o[4] = G.v0; o[5] = G.v1; o[6] = G.s;
+    }
   }
+  __syncthreads();
+  if (wave_active) {
+    // the state entering the wave, then entering the thread
+    double Q = 1.0, P = 0.0, D = 0.0;
+    for (int w = 0; w < wid; ++w) {
+      const double* o = fwd_lds + 7 * w;
+      const FwdMap X = {o[0], o[1], o[2], o[3], o[4], o[5], o[6]};
+      fwd_apply(X, Q, P, D);
+      vec_normalize(Q, P, D);
+    }
+    const FwdMap Y = fwd_shfl_up(G, 1);
+    if (lane > 0) {
+      fwd_apply(Y, Q, P, D);
+      vec_normalize(Q, P, D);
+    }
+    // each row's c' (into m) and d' (into q1): rows of this thread only
+    for (int k = k0; k < k1; ++k) {
+      double a, b, c, r, sl;
+      spline_row(ks, n1, n2, k, a, b, c, r, sl);
+      const double q = fma(b, Q, -a * P);
+      D = fma(r, Q, -a * D);
+      P = c * Q;
+      Q = q;
+      vec_normalize(Q, P, D);
+      const double iq = recip(Q);
+      ks.m[k] = P * iq;
+      ks.q1[k] = D * iq;
+    }
+  }
+  // backward: M_k = d'_k - c'_k M_{k+1} as maps x -> al + be x, composed
+  // from the thread's last row down, then an in-wave suffix scan
+  double al = 0.0, be = 1.0;
+  if (wave_active) {
+    for (int k = k1 - 1; k >= k0; --k) {
+      const double cp = ks.m[k], dp = ks.q1[k];
+      al = fma(-cp, al, dp);
+      be = -cp * be;
+    }
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const double a2 = __shfl_down(al, d, kWave), b2 = __shfl_down(be, d, kWave);
+      if (lane + d < kWave) {
+        al = fma(be, a2, al);
+        be = be * b2;
+      }
+    }
+    if (lane == 0) {
+      bwd_lds[2 * wid] = al;
+      bwd_lds[2 * wid + 1] = be;
+    }
+  }
+  __syncthreads();
+  if (wave_active) {
+    // M at the first row after the wave, then after the thread
+    double Mn = 0.0;
+    for (int w = wact - 1; w > wid; --w) Mn = fma(bwd_lds[2 * w + 1], Mn, bwd_lds[2 * w]);
+    const double a2 = __shfl_down(al, 1, kWave), b2 = __shfl_down(be, 1, kWave);
+    if (lane + 1 < kWave) Mn = fma(b2, Mn, a2);
+    // second derivatives and segment coefficients of the thread's rows
+    for (int k = k1 - 1; k >= k0; --k) {
+      const double cp = ks.m[k], dp = ks.q1[k];
+      const double Mk = fma(-cp, Mn, dp);
+      const bool last = k == n1 - 1 || k == n1 + n2 - 1;
+      if (!last) {
+        const double g = (double)((int)ks.t[k + 1] - (int)ks.t[k]);
+        const double ig = recip(g);
+        const double bk = (ks.y[k + 1] - ks.y[k]) * ig - g * fma(2.0, Mk, Mn) * (1.0 / 6.0);
+        ks.q1[k] = 0.5 * bk;
+        ks.q3[k] = (Mn - Mk) * ig * (1.0 / 12.0);
+      }
+      ks.m[k] = Mk;
+      Mn = Mk;
+    }
+  }
+  __syncthreads();
 }
 
 // Walker over the segments of one envelope: the current segment [t0, t1),
@@ -451,16 +520,13 @@ __device__ __forceinline__ void rd_emit_both(const double (&h)[C], unsigned maxb
 }
 
 // Second derivatives and segment coefficients of the emitted knot systems
-// (n1 knots at offset 0, n2 at offset n1), with the barriers between the
-// phases; the knots must be complete (a barrier after emission).
+// (n1 knots at offset 0, n2 at offset n1); the knots must be complete (a
+// barrier after emission).  Ends with a barrier.
 template <int NT>
 __device__ __forceinline__ void finish_envelopes(const Knots ks, int nk1, int nk2, int tid) {
-  rd_rhs<NT>(ks, nk1, nk1, nk2, tid);
-  __syncthreads();
-  rd_solve<NT>(ks, nk1, nk1, nk2, tid);
-  __syncthreads();
-  seg_coeffs<NT>(ks, nk1, nk1, nk2, tid);
-  __syncthreads();
+  extern __shared__ __align__(16) unsigned char smem[];
+  solve_envelopes<NT>(ks, nk1, nk2, tid, reinterpret_cast<double*>(smem + kWaggBytes),
+                      reinterpret_cast<double*>(smem + kWaggBytes + kScanFwdBytes));
 }
 
 // One envelope (single-envelope mode): emitted, solved, coefficients formed.
@@ -541,7 +607,7 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
                                                           int K, int S, int area_bytes) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NW = NT / kWave;
-  static_assert(2 * NW * sizeof(double) <= kAggBytes, "wave sums exceed the LDS head");
+  static_assert(2 * NW * sizeof(double) <= kWaggBytes, "wave sums exceed the LDS head");
   const int tid0 = threadIdx.x;
   const WorkItem w = items[blockIdx.x];
   // the resident path holds at most kResidentMaxL samples: 32-bit indices
@@ -552,7 +618,7 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
 
   int* wagg = reinterpret_cast<int*>(smem);
   unsigned char* area = smem + kAggBytes;
-  const int capk = area_bytes / kKnotBytes;  // knots the LDS store can take: capk - 1
+  const int capk = area_bytes / kKnotBytes;  // knots the LDS store can take
   const int scap = (area_bytes / (int)sizeof(double)) / NT * NT;
   double* stage = reinterpret_cast<double*>(area);
   double* pub_first = reinterpret_cast<double*>(area);
@@ -624,8 +690,8 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
       const int nkmax = nmax + 2 * pmax, nkmin = nmin + 2 * pmin;
       ++n_sifts;
       n_knots += nkmax + nkmin;
-      const bool both_lds = nkmax + nkmin <= capk - 1;
-      const bool single = !both_lds && nkmax <= capk - 1 && nkmin <= capk - 1;
+      const bool both_lds = nkmax + nkmin <= capk;
+      const bool single = !both_lds && nkmax <= capk && nkmin <= capk;
       double num = 0.0, den = 0.0;
       if (both_lds) {
         // both envelopes at once in LDS: one solve, fused evaluation and update
