@@ -280,32 +280,62 @@ __device__ __forceinline__ void vec_normalize(double& Q, double& P, double& D) {
   D = __builtin_amdgcn_ldexp(D, -ex);
 }
 
-__device__ __forceinline__ FwdMap fwd_shfl_up(const FwdMap& X, int d) {
-  FwdMap Y;
-  Y.a00 = __shfl_up(X.a00, d, kWave);
-  Y.a01 = __shfl_up(X.a01, d, kWave);
-  Y.a10 = __shfl_up(X.a10, d, kWave);
-  Y.a11 = __shfl_up(X.a11, d, kWave);
-  Y.v0 = __shfl_up(X.v0, d, kWave);
-  Y.v1 = __shfl_up(X.v1, d, kWave);
-  Y.s = __shfl_up(X.s, d, kWave);
-  return Y;
+// A double moved across lanes by a DPP control (each 32-bit half moved the
+// same way); lanes the control gives no source keep 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, ROWS, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ FwdMap fwd_dpp(const FwdMap& X) {
+  return {dpp_move<CTRL, ROWS>(X.a00), dpp_move<CTRL, ROWS>(X.a01), dpp_move<CTRL, ROWS>(X.a10),
+          dpp_move<CTRL, ROWS>(X.a11), dpp_move<CTRL, ROWS>(X.v0),  dpp_move<CTRL, ROWS>(X.v1),
+          dpp_move<CTRL, ROWS>(X.s)};
+}
+
+// DPP controls: shift right by n within each row of 16 lanes; broadcast
+// lane 15 of each row to the next row; lane 31 to rows 2 and 3; shift the
+// whole wave right by one lane.
+constexpr int kDppRowShr = 0x110;
+constexpr int kDppRowBcast15 = 0x142;
+constexpr int kDppRowBcast31 = 0x143;
+constexpr int kDppWaveShr1 = 0x138;
+constexpr int kDppWaveShl1 = 0x130;
+
+// Inclusive scan of the maps over the lanes of a wave (lane l gets the
+// composition of lanes 0..l, later after earlier): Kogge-Stone within each
+// row of 16 lanes, then the row totals broadcast down the wave.
+__device__ __forceinline__ FwdMap fwd_wave_scan(FwdMap G, int lane) {
+  const int i = lane & 15;
+  { const FwdMap Y = fwd_dpp<kDppRowShr + 1, 0xf>(G); if (i >= 1) G = fwd_compose(G, Y); }
+  { const FwdMap Y = fwd_dpp<kDppRowShr + 2, 0xf>(G); if (i >= 2) G = fwd_compose(G, Y); }
+  { const FwdMap Y = fwd_dpp<kDppRowShr + 4, 0xf>(G); if (i >= 4) G = fwd_compose(G, Y); }
+  { const FwdMap Y = fwd_dpp<kDppRowShr + 8, 0xf>(G); if (i >= 8) G = fwd_compose(G, Y); }
+  { const FwdMap Y = fwd_dpp<kDppRowBcast15, 0xa>(G); if (lane & 16) G = fwd_compose(G, Y); }
+  { const FwdMap Y = fwd_dpp<kDppRowBcast31, 0xc>(G); if (lane & 32) G = fwd_compose(G, Y); }
+  return G;
 }
 
 // The equation of row k (0 <= k < n1 + n2; the systems are knots [0, n1)
-// and [n1, n1 + n2)): coefficients a, b, c, r, and the slope of segment k
-// (unused on a system's last knot).
+// and [n1, n1 + n2)): coefficients a, b, c, r, and for segment k (not on a
+// system's last knot) its slope, length g and 1/g.
 __device__ __forceinline__ void spline_row(const Knots ks, int n1, int n2, int k, double& a,
-                                           double& b, double& c, double& r, double& slope) {
+                                           double& b, double& c, double& r, double& slope,
+                                           double& g, double& ig) {
   const bool first = k == 0 || k == n1;
   const bool last = k == n1 - 1 || k == n1 + n2 - 1;
   const int t0 = ks.t[k];
   const double y0 = ks.y[k];
-  double s0 = 0.0, s1 = 0.0, g0 = 0.0, g1 = 0.0;
+  double s0 = 0.0, s1 = 0.0, g0 = 0.0, g1 = 0.0, i1 = 0.0;
   if (!last) {
     const int tp = ks.t[k + 1];
     g1 = (double)(tp - t0);
-    s1 = (ks.y[k + 1] - y0) * recip(g1);
+    i1 = recip(g1);
+    s1 = (ks.y[k + 1] - y0) * i1;
   }
   if (!first) {
     const int tm = ks.t[k - 1];
@@ -313,11 +343,66 @@ __device__ __forceinline__ void spline_row(const Knots ks, int n1, int n2, int k
     s0 = (y0 - ks.y[k - 1]) * recip(g0);
   }
   slope = s1;
+  g = g1;
+  ig = i1;
   if (first || last) {
     a = 0.0; b = 1.0; c = 0.0; r = 0.0;
   } else {
     a = g0; c = g1; b = 2.0 * (g0 + g1); r = 6.0 * (s1 - s0);
   }
+}
+
+// The state (Q, P, D) entering wave wid: the aggregates of waves 0..wid-1
+// applied to (1, 0, 0) in order.
+__device__ __forceinline__ void fwd_enter(const double* fwd_lds, int wid, double& Q, double& P,
+                                          double& D) {
+  Q = 1.0;
+  P = 0.0;
+  D = 0.0;
+  for (int w = 0; w < wid; ++w) {
+    const double* o = fwd_lds + 7 * w;
+    const FwdMap X = {o[0], o[1], o[2], o[3], o[4], o[5], o[6]};
+    fwd_apply(X, Q, P, D);
+    vec_normalize(Q, P, D);
+  }
+}
+
+// Suffix scan of back-substitution maps x -> al + be x over the lanes of a
+// wave (lane l gets lanes l..63 composed, l's map applied last): within
+// each row of 16 lanes by DPP shifts, then the later rows' totals.
+constexpr int kDppRowShl = 0x100;
+__device__ __forceinline__ void bwd_wave_scan(double& al, double& be, int lane) {
+  const int i = lane & 15;
+#define SEMD_BWD_STEP(n)                                                        \
+  {                                                                             \
+    const double a2 = dpp_move<kDppRowShl + n, 0xf>(al);                        \
+    const double b2 = dpp_move<kDppRowShl + n, 0xf>(be);                        \
+    if (i + n < 16) { al = fma(be, a2, al); be = be * b2; }                     \
+  }
+  SEMD_BWD_STEP(1)
+  SEMD_BWD_STEP(2)
+  SEMD_BWD_STEP(4)
+  SEMD_BWD_STEP(8)
+#undef SEMD_BWD_STEP
+  // rows 0..2 take row r+1's total (its lane 0), then rows 0..1 row r+2's
+  const int row = lane >> 4;
+  {
+    const int src = min(row + 1, 3) << 4;
+    const double a2 = __shfl(al, src, kWave), b2 = __shfl(be, src, kWave);
+    if (row < 3) { al = fma(be, a2, al); be = be * b2; }
+  }
+  {
+    const int src = min(row + 2, 3) << 4;
+    const double a2 = __shfl(al, src, kWave), b2 = __shfl(be, src, kWave);
+    if (row < 2) { al = fma(be, a2, al); be = be * b2; }
+  }
+}
+
+// M at the first row after wave wid: the later waves' maps applied to 0.
+__device__ __forceinline__ double bwd_after(const double* bwd_lds, int wid, int wact) {
+  double Mn = 0.0;
+  for (int w = wact - 1; w > wid; --w) Mn = fma(bwd_lds[2 * w + 1], Mn, bwd_lds[2 * w]);
+  return Mn;
 }
 
 // LDS head layout: block-scan ints and the SD sums (256 B), the forward
@@ -334,60 +419,110 @@ constexpr int kAggBytes = kWaggBytes + kScanFwdBytes + kScanBwdBytes;
 //   b_k = (y_{k+1} - y_k) / g - g (2 m_k + m_{k+1}) / 6;
 // the walker evaluates half of it (the envelope mean is the sum of the two
 // halves), so q1 = b_k / 2 and q3 = (m_{k+1} - m_k) / (12 g) are stored.
-// Rows go to the threads in blocks of R, over enough waves to keep every
-// SIMD busy.  Contains two barriers and ends with a third.
+// Up to one row per thread of the workgroup, the rows go one per thread
+// over as many waves as they need, their data kept in registers;
+// otherwise in blocks of R rows per thread over all waves, the forward
+// factors c', d' parked in m and q1 of the thread's own rows.  Contains two
+// barriers and ends with a third.
 template <int NT>
 __device__ __forceinline__ void solve_envelopes(const Knots ks, int n1, int n2, int tid,
                                                 double* fwd_lds, double* bwd_lds) {
   constexpr int NW = NT / kWave;
   static_assert(NW <= 16, "wave aggregates sized for 16 waves");
   const int rows = n1 + n2;
-  const int wact = min(NW, max(min(4, NW), (rows + 4 * kWave - 1) / (4 * kWave)));
-  const int R = (rows + wact * kWave - 1) / (wact * kWave);
   const int lane = tid & (kWave - 1), wid = tid / kWave;
-  const int k0 = tid * R, k1 = min(rows, k0 + R);
-  const bool wave_active = wid < wact;
+  if (rows <= NT) {
+    const int wact = (rows + kWave - 1) / kWave;
+    const bool wave_active = wid < wact;
+    const int k = tid;
+    const bool has = k < rows;
+    const bool last = k == n1 - 1 || k == n1 + n2 - 1;
+    double a = 0.0, b = 1.0, c = 0.0, r = 0.0, sl = 0.0, g = 0.0, ig = 0.0;
+    FwdMap G = fwd_identity();
+    if (has) {
+      spline_row(ks, n1, n2, k, a, b, c, r, sl, g, ig);
+      G = {b, -a, c, 0.0, r, 0.0, -a};
+      fwd_normalize(G);
+    }
+    if (wave_active) {
+      G = fwd_wave_scan(G, lane);
+      if (lane == kWave - 1) {
+        double* o = fwd_lds + 7 * wid;
+        o[0] = G.a00; o[1] = G.a01; o[2] = G.a10; o[3] = G.a11;
+        o[4] = G.v0; o[5] = G.v1; o[6] = G.s;
+      }
+    }
+    __syncthreads();
+    double cp = 0.0, dp = 0.0, al = 0.0, be = 1.0;
+    if (wave_active) {
+      double Q, P, D;
+      fwd_enter(fwd_lds, wid, Q, P, D);
+      const FwdMap Y = fwd_dpp<kDppWaveShr1, 0xf>(G);
+      if (lane > 0) fwd_apply(Y, Q, P, D);
+      if (has) {
+        const double q = fma(b, Q, -a * P);
+        D = fma(r, Q, -a * D);
+        P = c * Q;
+        const double iq = recip(q);
+        cp = P * iq;
+        dp = D * iq;
+        al = dp;
+        be = -cp;
+      }
+      bwd_wave_scan(al, be, lane);
+      if (lane == 0) {
+        bwd_lds[2 * wid] = al;
+        bwd_lds[2 * wid + 1] = be;
+      }
+    }
+    __syncthreads();
+    if (wave_active) {
+      double Mn = bwd_after(bwd_lds, wid, wact);
+      const double a2 = dpp_move<kDppWaveShl1, 0xf>(al), b2 = dpp_move<kDppWaveShl1, 0xf>(be);
+      if (lane + 1 < kWave) Mn = fma(b2, Mn, a2);
+      if (has) {
+        const double Mk = fma(-cp, Mn, dp);
+        if (!last) {
+          ks.q1[k] = 0.5 * (sl - g * fma(2.0, Mk, Mn) * (1.0 / 6.0));
+          ks.q3[k] = (Mn - Mk) * ig * (1.0 / 12.0);
+        }
+        ks.m[k] = Mk;
+      }
+    }
+    __syncthreads();
+    return;
+  }
 
-  // forward: the thread's aggregate, then the in-wave inclusive scan
+  // more rows than threads: blocks of R rows per thread over all waves
+  const int R = (rows + NT - 1) / NT;
+  const int k0 = tid * R, k1 = min(rows, k0 + R);
   FwdMap G = fwd_identity();
-  if (wave_active) {
-    for (int k = k0; k < k1; ++k) {
-      double a, b, c, r, sl;
-      spline_row(ks, n1, n2, k, a, b, c, r, sl);
-      G = fwd_row_after(a, b, c, r, G);
-      if (((k - k0) & 3) == 3) fwd_normalize(G);
-    }
-    fwd_normalize(G);
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      const FwdMap Y = fwd_shfl_up(G, d);
-      if (lane >= d) G = fwd_compose(G, Y);
-    }
-    if (lane == kWave - 1) {
-      double* o = fwd_lds + 7 * wid;
-      o[0] = G.a00; o[1] = G.a01; o[2] = G.a10; o[3] = G.a11;
-      o[4] = G.v0; o[5] = G.v1; o[6] = G.s;
-    }
+  for (int k = k0; k < k1; ++k) {
+    double a, b, c, r, sl, g, ig;
+    spline_row(ks, n1, n2, k, a, b, c, r, sl, g, ig);
+    G = fwd_row_after(a, b, c, r, G);
+    if (((k - k0) & 3) == 3) fwd_normalize(G);
+  }
+  fwd_normalize(G);
+  G = fwd_wave_scan(G, lane);
+  if (lane == kWave - 1) {
+    double* o = fwd_lds + 7 * wid;
+    o[0] = G.a00; o[1] = G.a01; o[2] = G.a10; o[3] = G.a11;
+    o[4] = G.v0; o[5] = G.v1; o[6] = G.s;
   }
   __syncthreads();
-  if (wave_active) {
-    // the state entering the wave, then entering the thread
-    double Q = 1.0, P = 0.0, D = 0.0;
-    for (int w = 0; w < wid; ++w) {
-      const double* o = fwd_lds + 7 * w;
-      const FwdMap X = {o[0], o[1], o[2], o[3], o[4], o[5], o[6]};
-      fwd_apply(X, Q, P, D);
-      vec_normalize(Q, P, D);
-    }
-    const FwdMap Y = fwd_shfl_up(G, 1);
+  {
+    double Q, P, D;
+    fwd_enter(fwd_lds, wid, Q, P, D);
+    const FwdMap Y = fwd_dpp<kDppWaveShr1, 0xf>(G);
     if (lane > 0) {
       fwd_apply(Y, Q, P, D);
       vec_normalize(Q, P, D);
     }
     // each row's c' (into m) and d' (into q1): rows of this thread only
     for (int k = k0; k < k1; ++k) {
-      double a, b, c, r, sl;
-      spline_row(ks, n1, n2, k, a, b, c, r, sl);
+      double a, b, c, r, sl, g, ig;
+      spline_row(ks, n1, n2, k, a, b, c, r, sl, g, ig);
       const double q = fma(b, Q, -a * P);
       D = fma(r, Q, -a * D);
       P = c * Q;
@@ -398,36 +533,23 @@ __device__ __forceinline__ void solve_envelopes(const Knots ks, int n1, int n2, 
       ks.q1[k] = D * iq;
     }
   }
-  // backward: M_k = d'_k - c'_k M_{k+1} as maps x -> al + be x, composed
-  // from the thread's last row down, then an in-wave suffix scan
+  // back-substitution maps composed from the thread's last row down
   double al = 0.0, be = 1.0;
-  if (wave_active) {
-    for (int k = k1 - 1; k >= k0; --k) {
-      const double cp = ks.m[k], dp = ks.q1[k];
-      al = fma(-cp, al, dp);
-      be = -cp * be;
-    }
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      const double a2 = __shfl_down(al, d, kWave), b2 = __shfl_down(be, d, kWave);
-      if (lane + d < kWave) {
-        al = fma(be, a2, al);
-        be = be * b2;
-      }
-    }
-    if (lane == 0) {
-      bwd_lds[2 * wid] = al;
-      bwd_lds[2 * wid + 1] = be;
-    }
+  for (int k = k1 - 1; k >= k0; --k) {
+    const double cp = ks.m[k], dp = ks.q1[k];
+    al = fma(-cp, al, dp);
+    be = -cp * be;
+  }
+  bwd_wave_scan(al, be, lane);
+  if (lane == 0) {
+    bwd_lds[2 * wid] = al;
+    bwd_lds[2 * wid + 1] = be;
   }
   __syncthreads();
-  if (wave_active) {
-    // M at the first row after the wave, then after the thread
-    double Mn = 0.0;
-    for (int w = wact - 1; w > wid; --w) Mn = fma(bwd_lds[2 * w + 1], Mn, bwd_lds[2 * w]);
-    const double a2 = __shfl_down(al, 1, kWave), b2 = __shfl_down(be, 1, kWave);
+  {
+    double Mn = bwd_after(bwd_lds, wid, NW);
+    const double a2 = dpp_move<kDppWaveShl1, 0xf>(al), b2 = dpp_move<kDppWaveShl1, 0xf>(be);
     if (lane + 1 < kWave) Mn = fma(b2, Mn, a2);
-    // second derivatives and segment coefficients of the thread's rows
     for (int k = k1 - 1; k >= k0; --k) {
       const double cp = ks.m[k], dp = ks.q1[k];
       const double Mk = fma(-cp, Mn, dp);

@@ -479,8 +479,12 @@ def test_engine_admission_budget_and_staggered_arrivals():
 # --------------------------------------------------------------------------
 
 def test_every_launch_shape_gives_identical_results():
-    # the shape table changes speed only: a face image (bucket 12288) and a
-    # 3000-sample series (bucket 3072) under every compiled shape that fits
+    # the shape table changes speed, not the decomposition: a face image
+    # (bucket 12288) and a 3000-sample series (bucket 3072) under every
+    # compiled shape that fits.  Shapes with the same thread count give the
+    # same bits; across thread counts the spline solve may associate its
+    # scans differently (when a sift has more knots than threads), so those
+    # agree to rounding.
     arch = semd.semd_tune_get().splitlines()[0]
     cases = [(workloads.config2(1)[0], 12288, 8), (workloads.config0(), 3072, 6)]
     shapes = [(256, 4), (256, 8), (256, 12), (256, 16), (512, 8), (512, 12), (512, 16),
@@ -488,18 +492,23 @@ def test_every_launch_shape_gives_identical_results():
     try:
         for it, bound, K in cases:
             x = dev(it.X)
-            ref = None
+            ref, by_nt = None, {}
             for nt, c in shapes:
                 if nt * c < bound:
                     continue
                 semd.semd_tune_set(f"{arch}\nlatency {bound} {nt} {c}\n")
                 out, n = semd.semd_decompose_ex(x, [it.M, it.N], 0, K, 10, path=ONCHIP)
                 got = (host(out), int(host(n)[0]))
+                if nt in by_nt:
+                    assert got[1] == by_nt[nt][1]
+                    assert_same(got[0], by_nt[nt][0], f"shape {nt}x{c}")
+                else:
+                    by_nt[nt] = got
                 if ref is None:
                     ref = got
                 else:
                     assert got[1] == ref[1]
-                    assert_same(got[0], ref[0], f"shape {nt}x{c}")
+                    assert np.abs(got[0] - ref[0]).max() <= 1e-12 * np.abs(it.X).max()
     finally:
         semd.semd_tune_reset()
 
