@@ -603,42 +603,66 @@ __device__ __forceinline__ double walk_at(Walk& w, const Knots& ks, int k) {
   return fma(fma(fma(w.q3, w.B, w.q2), w.B, w.q1), w.B, w.q0);
 }
 
-// Both kinds of knots in one pass over the thread's samples: maxima go to
-// ku (first rank emax of nmax), minima to kl (first rank emin of nmin).
+// h[c] for a lane-dependent c, by selects (no indexed register access).
+template <int C>
+__device__ __forceinline__ double pick(const double (&h)[C], int c) {
+  double y = h[0];
+#pragma unroll
+  for (int j = 1; j < C; ++j) y = (c == j) ? h[j] : y;
+  return y;
+}
+
+// The mirrored end knots of one kind (Sec. 2.1 Step 2 with the mirror
+// boundary) held by this thread: its knots of that kind (bits) have ranks
+// e.. among n, and ranks 0, 1, n-2, n-1 are mirrored about samples 0 and L-1.
+template <int C>
+__device__ __forceinline__ void emit_mirrors(const double (&h)[C], unsigned bits, unsigned NE,
+                                             int carry, int base, int L, int e, int n,
+                                             const Knots ks) {
+  const int cnt = __popc(bits);
+  if (cnt == 0 || (e >= 2 && e + cnt <= n - 2)) return;
+  const int Pp = n < 2 ? n : 2;
+  const int hi = 2 * (L - 1);
+  int g = e;
+  while (bits) {
+    const int c = __ffs(bits) - 1;
+    bits &= bits - 1u;
+    if (g < 2 || g >= n - 2) {
+      const int mid = run_mid(NE, carry, base, c);
+      const double y = pick(h, c);
+      if (g == 0) { ks.t[Pp - 1] = (int16_t)(-mid); ks.y[Pp - 1] = y; }
+      if (g == 1 && Pp == 2) { ks.t[0] = (int16_t)(-mid); ks.y[0] = y; }
+      if (g == n - 1) { ks.t[Pp + n] = (int16_t)(hi - mid); ks.y[Pp + n] = y; }
+      if (g == n - 2 && Pp == 2) { ks.t[Pp + n + 1] = (int16_t)(hi - mid); ks.y[Pp + n + 1] = y; }
+    }
+    ++g;
+  }
+}
+
+// Both kinds of knots, each thread walking its own extrema: maxima go to ku
+// (first rank emax of nmax), minima to kl (first rank emin of nmin).
 template <int C>
 __device__ __forceinline__ void rd_emit_both(const double (&h)[C], unsigned maxbits,
                                              unsigned minbits, unsigned NE, int carry, int base,
                                              int L, int emax, int nmax, int emin, int nmin,
                                              const Knots ku, const Knots kl) {
-  const unsigned any = maxbits | minbits;
-  // the sample slots holding a knot in any lane of the wave, one at a time
-  unsigned wave_any = any;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) wave_any |= __shfl_xor(wave_any, d, kWave);
-  wave_any = __builtin_amdgcn_readfirstlane(wave_any);
-  const int hi = 2 * (L - 1);
-  while (wave_any) {
-    const int c = __ffs(wave_any) - 1;
-    wave_any &= wave_any - 1u;
-    if ((any >> c) & 1u) {
-      const bool up = (maxbits >> c) & 1u;
-      const unsigned bits = up ? maxbits : minbits;
-      const int n = up ? nmax : nmin;
-      const Knots ks = up ? ku : kl;
-      const int Pp = n < 2 ? n : 2;
-      const int g = (up ? emax : emin) + __popc(bits & ((1u << c) - 1u));
-      const int mid = run_mid(NE, carry, base, c);
-      const double y = h[c];
-      ks.t[Pp + g] = (int16_t)mid;
-      ks.y[Pp + g] = y;
-      if (g < 2 || g >= n - 2) {
-        if (g == 0) { ks.t[Pp - 1] = (int16_t)(-mid); ks.y[Pp - 1] = y; }
-        if (g == 1 && Pp == 2) { ks.t[0] = (int16_t)(-mid); ks.y[0] = y; }
-        if (g == n - 1) { ks.t[Pp + n] = (int16_t)(hi - mid); ks.y[Pp + n] = y; }
-        if (g == n - 2 && Pp == 2) { ks.t[Pp + n + 1] = (int16_t)(hi - mid); ks.y[Pp + n + 1] = y; }
-      }
-    }
+  const int Pu = nmax < 2 ? nmax : 2, Pl = nmin < 2 ? nmin : 2;
+  unsigned any = maxbits | minbits;
+  while (any) {
+    const int c = __ffs(any) - 1;
+    any &= any - 1u;
+    const bool up = (maxbits >> c) & 1u;
+    const unsigned below = (1u << c) - 1u;
+    const int g = up ? Pu + emax + __popc(maxbits & below) : Pl + emin + __popc(minbits & below);
+    const int mid = run_mid(NE, carry, base, c);
+    const double y = pick(h, c);
+    int16_t* t = up ? ku.t : kl.t;
+    double* yy = up ? ku.y : kl.y;
+    t[g] = (int16_t)mid;
+    yy[g] = y;
   }
+  emit_mirrors(h, maxbits, NE, carry, base, L, emax, nmax, ku);
+  emit_mirrors(h, minbits, NE, carry, base, L, emin, nmin, kl);
 }
 
 // Second derivatives and segment coefficients of the emitted knot systems
