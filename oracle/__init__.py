@@ -77,7 +77,10 @@ def lib():
         L.semd_ref_eemd_sd.argtypes = [_d, C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_int,
                                        C.c_int, C.c_double, C.c_uint64, C.c_uint64, C.c_double,
                                        _d]
-        for name in ("semd_ref_serialize", "semd_ref_deserialize", "semd_ref_extrema",
+        L.semd_ref_ceemdan.argtypes = [_d, C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_int,
+                                       C.c_int, C.c_double, C.c_uint64, C.c_uint64, C.c_double,
+                                       _d, _int]
+        for name in ("semd_ref_ceemdan", "semd_ref_serialize", "semd_ref_deserialize", "semd_ref_extrema",
                      "semd_ref_spline_solve", "semd_ref_spline_eval", "semd_ref_envelope",
                      "semd_ref_emd", "semd_ref_decompose", "semd_ref_decompose_slices",
                      "semd_ref_emd_sd", "semd_ref_decompose_sd",
@@ -221,3 +224,14 @@ def eemd(Xcol, M: int, N: int, D: int, K: int, S: int, NR: int, beta: float, see
     _check(lib().semd_ref_eemd_sd(_p(X), M, N, D, K, S, NR, float(beta), seed, item, float(sd),
                                   _p(out)), "eemd")
     return out.reshape(K + 1, M * N)
+
+
+def ceemdan(Xcol, M: int, N: int, D: int, K: int, S: int, NR: int, eps: float, seed: int,
+            item: int = 0, sd: float = 0.0):
+    """Sec. 2.2 CEEMDAN of the serialized signal: ((K+1, M*N) slots, n_modes)."""
+    X = _f64(Xcol)
+    out = np.empty((K + 1) * M * N)
+    n = C.c_int()
+    _check(lib().semd_ref_ceemdan(_p(X), M, N, D, K, S, NR, float(eps), seed, item, float(sd),
+                                  _p(out), C.byref(n)), "ceemdan")
+    return out.reshape(K + 1, M * N), n.value

@@ -427,3 +427,97 @@ int semd_ref_eemd_sd(const double* X, int64_t M, int64_t N, int64_t D, int K, in
   free(x); free(xm); free(w); free(R); free(acc);
   return rc;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Sec. 2.2 -- CEEMDAN                                                        */
+/* ------------------------------------------------------------------------- */
+
+/* Population standard deviation of v[0..L): mean, then the mean squared
+   deviation, both summed in index order. */
+static double pop_std(const double* v, int64_t L) {
+  double s = 0.0;
+  for (int64_t k = 0; k < L; ++k) s = s + v[k];
+  const double mean = s / (double)L;
+  double q = 0.0;
+  for (int64_t k = 0; k < L; ++k) {
+    const double d = v[k] - mean;
+    q = q + d * d;
+  }
+  return sqrt(q / (double)L);
+}
+
+static int is_siftable(const double* v, int64_t L, int64_t* imax, int64_t* imin) {
+  int64_t na = 0, ni = 0;
+  if (L < 3) return 0;
+  semd_ref_extrema(v, L, imax, &na, imin, &ni);
+  return siftable(na, ni);
+}
+
+int semd_ref_ceemdan(const double* X, int64_t M, int64_t N, int64_t D, int K, int S, int NR,
+                     double eps, uint64_t seed, uint64_t item, double sd_threshold,
+                     double* out, int* n_modes) {
+  if (!X || !out || !n_modes || M < 1 || N < 1 || D < 0 || D > M || K < 1 || S < 1 || NR < 1)
+    return -1;
+  if (!isfinite(eps) || eps < 0.0 || !(sd_threshold >= 0.0)) return -1;
+  const int64_t L = semd_ref_serial_length(M, N, D);
+  const size_t nb = sizeof(double) * (size_t)L;
+  double* r = (double*)malloc(nb);
+  double* v = (double*)malloc(nb);
+  double* acc = (double*)malloc(nb);
+  double* modes = (double*)calloc((size_t)K * (size_t)L, sizeof(double));
+  double* E = (double*)malloc(nb * (size_t)NR * (size_t)(K + 1));  /* E[m] = EMD(w_m) */
+  double* F = (double*)malloc(nb * 2);                              /* one first mode */
+  int64_t* imax = (int64_t*)malloc(sizeof(int64_t) * (size_t)(L / 2 + 2));
+  int64_t* imin = (int64_t*)malloc(sizeof(int64_t) * (size_t)(L / 2 + 2));
+  if (!r || !v || !acc || !modes || !E || !F || !imax || !imin) {
+    free(r); free(v); free(acc); free(modes); free(E); free(F); free(imax); free(imin);
+    return -2;
+  }
+  int rc = semd_ref_serialize(X, M, N, D, r); /* r_0 = x */
+  for (int64_t k = 0; k < L && rc == 0; ++k)
+    if (!isfinite(r[k])) rc = -3;
+  /* E_i(w_m): the i-th mode of the EMD of noise realization m (zero if it
+     has fewer modes), i = 1..K; kept as slot i-1 of E[m]. */
+  for (int m = 0; m < NR && rc == 0; ++m) {
+    int nm = 0;
+    semd_ref_noise(seed, item, (uint64_t)m, L, v);
+    rc = semd_ref_emd_sd(v, L, K, S, sd_threshold, E + (size_t)m * (size_t)(K + 1) * (size_t)L,
+                         &nm, NULL);
+  }
+  int n = 0;
+  for (int i = 1; i <= K && rc == 0; ++i) {
+    /* stage i extracts mode i from r_{i-1}, if r_{i-1} can still be sifted */
+    if (!is_siftable(r, L, imax, imin)) break;
+    const double beta = eps * pop_std(r, L);
+    for (int64_t k = 0; k < L; ++k) acc[k] = 0.0;
+    for (int m = 0; m < NR && rc == 0; ++m) {
+      /* stage 1 adds beta_0 w_m (the EEMD step); stage i > 1 adds
+         beta_{i-1} E_{i-1}(w_m) */
+      if (i == 1) semd_ref_noise(seed, item, (uint64_t)m, L, v);
+      const double* e = (i == 1) ? v : E + ((size_t)m * (size_t)(K + 1) + (size_t)(i - 2)) * (size_t)L;
+      for (int64_t k = 0; k < L; ++k) {
+        const double be = beta * e[k];
+        v[k] = r[k] + be;
+      }
+      int nm = 0;
+      rc = semd_ref_emd_sd(v, L, 1, S, sd_threshold, F, &nm, NULL); /* first mode of v */
+      for (int64_t k = 0; k < L && rc == 0; ++k) acc[k] = acc[k] + F[k];
+    }
+    if (rc) break;
+    double* c = modes + (size_t)(i - 1) * (size_t)L;
+    for (int64_t k = 0; k < L; ++k) {
+      c[k] = acc[k] / (double)NR; /* the i-th CEEMDAN mode */
+      r[k] = r[k] - c[k];         /* r_i = r_{i-1} - c_i */
+    }
+    n = i;
+  }
+  if (rc == 0) {
+    const int64_t MN = M * N;
+    for (int i = 0; i < K; ++i)
+      semd_ref_deserialize(modes + (size_t)i * (size_t)L, M, N, D, out + (size_t)i * (size_t)MN);
+    semd_ref_deserialize(r, M, N, D, out + (size_t)K * (size_t)MN);
+    *n_modes = n;
+  }
+  free(r); free(v); free(acc); free(modes); free(E); free(F); free(imax); free(imin);
+  return rc;
+}

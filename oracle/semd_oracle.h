@@ -113,6 +113,21 @@ int semd_ref_eemd_sd(const double* X, int64_t M, int64_t N, int64_t D, int K, in
                      double beta, uint64_t seed, uint64_t item, double sd_threshold,
                      double* out);
 
+/* Sec. 2.2 CEEMDAN (Torres et al. 2011) on the serialized signal x.  With
+ * w_m the noise realization m of semd_ref_noise (m < NR), E_i(w) the i-th
+ * mode of the EMD of w (zero if it has fewer), F1(v) the first mode of the
+ * EMD of v and std the population standard deviation:
+ *   stage 1:      c_1 = mean_m F1(x + beta_0 w_m),               beta_0 = eps std(x)
+ *   stage i > 1:  c_i = mean_m F1(r_{i-1} + beta_{i-1} E_{i-1}(w_m)),
+ *                                                    beta_{i-1} = eps std(r_{i-1})
+ *   r_i = r_{i-1} - c_i (r_0 = x); a stage runs only while r_{i-1} is siftable
+ *   and i <= K.  Every EMD uses S sifts per mode and the SD rule when
+ *   sd_threshold > 0.  out: (K+1)*M*N doubles, modes 0..n-1, zeros, residue
+ *   in slot K; *n_modes = n. */
+int semd_ref_ceemdan(const double* X, int64_t M, int64_t N, int64_t D, int K, int S, int NR,
+                     double eps, uint64_t seed, uint64_t item, double sd_threshold,
+                     double* out, int* n_modes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -505,3 +505,50 @@ def test_sd_rule_in_slices_and_ensemble():
     assert ens.tobytes() == plain.tobytes()
     fixed, _ = oracle.decompose(it.X, M, N, 20, K, S)
     assert plain.tobytes() != fixed.tobytes()  # the rule does stop early here
+
+
+# --------------------------------------------------------------------------
+# CEEMDAN (Sec. 2.2)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("sd", [0.0, 0.2])
+def test_ceemdan_without_noise_is_emd(sd):
+    # eps = 0, NR = 1: every stage takes the first mode of the residue
+    # itself, which is exactly how EMD peels its modes off
+    it = workloads.config0()
+    ref, nr = oracle.decompose(it.X, it.M, it.N, 50, 6, 10, sd=sd)
+    out, n = oracle.ceemdan(it.X, it.M, it.N, 50, 6, 10, 1, 0.0, 3, 0, sd=sd)
+    assert n == nr
+    assert out.tobytes() == ref.tobytes()
+
+
+def test_ceemdan_is_complete_and_scale_equivariant():
+    it = workloads.config0()
+    M, N = it.M, it.N
+    out, n = oracle.ceemdan(it.X, M, N, 20, 6, 10, 6, 0.2, 11, 2)
+    assert 2 <= n <= 6
+    assert np.all(out[n:6] == 0.0)
+    assert np.abs(out.sum(0) - it.X).max() <= 1e-12 * np.abs(it.X).max()
+    # the noise amplitude follows the residue's spread, so scaling the input
+    # by a power of two scales every mode exactly
+    big, nb = oracle.ceemdan(it.X * 8.0, M, N, 20, 6, 10, 6, 0.2, 11, 2)
+    assert nb == n and big.tobytes() == (out * 8.0).tobytes()
+
+
+def test_ceemdan_monotone_input_has_no_mode():
+    x = np.linspace(-2.0, 3.0, 500) ** 3
+    out, n = oracle.ceemdan(x, 500, 1, 0, 4, 10, 4, 0.2, 1, 0)
+    assert n == 0
+    assert np.array_equal(out[4], x) and np.all(out[:4] == 0.0)
+
+
+def test_ceemdan_first_stage_is_the_ensemble_first_mode():
+    # stage 1 is the EEMD first mode with beta = eps * std(x)
+    it = workloads.config0()
+    M, N, D, eps = it.M, it.N, 50, 0.2
+    x = oracle.serialize(it.X, M, N, D)
+    beta = eps * float(np.sqrt(np.mean((x - np.mean(x)) ** 2)))
+    out, n = oracle.ceemdan(it.X, M, N, D, 1, 10, 5, eps, 9, 4)
+    ee = oracle.eemd(it.X, M, N, D, 1, 10, 5, beta, 9, 4)
+    assert n == 1
+    assert np.abs(out[0] - ee[0]).max() <= 1e-12 * np.abs(it.X).max()
