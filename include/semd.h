@@ -98,8 +98,9 @@ typedef struct {
  * NULL: receives the number of sifts performed, the number of envelope knots
  * used (mirrored knots included) and the number of sample-sifts (sum over
  * sifts of L); semd_decompose_batch only.  noise_sigma is the absolute EEMD
- * noise amplitude beta of Sec. 2.2 (semd_eemd_batch only), item_id selects the
- * item's noise streams. */
+ * noise amplitude beta of Sec. 2.2 for semd_eemd_batch, and the relative
+ * amplitude eps for semd_ceemdan_batch; item_id selects the item's noise
+ * streams. */
 typedef struct {
   const double* signal;
   double* imfs_out;
@@ -201,6 +202,23 @@ int semd_decompose_batch(const semd_item* items, int n, const semd_params* p,
  * slot-wise mean over m written to imfs_out (zero-filled slots included).
  * n_imfs_out receives the largest IMF count over the realizations. */
 int semd_eemd_batch(const semd_item* items, int n, const semd_params* p, hipStream_t stream);
+
+/* Serial-CEEMDAN (Sec. 2.2, Torres et al. 2011, on the serialized signal x of
+ * Sec. 3.2).  With w_m (m < NR = p->ensemble) the noise realizations of
+ * semd_eemd_batch, E_i(w) the i-th mode of the EMD of w (zero if it has
+ * fewer), F1(v) the first EMD mode of v, std the population standard
+ * deviation over the L serialized samples and eps = the item's noise_sigma:
+ *   mode 1:      c_1 = mean_m F1(x + eps std(x) w_m),
+ *   mode i > 1:  c_i = mean_m F1(r_{i-1} + eps std(r_{i-1}) E_{i-1}(w_m)),
+ *   r_i = r_{i-1} - c_i, r_0 = x.
+ * A mode is extracted while the residue can still be sifted (>= 1 maximum,
+ * >= 1 minimum, >= 3 extrema) and i <= K = p->max_imfs.  Every EMD uses
+ * p->sift_iters sifts per mode and p->stop_rule.  imfs_out receives the
+ * deserialized modes, zero slots, and the residue in slot K; n_imfs_out the
+ * number of modes (-5 for NaN/Inf input, all outputs zero).  Cost: about
+ * 2 * NR times an EMD of the item.  items, p: [host]; eps finite and >= 0. */
+int semd_ceemdan_batch(const semd_item* items, int n, const semd_params* p,
+                       hipStream_t stream);
 
 /* ---- single steps (each runs the kernels of the full path) -------------- */
 

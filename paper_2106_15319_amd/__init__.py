@@ -79,6 +79,8 @@ _EXPORTS = {
                                         C.c_void_p]),
     "semd_eemd_batch": (C.c_int, [C.POINTER(semd_item), C.c_int, C.POINTER(semd_params),
                                   C.c_void_p]),
+    "semd_ceemdan_batch": (C.c_int, [C.POINTER(semd_item), C.c_int, C.POINTER(semd_params),
+                                     C.c_void_p]),
     "semd_serialize": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_int, C.c_int,
                                  C.c_void_p, C.c_void_p]),
     "semd_deserialize": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_int, C.c_int,
@@ -321,6 +323,19 @@ def semd_eemd_batch(signals: Sequence[torch.Tensor], dims_list: Sequence[Sequenc
     arr, n = _items(signals, dims_list, outs, cviews, noise_sigmas, item_ids)
     p = _params(D, max_imfs, sift_iters, ensemble, seed, path=path, sd=sd)
     _check(lib().semd_eemd_batch(arr, n, C.byref(p), _stream(stream)), "semd_eemd_batch")
+
+
+def semd_ceemdan_batch(signals: Sequence[torch.Tensor], dims_list: Sequence[Sequence[int]],
+                       outs: Sequence[torch.Tensor], counts: torch.Tensor | None, D: int,
+                       max_imfs: int, sift_iters: int, ensemble: int, seed: int,
+                       eps: Sequence[float], item_ids: Sequence[int] | None = None,
+                       stream=None, path: int = SEMD_PATH_AUTO, sd: float = 0.0) -> None:
+    """Serial-CEEMDAN of every signal (NR = ensemble noise realizations, eps
+    the relative noise amplitude of each item)."""
+    cviews = [counts[i:i + 1] for i in range(len(signals))] if counts is not None else None
+    arr, n = _items(signals, dims_list, outs, cviews, eps, item_ids)
+    p = _params(D, max_imfs, sift_iters, ensemble, seed, path=path, sd=sd)
+    _check(lib().semd_ceemdan_batch(arr, n, C.byref(p), _stream(stream)), "semd_ceemdan_batch")
 
 
 def semd_serialize(X: torch.Tensor, dims: Sequence[int], D: int, x: torch.Tensor | None = None,

@@ -381,6 +381,8 @@ semd::StreamSig stream_sig(const semd::WorkItem& w, int K, int S, unsigned char*
   g.beta = w.beta;
   g.key = w.key;
   g.flags = w.flags;
+  g.addend = w.addend;
+  g.scale = w.scale;
   g.slot_stride = w.slot_stride;
   g.sd = w.sd;
   g.ntiles = (w.L + semd::kTile - 1) / semd::kTile;
@@ -856,7 +858,7 @@ int semd_eemd_batch(const semd_item* items, int n, const semd_params* p, hipStre
                                      p->transition_len, sd_of(p));
         w.beta = items[i].noise_sigma;
         w.key = semd::noise_key(p->seed, items[i].item_id, (uint64_t)m);
-        w.flags = 1;
+        w.flags = semd::kAddNoise;
         work.push_back(w);
       }
       so += (size_t)NR * per;
@@ -873,6 +875,144 @@ int semd_eemd_batch(const semd_item* items, int n, const semd_params* p, hipStre
     }
     (void)hipFreeAsync(cnt, stream);
     (void)hipFreeAsync(buf, stream);
+    if (rc) return rc;
+    i0 = i1;
+  }
+  return SEMD_OK;
+}
+
+int semd_ceemdan_batch(const semd_item* items, int n, const semd_params* p,
+                       hipStream_t stream) {
+  g_err[0] = 0;
+  int rc = check_params(p, true);
+  if (rc) return rc;
+  std::vector<Shape> shapes;
+  rc = check_items(items, n, p->transition_len, p->path, shapes);
+  if (rc) return rc;
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(items[i].noise_sigma) || items[i].noise_sigma < 0)
+      return fail(SEMD_EINVAL, "item %d: noise_sigma (eps) must be finite and >= 0", i);
+  const int K = p->max_imfs, NR = p->ensemble, S = p->sift_iters;
+  const double sd = sd_of(p);
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = size_t(8) << 30;
+  const size_t budget = std::max<size_t>(free_b / 4, size_t(256) << 20);
+  // per item: residue, K mode slots, NR noise decompositions (K+1 slots),
+  // NR stage outputs (2 slots), and the workspace of NR concurrent EMDs
+  auto item_doubles = [&](int64_t L) {
+    return (size_t)L * (1 + K + (size_t)NR * (K + 1) + (size_t)NR * 2);
+  };
+  int i0 = 0;
+  while (i0 < n) {
+    size_t bytes = 0;
+    int i1 = i0;
+    while (i1 < n) {
+      const size_t b = sizeof(double) * item_doubles(shapes[i1].L) +
+                       (size_t)NR * stream_bytes(shapes[i1].L) + sizeof(semd::CeemdanState);
+      if (i1 > i0 && bytes + b > budget) break;
+      bytes += b;
+      ++i1;
+    }
+    const int nw = i1 - i0;
+    size_t total = 0;
+    std::vector<size_t> off(nw);
+    for (int j = 0; j < nw; ++j) {
+      off[j] = total;
+      total += al256(sizeof(double) * item_doubles(shapes[i0 + j].L));
+    }
+    const size_t st_off = total;
+    total += al256(sizeof(semd::CeemdanState) * (size_t)nw);
+    unsigned char* arena = nullptr;
+    if (hipMallocAsync(reinterpret_cast<void**>(&arena), total, stream) != hipSuccess)
+      return fail(SEMD_ENOMEM, "CEEMDAN workspace of %zu bytes", total);
+    auto* st = reinterpret_cast<semd::CeemdanState*>(arena + st_off);
+    std::vector<semd::CeemdanJob> jobs(nw);
+    std::vector<double*> E(nw);
+    for (int j = 0; j < nw; ++j) {
+      const Shape& sh = shapes[i0 + j];
+      const int64_t L = sh.L;
+      double* base = reinterpret_cast<double*>(arena + off[j]);
+      semd::CeemdanJob& J = jobs[j];
+      J.r = base;
+      J.modes = base + L;
+      E[j] = J.modes + (size_t)K * L;
+      J.stage = E[j] + (size_t)NR * (K + 1) * L;
+      J.out = items[i0 + j].imfs_out;
+      J.n_out = items[i0 + j].n_imfs_out;
+      J.st = st + j;
+      J.M = sh.M;
+      J.N = sh.N;
+      J.L = L;
+      J.slot_stride = sh.M * sh.N;
+      J.D = p->transition_len;
+      J.NR = NR;
+      J.eps = items[i0 + j].noise_sigma;
+    }
+    void* d_jobs = nullptr;
+    rc = upload(jobs.data(), sizeof(semd::CeemdanJob) * jobs.size(), stream, &d_jobs);
+    if (rc) { (void)hipFreeAsync(arena, stream); return rc; }
+    const auto* dj = static_cast<const semd::CeemdanJob*>(d_jobs);
+    hipError_t e = hipSuccess;
+    // r_0 = x, the serialized signal (Sec. 3.2)
+    for (int j = 0; j < nw && e == hipSuccess; ++j)
+      e = semd::launch_serialize(items[i0 + j].signal, shapes[i0 + j].M, shapes[i0 + j].N,
+                                 p->transition_len, jobs[j].r, stream);
+    if (e != hipSuccess) rc = hip_fail(e, "CEEMDAN serialize launch");
+    // E_i(w_m): the full EMD of every noise realization
+    if (rc == SEMD_OK) {
+      std::vector<semd::WorkItem> work;
+      for (int j = 0; j < nw; ++j) {
+        const int64_t L = jobs[j].L;
+        const Shape flat{L, 1, L};
+        for (int m = 0; m < NR; ++m) {
+          semd::WorkItem w = make_work(nullptr, E[j] + (size_t)m * (K + 1) * L, nullptr, flat, 0,
+                                       sd);
+          w.flags = semd::kNoSignal | semd::kAddNoise;
+          w.beta = 1.0;
+          w.key = semd::noise_key(p->seed, items[i0 + j].item_id, (uint64_t)m);
+          work.push_back(w);
+        }
+      }
+      rc = run_work(work, K, S, p->path, stream);
+    }
+    if (rc == SEMD_OK) {
+      e = semd::launch_ceemdan_prep(dj, nw, K, stream);
+      if (e != hipSuccess) rc = hip_fail(e, "CEEMDAN prep launch");
+    }
+    // stage i: the ensemble's first modes of r_{i-1} + beta_{i-1} noise_i,
+    // noise_1 = w_m and noise_i = E_{i-1}(w_m), then their mean is mode i
+    for (int stage = 1; stage <= K && rc == SEMD_OK; ++stage) {
+      std::vector<semd::WorkItem> work;
+      for (int j = 0; j < nw; ++j) {
+        const int64_t L = jobs[j].L;
+        const Shape flat{L, 1, L};
+        for (int m = 0; m < NR; ++m) {
+          semd::WorkItem w = make_work(jobs[j].r, const_cast<double*>(jobs[j].stage) +
+                                                      (size_t)m * 2 * L,
+                                       nullptr, flat, 0, sd);
+          w.scale = &st[j].scale;
+          if (stage == 1) {
+            w.flags = semd::kAddNoise | semd::kScaleOnDevice;
+            w.key = semd::noise_key(p->seed, items[i0 + j].item_id, (uint64_t)m);
+          } else {
+            w.flags = semd::kAddBuffer | semd::kScaleOnDevice;
+            w.addend = E[j] + ((size_t)m * (K + 1) + (stage - 2)) * L;
+          }
+          work.push_back(w);
+        }
+      }
+      rc = run_work(work, 1, S, p->path, stream);
+      if (rc == SEMD_OK) {
+        e = semd::launch_ceemdan_combine(dj, nw, stage, stream);
+        if (e != hipSuccess) rc = hip_fail(e, "CEEMDAN combine launch");
+      }
+    }
+    if (rc == SEMD_OK) {
+      e = semd::launch_ceemdan_finish(dj, nw, K, stream);
+      if (e != hipSuccess) rc = hip_fail(e, "CEEMDAN finish launch");
+    }
+    (void)hipFreeAsync(d_jobs, stream);
+    (void)hipFreeAsync(arena, stream);
     if (rc) return rc;
     i0 = i1;
   }

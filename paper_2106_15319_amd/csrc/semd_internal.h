@@ -23,11 +23,20 @@ struct WorkItem {
   int32_t L;         // serialized length M*N + D*N - D
   double beta;       // EEMD noise amplitude
   uint64_t key;      // SplitMix64 stream key of this realization
-  int32_t flags;     // bit 0: add beta * noise to the serialized signal
+  int32_t flags;     // kAddNoise | kAddBuffer | kScaleOnDevice | kNoSignal
   int32_t pad;
   int64_t slot_stride;  // doubles from one output slot to the next (M*N when contiguous)
   double sd;         // SD stopping threshold; 0: fixed sift count
+  const double* addend;  // device, L doubles added (scaled) under kAddBuffer
+  const double* scale;   // device, one double replacing beta under kScaleOnDevice
 };
+
+// What the first load adds to the serialized signal x (Sec. 2.2):
+//   kAddNoise       x + b * w, w the realization's white noise (key);
+//   kAddBuffer      x + b * addend;
+//   kScaleOnDevice  b = *scale (else b = beta);
+//   kNoSignal       x = 0 (the input is not read).
+constexpr int32_t kAddNoise = 1, kAddBuffer = 2, kScaleOnDevice = 4, kNoSignal = 8;
 
 // Longest serialized signal the resident kernel handles (threads x samples
 // per thread of its largest instance).
@@ -87,6 +96,32 @@ hipError_t launch_ensemble_mean(const double* src, int NR, int64_t count, double
                                 hipStream_t stream);
 // n_out[0] = max over m of n_src[m] (error codes, negative, take precedence).
 hipError_t launch_max_count(const int32_t* n_src, int NR, int32_t* n_out, hipStream_t stream);
+
+// CEEMDAN (Sec. 2.2) per-item state and buffers, all device memory.
+struct CeemdanState {
+  double scale;   // beta of the next stage: eps * std of the current residue
+  int32_t alive;  // the current residue can still be sifted
+  int32_t n;      // modes extracted (-5: the input holds NaN/Inf)
+};
+struct CeemdanJob {
+  double* r;              // residue, L doubles (serialized domain)
+  double* modes;          // K x L mode slots (serialized domain)
+  const double* stage;    // NR x 2L: the stage's first modes (slot 0 of each)
+  double* out;            // (K+1) output slots, slot_stride apart (deserialized)
+  int32_t* n_out;         // or nullptr
+  CeemdanState* st;
+  int64_t M, N, L, slot_stride;
+  int32_t D, NR;
+  double eps;
+};
+// Zero the mode slots, mark non-finite input, and set the first stage's
+// state from r = x.
+hipError_t launch_ceemdan_prep(const CeemdanJob* jobs, int n, int K, hipStream_t stream);
+// Stage `stage` (1-based): mean of the NR first modes into mode slot
+// stage-1 and r -= mode (if alive); then alive and scale from the new r.
+hipError_t launch_ceemdan_combine(const CeemdanJob* jobs, int n, int stage, hipStream_t stream);
+// Deserialize the modes and residue into the outputs; mode count.
+hipError_t launch_ceemdan_finish(const CeemdanJob* jobs, int n, int K, hipStream_t stream);
 
 // SplitMix64: n-th output of the generator started at `state`.
 __host__ __device__ inline uint64_t splitmix64(uint64_t state, uint64_t n) {

@@ -154,8 +154,12 @@ __device__ __forceinline__ void rd_detect(const double (&h)[C], int base, int nv
     } else {
       kind = carry & 3;
     }
-    if (kind == kRise && ((F >> (c + 1)) & 1u)) maxbits |= 1u << c;
-    else if (kind == kFall && ((R >> (c + 1)) & 1u)) minbits |= 1u << c;
+    // (both masks updated by value: a store through a selected reference
+    // would keep them in scratch memory)
+    const unsigned is_max = (kind == kRise && ((F >> (c + 1)) & 1u)) ? 1u : 0u;
+    const unsigned is_min = (kind == kFall && ((R >> (c + 1)) & 1u)) ? 1u : 0u;
+    maxbits |= is_max << c;
+    minbits |= is_min << c;
   }
 }
 
@@ -603,12 +607,19 @@ __device__ __forceinline__ double walk_at(Walk& w, const Knots& ks, int k) {
   return fma(fma(fma(w.q3, w.B, w.q2), w.B, w.q1), w.B, w.q0);
 }
 
-// h[c] for a lane-dependent c, by selects (no indexed register access).
+// h[c] for a lane-dependent c, by selects.  Each element passes through an
+// empty asm so that the selects cannot be folded back into an indexed load,
+// which would move the whole array out of registers into scratch memory.
 template <int C>
 __device__ __forceinline__ double pick(const double (&h)[C], int c) {
   double y = h[0];
+  asm volatile("" : "+v"(y));
 #pragma unroll
-  for (int j = 1; j < C; ++j) y = (c == j) ? h[j] : y;
+  for (int j = 1; j < C; ++j) {
+    double v = h[j];
+    asm volatile("" : "+v"(v));
+    y = (c == j) ? v : y;
+  }
   return y;
 }
 
@@ -787,8 +798,12 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
     for (int k = c0 + tid0; k < c1; k += NT) {
       int i, m;
       div_small(k, R, invR, i, m);
-      double v = serial_at(w.X, M, D, i, m);
-      if (w.flags & 1) v = __dadd_rn(v, __dmul_rn(w.beta, noise_at(w.key, k)));
+      double v = (w.flags & kNoSignal) ? 0.0 : serial_at(w.X, M, D, i, m);
+      if (w.flags & (kAddNoise | kAddBuffer)) {
+        const double b = (w.flags & kScaleOnDevice) ? *w.scale : w.beta;
+        const double e = (w.flags & kAddNoise) ? noise_at(w.key, k) : w.addend[k];
+        v = __dadd_rn(v, __dmul_rn(b, e));
+      }
       bad |= !isfinite(v);
       stage[k - c0] = v;
       w.r[k] = v;
@@ -1108,6 +1123,166 @@ hipError_t launch_resident_cls(const WorkItem* d_items, int n, int maxL, int K, 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// CEEMDAN stages (Sec. 2.2): per-item bookkeeping between the ensembles of
+// first-mode extractions, one workgroup per item
+// ---------------------------------------------------------------------------
+
+constexpr int kCT = 256;  // threads of the CEEMDAN kernels
+
+// Can v[0..L) be sifted (>= 1 maximum, >= 1 minimum, >= 3 extrema)?  The
+// extrema are counted as changes of direction between consecutive steps
+// (pairs of unequal neighbouring samples): a rise then a fall brackets one
+// maximum, strict or an equal-valued run, a fall then a rise one minimum,
+// and a run touching an end has no step on that side.  Each thread counts
+// its own stretch of steps; thread 0 joins the stretches in order.
+__device__ bool block_siftable(const double* v, int64_t L, int* sc) {
+  __shared__ int flag;
+  const int tid = threadIdx.x;
+  if (L < 3) return false;
+  const int64_t pairs = L - 1;
+  const int64_t chunk = (pairs + kCT - 1) / kCT;
+  const int64_t a = min((int64_t)tid * chunk, pairs), b = min(a + chunk, pairs);
+  int first = 0, last = 0, nmax = 0, nmin = 0;
+  for (int64_t k = a; k < b; ++k) {
+    const double d0 = v[k], d1 = v[k + 1];
+    const int d = d1 > d0 ? 1 : (d1 < d0 ? -1 : 0);
+    if (d != 0) {
+      if (last != 0 && last != d) {
+        if (last > 0) ++nmax;
+        else ++nmin;
+      }
+      if (first == 0) first = d;
+      last = d;
+    }
+  }
+  sc[4 * tid] = first;
+  sc[4 * tid + 1] = last;
+  sc[4 * tid + 2] = nmax;
+  sc[4 * tid + 3] = nmin;
+  __syncthreads();
+  if (tid == 0) {
+    int prev = 0, tmax = 0, tmin = 0;
+    for (int t = 0; t < kCT; ++t) {
+      const int f = sc[4 * t];
+      if (f == 0) continue;
+      if (prev != 0 && prev != f) {
+        if (prev > 0) ++tmax;
+        else ++tmin;
+      }
+      tmax += sc[4 * t + 2];
+      tmin += sc[4 * t + 3];
+      prev = sc[4 * t + 1];
+    }
+    flag = (tmax >= 1 && tmin >= 1 && tmax + tmin >= 3) ? 1 : 0;
+  }
+  __syncthreads();
+  const bool ok = flag != 0;
+  __syncthreads();
+  return ok;
+}
+
+// Sum of v[0..L) (f = 0) or of (v - mean)^2 (f = 1): each thread sums its
+// stretch in order, thread 0 the stretches in order.
+__device__ double block_sum_dev(const double* v, int64_t L, double mean, int f, double* sd) {
+  __shared__ double total;
+  const int tid = threadIdx.x;
+  const int64_t chunk = (L + kCT - 1) / kCT;
+  const int64_t a = min((int64_t)tid * chunk, L), b = min(a + chunk, L);
+  double acc = 0.0;
+  for (int64_t k = a; k < b; ++k) {
+    const double x = v[k];
+    if (f == 0) {
+      acc = acc + x;
+    } else {
+      const double d = x - mean;
+      acc = acc + d * d;
+    }
+  }
+  sd[tid] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int i = 0; i < kCT; ++i) t = t + sd[i];
+    total = t;
+  }
+  __syncthreads();
+  const double r = total;
+  __syncthreads();
+  return r;
+}
+
+// The residue's siftability and the next stage's noise amplitude
+// eps * std(r) (population standard deviation).
+__device__ void ceemdan_assess(const CeemdanJob& J, int* sc, double* sd) {
+  const bool ok = block_siftable(J.r, J.L, sc);
+  const double mean = block_sum_dev(J.r, J.L, 0.0, 0, sd) / (double)J.L;
+  const double q = block_sum_dev(J.r, J.L, mean, 1, sd);
+  if (threadIdx.x == 0) {
+    J.st->alive = ok ? 1 : 0;
+    J.st->scale = J.eps * sqrt(q / (double)J.L);
+  }
+}
+
+__global__ void __launch_bounds__(kCT) ceemdan_prep_kernel(const CeemdanJob* __restrict__ jobs,
+                                                           int K) {
+  __shared__ int sc[4 * kCT];
+  __shared__ double sd[kCT];
+  const CeemdanJob J = jobs[blockIdx.x];
+  const int64_t KL = (int64_t)K * J.L;
+  for (int64_t i = threadIdx.x; i < KL; i += kCT) J.modes[i] = 0.0;
+  int bad = 0;
+  for (int64_t k = threadIdx.x; k < J.L; k += kCT) bad |= !isfinite(J.r[k]);
+  bad = __syncthreads_or(bad);
+  if (bad) {
+    if (threadIdx.x == 0) {
+      J.st->alive = 0;
+      J.st->scale = 0.0;
+      J.st->n = -5;
+    }
+    return;
+  }
+  if (threadIdx.x == 0) J.st->n = 0;
+  ceemdan_assess(J, sc, sd);
+}
+
+__global__ void __launch_bounds__(kCT) ceemdan_combine_kernel(const CeemdanJob* __restrict__ jobs,
+                                                              int stage) {
+  __shared__ int sc[4 * kCT];
+  __shared__ double sd[kCT];
+  const CeemdanJob J = jobs[blockIdx.x];
+  const int alive = J.st->alive;
+  __syncthreads();  // every thread has read the state before it changes
+  if (!alive) return;
+  double* mode = J.modes + (int64_t)(stage - 1) * J.L;
+  const int64_t L2 = 2 * J.L;
+  for (int64_t k = threadIdx.x; k < J.L; k += kCT) {
+    double acc = 0.0;
+    for (int m = 0; m < J.NR; ++m) acc = acc + J.stage[m * L2 + k];
+    const double c = acc / (double)J.NR;
+    mode[k] = c;
+    J.r[k] = J.r[k] - c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) J.st->n = stage;
+  ceemdan_assess(J, sc, sd);
+}
+
+__global__ void __launch_bounds__(kCT) ceemdan_finish_kernel(const CeemdanJob* __restrict__ jobs,
+                                                             int K) {
+  const CeemdanJob J = jobs[blockIdx.x];
+  const int q = blockIdx.y;  // output slot 0..K
+  const int n = J.st->n;
+  const double* src = q < K ? J.modes + (int64_t)q * J.L : J.r;
+  const int64_t MN = J.M * J.N, R = J.M + J.D;
+  double* dst = J.out + (int64_t)q * J.slot_stride;
+  for (int64_t o = threadIdx.x; o < MN; o += kCT) {
+    const int64_t i = o / J.M, m = o - i * J.M;
+    dst[o] = n < 0 ? 0.0 : src[i * R + m];
+  }
+  if (q == 0 && threadIdx.x == 0 && J.n_out) *J.n_out = n;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1211,6 +1386,24 @@ hipError_t launch_ensemble_mean(const double* src, int NR, int64_t count, double
 
 hipError_t launch_max_count(const int32_t* n_src, int NR, int32_t* n_out, hipStream_t stream) {
   hipLaunchKernelGGL(max_count_kernel, dim3(1), dim3(64), 0, stream, n_src, NR, n_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ceemdan_prep(const CeemdanJob* jobs, int n, int K, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(ceemdan_prep_kernel, dim3(n), dim3(kCT), 0, stream, jobs, K);
+  return hipGetLastError();
+}
+
+hipError_t launch_ceemdan_combine(const CeemdanJob* jobs, int n, int stage, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(ceemdan_combine_kernel, dim3(n), dim3(kCT), 0, stream, jobs, stage);
+  return hipGetLastError();
+}
+
+hipError_t launch_ceemdan_finish(const CeemdanJob* jobs, int n, int K, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(ceemdan_finish_kernel, dim3(n, K + 1), dim3(kCT), 0, stream, jobs, K);
   return hipGetLastError();
 }
 

@@ -76,7 +76,9 @@ struct StreamSig {
   uint64_t key;
   int64_t slot_stride;  // doubles from one output slot to the next
   double sd;        // SD stopping threshold; 0: fixed sift count
-  int32_t flags;    // bit 0: add beta * noise
+  const double* addend;  // added (scaled) under kAddBuffer
+  const double* scale;   // beta on the device under kScaleOnDevice
+  int32_t flags;    // as a WorkItem's
   int32_t ntiles;
   int32_t K;        // max IMFs
   int32_t S;        // sifts per IMF

@@ -298,8 +298,12 @@ __global__ void __launch_bounds__(kTT) st_load_kernel(const StreamSig* __restric
   int bad = 0;
   for (int k = a + threadIdx.x; k < b; k += kTT) {
     const int64_t i = k / R, m = k - i * R;
-    double v = serial_at(S.X, S.M, S.D, i, m);
-    if (S.flags & 1) v = __dadd_rn(v, __dmul_rn(S.beta, noise_at(S.key, k)));
+    double v = (S.flags & kNoSignal) ? 0.0 : serial_at(S.X, S.M, S.D, i, m);
+    if (S.flags & (kAddNoise | kAddBuffer)) {
+      const double b = (S.flags & kScaleOnDevice) ? *S.scale : S.beta;
+      const double e = (S.flags & kAddNoise) ? noise_at(S.key, k) : S.addend[k];
+      v = __dadd_rn(v, __dmul_rn(b, e));
+    }
     bad |= !isfinite(v);
     S.h[k] = v;
     S.r[k] = v;

@@ -121,6 +121,13 @@ def test_batch_validation():
     assert L.semd_eemd_batch(items, 2, C.byref(pe), None) == semd.SEMD_EINVAL
     pe = _p(NR=0)
     assert L.semd_eemd_batch(items, 2, C.byref(pe), None) == semd.SEMD_EINVAL
+    assert L.semd_ceemdan_batch(items, 2, C.byref(_p(NR=4)), None) == semd.SEMD_EINVAL
+    assert "eps" in L.semd_last_error().decode()
+    items[0].noise_sigma = float("nan")
+    assert L.semd_ceemdan_batch(items, 2, C.byref(_p(NR=4)), None) == semd.SEMD_EINVAL
+    items[0].noise_sigma = 0.2
+    assert L.semd_ceemdan_batch(items, 2, C.byref(_p(NR=0)), None) == semd.SEMD_EINVAL
+    assert L.semd_ceemdan_batch(items, 2, C.byref(_p(NR=2, K=0)), None) == semd.SEMD_EINVAL
     assert L.semd_decompose_batch(items, -1, C.byref(p), None) == semd.SEMD_EINVAL
     assert L.semd_decompose_batch(None, 2, C.byref(p), None) == semd.SEMD_EINVAL
 

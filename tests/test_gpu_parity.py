@@ -680,3 +680,51 @@ def test_mask_series_sweep_matches_oracle(D, rule):
     K, S, sd = (8, 10, 0.0) if rule == "fixed" else (8, 100, 0.05)
     out, n = semd.semd_decompose_ex(dev(it.X), [it.M, it.N], D, K, S, sd=sd)
     _check_sd(it.X, it.M, it.N, D, K, S, sd, host(out), int(host(n)[0]), [])
+
+
+# --------------------------------------------------------------------------
+# CEEMDAN
+# --------------------------------------------------------------------------
+
+def _ceemdan(items, D, K, S, NR, seed, eps, path=semd.SEMD_PATH_AUTO, sd=0.0, ids=None):
+    outs = [torch.empty((K + 1, i.M * i.N), dtype=torch.float64, device=DEV) for i in items]
+    cnt = torch.empty(len(items), dtype=torch.int32, device=DEV)
+    semd.semd_ceemdan_batch([dev(i.X) for i in items], [[i.M, i.N] for i in items], outs, cnt, D,
+                            K, S, NR, seed, eps, ids, path=path, sd=sd)
+    return [host(o) for o in outs], [int(c) for c in host(cnt)]
+
+
+@pytest.mark.parametrize("path", [semd.SEMD_PATH_AUTO, STREAM])
+@pytest.mark.parametrize("sd", [0.0, 0.2])
+def test_ceemdan_matches_oracle(path, sd):
+    items = [workloads.config0(), workloads.config5()]
+    K, S, NR, seed, D = 6, 10, 6, 31, 50
+    outs, ns = _ceemdan(items, D, K, S, NR, seed, [0.2, 0.1], path=path, sd=sd, ids=[4, 9])
+    for k, (it, eps, iid) in enumerate(zip(items, [0.2, 0.1], [4, 9])):
+        ref, nr = oracle.ceemdan(it.X, it.M, it.N, D, K, S, NR, eps, seed, iid, sd=sd)
+        assert ns[k] == nr
+        err = np.abs(outs[k] - ref).max()
+        assert err <= TOL * np.abs(it.X).max(), (k, err)
+
+
+def test_ceemdan_without_noise_is_the_plain_decomposition():
+    it = workloads.config2(1)[0]
+    K, S, D = 8, 10, 20
+    outs, ns = _ceemdan([it], D, K, S, 1, 5, [0.0])
+    plain, n = semd.semd_decompose_ex(dev(it.X), [it.M, it.N], D, K, S)
+    assert ns[0] == int(host(n)[0])
+    assert_same(outs[0], host(plain), "CEEMDAN(eps=0, NR=1) vs EMD")
+
+
+def test_ceemdan_long_signal_and_edge_cases():
+    long_it = workloads.config3_item(11, (20000, 2))  # streaming path
+    mono = workloads.Item(np.linspace(-2.0, 3.0, 700) ** 3, 700, 1)
+    bad = workloads.Item(np.ones(300), 300, 1)
+    bad.X[17] = np.inf
+    K, S, NR, seed = 3, 8, 2, 77
+    outs, ns = _ceemdan([long_it, mono, bad], 0, K, S, NR, seed, [0.2, 0.2, 0.2])
+    ref, nr = oracle.ceemdan(long_it.X, long_it.M, long_it.N, 0, K, S, NR, 0.2, seed, 0)
+    assert ns[0] == nr
+    assert np.abs(outs[0] - ref).max() <= TOL * np.abs(long_it.X).max()
+    assert ns[1] == 0 and np.array_equal(outs[1][K], mono.X) and np.all(outs[1][:K] == 0.0)
+    assert ns[2] == -semd.SEMD_ENONFINITE and np.all(outs[2] == 0.0)
