@@ -21,6 +21,8 @@ Other workloads (--workload), each printing one line of the same shape:
             engine against plain per-request decompositions
   dsweep    the transition-length sweep of Sec. 4.1 (D = 1..500) on the
             six-variate pick-up-mask series, fixed and SD stopping rules
+  ensembles serial-CEEMDAN, serial-EEMD and serial-EMD of that series at
+            D = 50 (the serial-version comparison of Sec. 4.1)
 
 Prints one JSON line.
 """
@@ -544,6 +546,78 @@ def run_eemd(args, semd, torch, workloads):
     return res
 
 
+def run_ensembles(args, semd, torch, workloads):
+    """The serial-version comparison of Sec. 4.1 (its Fig. 6 timing) on the
+    six-variate pick-up-mask series, D = 50: serial-EMD, serial-EEMD
+    (NR = 100, beta = 0.2 std of the serialized signal) and serial-CEEMDAN
+    (NR = 100, eps = 0.2), each one plain call on one signal; the step is
+    the CEEMDAN decomposition."""
+    dev = torch.device("cuda:0")
+    it = workloads.config5()
+    M, N, D, K, S, NR, eps, seed = it.M, it.N, 50, 8, 10, 100, 0.2, 2106
+    X = torch.from_numpy(it.X).to(dev)
+    out = torch.empty((K + 1, M * N), dtype=torch.float64, device=dev)
+    cnt = torch.empty(1, dtype=torch.int32, device=dev)
+    xs = semd.semd_serialize(X, [M, N], D)
+    beta = 0.2 * float(xs.std(unbiased=False).item())
+
+    def emd():
+        semd.semd_decompose_ex(X, [M, N], D, K, S, out, cnt)
+
+    def eemd():
+        semd.semd_eemd_batch([X], [[M, N]], [out], cnt, D, K, S, NR, seed, [beta], [0])
+
+    def ceemdan():
+        semd.semd_ceemdan_batch([X], [[M, N]], [out], cnt, D, K, S, NR, seed, [eps], [0])
+
+    def timed(fn, reps):
+        for _ in range(max(args.warmup, 1)):
+            fn()
+        torch.cuda.synchronize()
+        lat = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - t0) * 1e3)
+        return lat
+
+    reps = max(min(args.steps, 10), 1)
+    lat_c = timed(ceemdan, reps)
+    n_c = int(cnt.cpu()[0])
+    lat_e = timed(eemd, reps)
+    n_e = int(cnt.cpu()[0])
+    lat_m = timed(emd, reps)
+    ms = pct(lat_c, 50)
+    res = base_record(args, M * N / (ms / 1e3), ms)
+    res["steps"] = reps
+    res["config"] = {"workload": "six-variate pick-up-mask series 6 x 1000 (Sec. 4.1), D=50; "
+                                 "serial-CEEMDAN per step (NR=100, eps=0.2), serial-EEMD and "
+                                 "serial-EMD beside it", "M": M, "N": N, "D": D,
+                     "max_imfs": K, "sift_iters": S, "realizations": NR, "eps": eps,
+                     "eemd_beta": beta}
+    res["latency_ms"] = {"ceemdan_p50": ms, "ceemdan_p99": pct(lat_c, 99),
+                         "eemd_p50": pct(lat_e, 50), "eemd_p99": pct(lat_e, 99),
+                         "emd_p50": pct(lat_m, 50), "emd_p99": pct(lat_m, 99)}
+    res["modes"] = {"ceemdan": n_c, "eemd_max": n_e}
+    res["paper_context"] = {"serial_emd_ms": 10.96, "serial_eemd_ms": 397.92,
+                            "serial_ceemdan_ms": 1154.97, "hardware": "i7-6700HQ laptop",
+                            "note": "D = 50; the paper's NR and stopping rule are those "
+                                    "recommended by the methods' authors, not stated"}
+    res["roofline"] = None
+    if not args.no_cpu:
+        import oracle
+        oracle.lib()
+        t1 = time.perf_counter()
+        oracle.ceemdan(it.X, M, N, D, K, S, NR, eps, seed, 0)
+        dt = time.perf_counter() - t1
+        res["cpu_baseline"] = {"value": M * N / dt, "unit": "samples/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"one oracle CEEMDAN of the series (NR={NR}), {dt:.2f} s "
+                                         "on one thread"}
+    return res
+
+
 def run_serving(args, semd, torch, workloads):
     """Poisson arrivals of the serving mix: engine against plain."""
     from paper_2106_15319_amd import serving
@@ -598,7 +672,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload",
-                    choices=["faces", "series", "textures", "eemd", "serving", "dsweep"],
+                    choices=["faces", "series", "textures", "eemd", "serving", "dsweep",
+                             "ensembles"],
                     default="faces")
     ap.add_argument("--sd", type=float, default=0.05, help="dsweep: SD stopping threshold")
     ap.add_argument("--batch", type=int, default=1024, help="faces: images per step")
@@ -633,7 +708,8 @@ def main() -> int:
     assert torch.cuda.is_available(), "bench.py needs the HIP device"
     torch.cuda.set_device(0)
     run = {"faces": run_faces, "series": run_series, "textures": run_textures,
-           "eemd": run_eemd, "serving": run_serving, "dsweep": run_dsweep}[args.workload]
+           "eemd": run_eemd, "serving": run_serving, "dsweep": run_dsweep,
+           "ensembles": run_ensembles}[args.workload]
     res = run(args, semd, torch, workloads)
     print(json.dumps(res), flush=True)
     return 0
