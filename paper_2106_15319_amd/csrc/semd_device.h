@@ -13,8 +13,7 @@ namespace semd {
 namespace dev {
 
 constexpr int kWave = 64;
-constexpr int kChunk = 8;    // interior spline unknowns solved per thread
-constexpr int kHalo = 32;    // knots swept on each side beyond a chunk
+constexpr int kHalo = 32;    // rows a streaming solve window reaches beyond its block
 constexpr int kRise = 1;
 constexpr int kFall = 2;
 
@@ -163,6 +162,171 @@ __device__ __forceinline__ void emit_knots(const double (&h)[C], unsigned bits, 
       }
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Scans for the natural-spline solve (Sec. 2.1 Step 2).  Forward
+// elimination of the tridiagonal system in homogeneous form, one row being
+// the linear map  Q' = b Q - a P,  P' = c Q,  D' = r Q - a D  (so that
+// c' = P/Q and d' = D/Q), composes associatively and is scanned as 3x3 maps
+// of the shape [[A, 0], [v^T, s]]; back-substitution M = d' - c' M_next is
+// scanned as affine maps from the end.  Powers of two rescale the
+// homogeneous quantities exactly, changing no ratio.
+// ---------------------------------------------------------------------------
+
+// One forward map, x -> (a00 Q + a01 P, a10 Q + a11 P, v0 Q + v1 P + s D).
+struct FwdMap {
+  double a00, a01, a10, a11, v0, v1, s;
+};
+
+__device__ __forceinline__ FwdMap fwd_identity() { return {1.0, 0.0, 0.0, 1.0, 0.0, 0.0, 1.0}; }
+
+// X after Y.
+__device__ __forceinline__ FwdMap fwd_compose(const FwdMap& X, const FwdMap& Y) {
+  FwdMap Z;
+  Z.a00 = fma(X.a00, Y.a00, X.a01 * Y.a10);
+  Z.a01 = fma(X.a00, Y.a01, X.a01 * Y.a11);
+  Z.a10 = fma(X.a10, Y.a00, X.a11 * Y.a10);
+  Z.a11 = fma(X.a10, Y.a01, X.a11 * Y.a11);
+  Z.v0 = fma(X.v0, Y.a00, fma(X.v1, Y.a10, X.s * Y.v0));
+  Z.v1 = fma(X.v0, Y.a01, fma(X.v1, Y.a11, X.s * Y.v1));
+  Z.s = X.s * Y.s;
+  return Z;
+}
+
+// Row k's map after X: a cheaper compose for the sparse row map.
+__device__ __forceinline__ FwdMap fwd_row_after(double a, double b, double c, double r,
+                                                const FwdMap& X) {
+  FwdMap Z;
+  Z.a00 = fma(b, X.a00, -a * X.a10);
+  Z.a01 = fma(b, X.a01, -a * X.a11);
+  Z.a10 = c * X.a00;
+  Z.a11 = c * X.a01;
+  Z.v0 = fma(r, X.a00, -a * X.v0);
+  Z.v1 = fma(r, X.a01, -a * X.v1);
+  Z.s = -a * X.s;
+  return Z;
+}
+
+// Exact rescaling by a power of two bringing |A| near 1.
+__device__ __forceinline__ void fwd_normalize(FwdMap& X) {
+  const int ex = __builtin_amdgcn_frexp_exp(fabs(X.a00) + fabs(X.a01) + fabs(X.a10) +
+                                            fabs(X.a11));
+  X.a00 = __builtin_amdgcn_ldexp(X.a00, -ex);
+  X.a01 = __builtin_amdgcn_ldexp(X.a01, -ex);
+  X.a10 = __builtin_amdgcn_ldexp(X.a10, -ex);
+  X.a11 = __builtin_amdgcn_ldexp(X.a11, -ex);
+  X.v0 = __builtin_amdgcn_ldexp(X.v0, -ex);
+  X.v1 = __builtin_amdgcn_ldexp(X.v1, -ex);
+  X.s = __builtin_amdgcn_ldexp(X.s, -ex);
+}
+
+__device__ __forceinline__ void fwd_apply(const FwdMap& X, double& Q, double& P, double& D) {
+  const double q = fma(X.a00, Q, X.a01 * P);
+  const double p = fma(X.a10, Q, X.a11 * P);
+  D = fma(X.v0, Q, fma(X.v1, P, X.s * D));
+  Q = q;
+  P = p;
+}
+
+__device__ __forceinline__ void vec_normalize(double& Q, double& P, double& D) {
+  const int ex = __builtin_amdgcn_frexp_exp(Q);  // Q > 0
+  Q = __builtin_amdgcn_ldexp(Q, -ex);
+  P = __builtin_amdgcn_ldexp(P, -ex);
+  D = __builtin_amdgcn_ldexp(D, -ex);
+}
+
+// A double moved across lanes by a DPP control (each 32-bit half moved the
+// same way); lanes the control gives no source keep 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, ROWS, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ FwdMap fwd_dpp(const FwdMap& X) {
+  return {dpp_move<CTRL, ROWS>(X.a00), dpp_move<CTRL, ROWS>(X.a01), dpp_move<CTRL, ROWS>(X.a10),
+          dpp_move<CTRL, ROWS>(X.a11), dpp_move<CTRL, ROWS>(X.v0),  dpp_move<CTRL, ROWS>(X.v1),
+          dpp_move<CTRL, ROWS>(X.s)};
+}
+
+// DPP controls: shift right by n within each row of 16 lanes; broadcast
+// lane 15 of each row to the next row; lane 31 to rows 2 and 3; shift the
+// whole wave right by one lane.
+constexpr int kDppRowShr = 0x110;
+constexpr int kDppRowBcast15 = 0x142;
+constexpr int kDppRowBcast31 = 0x143;
+constexpr int kDppWaveShr1 = 0x138;
+constexpr int kDppWaveShl1 = 0x130;
+
+// Inclusive scan of the maps over the lanes of a wave (lane l gets the
+// composition of lanes 0..l, later after earlier): Kogge-Stone within each
+// row of 16 lanes, then the row totals broadcast down the wave.
+__device__ __forceinline__ FwdMap fwd_wave_scan(FwdMap G, int lane) {
+  const int i = lane & 15;
+  { const FwdMap Y = fwd_dpp<kDppRowShr + 1, 0xf>(G); if (i >= 1) G = fwd_compose(G, Y); }
+  { const FwdMap Y = fwd_dpp<kDppRowShr + 2, 0xf>(G); if (i >= 2) G = fwd_compose(G, Y); }
+  { const FwdMap Y = fwd_dpp<kDppRowShr + 4, 0xf>(G); if (i >= 4) G = fwd_compose(G, Y); }
+  { const FwdMap Y = fwd_dpp<kDppRowShr + 8, 0xf>(G); if (i >= 8) G = fwd_compose(G, Y); }
+  { const FwdMap Y = fwd_dpp<kDppRowBcast15, 0xa>(G); if (lane & 16) G = fwd_compose(G, Y); }
+  { const FwdMap Y = fwd_dpp<kDppRowBcast31, 0xc>(G); if (lane & 32) G = fwd_compose(G, Y); }
+  return G;
+}
+
+// The state (Q, P, D) entering wave wid: the aggregates of waves 0..wid-1
+// applied to (1, 0, 0) in order.
+__device__ __forceinline__ void fwd_enter(const double* fwd_lds, int wid, double& Q, double& P,
+                                          double& D) {
+  Q = 1.0;
+  P = 0.0;
+  D = 0.0;
+  for (int w = 0; w < wid; ++w) {
+    const double* o = fwd_lds + 7 * w;
+    const FwdMap X = {o[0], o[1], o[2], o[3], o[4], o[5], o[6]};
+    fwd_apply(X, Q, P, D);
+    vec_normalize(Q, P, D);
+  }
+}
+
+// Suffix scan of back-substitution maps x -> al + be x over the lanes of a
+// wave (lane l gets lanes l..63 composed, l's map applied last): within
+// each row of 16 lanes by DPP shifts, then the later rows' totals.
+constexpr int kDppRowShl = 0x100;
+__device__ __forceinline__ void bwd_wave_scan(double& al, double& be, int lane) {
+  const int i = lane & 15;
+#define SEMD_BWD_STEP(n)                                                        \
+  {                                                                             \
+    const double a2 = dpp_move<kDppRowShl + n, 0xf>(al);                        \
+    const double b2 = dpp_move<kDppRowShl + n, 0xf>(be);                        \
+    if (i + n < 16) { al = fma(be, a2, al); be = be * b2; }                     \
+  }
+  SEMD_BWD_STEP(1)
+  SEMD_BWD_STEP(2)
+  SEMD_BWD_STEP(4)
+  SEMD_BWD_STEP(8)
+#undef SEMD_BWD_STEP
+  // rows 0..2 take row r+1's total (its lane 0), then rows 0..1 row r+2's
+  const int row = lane >> 4;
+  {
+    const int src = min(row + 1, 3) << 4;
+    const double a2 = __shfl(al, src, kWave), b2 = __shfl(be, src, kWave);
+    if (row < 3) { al = fma(be, a2, al); be = be * b2; }
+  }
+  {
+    const int src = min(row + 2, 3) << 4;
+    const double a2 = __shfl(al, src, kWave), b2 = __shfl(be, src, kWave);
+    if (row < 2) { al = fma(be, a2, al); be = be * b2; }
+  }
+}
+
+// M at the first row after wave wid: the later waves' maps applied to 0.
+__device__ __forceinline__ double bwd_after(const double* bwd_lds, int wid, int wact) {
+  double Mn = 0.0;
+  for (int w = wact - 1; w > wid; --w) Mn = fma(bwd_lds[2 * w + 1], Mn, bwd_lds[2 * w]);
+  return Mn;
 }
 
 }  // namespace dev

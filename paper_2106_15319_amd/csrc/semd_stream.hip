@@ -30,7 +30,7 @@ using namespace dev;
 
 constexpr int kTT = kTileThreads;     // threads per tile workgroup
 constexpr int kTC = kTile / kTT;      // samples per thread
-constexpr int kSB = kTT * kChunk;     // interior unknowns per solve block
+constexpr int kSB = 2048;             // interior rows per solve block
 constexpr int kNW = kTT / kWave;
 
 __device__ __forceinline__ bool sifting(const SigStatus& st) {
@@ -532,124 +532,30 @@ __global__ void __launch_bounds__(kTT) st_compact_kernel(const StreamSig* __rest
 // Solve
 // ---------------------------------------------------------------------------
 
-// Second derivatives of interior rows s..e (s = 1 + ch*kChunk) of one knot
-// system of n knots staged in LDS (element j at j - w0), by windowed Thomas
-// sweeps: forward from kHalo rows before the chunk, backward from kHalo rows
-// after it, joined at row e, then back-substitution (the damping argument is
-// the resident solver's).  The backward factors at row e+1 also give
-// m_{e+1}, so the chunk writes the power-form coefficients of its segments
-// s..e (and segment 0 when it holds row 1): on [t_j, t_{j+1}), B = k - t_j,
-// g = t_{j+1} - t_j, the spline is
+// One block per (signal, envelope, kSB interior rows r0 .. r1-1): the knots
+// of the block's window (its rows plus kHalo on each side, and their
+// neighbours) are staged in LDS and the window's rows a0..a1 are solved
+// exactly by the scans of the on-chip solver (each thread a stretch of R
+// consecutive rows), started as if the rows beyond the window did not
+// exist.  Windows that reach the ends of the system are exact; elsewhere the
+// coupling a window drops is damped by at least (2 - sqrt 3)^kHalo at the
+// block's own rows, because the matrix is symmetric with every diagonal
+// twice its row's off-diagonal sum, so the Jacobi-scaled matrix has
+// condition number at most 3 and an inverse whose entries decay
+// geometrically at that rate.  Each thread writes the power-form
+// coefficients of the segments of its rows in r0..r1-1 (and segment 0 when
+// it holds row 1): on [t_j, t_{j+1}), B = k - t_j, g = t_{j+1} - t_j,
 //   y_j + b_j B + (m_j / 2) B^2 + ((m_{j+1} - m_j) / (6 g)) B^3,
 //   b_j = (y_{j+1} - y_j) / g - g (2 m_j + m_{j+1}) / 6,
-// stored halved (the envelope mean is the sum of two halves): q1 = b_j / 2,
-// q3 = (m_{j+1} - m_j) / (12 g).
-__device__ __forceinline__ void st_solve_chunk(const int32_t* __restrict__ lt,
-                                               const double* __restrict__ ly, int w0, int n,
-                                               int ch, SegRec* __restrict__ seg) {
-  const int s = 1 + ch * kChunk;
-  const int e = min(s + kChunk - 1, n - 2);
-  const int ws = max(1, s - kHalo);
-  const int we = min(n - 2, e + kHalo);
-#define T(j) ((double)lt[(j) - w0])
-#define Y(j) (ly[(j) - w0])
-  double ftp = T(ws - 1), ft = T(ws), fy = Y(ws);
-  double fsp = (fy - Y(ws - 1)) * recip(ft - ftp);
-  double cp = 0.0, dp = 0.0;
-  double btn = T(we + 1), bt = T(we), by = Y(we);
-  double bsn = (Y(we + 1) - by) * recip(btn - bt);
-  double aa = 0.0, dd = 0.0;
-  const int nf = s - ws;                    // forward halo rows ws .. s-1
-  const int nb = (e < n - 2) ? we - e : 0;  // backward rows we .. e+1
-  const int steps = max(nf, nb);
-#pragma unroll 1
-  for (int i = 0; i < steps; ++i) {
-    if (i < nf) {
-      const double tn = T(ws + i + 1), yn = Y(ws + i + 1);
-      const double g0 = ft - ftp, g1 = tn - ft;
-      const double sn = (yn - fy) * recip(g1);
-      const double inv = recip(fma(-g0, cp, 2.0 * (g0 + g1)));
-      cp = g1 * inv;
-      dp = fma(-g0, dp, 6.0 * (sn - fsp)) * inv;
-      ftp = ft; ft = tn; fy = yn; fsp = sn;
-    }
-    if (i < nb) {
-      const int j = we - i;
-      const double tp = T(j - 1), yp = Y(j - 1);
-      const double g1 = btn - bt, g0 = bt - tp;
-      const double sp = (by - yp) * recip(g0);
-      const double inv = recip(fma(-g1, aa, 2.0 * (g0 + g1)));
-      aa = g0 * inv;
-      dd = fma(-g1, dd, 6.0 * (bsn - sp)) * inv;
-      btn = bt; bt = tp; by = yp; bsn = sp;
-    }
-  }
-  double cpa[kChunk], dpa[kChunk];
-#pragma unroll
-  for (int q = 0; q < kChunk; ++q) {
-    cpa[q] = 0.0;
-    dpa[q] = 0.0;
-    if (s + q <= e) {
-      const double tn = T(s + q + 1), yn = Y(s + q + 1);
-      const double g0 = ft - ftp, g1 = tn - ft;
-      const double sn = (yn - fy) * recip(g1);
-      const double inv = recip(fma(-g0, cp, 2.0 * (g0 + g1)));
-      cp = g1 * inv;
-      dp = fma(-g0, dp, 6.0 * (sn - fsp)) * inv;
-      cpa[q] = cp;
-      dpa[q] = dp;
-      ftp = ft; ft = tn; fy = yn; fsp = sn;
-    }
-  }
-  // M_e = d'_e - c'_e M_{e+1} with M_{e+1} = dd - aa M_e from the right, or
-  // M_e = d'_e on the last row (M_{n-1} = 0)
-  double Ms[kChunk + 1];
-  const double Me = (e < n - 2) ? fma(-cp, dd, dp) * recip(fma(-cp, aa, 1.0)) : dp;
-#pragma unroll
-  for (int q = 0; q <= kChunk; ++q) Ms[q] = 0.0;
-  double Mn = Me;
-#pragma unroll
-  for (int q = kChunk - 1; q >= 0; --q) {
-    if (s + q == e) Ms[q] = Me;
-    if (s + q < e) {
-      Mn = fma(-cpa[q], Mn, dpa[q]);
-      Ms[q] = Mn;
-    }
-  }
-  const double Mafter = (e < n - 2) ? fma(-aa, Me, dd) : 0.0;  // m_{e+1}
-#pragma unroll
-  for (int q = 0; q < kChunk; ++q) {
-    const int j = s + q;
-    if (j <= e) {
-      const double m0 = Ms[q], m1 = (j < e) ? Ms[q + 1] : Mafter;
-      const double t0 = T(j), t1 = T(j + 1), y0 = Y(j);
-      const double g = t1 - t0;
-      const double ig = recip(g);
-      const double b = (Y(j + 1) - y0) * ig - g * fma(2.0, m0, m1) * (1.0 / 6.0);
-      seg[j] = SegRec{t0, t1, 0.5 * y0, 0.5 * b, 0.25 * m0, (m1 - m0) * ig * (1.0 / 12.0)};
-    }
-  }
-  if (s == 1) {  // segment 0, with m_0 = 0
-    const double m1 = Ms[0];
-    const double t0 = T(0), t1 = T(1), y0 = Y(0);
-    const double g = t1 - t0;
-    const double ig = recip(g);
-    const double b = (Y(1) - y0) * ig - g * m1 * (1.0 / 6.0);
-    seg[0] = SegRec{t0, t1, 0.5 * y0, 0.5 * b, 0.0, m1 * ig * (1.0 / 12.0)};
-  }
-#undef T
-#undef Y
-}
-
-// One block per (signal, envelope, kSB interior unknowns): the knots the
-// block's chunks read (their rows plus kHalo+1 on each side) are staged in
-// LDS, each thread solves one chunk and writes its second derivatives and
-// segment coefficients.
+// stored halved (the envelope mean is the sum of two halves).
 __global__ void __launch_bounds__(kTT) st_solve_kernel(const StreamSig* __restrict__ sigs,
                                                        const int4* __restrict__ blocks) {
   constexpr int kW = kSB + 2 * kHalo + 4;
+  constexpr int kRMax = (kSB + 2 * kHalo + kTT - 1) / kTT;
   __shared__ int32_t lt[kW];
   __shared__ double ly[kW];
+  __shared__ double fwd_lds[7 * kNW];
+  __shared__ double bwd_lds[2 * kNW];
   const int4 bv = blocks[blockIdx.x];  // (signal, envelope, block)
   const StreamSig& S = sigs[bv.x];
   if (!sifting(*S.st)) return;
@@ -660,7 +566,8 @@ __global__ void __launch_bounds__(kTT) st_solve_kernel(const StreamSig* __restri
   const int r0 = 1 + bv.z * kSB;
   if (n2 < 3 || r0 > n2 - 2) return;
   const int r1 = min(r0 + kSB, n2 - 1);  // rows r0 .. r1-1
-  const int w0 = max(0, r0 - kHalo - 1), w1 = min(n2 - 1, r1 + kHalo);
+  const int a0 = max(1, r0 - kHalo), a1 = min(n2 - 2, r1 - 1 + kHalo);
+  const int w0 = a0 - 1, w1 = a1 + 1;    // knots read
   const int32_t* kt = S.kt[env];
   const double* ky = S.ky[env];
   for (int i = threadIdx.x; i <= w1 - w0; i += kTT) {
@@ -668,9 +575,112 @@ __global__ void __launch_bounds__(kTT) st_solve_kernel(const StreamSig* __restri
     ly[i] = ky[w0 + i];
   }
   __syncthreads();
-  const int ch = (r0 - 1) / kChunk + threadIdx.x;
-  if (1 + ch * kChunk < r1)
-    st_solve_chunk(lt, ly, w0, n2, ch, S.seg[env]);
+#define T(j) ((double)lt[(j) - w0])
+#define Y(j) (ly[(j) - w0])
+  const int rows = a1 - a0 + 1;
+  const int R = (rows + kTT - 1) / kTT;  // <= kRMax
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int j0 = a0 + threadIdx.x * R;
+  // row j's equation a M_{j-1} + b M_j + c M_{j+1} = r
+  auto row = [&](int j, double& a, double& b, double& c, double& r) {
+    const double tm = T(j - 1), t0 = T(j), tp = T(j + 1);
+    a = t0 - tm;
+    c = tp - t0;
+    b = 2.0 * (a + c);
+    r = 6.0 * ((Y(j + 1) - Y(j)) * recip(c) - (Y(j) - Y(j - 1)) * recip(a));
+  };
+  FwdMap G = fwd_identity();
+#pragma unroll
+  for (int q = 0; q < kRMax; ++q) {
+    const int j = j0 + q;
+    if (q < R && j <= a1) {
+      double a, b, c, r;
+      row(j, a, b, c, r);
+      G = fwd_row_after(a, b, c, r, G);
+      if ((q & 3) == 3) fwd_normalize(G);
+    }
+  }
+  fwd_normalize(G);
+  G = fwd_wave_scan(G, lane);
+  if (lane == kWave - 1) {
+    double* o = fwd_lds + 7 * wid;
+    o[0] = G.a00; o[1] = G.a01; o[2] = G.a10; o[3] = G.a11;
+    o[4] = G.v0; o[5] = G.v1; o[6] = G.s;
+  }
+  __syncthreads();
+  double cpa[kRMax], dpa[kRMax];
+  {
+    double Q, P, D;
+    fwd_enter(fwd_lds, wid, Q, P, D);
+    const FwdMap Y1 = fwd_dpp<kDppWaveShr1, 0xf>(G);
+    if (lane > 0) {
+      fwd_apply(Y1, Q, P, D);
+      vec_normalize(Q, P, D);
+    }
+#pragma unroll
+    for (int q = 0; q < kRMax; ++q) {
+      cpa[q] = 0.0;
+      dpa[q] = 0.0;
+      const int j = j0 + q;
+      if (q < R && j <= a1) {
+        double a, b, c, r;
+        row(j, a, b, c, r);
+        const double qn = fma(b, Q, -a * P);
+        D = fma(r, Q, -a * D);
+        P = c * Q;
+        Q = qn;
+        vec_normalize(Q, P, D);
+        const double iq = recip(Q);
+        cpa[q] = P * iq;
+        dpa[q] = D * iq;
+      }
+    }
+  }
+  // back-substitution maps composed from the thread's last row down
+  double al = 0.0, be = 1.0;
+#pragma unroll
+  for (int q = kRMax - 1; q >= 0; --q) {
+    if (q < R && j0 + q <= a1) {
+      al = fma(-cpa[q], al, dpa[q]);
+      be = -cpa[q] * be;
+    }
+  }
+  bwd_wave_scan(al, be, lane);
+  if (lane == 0) {
+    bwd_lds[2 * wid] = al;
+    bwd_lds[2 * wid + 1] = be;
+  }
+  __syncthreads();
+  double Mn = bwd_after(bwd_lds, wid, kNW);
+  {
+    const double a2 = dpp_move<kDppWaveShl1, 0xf>(al), b2 = dpp_move<kDppWaveShl1, 0xf>(be);
+    if (lane + 1 < kWave) Mn = fma(b2, Mn, a2);
+  }
+  SegRec* seg = S.seg[env];
+#pragma unroll
+  for (int q = kRMax - 1; q >= 0; --q) {
+    const int j = j0 + q;
+    if (q < R && j <= a1) {
+      const double Mj = fma(-cpa[q], Mn, dpa[q]);
+      if (j >= r0 && j < r1) {
+        const double t0 = T(j), t1 = T(j + 1), y0 = Y(j);
+        const double g = t1 - t0;
+        const double ig = recip(g);
+        const double b = (Y(j + 1) - y0) * ig - g * fma(2.0, Mj, Mn) * (1.0 / 6.0);
+        seg[j] = SegRec{t0, t1, 0.5 * y0, 0.5 * b, 0.25 * Mj, (Mn - Mj) * ig * (1.0 / 12.0)};
+        if (j == 1) {  // segment 0, with m_0 = 0
+          const double s0 = T(0), s1 = T(1), z0 = Y(0);
+          const double h = s1 - s0;
+          const double ih = recip(h);
+          const double b0 = (Y(1) - z0) * ih - h * Mj * (1.0 / 6.0);
+          seg[0] = SegRec{s0, s1, 0.5 * z0, 0.5 * b0, 0.0, Mj * ih * (1.0 / 12.0)};
+        }
+      }
+      Mn = Mj;
+    }
+  }
+#undef T
+#undef Y
 }
 
 // Walker over the segments of one envelope of a streaming signal, reading
