@@ -62,9 +62,9 @@ struct ResidentClass {
 };
 ResidentClass resident_class(int maxL);
 
-// Bytes of the kernel's reusable LDS area for signals up to maxL samples,
-// at most max_area (and at least what the block-end publication and the
-// staging window need).
+// Bytes of the kernel's reusable LDS area (staging window, knot store) for
+// signals up to maxL samples, at most max_area (and at least what the
+// staging window needs).
 size_t resident_area_bytes(int maxL, int nt, size_t max_area);
 
 // The compiled launch shapes: up to cap of them into out; returns how many

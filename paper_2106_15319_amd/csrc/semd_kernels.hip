@@ -260,6 +260,10 @@ constexpr int kWaggBytes = 256;
 constexpr int kScanFwdBytes = 7 * 16 * (int)sizeof(double);
 constexpr int kScanBwdBytes = 2 * 16 * (int)sizeof(double);
 constexpr int kAggBytes = kWaggBytes + kScanFwdBytes + kScanBwdBytes;
+// Bytes of the detection's published block ends for NT threads.
+__host__ __device__ constexpr int pub_bytes(int NT) {
+  return (NT * (2 * (int)sizeof(double) + (int)sizeof(int)) + 15) & ~15;
+}
 
 // Second derivatives m and segment coefficients q1, q3 of the knot systems
 // [0, n1) and [n1, n1 + n2) (n2 = 0: one system).  On [t_k, t_{k+1}), with
@@ -595,11 +599,14 @@ __device__ __forceinline__ void div_small(int k, int R, float invR, int& q, int&
 // Resident Serial-EMD kernel: one workgroup per work item
 // ---------------------------------------------------------------------------
 
-// LDS: 256 B of wave totals, then one area (area_bytes) used in turn as
+// LDS: the head (wave totals and the spline scans' wave aggregates), the
+// published block ends of the extremum detection (20 B per thread), then one
+// area (area_bytes) used in turn as
 //   - a staging window of the signal (a multiple of NT doubles) at load and
 //     IMF ends, so global reads and writes stay coalesced;
-//   - the published block ends of the extremum detection (20 B per thread);
 //   - the knot store (34 B per knot).
+// Detection writes only its own region, so a sift starts while slower waves
+// still evaluate the previous sift's envelopes from the knot store.
 // A sift keeps both envelopes' knots in LDS when they fit together (one
 // solve, one fused evaluation, mean and update); else one envelope at a time
 // when each fits (the upper envelope parked in global memory); else both in
@@ -619,13 +626,13 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
   const float invR = 1.0f / (float)R;
 
   int* wagg = reinterpret_cast<int*>(smem);
-  unsigned char* area = smem + kAggBytes;
+  double* pub_first = reinterpret_cast<double*>(smem + kAggBytes);
+  double* pub_last = pub_first + NT;
+  int* pub_key = reinterpret_cast<int*>(pub_last + NT);
+  unsigned char* area = smem + kAggBytes + pub_bytes(NT);
   const int capk = area_bytes / kKnotBytes;  // knots the LDS store can take
   const int scap = (area_bytes / (int)sizeof(double)) / NT * NT;
   double* stage = reinterpret_cast<double*>(area);
-  double* pub_first = reinterpret_cast<double*>(area);
-  double* pub_last = pub_first + NT;
-  int* pub_key = reinterpret_cast<int*>(pub_last + NT);
   const Knots lk = knots_in(area, capk);
   const Knots gk = knots_in(reinterpret_cast<unsigned char*>(w.u), resident_gknot_cap(L));
 
@@ -671,7 +678,6 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
   while (nimf < K) {
     bool stop = false;
     for (int s = 0; s < S; ++s) {
-      __syncthreads();  // previous readers of the LDS area are done
       // Values derived from the thread's position are recomputed every sift
       // rather than hoisted out of the loop and held in registers throughout.
       int tid = tid0, base = base0, nv = nv0;
@@ -958,8 +964,9 @@ hipError_t launch_resident_cls(const WorkItem* d_items, int n, int maxL, int K, 
   wg_cu = std::min(wg_cu, std::max(1, (n + device_cus() - 1) / device_cus()));
   const size_t per_wg = (kLdsPerCU / (size_t)wg_cu) & ~size_t(511);
   const size_t limit = std::min(per_wg, kLdsPerCU) - (size_t)attr.sharedSizeBytes;
-  const size_t area = resident_area_bytes(maxL, NT, limit - kAggBytes);
-  const size_t lds = kAggBytes + area;
+  const size_t head = kAggBytes + pub_bytes(NT);
+  const size_t area = resident_area_bytes(maxL, NT, limit - head);
+  const size_t lds = head + area;
   if (lds > kLdsPerCU - (size_t)attr.sharedSizeBytes) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1147,12 +1154,11 @@ ResidentClass resident_class(int maxL) {
 }
 
 size_t resident_area_bytes(int maxL, int nt, size_t max_area) {
-  const size_t pub = (size_t)nt * (2 * sizeof(double) + sizeof(int));
   const size_t stage = (size_t)nt * sizeof(double);
   // both envelopes of any sift (at most L + 6 knots) if the budget allows
   const size_t dual = (size_t)kKnotBytes * ((size_t)maxL + 16);
   size_t area = std::min(dual, max_area);
-  area = std::max(area, std::max(pub, stage));
+  area = std::max(area, stage);
   return area & ~size_t(15);
 }
 
