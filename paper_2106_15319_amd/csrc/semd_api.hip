@@ -952,6 +952,8 @@ int semd_ceemdan_batch(const semd_item* items, int n, const semd_params* p,
     rc = upload(jobs.data(), sizeof(semd::CeemdanJob) * jobs.size(), stream, &d_jobs);
     if (rc) { (void)hipFreeAsync(arena, stream); return rc; }
     const auto* dj = static_cast<const semd::CeemdanJob*>(d_jobs);
+    int64_t maxL = 0;
+    for (int j = 0; j < nw; ++j) maxL = std::max(maxL, jobs[j].L);
     hipError_t e = hipSuccess;
     // r_0 = x, the serialized signal (Sec. 3.2)
     for (int j = 0; j < nw && e == hipSuccess; ++j)
@@ -1003,7 +1005,7 @@ int semd_ceemdan_batch(const semd_item* items, int n, const semd_params* p,
       }
       rc = run_work(work, 1, S, p->path, stream);
       if (rc == SEMD_OK) {
-        e = semd::launch_ceemdan_combine(dj, nw, stage, stream);
+        e = semd::launch_ceemdan_combine(dj, nw, maxL, stage, stream);
         if (e != hipSuccess) rc = hip_fail(e, "CEEMDAN combine launch");
       }
     }

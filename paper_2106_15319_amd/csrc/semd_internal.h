@@ -119,7 +119,9 @@ struct CeemdanJob {
 hipError_t launch_ceemdan_prep(const CeemdanJob* jobs, int n, int K, hipStream_t stream);
 // Stage `stage` (1-based): mean of the NR first modes into mode slot
 // stage-1 and r -= mode (if alive); then alive and scale from the new r.
-hipError_t launch_ceemdan_combine(const CeemdanJob* jobs, int n, int stage, hipStream_t stream);
+// maxL: the longest item.
+hipError_t launch_ceemdan_combine(const CeemdanJob* jobs, int n, int64_t maxL, int stage,
+                                  hipStream_t stream);
 // Deserialize the modes and residue into the outputs; mode count.
 hipError_t launch_ceemdan_finish(const CeemdanJob* jobs, int n, int K, hipStream_t stream);
 

@@ -1098,24 +1098,37 @@ __global__ void __launch_bounds__(kCT) ceemdan_prep_kernel(const CeemdanJob* __r
   ceemdan_assess(J, sc, sd);
 }
 
+// Mode `stage` of item blockIdx.x, samples of tile blockIdx.y: the mean of
+// the NR first modes (summed in m order) into the mode slot, r -= mode.
+constexpr int kCTile = kCT * 8;
 __global__ void __launch_bounds__(kCT) ceemdan_combine_kernel(const CeemdanJob* __restrict__ jobs,
                                                               int stage) {
+  const CeemdanJob J = jobs[blockIdx.x];
+  if (!J.st->alive) return;
+  double* mode = J.modes + (int64_t)(stage - 1) * J.L;
+  const int64_t L2 = 2 * J.L;
+  const int64_t k0 = (int64_t)blockIdx.y * kCTile;
+  const int64_t k1 = min(J.L, k0 + kCTile);
+  for (int64_t k = k0 + threadIdx.x; k < k1; k += kCT) {
+    double acc = 0.0;
+#pragma unroll 8
+    for (int m = 0; m < J.NR; ++m) acc = acc + J.stage[m * L2 + k];
+    const double c = acc / (double)J.NR;
+    mode[k] = c;
+    J.r[k] = J.r[k] - c;
+  }
+}
+
+// After mode `stage`: the mode count, and whether the new residue can still
+// be sifted and the next stage's amplitude.
+__global__ void __launch_bounds__(kCT) ceemdan_assess_kernel(const CeemdanJob* __restrict__ jobs,
+                                                             int stage) {
   __shared__ int sc[4 * kCT];
   __shared__ double sd[kCT];
   const CeemdanJob J = jobs[blockIdx.x];
   const int alive = J.st->alive;
   __syncthreads();  // every thread has read the state before it changes
   if (!alive) return;
-  double* mode = J.modes + (int64_t)(stage - 1) * J.L;
-  const int64_t L2 = 2 * J.L;
-  for (int64_t k = threadIdx.x; k < J.L; k += kCT) {
-    double acc = 0.0;
-    for (int m = 0; m < J.NR; ++m) acc = acc + J.stage[m * L2 + k];
-    const double c = acc / (double)J.NR;
-    mode[k] = c;
-    J.r[k] = J.r[k] - c;
-  }
-  __syncthreads();
   if (threadIdx.x == 0) J.st->n = stage;
   ceemdan_assess(J, sc, sd);
 }
@@ -1246,9 +1259,12 @@ hipError_t launch_ceemdan_prep(const CeemdanJob* jobs, int n, int K, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_ceemdan_combine(const CeemdanJob* jobs, int n, int stage, hipStream_t stream) {
+hipError_t launch_ceemdan_combine(const CeemdanJob* jobs, int n, int64_t maxL, int stage,
+                                  hipStream_t stream) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(ceemdan_combine_kernel, dim3(n), dim3(kCT), 0, stream, jobs, stage);
+  const int tiles = (int)((maxL + kCTile - 1) / kCTile);
+  hipLaunchKernelGGL(ceemdan_combine_kernel, dim3(n, tiles), dim3(kCT), 0, stream, jobs, stage);
+  hipLaunchKernelGGL(ceemdan_assess_kernel, dim3(n), dim3(kCT), 0, stream, jobs, stage);
   return hipGetLastError();
 }
 
