@@ -582,6 +582,7 @@ __device__ __forceinline__ void sift_both(double (&h)[C], unsigned maxbits, unsi
 
 // Hides a value's origin from the optimizer (no instruction is emitted).
 __device__ __forceinline__ void opaque(int& v) { asm volatile("" : "+v"(v)); }
+__device__ __forceinline__ void opaque(unsigned& v) { asm volatile("" : "+v"(v)); }
 
 // Samples of the chunk [c0, c1) of the signal that thread-owned slot c maps to.
 __device__ __forceinline__ bool in_chunk(int k, int c0, int c1) { return k >= c0 && k < c1; }
@@ -688,9 +689,19 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
       int carry;
       rd_detect<NT, C>(h, base, nv, L, tid, pub_first, pub_last, pub_key, Rm, Fm, carry,
                        maxbits, minbits);
+      // The masks are kept as masks: otherwise their popcounts get rebuilt
+      // from the individual comparison bits, all of which then stay live.
+      opaque(maxbits);
+      opaque(minbits);
+      opaque(Rm);
+      opaque(Fm);
       int tot;
-      const int excl = block_excl_sum<NW>((__popc(maxbits) << 16) | __popc(minbits), wagg,
-                                          tid & (kWave - 1), tid / kWave, tot);
+      int excl = block_excl_sum<NW>((__popc(maxbits) << 16) | __popc(minbits), wagg,
+                                    tid & (kWave - 1), tid / kWave, tot);
+      // (summed now: otherwise the wave totals stay live, one register each,
+      // until the ranks are used)
+      opaque(excl);
+      opaque(tot);
       const int nmax = tot >> 16, nmin = tot & 0xffff;
       if (!(nmax >= 1 && nmin >= 1 && nmax + nmin >= 3)) {
         stop = (s == 0);  // the residue itself is not siftable: decomposition ends
