@@ -1,21 +1,24 @@
 // HIP kernels of the Serial-EMD hot path for gfx950 (MI355X), FP64 throughout.
 //
 // Resident path: one workgroup decomposes one serialized signal (or one EEMD
-// realization) completely on chip.  The candidate h lives in registers in a
-// blocked layout (thread t owns samples [t*C, t*C + C)); the knots of one
-// envelope and their spline second derivatives live in LDS; the residue r is
-// read and written once per IMF.  Per sift:
+// or CEEMDAN realization) completely on chip.  The candidate h lives in
+// registers in a blocked layout (thread t owns samples [t*C, t*C + C)); the
+// knots of the envelopes, their spline second derivatives and segment
+// coefficients live in LDS; the residue r is read and written once per IMF.
+// Per sift:
 //   extrema (Sec. 2.1 Step 1)   neighbour exchange through LDS, plateau runs
 //                                resolved by a walk over published run starts,
 //                                per-thread counts, one block scan (wave
 //                                shuffles + LDS wave totals) for compaction;
-//   envelopes (Step 2)           knots + mirrored end knots written to LDS,
-//                                natural-spline second derivatives by windowed
-//                                Thomas sweeps (one thread per chunk of knots),
+//   envelopes (Step 2)           each thread writes its own knots, a few the
+//                                mirrored end knots; natural-spline second
+//                                derivatives by two block-wide scans (forward
+//                                elimination maps, then back-substitution);
 //                                evaluation by a per-thread walk over segments;
-//   mean and update (Steps 3-4)  fused into the lower-envelope evaluation.
-// Serialization (Sec. 3.2) and the EEMD noise (Sec. 2.2) are fused into the
-// first load; deserialization (Sec. 3.3) into the IMF and residue stores.
+//   mean and update (Steps 3-4)  fused into the evaluation.
+// Serialization (Sec. 3.2) and the ensemble noise (Sec. 2.2) are fused into
+// the first load; deserialization (Sec. 3.3) into the IMF and residue stores.
+// The file also holds the single-step kernels and the CEEMDAN stage kernels.
 #include <algorithm>
 
 #include "semd_device.h"

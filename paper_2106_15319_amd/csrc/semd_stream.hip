@@ -9,10 +9,12 @@
 //   scan     (signals)  run-start carries and knot ranks across the tiles of
 //                       a signal, knot totals, siftability, stop flags;
 //   compact  (tiles)    knots (and mirrored end knots) written at their ranks;
-//   solve    (blocks)   natural-spline second derivatives, blocks of knots
-//                       staged in LDS, windowed Thomas sweeps per chunk;
-//   eval     (tiles)    the tile's knots staged in LDS, both envelopes walked
-//                       per thread, mean removed from h.
+//   solve    (blocks)   natural-spline second derivatives and segment
+//                       records, each block's window of knots staged in LDS
+//                       and solved exactly by block-wide scans;
+//   eval     (tiles)    both envelopes walked per thread over the segment
+//                       records, mean removed from h, the sifted tile's
+//                       extrema detected while it is on chip.
 // Every signal carries its own phase (sift index, IMFs ended); the scan
 // decides each step's action per signal, and the evaluation also performs
 // IMF ends and final outputs, so signals in different phases share one
