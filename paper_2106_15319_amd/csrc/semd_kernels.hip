@@ -34,10 +34,11 @@ using namespace dev;
 // [t*C, t*C + C) of the signal in registers h[])
 // ---------------------------------------------------------------------------
 
-// Knot store of the envelopes of one sift.  Knot j holds abscissa t_j, value
-// y_j and spline second derivative m_j; once the derivatives are known, q1_j
-// and q3_j hold the linear and cubic coefficients of segment [t_j, t_{j+1})
-// in the power form used by the walker (solve_envelopes).  34 bytes per knot.
+// Knot store of the envelopes of one sift.  Knot j holds abscissa t_j and
+// value y_j; the solve (solve_envelopes) leaves the halved power-form
+// coefficients of segment [t_j, t_{j+1}) that the walker reads: y_j / 2 in y,
+// m_j / 4 in m (m_j the spline second derivative), and the linear and cubic
+// coefficients in q1 and q3.  34 bytes per knot.
 struct Knots {
   double* y;
   double* m;
@@ -230,11 +231,12 @@ __device__ __forceinline__ void rd_emit(const double (&h)[C], unsigned bits, uns
 // system's last knot) its slope, length g and 1/g.
 __device__ __forceinline__ void spline_row(const Knots ks, int n1, int n2, int k, double& a,
                                            double& b, double& c, double& r, double& slope,
-                                           double& g, double& ig) {
+                                           double& g, double& ig, double& yk) {
   const bool first = k == 0 || k == n1;
   const bool last = k == n1 - 1 || k == n1 + n2 - 1;
   const int t0 = ks.t[k];
   const double y0 = ks.y[k];
+  yk = y0;
   double s0 = 0.0, s1 = 0.0, g0 = 0.0, g1 = 0.0, i1 = 0.0;
   if (!last) {
     const int tp = ks.t[k + 1];
@@ -293,10 +295,10 @@ __device__ __forceinline__ void solve_envelopes(const Knots ks, int n1, int n2, 
     const int k = tid;
     const bool has = k < rows;
     const bool last = k == n1 - 1 || k == n1 + n2 - 1;
-    double a = 0.0, b = 1.0, c = 0.0, r = 0.0, sl = 0.0, g = 0.0, ig = 0.0;
+    double a = 0.0, b = 1.0, c = 0.0, r = 0.0, sl = 0.0, g = 0.0, ig = 0.0, yk = 0.0;
     FwdMap G = fwd_identity();
     if (has) {
-      spline_row(ks, n1, n2, k, a, b, c, r, sl, g, ig);
+      spline_row(ks, n1, n2, k, a, b, c, r, sl, g, ig, yk);
       G = {b, -a, c, 0.0, r, 0.0, -a};
       fwd_normalize(G);
     }
@@ -342,7 +344,8 @@ __device__ __forceinline__ void solve_envelopes(const Knots ks, int n1, int n2, 
           ks.q1[k] = 0.5 * (sl - g * fma(2.0, Mk, Mn) * (1.0 / 6.0));
           ks.q3[k] = (Mn - Mk) * ig * (1.0 / 12.0);
         }
-        ks.m[k] = Mk;
+        ks.m[k] = 0.25 * Mk;
+        ks.y[k] = 0.5 * yk;
       }
     }
     __syncthreads();
@@ -354,8 +357,8 @@ __device__ __forceinline__ void solve_envelopes(const Knots ks, int n1, int n2, 
   const int k0 = tid * R, k1 = min(rows, k0 + R);
   FwdMap G = fwd_identity();
   for (int k = k0; k < k1; ++k) {
-    double a, b, c, r, sl, g, ig;
-    spline_row(ks, n1, n2, k, a, b, c, r, sl, g, ig);
+    double a, b, c, r, sl, g, ig, yk;
+    spline_row(ks, n1, n2, k, a, b, c, r, sl, g, ig, yk);
     G = fwd_row_after(a, b, c, r, G);
     if (((k - k0) & 3) == 3) fwd_normalize(G);
   }
@@ -377,8 +380,8 @@ __device__ __forceinline__ void solve_envelopes(const Knots ks, int n1, int n2, 
     }
     // each row's c' (into m) and d' (into q1): rows of this thread only
     for (int k = k0; k < k1; ++k) {
-      double a, b, c, r, sl, g, ig;
-      spline_row(ks, n1, n2, k, a, b, c, r, sl, g, ig);
+      double a, b, c, r, sl, g, ig, yk;
+      spline_row(ks, n1, n2, k, a, b, c, r, sl, g, ig, yk);
       const double q = fma(b, Q, -a * P);
       D = fma(r, Q, -a * D);
       P = c * Q;
@@ -417,10 +420,12 @@ __device__ __forceinline__ void solve_envelopes(const Knots ks, int n1, int n2, 
         ks.q1[k] = 0.5 * bk;
         ks.q3[k] = (Mn - Mk) * ig * (1.0 / 12.0);
       }
-      ks.m[k] = Mk;
+      ks.m[k] = 0.25 * Mk;
       Mn = Mk;
     }
   }
+  __syncthreads();  // the values of the neighbours' rows have been read
+  for (int k = k0; k < k1; ++k) ks.y[k] = 0.5 * ks.y[k];
   __syncthreads();
 }
 
@@ -435,9 +440,9 @@ __device__ __forceinline__ void walk_load(Walk& w, const Knots& ks, int j) {
   w.j = j;
   w.t0 = ks.t[j];
   w.t1 = ks.t[j + 1];
-  w.q0 = 0.5 * ks.y[j];
+  w.q0 = ks.y[j];
   w.q1 = ks.q1[j];
-  w.q2 = 0.25 * ks.m[j];
+  w.q2 = ks.m[j];
   w.q3 = ks.q3[j];
 }
 
