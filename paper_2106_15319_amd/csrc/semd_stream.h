@@ -13,10 +13,10 @@ constexpr int kTileThreads = 256;
 // Knots of one kind a tile can hold (a strict extremum needs two steps).
 constexpr int kTileKnots = kTile / 2 + 8;
 
-// One spline segment as the evaluation reads it: its knots and the halved
-// power-form coefficients, S(k)/2 = ((q3 B + q2) B + q1) B + q0, B = k - t0.
+// One spline segment [t_j, t_{j+1}) as the evaluation reads it: the halved
+// power-form coefficients, S(k)/2 = ((q3 B + q2) B + q1) B + q0, B = k - t_j
+// (the knots themselves come from the knot-position array).
 struct alignas(16) SegRec {
-  double t0, t1;
   double q0, q1, q2, q3;
 };
 

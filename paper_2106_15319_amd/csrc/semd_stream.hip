@@ -669,13 +669,13 @@ __global__ void __launch_bounds__(kTT) st_solve_kernel(const StreamSig* __restri
         const double g = t1 - t0;
         const double ig = recip(g);
         const double b = (Y(j + 1) - y0) * ig - g * fma(2.0, Mj, Mn) * (1.0 / 6.0);
-        seg[j] = SegRec{t0, t1, 0.5 * y0, 0.5 * b, 0.25 * Mj, (Mn - Mj) * ig * (1.0 / 12.0)};
+        seg[j] = SegRec{0.5 * y0, 0.5 * b, 0.25 * Mj, (Mn - Mj) * ig * (1.0 / 12.0)};
         if (j == 1) {  // segment 0, with m_0 = 0
           const double s0 = T(0), s1 = T(1), z0 = Y(0);
           const double h = s1 - s0;
           const double ih = recip(h);
           const double b0 = (Y(1) - z0) * ih - h * Mj * (1.0 / 6.0);
-          seg[0] = SegRec{s0, s1, 0.5 * z0, 0.5 * b0, 0.0, Mj * ih * (1.0 / 12.0)};
+          seg[0] = SegRec{0.5 * z0, 0.5 * b0, 0.0, Mj * ih * (1.0 / 12.0)};
         }
       }
       Mn = Mj;
@@ -686,10 +686,10 @@ __global__ void __launch_bounds__(kTT) st_solve_kernel(const StreamSig* __restri
 }
 
 // Walker over the segments of one envelope of a streaming signal, reading
-// the segment records in global memory: the current segment [t0, t1), its
-// halved power-form coefficients and B = k - t0.
+// the segment records and knot positions in global memory: the current
+// segment j = [t0, t1), its halved power-form coefficients and B = k - t0.
 struct StWalk {
-  int j;
+  int j, t1;
   SegRec cur;
   double B;
 };
@@ -697,18 +697,26 @@ struct StWalk {
 // Position at the segment holding sample k from segment j (whose left knot
 // lies at or before k; the last knot lies beyond the signal).
 __device__ __forceinline__ void st_walk_init(StWalk& w, const StreamSig& S, int e, int j, int k) {
-  const SegRec* seg = S.seg[e];
+  const int32_t* kt = S.kt[e];
+  int t0 = kt[j], t1 = kt[j + 1];
+  while (t1 <= k) {
+    ++j;
+    t0 = t1;
+    t1 = kt[j + 1];
+  }
   w.j = j;
-  w.cur = seg[j];
-  while (w.cur.t1 <= (double)k) w.cur = seg[++w.j];
-  w.B = (double)k - w.cur.t0;
+  w.t1 = t1;
+  w.cur = S.seg[e][j];
+  w.B = (double)(k - t0);
 }
 
 // Half the envelope at sample k (one step from k-1 crosses at most one knot).
 __device__ __forceinline__ double st_walk_at(StWalk& w, const StreamSig& S, int e, int k) {
-  if (w.cur.t1 <= (double)k) {
-    w.cur = S.seg[e][++w.j];
-    w.B = (double)k - w.cur.t0;
+  if (w.t1 <= k) {
+    ++w.j;
+    w.B = (double)(k - w.t1);
+    w.t1 = S.kt[e][w.j + 1];
+    w.cur = S.seg[e][w.j];
   }
   return fma(fma(fma(w.cur.q3, w.B, w.cur.q2), w.B, w.cur.q1), w.B, w.cur.q0);
 }
