@@ -728,3 +728,15 @@ def test_ceemdan_long_signal_and_edge_cases():
     assert np.abs(outs[0] - ref).max() <= TOL * np.abs(long_it.X).max()
     assert ns[1] == 0 and np.array_equal(outs[1][K], mono.X) and np.all(outs[1][:K] == 0.0)
     assert ns[2] == -semd.SEMD_ENONFINITE and np.all(outs[2] == 0.0)
+
+
+@pytest.mark.parametrize("L", [6000, 8192, 12000])
+def test_knot_store_modes_over_several_sifts(L):
+    # white noise puts about 2L/3 knots into a sift: around these lengths the
+    # on-chip kernel moves between both envelopes in LDS, one at a time in
+    # LDS (the upper one parked in global memory), and the global knot store
+    x = np.random.default_rng(4000 + L).standard_normal(L)
+    out, n = semd.semd_decompose_ex(dev(x), [L, 1], 0, 3, 4, path=ONCHIP)
+    ref, nr, st = oracle.emd(x, 3, 4, with_stats=True)
+    r = compare(host(out), int(host(n)[0]), ref, nr, np.abs(x).max(), st["min_gap"])
+    assert_parity(r, f"white noise L={L}")
