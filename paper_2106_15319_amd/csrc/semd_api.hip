@@ -359,8 +359,7 @@ size_t stream_bytes(int64_t L) {
   const size_t cap = (size_t)((L - 1) / 2 + 12);
   const size_t ntiles = (size_t)((L + semd::kTile - 1) / semd::kTile);
   return 2 * al256(sizeof(double) * (size_t)L) +
-         2 * (al256(sizeof(int32_t) * cap) + al256(sizeof(double) * cap) +
-              al256(sizeof(semd::SegRec) * cap)) +
+         2 * (al256(sizeof(int32_t) * cap) + 2 * al256(sizeof(double) * cap)) +
          al256(sizeof(semd::TileInfo) * ntiles) + al256(sizeof(double) * 2 * ntiles) +
          al256(sizeof(int32_t) * 2 * semd::kTileThreads * ntiles) +
          2 * (al256(sizeof(int32_t) * semd::kTileKnots * ntiles) +
@@ -400,7 +399,7 @@ semd::StreamSig stream_sig(const semd::WorkItem& w, int K, int S, unsigned char*
   for (int e = 0; e < 2; ++e) {
     g.kt[e] = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (size_t)g.cap));
     g.ky[e] = reinterpret_cast<double*>(take(sizeof(double) * (size_t)g.cap));
-    g.seg[e] = reinterpret_cast<semd::SegRec*>(take(sizeof(semd::SegRec) * (size_t)g.cap));
+    g.km[e] = reinterpret_cast<double*>(take(sizeof(double) * (size_t)g.cap));
   }
   g.tinfo = reinterpret_cast<semd::TileInfo*>(take(sizeof(semd::TileInfo) * (size_t)g.ntiles));
   g.edge = reinterpret_cast<double*>(take(sizeof(double) * 2 * (size_t)g.ntiles));

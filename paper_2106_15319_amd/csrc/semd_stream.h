@@ -13,13 +13,6 @@ constexpr int kTileThreads = 256;
 // Knots of one kind a tile can hold (a strict extremum needs two steps).
 constexpr int kTileKnots = kTile / 2 + 8;
 
-// One spline segment [t_j, t_{j+1}) as the evaluation reads it: the halved
-// power-form coefficients, S(k)/2 = ((q3 B + q2) B + q1) B + q0, B = k - t_j
-// (the knots themselves come from the knot-position array).
-struct alignas(16) SegRec {
-  double q0, q1, q2, q3;
-};
-
 // What the scan needs from, and gives back to, one tile.
 struct TileInfo {
   int32_t cnt[2];     // extrema found by detection, the continued run excluded
@@ -86,7 +79,7 @@ struct StreamSig {
   double* r;        // residue, L doubles
   int32_t* kt[2];   // knot abscissae (maxima, minima), cap each
   double* ky[2];    // knot values
-  SegRec* seg[2];   // segment j = [t_j, t_{j+1}) of each envelope, for evaluation
+  double* km[2];    // the envelopes' second derivatives at the knots
   int32_t cap;      // knots per envelope
   int32_t pad;
   TileInfo* tinfo;  // ntiles

@@ -544,12 +544,10 @@ __global__ void __launch_bounds__(kTT) st_compact_kernel(const StreamSig* __rest
 // block's own rows, because the matrix is symmetric with every diagonal
 // twice its row's off-diagonal sum, so the Jacobi-scaled matrix has
 // condition number at most 3 and an inverse whose entries decay
-// geometrically at that rate.  Each thread writes the power-form
-// coefficients of the segments of its rows in r0..r1-1 (and segment 0 when
-// it holds row 1): on [t_j, t_{j+1}), B = k - t_j, g = t_{j+1} - t_j,
-//   y_j + b_j B + (m_j / 2) B^2 + ((m_{j+1} - m_j) / (6 g)) B^3,
-//   b_j = (y_{j+1} - y_j) / g - g (2 m_j + m_{j+1}) / 6,
-// stored halved (the envelope mean is the sum of two halves).
+// geometrically at that rate.  Each thread writes the second derivatives
+// m_j of its rows in r0..r1-1, and the zeros of the two end knots when it
+// holds row 1 or row n-2; the evaluation forms each segment's cubic from
+// the knots at its ends.
 __global__ void __launch_bounds__(kTT) st_solve_kernel(const StreamSig* __restrict__ sigs,
                                                        const int4* __restrict__ blocks) {
   constexpr int kW = kSB + 2 * kHalo + 4;
@@ -658,25 +656,16 @@ __global__ void __launch_bounds__(kTT) st_solve_kernel(const StreamSig* __restri
     const double a2 = dpp_move<kDppWaveShl1, 0xf>(al), b2 = dpp_move<kDppWaveShl1, 0xf>(be);
     if (lane + 1 < kWave) Mn = fma(b2, Mn, a2);
   }
-  SegRec* seg = S.seg[env];
+  double* km = S.km[env];
 #pragma unroll
   for (int q = kRMax - 1; q >= 0; --q) {
     const int j = j0 + q;
     if (q < R && j <= a1) {
       const double Mj = fma(-cpa[q], Mn, dpa[q]);
       if (j >= r0 && j < r1) {
-        const double t0 = T(j), t1 = T(j + 1), y0 = Y(j);
-        const double g = t1 - t0;
-        const double ig = recip(g);
-        const double b = (Y(j + 1) - y0) * ig - g * fma(2.0, Mj, Mn) * (1.0 / 6.0);
-        seg[j] = SegRec{0.5 * y0, 0.5 * b, 0.25 * Mj, (Mn - Mj) * ig * (1.0 / 12.0)};
-        if (j == 1) {  // segment 0, with m_0 = 0
-          const double s0 = T(0), s1 = T(1), z0 = Y(0);
-          const double h = s1 - s0;
-          const double ih = recip(h);
-          const double b0 = (Y(1) - z0) * ih - h * Mj * (1.0 / 6.0);
-          seg[0] = SegRec{0.5 * z0, 0.5 * b0, 0.0, Mj * ih * (1.0 / 12.0)};
-        }
+        km[j] = Mj;
+        if (j == 1) km[0] = 0.0;            // natural end conditions
+        if (j == n2 - 2) km[n2 - 1] = 0.0;
       }
       Mn = Mj;
     }
@@ -686,13 +675,35 @@ __global__ void __launch_bounds__(kTT) st_solve_kernel(const StreamSig* __restri
 }
 
 // Walker over the segments of one envelope of a streaming signal, reading
-// the segment records and knot positions in global memory: the current
-// segment j = [t0, t1), its halved power-form coefficients and B = k - t0.
+// the knots (position, value, second derivative) in global memory: the
+// current segment j = [t0, t1), its right knot (t1, y1, m1), its halved
+// power-form coefficients and B = k - t0.  On [t_j, t_{j+1}), with
+// B = k - t_j and g = t_{j+1} - t_j, the natural spline is
+//   y_j + b_j B + (m_j / 2) B^2 + ((m_{j+1} - m_j) / (6 g)) B^3,
+//   b_j = (y_{j+1} - y_j) / g - g (2 m_j + m_{j+1}) / 6,
+// and the walker evaluates half of it (the envelope mean is the sum of two
+// halves).
 struct StWalk {
   int j, t1;
-  SegRec cur;
-  double B;
+  double y1, m1, B, q0, q1, q2, q3;
 };
+
+// The coefficients of segment j from its left knot (t0, y0, m0) and the
+// right knot loaded here.
+__device__ __forceinline__ void st_walk_segment(StWalk& w, const StreamSig& S, int e, int j,
+                                                int t0, double y0, double m0) {
+  w.j = j;
+  w.t1 = S.kt[e][j + 1];
+  w.y1 = S.ky[e][j + 1];
+  w.m1 = S.km[e][j + 1];
+  const double g = (double)(w.t1 - t0);
+  const double ig = recip(g);
+  const double b = (w.y1 - y0) * ig - g * fma(2.0, m0, w.m1) * (1.0 / 6.0);
+  w.q0 = 0.5 * y0;
+  w.q1 = 0.5 * b;
+  w.q2 = 0.25 * m0;
+  w.q3 = (w.m1 - m0) * ig * (1.0 / 12.0);
+}
 
 // Position at the segment holding sample k from segment j (whose left knot
 // lies at or before k; the last knot lies beyond the signal).
@@ -704,21 +715,17 @@ __device__ __forceinline__ void st_walk_init(StWalk& w, const StreamSig& S, int 
     t0 = t1;
     t1 = kt[j + 1];
   }
-  w.j = j;
-  w.t1 = t1;
-  w.cur = S.seg[e][j];
+  st_walk_segment(w, S, e, j, t0, S.ky[e][j], S.km[e][j]);
   w.B = (double)(k - t0);
 }
 
 // Half the envelope at sample k (one step from k-1 crosses at most one knot).
 __device__ __forceinline__ double st_walk_at(StWalk& w, const StreamSig& S, int e, int k) {
   if (w.t1 <= k) {
-    ++w.j;
     w.B = (double)(k - w.t1);
-    w.t1 = S.kt[e][w.j + 1];
-    w.cur = S.seg[e][w.j];
+    st_walk_segment(w, S, e, w.j + 1, w.t1, w.y1, w.m1);
   }
-  return fma(fma(fma(w.cur.q3, w.B, w.cur.q2), w.B, w.cur.q1), w.B, w.cur.q0);
+  return fma(fma(fma(w.q3, w.B, w.q2), w.B, w.q1), w.B, w.q0);
 }
 
 // ---------------------------------------------------------------------------
@@ -726,9 +733,9 @@ __device__ __forceinline__ double st_walk_at(StWalk& w, const StreamSig& S, int 
 // ---------------------------------------------------------------------------
 
 // One step's work on the tile's samples:
-//   kSift, kSiftLast  envelope means removed (Sec. 2.1 Steps 2-4): the knots
-//                     whose segments cover the tile are staged in LDS and
-//                     each thread walks them over its samples;
+//   kSift, kSiftLast  envelope means removed (Sec. 2.1 Steps 2-4): each
+//                     thread walks the knots covering its samples, starting
+//                     from the ranks compaction recorded;
 //   kSiftLast, kEndImf  IMF end: the candidate is stored in its output slot
 //                     (deserialized, Sec. 3.3), r <- r - h, h <- r;
 //   final             residue into slot K, unused IMF slots zero (Sec. 4.3),
