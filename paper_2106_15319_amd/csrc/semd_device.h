@@ -17,6 +17,43 @@ constexpr int kHalo = 32;    // rows a streaming solve window reaches beyond its
 constexpr int kRise = 1;
 constexpr int kFall = 2;
 
+// DPP controls: shift right (left) by n within each row of 16 lanes;
+// broadcast lane 15 of each row to the next row; lane 31 to rows 2 and 3;
+// shift the whole wave right (left) by one lane.
+constexpr int kDppRowShr = 0x110;
+constexpr int kDppRowShl = 0x100;
+constexpr int kDppRowBcast15 = 0x142;
+constexpr int kDppRowBcast31 = 0x143;
+constexpr int kDppWaveShr1 = 0x138;
+constexpr int kDppWaveShl1 = 0x130;
+
+// An int moved across lanes by a DPP control; lanes the control gives no
+// source, and lanes of rows outside ROWS, get FILL.
+template <int CTRL, int ROWS, int FILL = 0>
+__device__ __forceinline__ int dpp_int(int x) {
+  return __builtin_amdgcn_update_dpp(FILL, x, CTRL, ROWS, 0xf, false);
+}
+
+// The same for an int64 (each 32-bit half moved the same way; fill 0).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int64_t dpp_i64(int64_t x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, ROWS, 0xf, false);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// A double moved across lanes by a DPP control (each 32-bit half moved the
+// same way); lanes the control gives no source, and lanes of rows outside
+// ROWS, get 0.0, or 1.0 when ONE is set.
+template <int CTRL, int ROWS, bool ONE = false>
+__device__ __forceinline__ double dpp_move(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(ONE ? 0x3ff00000 : 0, (int)(v >> 32), CTRL, ROWS,
+                                             0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // ---------------------------------------------------------------------------
 // Small helpers
 // ---------------------------------------------------------------------------
@@ -60,16 +97,17 @@ __host__ __device__ constexpr int knot_cap(int L) {
 
 __host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
 
-// Block-wide exclusive prefix sum of one int per thread (wave shuffles, then
-// the wave totals through LDS).  Contains one barrier.
+// Block-wide exclusive prefix sum of one int per thread (a DPP scan within
+// each wave, then the wave totals through LDS).  Contains one barrier.
 template <int NW>
 __device__ __forceinline__ int block_excl_sum(int v, int* wagg, int lane, int wid, int& total) {
   int inc = v;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const int u = __shfl_up(inc, d, kWave);
-    if (lane >= d) inc += u;
-  }
+  inc += dpp_int<kDppRowShr + 1, 0xf>(inc);
+  inc += dpp_int<kDppRowShr + 2, 0xf>(inc);
+  inc += dpp_int<kDppRowShr + 4, 0xf>(inc);
+  inc += dpp_int<kDppRowShr + 8, 0xf>(inc);
+  inc += dpp_int<kDppRowBcast15, 0xa>(inc);
+  inc += dpp_int<kDppRowBcast31, 0xc>(inc);
   if (lane == kWave - 1) wagg[wid] = inc;
   __syncthreads();
   int before = 0, tot = 0;
@@ -83,18 +121,24 @@ __device__ __forceinline__ int block_excl_sum(int v, int* wagg, int lane, int wi
   return before + inc - v;
 }
 
-// Block-wide sums of two doubles per thread (wave shuffles, then the wave
-// sums through LDS, 2*NW doubles, added in wave order so every thread gets
-// the same totals).  Contains one barrier; wsum must not be in use.
+// Block-wide sums of two doubles per thread (a DPP scan within each wave,
+// whose last lane holds the wave's sums, then the wave sums through LDS,
+// 2*NW doubles, added in wave order so every thread gets the same totals).
+// Contains one barrier; wsum must not be in use.
 template <int NW>
 __device__ __forceinline__ void block_sum2(double a, double b, double* wsum, int lane, int wid,
                                            double& ta, double& tb) {
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    a += __shfl_xor(a, d, kWave);
-    b += __shfl_xor(b, d, kWave);
-  }
-  if (lane == 0) {
+#define SEMD_SUM_STEP(ctrl, rows)            \
+  a += dpp_move<ctrl, rows>(a);              \
+  b += dpp_move<ctrl, rows>(b);
+  SEMD_SUM_STEP(kDppRowShr + 1, 0xf)
+  SEMD_SUM_STEP(kDppRowShr + 2, 0xf)
+  SEMD_SUM_STEP(kDppRowShr + 4, 0xf)
+  SEMD_SUM_STEP(kDppRowShr + 8, 0xf)
+  SEMD_SUM_STEP(kDppRowBcast15, 0xa)
+  SEMD_SUM_STEP(kDppRowBcast31, 0xc)
+#undef SEMD_SUM_STEP
+  if (lane == kWave - 1) {
     wsum[2 * wid] = a;
     wsum[2 * wid + 1] = b;
   }
@@ -236,43 +280,30 @@ __device__ __forceinline__ void vec_normalize(double& Q, double& P, double& D) {
   D = __builtin_amdgcn_ldexp(D, -ex);
 }
 
-// A double moved across lanes by a DPP control (each 32-bit half moved the
-// same way); lanes the control gives no source keep 0.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_move(double x) {
-  const long long v = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, ROWS, 0xf, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
+// A map moved across lanes; lanes without a source get the identity, which
+// composes and applies exactly (no rounding), so that the scans need no
+// per-lane selection.
 template <int CTRL, int ROWS>
 __device__ __forceinline__ FwdMap fwd_dpp(const FwdMap& X) {
-  return {dpp_move<CTRL, ROWS>(X.a00), dpp_move<CTRL, ROWS>(X.a01), dpp_move<CTRL, ROWS>(X.a10),
-          dpp_move<CTRL, ROWS>(X.a11), dpp_move<CTRL, ROWS>(X.v0),  dpp_move<CTRL, ROWS>(X.v1),
-          dpp_move<CTRL, ROWS>(X.s)};
+  return {dpp_move<CTRL, ROWS, true>(X.a00), dpp_move<CTRL, ROWS>(X.a01),
+          dpp_move<CTRL, ROWS>(X.a10),       dpp_move<CTRL, ROWS, true>(X.a11),
+          dpp_move<CTRL, ROWS>(X.v0),        dpp_move<CTRL, ROWS>(X.v1),
+          dpp_move<CTRL, ROWS, true>(X.s)};
 }
 
-// DPP controls: shift right by n within each row of 16 lanes; broadcast
-// lane 15 of each row to the next row; lane 31 to rows 2 and 3; shift the
-// whole wave right by one lane.
-constexpr int kDppRowShr = 0x110;
-constexpr int kDppRowBcast15 = 0x142;
-constexpr int kDppRowBcast31 = 0x143;
-constexpr int kDppWaveShr1 = 0x138;
-constexpr int kDppWaveShl1 = 0x130;
 
 // Inclusive scan of the maps over the lanes of a wave (lane l gets the
 // composition of lanes 0..l, later after earlier): Kogge-Stone within each
 // row of 16 lanes, then the row totals broadcast down the wave.
-__device__ __forceinline__ FwdMap fwd_wave_scan(FwdMap G, int lane) {
-  const int i = lane & 15;
-  { const FwdMap Y = fwd_dpp<kDppRowShr + 1, 0xf>(G); if (i >= 1) G = fwd_compose(G, Y); }
-  { const FwdMap Y = fwd_dpp<kDppRowShr + 2, 0xf>(G); if (i >= 2) G = fwd_compose(G, Y); }
-  { const FwdMap Y = fwd_dpp<kDppRowShr + 4, 0xf>(G); if (i >= 4) G = fwd_compose(G, Y); }
-  { const FwdMap Y = fwd_dpp<kDppRowShr + 8, 0xf>(G); if (i >= 8) G = fwd_compose(G, Y); }
-  { const FwdMap Y = fwd_dpp<kDppRowBcast15, 0xa>(G); if (lane & 16) G = fwd_compose(G, Y); }
-  { const FwdMap Y = fwd_dpp<kDppRowBcast31, 0xc>(G); if (lane & 32) G = fwd_compose(G, Y); }
+__device__ __forceinline__ FwdMap fwd_wave_scan(FwdMap G) {
+  // (the first n lanes of each row under a shift by n, and the rows a
+  // broadcast skips, compose with the identity)
+  G = fwd_compose(G, fwd_dpp<kDppRowShr + 1, 0xf>(G));
+  G = fwd_compose(G, fwd_dpp<kDppRowShr + 2, 0xf>(G));
+  G = fwd_compose(G, fwd_dpp<kDppRowShr + 4, 0xf>(G));
+  G = fwd_compose(G, fwd_dpp<kDppRowShr + 8, 0xf>(G));
+  G = fwd_compose(G, fwd_dpp<kDppRowBcast15, 0xa>(G));
+  G = fwd_compose(G, fwd_dpp<kDppRowBcast31, 0xc>(G));
   return G;
 }
 
@@ -293,15 +324,20 @@ __device__ __forceinline__ void fwd_enter(const double* fwd_lds, int wid, double
 
 // Suffix scan of back-substitution maps x -> al + be x over the lanes of a
 // wave (lane l gets lanes l..63 composed, l's map applied last): within
-// each row of 16 lanes by DPP shifts, then the later rows' totals.
-constexpr int kDppRowShl = 0x100;
+// each row of 16 lanes by DPP shifts, then the later rows' totals.  With
+// kFill the last n lanes of each row under a shift by n compose with the
+// identity x -> 0 + 1 x (exact) instead of keeping their maps by a select;
+// the two give the same values and differ only in register demand.
+template <bool kFill = true>
 __device__ __forceinline__ void bwd_wave_scan(double& al, double& be, int lane) {
-  const int i = lane & 15;
 #define SEMD_BWD_STEP(n)                                                        \
   {                                                                             \
     const double a2 = dpp_move<kDppRowShl + n, 0xf>(al);                        \
-    const double b2 = dpp_move<kDppRowShl + n, 0xf>(be);                        \
-    if (i + n < 16) { al = fma(be, a2, al); be = be * b2; }                     \
+    const double b2 = dpp_move<kDppRowShl + n, 0xf, kFill>(be);                 \
+    if (kFill || (lane & 15) + n < 16) {                                        \
+      al = fma(be, a2, al);                                                     \
+      be = be * b2;                                                             \
+    }                                                                           \
   }
   SEMD_BWD_STEP(1)
   SEMD_BWD_STEP(2)

@@ -303,7 +303,7 @@ __device__ __forceinline__ void solve_envelopes(const Knots ks, int n1, int n2, 
       fwd_normalize(G);
     }
     if (wave_active) {
-      G = fwd_wave_scan(G, lane);
+      G = fwd_wave_scan(G);
       if (lane == kWave - 1) {
         double* o = fwd_lds + 7 * wid;
         o[0] = G.a00; o[1] = G.a01; o[2] = G.a10; o[3] = G.a11;
@@ -363,7 +363,7 @@ __device__ __forceinline__ void solve_envelopes(const Knots ks, int n1, int n2, 
     if (((k - k0) & 3) == 3) fwd_normalize(G);
   }
   fwd_normalize(G);
-  G = fwd_wave_scan(G, lane);
+  G = fwd_wave_scan(G);
   if (lane == kWave - 1) {
     double* o = fwd_lds + 7 * wid;
     o[0] = G.a00; o[1] = G.a01; o[2] = G.a10; o[3] = G.a11;

@@ -39,14 +39,35 @@ __device__ __forceinline__ bool sifting(const SigStatus& st) {
   return st.action == kSift || st.action == kSiftLast;
 }
 
+// Inclusive scans within a wave by DPP moves (Kogge-Stone within each row of
+// 16 lanes, then the row totals broadcast down the wave): maximum, sum.
+constexpr int kIntMin = -2147483647 - 1;
+__device__ __forceinline__ int wave_incl_max(int v) {
+  v = max(v, dpp_int<kDppRowShr + 1, 0xf, kIntMin>(v));
+  v = max(v, dpp_int<kDppRowShr + 2, 0xf, kIntMin>(v));
+  v = max(v, dpp_int<kDppRowShr + 4, 0xf, kIntMin>(v));
+  v = max(v, dpp_int<kDppRowShr + 8, 0xf, kIntMin>(v));
+  v = max(v, dpp_int<kDppRowBcast15, 0xa, kIntMin>(v));
+  v = max(v, dpp_int<kDppRowBcast31, 0xc, kIntMin>(v));
+  return v;
+}
+__device__ __forceinline__ int64_t wave_incl_sum64(int64_t v) {
+  v += dpp_i64<kDppRowShr + 1, 0xf>(v);
+  v += dpp_i64<kDppRowShr + 2, 0xf>(v);
+  v += dpp_i64<kDppRowShr + 4, 0xf>(v);
+  v += dpp_i64<kDppRowShr + 8, 0xf>(v);
+  v += dpp_i64<kDppRowBcast15, 0xa>(v);
+  v += dpp_i64<kDppRowBcast31, 0xc>(v);
+  return v;
+}
+
 // Block-wide reductions / scans over kTT threads (one barrier each, plus one
 // on entry so the LDS scratch can be reused back to back).
 __device__ __forceinline__ int block_max(int v, int* scratch) {
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) v = max(v, __shfl_xor(v, d, kWave));
+  v = wave_incl_max(v);
   __syncthreads();
-  if (lane == 0) scratch[wid] = v;
+  if (lane == kWave - 1) scratch[wid] = v;
   __syncthreads();
   int m = scratch[0];
 #pragma unroll
@@ -58,12 +79,7 @@ __device__ __forceinline__ int block_max(int v, int* scratch) {
 __device__ __forceinline__ int64_t block_excl_sum64(int64_t v, int64_t* scratch,
                                                     int64_t& total) {
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  int64_t inc = v;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const int64_t u = __shfl_up(inc, d, kWave);
-    if (lane >= d) inc += u;
-  }
+  const int64_t inc = wave_incl_sum64(v);
   __syncthreads();
   if (lane == kWave - 1) scratch[wid] = inc;
   __syncthreads();
@@ -80,13 +96,8 @@ __device__ __forceinline__ int64_t block_excl_sum64(int64_t v, int64_t* scratch,
 
 __device__ __forceinline__ int block_excl_max(int v, int* scratch, int& total) {
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  int inc = v;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const int u = __shfl_up(inc, d, kWave);
-    if (lane >= d) inc = max(inc, u);
-  }
-  const int ex_in_wave = __shfl_up(inc, 1, kWave);
+  const int inc = wave_incl_max(v);
+  const int ex_in_wave = dpp_int<kDppWaveShr1, 0xf, kIntMin>(inc);  // (lane 0: unused)
   __syncthreads();
   if (lane == kWave - 1) scratch[wid] = inc;
   __syncthreads();
@@ -601,7 +612,7 @@ __global__ void __launch_bounds__(kTT) st_solve_kernel(const StreamSig* __restri
     }
   }
   fwd_normalize(G);
-  G = fwd_wave_scan(G, lane);
+  G = fwd_wave_scan(G);
   if (lane == kWave - 1) {
     double* o = fwd_lds + 7 * wid;
     o[0] = G.a00; o[1] = G.a01; o[2] = G.a10; o[3] = G.a11;
@@ -645,7 +656,7 @@ __global__ void __launch_bounds__(kTT) st_solve_kernel(const StreamSig* __restri
       be = -cpa[q] * be;
     }
   }
-  bwd_wave_scan(al, be, lane);
+  bwd_wave_scan<false>(al, be, lane);  // (the fill raises this kernel's registers)
   if (lane == 0) {
     bwd_lds[2 * wid] = al;
     bwd_lds[2 * wid + 1] = be;
