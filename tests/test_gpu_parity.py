@@ -141,6 +141,40 @@ def test_config2_faces_batch_subset(D):
     assert len(ties) <= 1
 
 
+def test_config2_full_face_batch_sampled():
+    """The face batch at its full size in the launch configuration the bench
+    times (1,024 images of 112x92, D = 0, K = 8, S = 10, one batched launch
+    through prepared descriptors): 16 images spread over the batch against
+    the oracle element by element, and for every image the IMF count in
+    range, the unused slots zero and the slots summing back to the input."""
+    K, S = 8, 10
+    items = workloads.config2(1024)
+    M, N = items[0].M, items[0].N
+    n = len(items)
+    X = torch.from_numpy(np.stack([it.X for it in items])).to(DEV)
+    out = torch.empty((n, K + 1, M * N), dtype=torch.float64, device=DEV)
+    counts = torch.zeros(n, dtype=torch.int32, device=DEV)
+    semd.PreparedBatch([X[i] for i in range(n)], [[M, N]] * n, [out[i] for i in range(n)],
+                       counts, 0, K, S).run()
+    cnt = host(counts)
+    assert cnt.min() >= 1 and cnt.max() <= K
+    # slots n_imfs .. K-1 zero, all slots summing back to the input
+    slot = torch.arange(K, device=DEV).view(1, K, 1)
+    unused = slot >= counts.view(n, 1, 1).long()
+    assert float((out[:, :K] * unused).abs().max()) == 0.0
+    xmax = X.abs().amax(dim=1)
+    recon = (out.sum(dim=1) - X).abs().amax(dim=1)
+    assert bool((recon <= 1e-12 * xmax).all()), float((recon / xmax).max())
+    rng = np.random.default_rng(2106)
+    pick = sorted(set([0, 1, 255, 256, 511, 512, 767, n - 1] +
+                      rng.choice(n, 8, replace=False).tolist()))
+    ties = []
+    o = host(out[pick])
+    for j, i in enumerate(pick):
+        _check_item(items[i].X, M, N, 0, K, S, o[j], int(cnt[i]), ties)
+    assert len(ties) <= 1
+
+
 def test_config1_textures_subset():
     items = workloads.config1(4)
     ties = []
@@ -251,6 +285,31 @@ def test_eemd_matches_oracle():
     err = np.abs(host(out) - ref).max()
     assert err <= TOL * np.abs(it.X).max(), err
     assert 1 <= int(host(cnt)[0]) <= K
+
+
+def test_eemd_uneven_subset_full_size_sampled():
+    """The uneven-series EEMD workload at the size the bench times (the first
+    32 series of the batch, 64 realizations each, K = 6, S = 10, one
+    semd_eemd_batch call through prepared descriptors): the two shortest
+    series against the oracle element by element, every IMF count in
+    range and every output finite."""
+    K, S, D, NR, seed = 6, 10, 0, 64, 2106
+    shapes = workloads.config3_shapes(4096)
+    items = [workloads.config3_item(i, shapes[i]) for i in range(32)]
+    Xs = [dev(it.X) for it in items]
+    outs = [torch.empty((K + 1, it.M * it.N), dtype=torch.float64, device=DEV) for it in items]
+    cnt = torch.empty(len(items), dtype=torch.int32, device=DEV)
+    sig = [0.2 * float(np.std(it.X)) for it in items]
+    semd.PreparedBatch(Xs, [[it.M, it.N] for it in items], outs, cnt, D, K, S, ensemble=NR,
+                       seed=seed, noise_sigmas=sig, item_ids=list(range(32))).run()
+    c = host(cnt)
+    assert c.min() >= 1 and c.max() <= K
+    assert all(bool(torch.isfinite(o).all()) for o in outs)
+    for i in sorted(range(32), key=lambda i: items[i].M * items[i].N)[:2]:
+        it = items[i]
+        ref = oracle.eemd(it.X, it.M, it.N, D, K, S, NR, sig[i], seed, i)
+        err = np.abs(host(outs[i]) - ref).max()
+        assert err <= TOL * np.abs(it.X).max(), (i, err)
 
 
 def test_eemd_zero_noise_single_realization_is_emd():
