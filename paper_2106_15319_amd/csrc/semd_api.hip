@@ -294,7 +294,7 @@ semd::ResidentClass class_for(int L, int regime) {
     const int b = bucket_of(L);
     if (g_tune.set[regime][b]) return g_tune.cls[regime][b];
   }
-  return semd::resident_class(L);
+  return semd::resident_class(L, regime);
 }
 
 bool class_compiled(semd::ResidentClass c) {

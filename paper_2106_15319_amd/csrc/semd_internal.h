@@ -55,12 +55,13 @@ __host__ __device__ constexpr int64_t resident_ws_doubles(int64_t L) {
 
 // Launch shape of the resident kernel: threads per workgroup and samples per
 // thread.  resident_class() is the default choice for the longest signal of a
-// launch (a tuned table may choose another).
+// launch of few signals (regime 0) or of at least one per compute unit
+// (regime 1); a tuned table may choose another.
 struct ResidentClass {
   int nt;
   int c;
 };
-ResidentClass resident_class(int maxL);
+ResidentClass resident_class(int maxL, int regime);
 
 // Bytes of the kernel's reusable LDS area (staging window, knot store) for
 // signals up to maxL samples, at most max_area (and at least what the

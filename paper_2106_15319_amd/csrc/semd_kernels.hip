@@ -1173,12 +1173,15 @@ __global__ void __launch_bounds__(kCT) ceemdan_finish_kernel(const CeemdanJob* _
 // Launchers
 // ---------------------------------------------------------------------------
 
-// Threads and samples per thread for signals up to maxL samples.
-// Defaults: the shapes the tuner picks on MI355X (more threads per signal
-// beat more signals per CU: the sift phases are bound by latency).
-ResidentClass resident_class(int maxL) {
-  if (maxL <= 256 * 4) return {256, 4};
-  if (maxL <= 1024 * 4 && maxL <= 2048) return {1024, 4};
+// Threads and samples per thread for signals up to maxL samples, for a
+// launch of few signals (regime 0: each has a CU to itself) or of at least
+// one per CU (regime 1).  Defaults: the shapes the tuner picks on MI355X
+// (more threads per signal beat more signals per CU, the sift phases being
+// bound by latency, except for short signals in full launches).
+ResidentClass resident_class(int maxL, int regime) {
+  if (regime == 1 && maxL <= 256 * 4) return {256, 4};
+  if (regime == 1 && maxL <= 256 * 8) return {256, 8};
+  if (regime == 0 && maxL <= 1024 * 3) return {1024, 4};
   if (maxL <= 512 * 8) return {512, 8};
   if (maxL <= 1024 * 8) return {1024, 8};
   if (maxL <= 1024 * 12) return {1024, 12};
