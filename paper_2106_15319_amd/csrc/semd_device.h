@@ -280,6 +280,14 @@ __device__ __forceinline__ void vec_normalize(double& Q, double& P, double& D) {
   D = __builtin_amdgcn_ldexp(D, -ex);
 }
 
+// A double of lane `src` (the same for the whole wave) to every lane.
+__device__ __forceinline__ double lane_value(double x, int src) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)v, src);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // A map moved across lanes; lanes without a source get the identity, which
 // composes and applies exactly (no rounding), so that the scans need no
 // per-lane selection.
@@ -344,8 +352,22 @@ __device__ __forceinline__ void bwd_wave_scan(double& al, double& be, int lane) 
   SEMD_BWD_STEP(4)
   SEMD_BWD_STEP(8)
 #undef SEMD_BWD_STEP
-  // rows 0..2 take row r+1's total (its lane 0), then rows 0..1 row r+2's
   const int row = lane >> 4;
+  if (kFill) {
+    // the totals of rows 1..3 (their lane 0) read out and composed once:
+    // after row 2 comes T3, after row 1 T2 T3, after row 0 T1 T2 T3
+    const double a1 = lane_value(al, 16), b1 = lane_value(be, 16);
+    const double a2 = lane_value(al, 32), b2 = lane_value(be, 32);
+    const double a3 = lane_value(al, 48), b3 = lane_value(be, 48);
+    const double s1a = fma(b2, a3, a2), s1b = b2 * b3;
+    const double s0a = fma(b1, s1a, a1), s0b = b1 * s1b;
+    const double sa = row == 0 ? s0a : (row == 1 ? s1a : (row == 2 ? a3 : 0.0));
+    const double sb = row == 0 ? s0b : (row == 1 ? s1b : (row == 2 ? b3 : 1.0));
+    al = fma(be, sa, al);
+    be = be * sb;
+    return;
+  }
+  // rows 0..2 take row r+1's total (its lane 0), then rows 0..1 row r+2's
   {
     const int src = min(row + 1, 3) << 4;
     const double a2 = __shfl(al, src, kWave), b2 = __shfl(be, src, kWave);
