@@ -86,15 +86,19 @@ __device__ __forceinline__ void rd_detect(const double (&h)[C], int base, int nv
                                           double* pub_first, double* pub_last, int* pub_key,
                                           unsigned& R, unsigned& F, int& carry,
                                           unsigned& maxbits, unsigned& minbits) {
+  // step bits b = C-1 .. 1 shifted in from the top (doubling plus the
+  // comparison: one add with carry each), then the bits of samples beyond
+  // nv cleared
   R = 0u;
   F = 0u;
 #pragma unroll
-  for (int b = 1; b < C; ++b) {
-    if (b < nv) {
-      R |= (h[b] > h[b - 1] ? 1u : 0u) << b;
-      F |= (h[b] < h[b - 1] ? 1u : 0u) << b;
-    }
+  for (int b = C - 1; b >= 1; --b) {
+    R = R + R + (h[b] > h[b - 1] ? 1u : 0u);
+    F = F + F + (h[b] < h[b - 1] ? 1u : 0u);
   }
+  const unsigned live = nv > 0 ? (1u << nv) - 1u : 0u;
+  R = (R << 1) & live;
+  F = (F << 1) & live;
   if (nv > 0) {
     const unsigned inner = R | F;
     int key = -1;
@@ -315,8 +319,7 @@ __device__ __forceinline__ void solve_envelopes(const Knots ks, int n1, int n2, 
     if (wave_active) {
       double Q, P, D;
       fwd_enter(fwd_lds, wid, Q, P, D);
-      const FwdMap Y = fwd_dpp<kDppWaveShr1, 0xf>(G);
-      if (lane > 0) fwd_apply(Y, Q, P, D);
+      fwd_apply(fwd_dpp<kDppWaveShr1, 0xf>(G), Q, P, D);  // (lane 0: the identity)
       if (has) {
         const double q = fma(b, Q, -a * P);
         D = fma(r, Q, -a * D);
@@ -336,8 +339,8 @@ __device__ __forceinline__ void solve_envelopes(const Knots ks, int n1, int n2, 
     __syncthreads();
     if (wave_active) {
       double Mn = bwd_after(bwd_lds, wid, wact);
-      const double a2 = dpp_move<kDppWaveShl1, 0xf>(al), b2 = dpp_move<kDppWaveShl1, 0xf>(be);
-      if (lane + 1 < kWave) Mn = fma(b2, Mn, a2);
+      // (lane 63: the identity x -> 0 + 1 x)
+      Mn = fma(dpp_move<kDppWaveShl1, 0xf, true>(be), Mn, dpp_move<kDppWaveShl1, 0xf>(al));
       if (has) {
         const double Mk = fma(-cp, Mn, dp);
         if (!last) {
@@ -373,11 +376,8 @@ __device__ __forceinline__ void solve_envelopes(const Knots ks, int n1, int n2, 
   {
     double Q, P, D;
     fwd_enter(fwd_lds, wid, Q, P, D);
-    const FwdMap Y = fwd_dpp<kDppWaveShr1, 0xf>(G);
-    if (lane > 0) {
-      fwd_apply(Y, Q, P, D);
-      vec_normalize(Q, P, D);
-    }
+    fwd_apply(fwd_dpp<kDppWaveShr1, 0xf>(G), Q, P, D);  // (lane 0: the identity)
+    vec_normalize(Q, P, D);
     // each row's c' (into m) and d' (into q1): rows of this thread only
     for (int k = k0; k < k1; ++k) {
       double a, b, c, r, sl, g, ig, yk;
@@ -407,8 +407,8 @@ __device__ __forceinline__ void solve_envelopes(const Knots ks, int n1, int n2, 
   __syncthreads();
   {
     double Mn = bwd_after(bwd_lds, wid, NW);
-    const double a2 = dpp_move<kDppWaveShl1, 0xf>(al), b2 = dpp_move<kDppWaveShl1, 0xf>(be);
-    if (lane + 1 < kWave) Mn = fma(b2, Mn, a2);
+    // (lane 63: the identity x -> 0 + 1 x)
+    Mn = fma(dpp_move<kDppWaveShl1, 0xf, true>(be), Mn, dpp_move<kDppWaveShl1, 0xf>(al));
     for (int k = k1 - 1; k >= k0; --k) {
       const double cp = ks.m[k], dp = ks.q1[k];
       const double Mk = fma(-cp, Mn, dp);
