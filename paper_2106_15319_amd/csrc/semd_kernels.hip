@@ -429,16 +429,16 @@ __device__ __forceinline__ void solve_envelopes(const Knots ks, int n1, int n2, 
   __syncthreads();
 }
 
-// Walker over the segments of one envelope: the current segment [t0, t1),
-// its halved power-form coefficients and the local abscissa B = k - t0.
+// Walker over the segments of one envelope: the current segment j =
+// [t_j, t1), its halved power-form coefficients and the local abscissa
+// B = k - t_j.
 struct Walk {
-  int j, t0, t1;
+  int j, t1;
   double B, q0, q1, q2, q3;
 };
 
 __device__ __forceinline__ void walk_load(Walk& w, const Knots& ks, int j) {
   w.j = j;
-  w.t0 = ks.t[j];
   w.t1 = ks.t[j + 1];
   w.q0 = ks.y[j];
   w.q1 = ks.q1[j];
@@ -449,17 +449,22 @@ __device__ __forceinline__ void walk_load(Walk& w, const Knots& ks, int j) {
 // Position at the segment holding sample k, starting from segment j (whose
 // left knot lies at or before k; the last knot lies beyond the signal).
 __device__ __forceinline__ void walk_init(Walk& w, const Knots& ks, int j, int k) {
+  int t0 = ks.t[j];
   walk_load(w, ks, j);
-  while (w.t1 <= k) walk_load(w, ks, w.j + 1);
-  w.B = (double)(k - w.t0);
+  while (w.t1 <= k) {
+    t0 = w.t1;
+    walk_load(w, ks, w.j + 1);
+  }
+  w.B = (double)(k - t0);
 }
 
 // Half the envelope at sample k, the walker standing at k (knots are
-// distinct integers, so one step from k-1 crosses at most one of them).
+// distinct integers, so one step from k-1 crosses at most one of them, and
+// the new segment starts where the old one ends).
 __device__ __forceinline__ double walk_at(Walk& w, const Knots& ks, int k) {
   if (w.t1 <= k) {
+    w.B = (double)(k - w.t1);
     walk_load(w, ks, w.j + 1);
-    w.B = (double)(k - w.t0);
   }
   return fma(fma(fma(w.q3, w.B, w.q2), w.B, w.q1), w.B, w.q0);
 }
