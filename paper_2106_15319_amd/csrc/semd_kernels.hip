@@ -597,6 +597,11 @@ __device__ __forceinline__ void sift_both(double (&h)[C], unsigned maxbits, unsi
 __device__ __forceinline__ void opaque(int& v) { asm volatile("" : "+v"(v)); }
 __device__ __forceinline__ void opaque(unsigned& v) { asm volatile("" : "+v"(v)); }
 
+// Position in the staging window of chunk sample j (blocks of C samples,
+// each followed by one spare double).
+template <int C>
+__device__ __forceinline__ int stage_at(int j) { return j + j / C; }
+
 // Samples of the chunk [c0, c1) of the signal that thread-owned slot c maps to.
 __device__ __forceinline__ bool in_chunk(int k, int c0, int c1) { return k >= c0 && k < c1; }
 
@@ -645,7 +650,10 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
   int* pub_key = reinterpret_cast<int*>(pub_last + NT);
   unsigned char* area = smem + kAggBytes + pub_bytes(NT);
   const int capk = area_bytes / kKnotBytes;  // knots the LDS store can take
-  const int scap = (area_bytes / (int)sizeof(double)) / NT * NT;
+  // Staging window for loads and IMF ends: the samples of whole thread
+  // blocks, each block followed by one spare double, so that the blocked
+  // accesses (stride C + 1 doubles, C even) fall on distinct LDS banks.
+  const int scap = (area_bytes / (int)sizeof(double)) / (C + 1) * C;
   double* stage = reinterpret_cast<double*>(area);
   const Knots lk = knots_in(area, capk);
   const Knots gk = knots_in(reinterpret_cast<unsigned char*>(w.u), resident_gknot_cap(L));
@@ -671,13 +679,13 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
         v = __dadd_rn(v, __dmul_rn(b, e));
       }
       bad |= !isfinite(v);
-      stage[k - c0] = v;
+      stage[stage_at<C>(k - c0)] = v;
       w.r[k] = v;
     }
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < C; ++c)
-      if (c < nv0 && in_chunk(base0 + c, c0, c1)) h[c] = stage[base0 + c - c0];
+      if (c < nv0 && in_chunk(base0 + c, c0, c1)) h[c] = stage[stage_at<C>(base0 - c0) + c];
   }
   const int64_t SS = w.slot_stride;
   if (__syncthreads_or(bad)) {
@@ -790,7 +798,7 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
       __syncthreads();
 #pragma unroll
       for (int c = 0; c < C; ++c)
-        if (c < nv && in_chunk(base + c, c0, c1)) stage[base + c - c0] = h[c];
+        if (c < nv && in_chunk(base + c, c0, c1)) stage[stage_at<C>(base - c0) + c] = h[c];
       __syncthreads();
       for (int k0 = c0 + tid; k0 < c1; k0 += 4 * NT) {
         // four elements per pass, their residue loads issued together
@@ -804,10 +812,11 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
         for (int u = 0; u < 4; ++u) {
           const int k = k0 + u * NT;
           if (k < c1) {
-            const double hk = stage[k - c0];
+            const int si = stage_at<C>(k - c0);
+            const double hk = stage[si];
             const double nr = rk[u] - hk;
             w.r[k] = nr;
-            stage[k - c0] = nr;
+            stage[si] = nr;
             int i, m;
             div_small(k, R, invR, i, m);
             if (m < M) slot[i * M + m] = hk;
@@ -817,7 +826,7 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
       __syncthreads();
 #pragma unroll
       for (int c = 0; c < C; ++c)
-        if (c < nv && in_chunk(base + c, c0, c1)) h[c] = stage[base + c - c0];
+        if (c < nv && in_chunk(base + c, c0, c1)) h[c] = stage[stage_at<C>(base - c0) + c];
     }
     ++nimf;
   }
