@@ -112,10 +112,18 @@ __device__ __forceinline__ int block_excl_max(int v, int* scratch, int& total) {
   return lane > 0 ? max(before, ex_in_wave) : before;
 }
 
+// Position of tile sample i in the LDS tile buffer: within each block of
+// kTC = 8 samples (one thread's), the sample index is XORed with bits 2..4
+// of the block index, so that the threads' blocked accesses (stride 8
+// doubles) fall on distinct banks for 32 lanes, while consecutive samples
+// stay within their block.
+static_assert(kTC == 8, "tile buffer swizzle assumes 8 samples per thread");
+__device__ __forceinline__ int tsw(int i) { return i ^ ((i >> 5) & 7); }
+
 // Stage samples a .. a+n-1 of h in LDS and return the halo neighbours.
 __device__ __forceinline__ void stage_tile(const double* __restrict__ h, int a, int n, int L,
                                            double* tbuf, double& prev, double& next) {
-  for (int i = threadIdx.x; i < n; i += kTT) tbuf[i] = h[a + i];
+  for (int i = threadIdx.x; i < n; i += kTT) tbuf[tsw(i)] = h[a + i];
   prev = a > 0 ? h[a - 1] : 0.0;
   next = a + n < L ? h[a + n] : 0.0;
 }
@@ -365,12 +373,12 @@ __global__ void __launch_bounds__(kTT) st_detect_kernel(const StreamSig* __restr
   if (threadIdx.x == 0) cont_exit = 0;
   __syncthreads();
   const int first_key =
-      a == 0 ? 0 : (prev != tbuf[0] ? a * 4 + step_kind(prev, tbuf[0]) : kCont);
+      a == 0 ? 0 : (prev != tbuf[tsw(0)] ? a * 4 + step_kind(prev, tbuf[tsw(0)]) : kCont);
   double h[kTC];
 #pragma unroll
   for (int c = 0; c < kTC; ++c) {
     const int i = threadIdx.x * kTC + c;
-    h[c] = i < n ? tbuf[i] : 0.0;
+    h[c] = i < n ? tbuf[tsw(i)] : 0.0;
   }
   TileDet d;
   tile_detect<kTC>(h, a, n, L, threadIdx.x, first_key, next, pub_first, pub_last, pub_key,
@@ -769,7 +777,7 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
   if (action == kIdle) return;
   const int L = S.L;
   const int a = tv.y * kTile, n = min(kTile, L - a);
-  for (int i = threadIdx.x; i < n; i += kTT) tbuf[i] = S.h[a + i];
+  for (int i = threadIdx.x; i < n; i += kTT) tbuf[tsw(i)] = S.h[a + i];
   if (action == kSift || action == kSiftLast) {
     const int lb = threadIdx.x * kTC;
     const int nv = max(0, min(kTC, n - lb));
@@ -811,10 +819,10 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
           const int k = k0 + c;
           const double up = st_walk_at(wk[0], S, 0, k);
           const double lo = st_walk_at(wk[1], S, 1, k);
-          const double m = up + lo, hk = tbuf[lb + c];
+          const double m = up + lo, hk = tbuf[tsw(lb + c)];
           num = fma(m, m, num);
           den = fma(hk, hk, den);
-          tbuf[lb + c] = hk - m;
+          tbuf[tsw(lb + c)] = hk - m;
           wk[0].B += 1.0;
           wk[1].B += 1.0;
         }
@@ -844,10 +852,10 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
       const double prev = a > 0 ? halo[0] : 0.0;
       const double next = a + n < L ? halo[1] : 0.0;
       const int first_key =
-          a == 0 ? 0 : (prev != tbuf[0] ? a * 4 + step_kind(prev, tbuf[0]) : kCont);
+          a == 0 ? 0 : (prev != tbuf[tsw(0)] ? a * 4 + step_kind(prev, tbuf[tsw(0)]) : kCont);
       double h[kTC];
 #pragma unroll
-      for (int c = 0; c < kTC; ++c) h[c] = lb + c < n ? tbuf[lb + c] : 0.0;
+      for (int c = 0; c < kTC; ++c) h[c] = lb + c < n ? tbuf[tsw(lb + c)] : 0.0;
       TileDet d;
       tile_detect<kTC>(h, a, n, L, threadIdx.x, first_key, next, pub_first, pub_last, pub_key,
                        &cont_exit, &cont_pos, &cont_y, d);
@@ -861,10 +869,10 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
     double* slot = S.out + (int64_t)st->slot * S.slot_stride;
     for (int i = threadIdx.x; i < n; i += kTT) {
       const int k = a + i;
-      const double hk = tbuf[i];
+      const double hk = tbuf[tsw(i)];
       const double nr = S.r[k] - hk;
       S.r[k] = nr;
-      tbuf[i] = nr;
+      tbuf[tsw(i)] = nr;
       const int64_t ii = k / R, m = k - ii * R;
       if (m < M) slot[ii * M + m] = hk;
     }
@@ -878,7 +886,7 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
       if (m < M) {
         const int64_t o = ii * M + m;
         for (int q = nimf; q < K; ++q) S.out[q * S.slot_stride + o] = 0.0;
-        S.out[(int64_t)K * S.slot_stride + o] = bad ? 0.0 : tbuf[i];
+        S.out[(int64_t)K * S.slot_stride + o] = bad ? 0.0 : tbuf[tsw(i)];
       }
     }
     if (tv.y == 0 && threadIdx.x == 0) {
@@ -891,7 +899,7 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
       S.st->done = 1;
     }
   } else {
-    for (int i = threadIdx.x; i < n; i += kTT) S.h[a + i] = tbuf[i];
+    for (int i = threadIdx.x; i < n; i += kTT) S.h[a + i] = tbuf[tsw(i)];
   }
 }
 
