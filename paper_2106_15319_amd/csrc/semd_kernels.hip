@@ -356,7 +356,10 @@ __device__ __forceinline__ void solve_envelopes(const Knots ks, int n1, int n2, 
   }
 
   // more rows than threads: blocks of R rows per thread over all waves
-  const int R = (rows + NT - 1) / NT;
+  // (R a multiple of 4 is raised by one: row blocks whose starts lie a
+  // multiple of 8 doubles apart would share LDS banks 4 ways or more)
+  int R = (rows + NT - 1) / NT;
+  R += (R & 3) == 0 ? 1 : 0;
   const int k0 = tid * R, k1 = min(rows, k0 + R);
   FwdMap G = fwd_identity();
   for (int k = k0; k < k1; ++k) {

@@ -597,7 +597,10 @@ __global__ void __launch_bounds__(kTT) st_solve_kernel(const StreamSig* __restri
 #define T(j) ((double)lt[(j) - w0])
 #define Y(j) (ly[(j) - w0])
   const int rows = a1 - a0 + 1;
-  const int R = (rows + kTT - 1) / kTT;  // <= kRMax
+  // (<= kRMax; a multiple of 4 is raised by one: row blocks whose starts
+  // lie a multiple of 8 doubles apart would share LDS banks 4 ways or more)
+  int R = (rows + kTT - 1) / kTT;
+  R += (R & 3) == 0 ? 1 : 0;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int j0 = a0 + threadIdx.x * R;
   // row j's equation a M_{j-1} + b M_j + c M_{j+1} = r
