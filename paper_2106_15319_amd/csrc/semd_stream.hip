@@ -147,17 +147,22 @@ struct TileDet {
 // of a run that started before the tile, or kCont when that key is unknown
 // (its extremum, if any, is then left to the scan: the direction the run is
 // left in is written to *cont_exit, the sample it ends at to *cont_pos and
-// its value to *cont_y).  next is sample a+n when a+n < L.
+// its value to *cont_y).  next is sample a+n when a+n < L.  The tile buffer
+// tb holds the same samples (swizzled positions), from which the
+// neighbouring threads' first and last samples are read.
 // Bit b of the rise (fall) mask marks sample b above (below) sample b-1, bit
 // C the step to the next thread's first sample; a sample closes a run when
 // its next step is not flat, and the run is a maximum when entered rising
 // and left falling (minimum: the reverse).  Contains one barrier.
 template <int C>
 __device__ __forceinline__ void tile_detect(const double (&h)[C], int a, int n, int L, int tid,
-                                            int first_key, double next, double* pub_first,
-                                            double* pub_last, int* pub_key, int* cont_exit,
-                                            int* cont_pos, double* cont_y, TileDet& d) {
+                                            int first_key, double next, const double* tb,
+                                            int* pub_key, int* cont_exit, int* cont_pos,
+                                            double* cont_y, TileDet& d) {
   const int lb = tid * C, base = a + lb;
+  // first and last sample of thread t's block (t holding at least one)
+  auto first_of = [&](int t) { return tb[tsw(t * C)]; };
+  auto last_of = [&](int t) { return tb[tsw(min(t * C + C, n) - 1)]; };
   const int nv = max(0, min(C, n - lb));
   unsigned R = 0u, F = 0u;
 #pragma unroll
@@ -174,14 +179,6 @@ __device__ __forceinline__ void tile_detect(const double (&h)[C], int a, int n, 
       const int b = 31 - __clz(inner);
       key = (base + b) * 4 + (((R >> b) & 1u) ? kRise : kFall);
     }
-    double last = h[C - 1];
-    if (nv < C) {
-#pragma unroll
-      for (int c = 0; c < C - 1; ++c)
-        if (c == nv - 1) last = h[c];
-    }
-    pub_first[tid] = h[0];
-    pub_last[tid] = last;
     pub_key[tid] = key;
   }
   __syncthreads();
@@ -193,7 +190,7 @@ __device__ __forceinline__ void tile_detect(const double (&h)[C], int a, int n, 
   if (nv <= 0) return;
   int carry = first_key;
   if (tid > 0) {
-    const double prev = pub_last[tid - 1];
+    const double prev = last_of(tid - 1);
     R |= h[0] > prev ? 1u : 0u;
     F |= h[0] < prev ? 1u : 0u;
     if (prev != h[0]) {
@@ -205,7 +202,7 @@ __device__ __forceinline__ void tile_detect(const double (&h)[C], int a, int n, 
         const int kk = pub_key[tau];
         if (kk >= 0) { carry = kk; break; }
         if (tau == 0) { carry = first_key; break; }
-        const double pl = pub_last[tau - 1], pf = pub_first[tau];
+        const double pl = last_of(tau - 1), pf = first_of(tau);
         if (pl != pf) { carry = (a + tau * C) * 4 + step_kind(pl, pf); break; }
         --tau;
       }
@@ -216,7 +213,7 @@ __device__ __forceinline__ void tile_detect(const double (&h)[C], int a, int n, 
     F |= (first_key & 3) == kFall ? 1u : 0u;
   }
   if (nv == C && base + C < L) {
-    const double nx = (lb + C < n) ? pub_first[tid + 1] : next;
+    const double nx = (lb + C < n) ? first_of(tid + 1) : next;
     R |= (nx > h[C - 1] ? 1u : 0u) << C;
     F |= (nx < h[C - 1] ? 1u : 0u) << C;
   }
@@ -357,7 +354,6 @@ __global__ void __launch_bounds__(kTT) st_load_kernel(const StreamSig* __restric
 __global__ void __launch_bounds__(kTT) st_detect_kernel(const StreamSig* __restrict__ sigs,
                                                         const int2* __restrict__ tiles) {
   __shared__ double tbuf[kTile];
-  __shared__ double pub_first[kTT], pub_last[kTT];
   __shared__ int pub_key[kTT];
   __shared__ int scratch[kNW];
   __shared__ int64_t scratch64[kNW];
@@ -381,7 +377,7 @@ __global__ void __launch_bounds__(kTT) st_detect_kernel(const StreamSig* __restr
     h[c] = i < n ? tbuf[tsw(i)] : 0.0;
   }
   TileDet d;
-  tile_detect<kTC>(h, a, n, L, threadIdx.x, first_key, next, pub_first, pub_last, pub_key,
+  tile_detect<kTC>(h, a, n, L, threadIdx.x, first_key, next, tbuf, pub_key,
                    &cont_exit, &cont_pos, &cont_y, d);
   __syncthreads();
   record_tile(d, h, a, first_key, cont_exit, cont_pos, cont_y, S, tv.y, scratch64, scratch);
@@ -765,7 +761,6 @@ __device__ __forceinline__ double st_walk_at(StWalk& w, const StreamSig& S, int 
 __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restrict__ sigs,
                                                       const int2* __restrict__ tiles) {
   __shared__ double tbuf[kTile];
-  __shared__ double pub_first[kTT], pub_last[kTT];
   __shared__ int pub_key[kTT];
   __shared__ int scratch[kNW];
   __shared__ int64_t scratch64[kNW];
@@ -860,7 +855,7 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
 #pragma unroll
       for (int c = 0; c < kTC; ++c) h[c] = lb + c < n ? tbuf[tsw(lb + c)] : 0.0;
       TileDet d;
-      tile_detect<kTC>(h, a, n, L, threadIdx.x, first_key, next, pub_first, pub_last, pub_key,
+      tile_detect<kTC>(h, a, n, L, threadIdx.x, first_key, next, tbuf, pub_key,
                        &cont_exit, &cont_pos, &cont_y, d);
       __syncthreads();
       record_tile(d, h, a, first_key, cont_exit, cont_pos, cont_y, S, tv.y, scratch64, scratch);
