@@ -218,6 +218,10 @@ __device__ __forceinline__ void emit_knots(const double (&h)[C], unsigned bits, 
 // homogeneous quantities exactly, changing no ratio.
 // ---------------------------------------------------------------------------
 
+// Doubles per wave aggregate of the forward scan in LDS (7 used, padded to
+// 16-byte multiples so an aggregate is read with 128-bit loads).
+constexpr int kFwdStride = 8;
+
 // One forward map, x -> (a00 Q + a01 P, a10 Q + a11 P, v0 Q + v1 P + s D).
 struct FwdMap {
   double a00, a01, a10, a11, v0, v1, s;
@@ -323,8 +327,9 @@ __device__ __forceinline__ void fwd_enter(const double* fwd_lds, int wid, double
   P = 0.0;
   D = 0.0;
   for (int w = 0; w < wid; ++w) {
-    const double* o = fwd_lds + 7 * w;
-    const FwdMap X = {o[0], o[1], o[2], o[3], o[4], o[5], o[6]};
+    const double2* o = reinterpret_cast<const double2*>(fwd_lds + kFwdStride * w);
+    const double2 x0 = o[0], x1 = o[1], x2 = o[2], x3 = o[3];
+    const FwdMap X = {x0.x, x0.y, x1.x, x1.y, x2.x, x2.y, x3.x};
     fwd_apply(X, Q, P, D);
     vec_normalize(Q, P, D);
   }

@@ -266,7 +266,7 @@ __device__ __forceinline__ void spline_row(const Knots ks, int n1, int n2, int k
 // LDS head layout: block-scan ints and the SD sums (256 B), the forward
 // wave aggregates (7 doubles per wave), the backward ones (2 per wave).
 constexpr int kWaggBytes = 256;
-constexpr int kScanFwdBytes = 7 * 16 * (int)sizeof(double);
+constexpr int kScanFwdBytes = kFwdStride * 16 * (int)sizeof(double);
 constexpr int kScanBwdBytes = 2 * 16 * (int)sizeof(double);
 constexpr int kAggBytes = kWaggBytes + kScanFwdBytes + kScanBwdBytes;
 // Bytes of the detection's published block ends for NT threads.
@@ -309,7 +309,7 @@ __device__ __forceinline__ void solve_envelopes(const Knots ks, int n1, int n2, 
     if (wave_active) {
       G = fwd_wave_scan(G);
       if (lane == kWave - 1) {
-        double* o = fwd_lds + 7 * wid;
+        double* o = fwd_lds + kFwdStride * wid;
         o[0] = G.a00; o[1] = G.a01; o[2] = G.a10; o[3] = G.a11;
         o[4] = G.v0; o[5] = G.v1; o[6] = G.s;
       }
@@ -371,7 +371,7 @@ __device__ __forceinline__ void solve_envelopes(const Knots ks, int n1, int n2, 
   fwd_normalize(G);
   G = fwd_wave_scan(G);
   if (lane == kWave - 1) {
-    double* o = fwd_lds + 7 * wid;
+    double* o = fwd_lds + kFwdStride * wid;
     o[0] = G.a00; o[1] = G.a01; o[2] = G.a10; o[3] = G.a11;
     o[4] = G.v0; o[5] = G.v1; o[6] = G.s;
   }

@@ -569,7 +569,7 @@ __global__ void __launch_bounds__(kTT) st_solve_kernel(const StreamSig* __restri
   constexpr int kRMax = (kSB + 2 * kHalo + kTT - 1) / kTT;
   __shared__ int32_t lt[kW];
   __shared__ double ly[kW];
-  __shared__ double fwd_lds[7 * kNW];
+  __shared__ __align__(16) double fwd_lds[kFwdStride * kNW];
   __shared__ double bwd_lds[2 * kNW];
   const int4 bv = blocks[blockIdx.x];  // (signal, envelope, block)
   const StreamSig& S = sigs[bv.x];
@@ -621,7 +621,7 @@ __global__ void __launch_bounds__(kTT) st_solve_kernel(const StreamSig* __restri
   fwd_normalize(G);
   G = fwd_wave_scan(G);
   if (lane == kWave - 1) {
-    double* o = fwd_lds + 7 * wid;
+    double* o = fwd_lds + kFwdStride * wid;
     o[0] = G.a00; o[1] = G.a01; o[2] = G.a10; o[3] = G.a11;
     o[4] = G.v0; o[5] = G.v1; o[6] = G.s;
   }
