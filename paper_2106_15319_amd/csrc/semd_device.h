@@ -110,14 +110,16 @@ __device__ __forceinline__ int block_excl_sum(int v, int* wagg, int lane, int wi
   inc += dpp_int<kDppRowBcast31, 0xc>(inc);
   if (lane == kWave - 1) wagg[wid] = inc;
   __syncthreads();
-  int before = 0, tot = 0;
-#pragma unroll
-  for (int w = 0; w < NW; ++w) {
-    const int a = wagg[w];
-    before += (w < wid) ? a : 0;
-    tot += a;
-  }
-  total = tot;
+  // the wave totals, one per lane of the first row, scanned the same way
+  static_assert(NW <= 16, "wave totals fit one row of lanes");
+  int w = lane < NW ? wagg[lane] : 0;
+  w += dpp_int<kDppRowShr + 1, 0xf>(w);
+  w += dpp_int<kDppRowShr + 2, 0xf>(w);
+  w += dpp_int<kDppRowShr + 4, 0xf>(w);
+  w += dpp_int<kDppRowShr + 8, 0xf>(w);
+  const int uw = __builtin_amdgcn_readfirstlane(wid);
+  total = __builtin_amdgcn_readlane(w, NW - 1);
+  const int before = uw > 0 ? __builtin_amdgcn_readlane(w, uw - 1) : 0;
   return before + inc - v;
 }
 
