@@ -42,6 +42,14 @@ __device__ __forceinline__ int64_t dpp_i64(int64_t x) {
   return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
+// A double of lane `src` (the same for the whole wave) to every lane.
+__device__ __forceinline__ double lane_value(double x, int src) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)v, src);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // A double moved across lanes by a DPP control (each 32-bit half moved the
 // same way); lanes the control gives no source, and lanes of rows outside
 // ROWS, get 0.0, or 1.0 when ONE is set.
@@ -125,8 +133,9 @@ __device__ __forceinline__ int block_excl_sum(int v, int* wagg, int lane, int wi
 
 // Block-wide sums of two doubles per thread (a DPP scan within each wave,
 // whose last lane holds the wave's sums, then the wave sums through LDS,
-// 2*NW doubles, added in wave order so every thread gets the same totals).
-// Contains one barrier; wsum must not be in use.
+// 2*NW doubles, added by one wave-wide scan whose result every thread
+// reads, so all get the same totals).  Contains one barrier; wsum must not
+// be in use.
 template <int NW>
 __device__ __forceinline__ void block_sum2(double a, double b, double* wsum, int lane, int wid,
                                            double& ta, double& tb) {
@@ -145,14 +154,19 @@ __device__ __forceinline__ void block_sum2(double a, double b, double* wsum, int
     wsum[2 * wid + 1] = b;
   }
   __syncthreads();
-  double sa = 0.0, sb = 0.0;
-#pragma unroll
-  for (int w = 0; w < NW; ++w) {
-    sa += wsum[2 * w];
-    sb += wsum[2 * w + 1];
-  }
-  ta = sa;
-  tb = sb;
+  // the wave sums, one pair per lane of the first row, added by DPP shifts
+  static_assert(NW <= 16, "wave sums fit one row of lanes");
+  double sa = lane < NW ? wsum[2 * lane] : 0.0, sb = lane < NW ? wsum[2 * lane + 1] : 0.0;
+  sa += dpp_move<kDppRowShr + 1, 0xf>(sa);
+  sb += dpp_move<kDppRowShr + 1, 0xf>(sb);
+  sa += dpp_move<kDppRowShr + 2, 0xf>(sa);
+  sb += dpp_move<kDppRowShr + 2, 0xf>(sb);
+  sa += dpp_move<kDppRowShr + 4, 0xf>(sa);
+  sb += dpp_move<kDppRowShr + 4, 0xf>(sb);
+  sa += dpp_move<kDppRowShr + 8, 0xf>(sa);
+  sb += dpp_move<kDppRowShr + 8, 0xf>(sb);
+  ta = lane_value(sa, NW - 1);
+  tb = lane_value(sb, NW - 1);
 }
 
 // 1/x for positive normal x: the hardware reciprocal estimate refined by two
@@ -286,14 +300,6 @@ __device__ __forceinline__ void vec_normalize(double& Q, double& P, double& D) {
   D = __builtin_amdgcn_ldexp(D, -ex);
 }
 
-// A double of lane `src` (the same for the whole wave) to every lane.
-__device__ __forceinline__ double lane_value(double x, int src) {
-  const long long v = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_readlane((int)v, src);
-  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), src);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
 // A map moved across lanes; lanes without a source get the identity, which
 // composes and applies exactly (no rounding), so that the scans need no
 // per-lane selection.
@@ -328,7 +334,9 @@ __device__ __forceinline__ void fwd_enter(const double* fwd_lds, int wid, double
   Q = 1.0;
   P = 0.0;
   D = 0.0;
-  for (int w = 0; w < wid; ++w) {
+  // (the wave index is the same in every lane: a scalar loop)
+  const int uw = __builtin_amdgcn_readfirstlane(wid);
+  for (int w = 0; w < uw; ++w) {
     const double2* o = reinterpret_cast<const double2*>(fwd_lds + kFwdStride * w);
     const double2 x0 = o[0], x1 = o[1], x2 = o[2], x3 = o[3];
     const FwdMap X = {x0.x, x0.y, x1.x, x1.y, x2.x, x2.y, x3.x};
@@ -390,7 +398,9 @@ __device__ __forceinline__ void bwd_wave_scan(double& al, double& be, int lane) 
 // M at the first row after wave wid: the later waves' maps applied to 0.
 __device__ __forceinline__ double bwd_after(const double* bwd_lds, int wid, int wact) {
   double Mn = 0.0;
-  for (int w = wact - 1; w > wid; --w) Mn = fma(bwd_lds[2 * w + 1], Mn, bwd_lds[2 * w]);
+  // (wave index and count are the same in every lane: a scalar loop)
+  const int uw = __builtin_amdgcn_readfirstlane(wid), ua = __builtin_amdgcn_readfirstlane(wact);
+  for (int w = ua - 1; w > uw; --w) Mn = fma(bwd_lds[2 * w + 1], Mn, bwd_lds[2 * w]);
   return Mn;
 }
 
