@@ -324,7 +324,7 @@ int run_resident(std::vector<semd::WorkItem>& work, int K, int S, hipStream_t st
   int64_t off = 0;
   for (auto& w : work) {
     w.r = ws + off;
-    w.u = w.r + ((w.L + 1) & ~1);  // 16-byte aligned (the knot store's pairs)
+    w.u = w.r + w.L;
     off += semd::resident_ws_doubles(w.L);
   }
   void* d_items = nullptr;

@@ -50,7 +50,7 @@ __host__ __device__ constexpr int resident_gknot_cap(int L) { return L + 16; }
 // which holds either the parked upper envelope (L doubles) or the global knot
 // store (4 doubles and one int16 per knot).
 __host__ __device__ constexpr int64_t resident_ws_doubles(int64_t L) {
-  return (L + 4 * (L + 16) + ((L + 16) * 2 + 7) / 8 + 3) & ~int64_t(1);
+  return L + 4 * (L + 16) + ((L + 16) * 2 + 7) / 8 + 2;
 }
 
 // Launch shape of the resident kernel: threads per workgroup and samples per

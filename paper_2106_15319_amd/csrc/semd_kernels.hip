@@ -40,26 +40,32 @@ using namespace dev;
 // m_j / 4 in m (m_j the spline second derivative), and the linear and cubic
 // coefficients in q1 and q3.  34 bytes per knot.
 struct Knots {
-  double2* yq;  // (y, q1) of each knot
-  double2* mq;  // (m, q3) of each knot
+  double* y;
+  double* m;
+  double* q1;
+  double* q3;
   int16_t* t;
 };
 
 constexpr int kKnotBytes = 4 * (int)sizeof(double) + (int)sizeof(int16_t);
 
-// A store of cap knots in the 16-byte-aligned region p.
+// A store of cap knots in the region p.
 __device__ __forceinline__ Knots knots_in(unsigned char* p, int cap) {
   Knots s;
-  s.yq = reinterpret_cast<double2*>(p);
-  s.mq = s.yq + cap;
-  s.t = reinterpret_cast<int16_t*>(s.mq + cap);
+  s.y = reinterpret_cast<double*>(p);
+  s.m = s.y + cap;
+  s.q1 = s.m + cap;
+  s.q3 = s.q1 + cap;
+  s.t = reinterpret_cast<int16_t*>(s.q3 + cap);
   return s;
 }
 
 __device__ __forceinline__ Knots knots_from(const Knots& a, int o) {
   Knots s;
-  s.yq = a.yq + o;
-  s.mq = a.mq + o;
+  s.y = a.y + o;
+  s.m = a.m + o;
+  s.q1 = a.q1 + o;
+  s.q3 = a.q3 + o;
   s.t = a.t + o;
   return s;
 }
@@ -189,12 +195,12 @@ __device__ __forceinline__ void rd_emit(const double (&h)[C], unsigned bits, uns
       const int mid = run_mid(NE, carry, base, c);
       const double y = h[c];
       ks.t[Pp + g] = (int16_t)mid;
-      ks.yq[Pp + g].x = y;
+      ks.y[Pp + g] = y;
       if (g < 2 || g >= n - 2) {
-        if (g == 0) { ks.t[Pp - 1] = (int16_t)(-mid); ks.yq[Pp - 1].x = y; }
-        if (g == 1 && Pp == 2) { ks.t[0] = (int16_t)(-mid); ks.yq[0].x = y; }
-        if (g == n - 1) { ks.t[Pp + n] = (int16_t)(hi - mid); ks.yq[Pp + n].x = y; }
-        if (g == n - 2 && Pp == 2) { ks.t[Pp + n + 1] = (int16_t)(hi - mid); ks.yq[Pp + n + 1].x = y; }
+        if (g == 0) { ks.t[Pp - 1] = (int16_t)(-mid); ks.y[Pp - 1] = y; }
+        if (g == 1 && Pp == 2) { ks.t[0] = (int16_t)(-mid); ks.y[0] = y; }
+        if (g == n - 1) { ks.t[Pp + n] = (int16_t)(hi - mid); ks.y[Pp + n] = y; }
+        if (g == n - 2 && Pp == 2) { ks.t[Pp + n + 1] = (int16_t)(hi - mid); ks.y[Pp + n + 1] = y; }
       }
     }
   }
@@ -233,19 +239,19 @@ __device__ __forceinline__ void spline_row(const Knots ks, int n1, int n2, int k
   const bool first = k == 0 || k == n1;
   const bool last = k == n1 - 1 || k == n1 + n2 - 1;
   const int t0 = ks.t[k];
-  const double y0 = ks.yq[k].x;
+  const double y0 = ks.y[k];
   yk = y0;
   double s0 = 0.0, s1 = 0.0, g0 = 0.0, g1 = 0.0, i1 = 0.0;
   if (!last) {
     const int tp = ks.t[k + 1];
     g1 = (double)(tp - t0);
     i1 = recip(g1);
-    s1 = (ks.yq[k + 1].x - y0) * i1;
+    s1 = (ks.y[k + 1] - y0) * i1;
   }
   if (!first) {
     const int tm = ks.t[k - 1];
     g0 = (double)(t0 - tm);
-    s0 = (y0 - ks.yq[k - 1].x) * recip(g0);
+    s0 = (y0 - ks.y[k - 1]) * recip(g0);
   }
   slope = s1;
   g = g1;
@@ -338,11 +344,11 @@ __device__ __forceinline__ void solve_envelopes(const Knots ks, int n1, int n2, 
       if (has) {
         const double Mk = fma(-cp, Mn, dp);
         if (!last) {
-          ks.yq[k].y = 0.5 * (sl - g * fma(2.0, Mk, Mn) * (1.0 / 6.0));
-          ks.mq[k].y = (Mn - Mk) * ig * (1.0 / 12.0);
+          ks.q1[k] = 0.5 * (sl - g * fma(2.0, Mk, Mn) * (1.0 / 6.0));
+          ks.q3[k] = (Mn - Mk) * ig * (1.0 / 12.0);
         }
-        ks.mq[k].x = 0.25 * Mk;
-        ks.yq[k].x = 0.5 * yk;
+        ks.m[k] = 0.25 * Mk;
+        ks.y[k] = 0.5 * yk;
       }
     }
     __syncthreads();
@@ -385,14 +391,14 @@ __device__ __forceinline__ void solve_envelopes(const Knots ks, int n1, int n2, 
       Q = q;
       vec_normalize(Q, P, D);
       const double iq = recip(Q);
-      ks.mq[k].x = P * iq;
-      ks.yq[k].y = D * iq;
+      ks.m[k] = P * iq;
+      ks.q1[k] = D * iq;
     }
   }
   // back-substitution maps composed from the thread's last row down
   double al = 0.0, be = 1.0;
   for (int k = k1 - 1; k >= k0; --k) {
-    const double cp = ks.mq[k].x, dp = ks.yq[k].y;
+    const double cp = ks.m[k], dp = ks.q1[k];
     al = fma(-cp, al, dp);
     be = -cp * be;
   }
@@ -407,22 +413,22 @@ __device__ __forceinline__ void solve_envelopes(const Knots ks, int n1, int n2, 
     // (lane 63: the identity x -> 0 + 1 x)
     Mn = fma(dpp_move<kDppWaveShl1, 0xf, true>(be), Mn, dpp_move<kDppWaveShl1, 0xf>(al));
     for (int k = k1 - 1; k >= k0; --k) {
-      const double cp = ks.mq[k].x, dp = ks.yq[k].y;
+      const double cp = ks.m[k], dp = ks.q1[k];
       const double Mk = fma(-cp, Mn, dp);
       const bool last = k == n1 - 1 || k == n1 + n2 - 1;
       if (!last) {
         const double g = (double)((int)ks.t[k + 1] - (int)ks.t[k]);
         const double ig = recip(g);
-        const double bk = (ks.yq[k + 1].x - ks.yq[k].x) * ig - g * fma(2.0, Mk, Mn) * (1.0 / 6.0);
-        ks.yq[k].y = 0.5 * bk;
-        ks.mq[k].y = (Mn - Mk) * ig * (1.0 / 12.0);
+        const double bk = (ks.y[k + 1] - ks.y[k]) * ig - g * fma(2.0, Mk, Mn) * (1.0 / 6.0);
+        ks.q1[k] = 0.5 * bk;
+        ks.q3[k] = (Mn - Mk) * ig * (1.0 / 12.0);
       }
-      ks.mq[k].x = 0.25 * Mk;
+      ks.m[k] = 0.25 * Mk;
       Mn = Mk;
     }
   }
   __syncthreads();  // the values of the neighbours' rows have been read
-  for (int k = k0; k < k1; ++k) ks.yq[k].x = 0.5 * ks.yq[k].x;
+  for (int k = k0; k < k1; ++k) ks.y[k] = 0.5 * ks.y[k];
   __syncthreads();
 }
 
@@ -437,11 +443,10 @@ struct Walk {
 __device__ __forceinline__ void walk_load(Walk& w, const Knots& ks, int j) {
   w.j = j;
   w.t1 = ks.t[j + 1];
-  const double2 yq = ks.yq[j], mq = ks.mq[j];
-  w.q0 = yq.x;
-  w.q1 = yq.y;
-  w.q2 = mq.x;
-  w.q3 = mq.y;
+  w.q0 = ks.y[j];
+  w.q1 = ks.q1[j];
+  w.q2 = ks.m[j];
+  w.q3 = ks.q3[j];
 }
 
 // Position at the segment holding sample k, starting from segment j (whose
@@ -501,10 +506,10 @@ __device__ __forceinline__ void emit_mirrors(const double (&h)[C], unsigned bits
     if (g < 2 || g >= n - 2) {
       const int mid = run_mid(NE, carry, base, c);
       const double y = pick(h, c);
-      if (g == 0) { ks.t[Pp - 1] = (int16_t)(-mid); ks.yq[Pp - 1].x = y; }
-      if (g == 1 && Pp == 2) { ks.t[0] = (int16_t)(-mid); ks.yq[0].x = y; }
-      if (g == n - 1) { ks.t[Pp + n] = (int16_t)(hi - mid); ks.yq[Pp + n].x = y; }
-      if (g == n - 2 && Pp == 2) { ks.t[Pp + n + 1] = (int16_t)(hi - mid); ks.yq[Pp + n + 1].x = y; }
+      if (g == 0) { ks.t[Pp - 1] = (int16_t)(-mid); ks.y[Pp - 1] = y; }
+      if (g == 1 && Pp == 2) { ks.t[0] = (int16_t)(-mid); ks.y[0] = y; }
+      if (g == n - 1) { ks.t[Pp + n] = (int16_t)(hi - mid); ks.y[Pp + n] = y; }
+      if (g == n - 2 && Pp == 2) { ks.t[Pp + n + 1] = (int16_t)(hi - mid); ks.y[Pp + n + 1] = y; }
     }
     ++g;
   }
@@ -528,9 +533,9 @@ __device__ __forceinline__ void rd_emit_both(const double (&h)[C], unsigned maxb
     const int mid = run_mid(NE, carry, base, c);
     const double y = pick(h, c);
     int16_t* t = up ? ku.t : kl.t;
-    double2* yy = up ? ku.yq : kl.yq;
+    double* yy = up ? ku.y : kl.y;
     t[g] = (int16_t)mid;
-    yy[g].x = y;
+    yy[g] = y;
   }
   emit_mirrors(h, maxbits, NE, carry, base, L, emax, nmax, ku);
   emit_mirrors(h, minbits, NE, carry, base, L, emin, nmin, kl);
