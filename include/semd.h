@@ -55,7 +55,7 @@ typedef enum {
   SEMD_EDEVICE = 3,      /* a HIP call or kernel launch failed             */
   SEMD_EBUSY = 4,        /* serving engine: request exceeds free budget    */
   SEMD_ENONFINITE = 5,   /* input holds NaN/Inf (reported via n_imfs)      */
-  SEMD_EUNSUPPORTED = 6  /* valid request this build cannot run            */
+  SEMD_EUNSUPPORTED = 6  /* valid request the library cannot run          */
 } semd_status;
 
 typedef enum { SEMD_BOUNDARY_MIRROR = 0 } semd_boundary;

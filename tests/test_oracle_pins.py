@@ -409,7 +409,7 @@ def test_two_extrema_residue_is_not_sifted():
 
 
 def test_noise_stream_definition():
-    # Stream layout of this build (a convention, not the paper's): stream key
+    # Stream layout of this library (a convention, not the paper's): stream key
     # s2 = SM(SM(seed, item+1), m+1); sample k sums the 12 outputs
     # SM(s2, 12k+1..12k+12) >> 11 as integers, subtracts 6*2^53, converts to
     # double once and scales by 2^-53.  SM(s, n) is the n-th SplitMix64 output.
