@@ -31,13 +31,19 @@ class Stats(C.Structure):
                 ("sd_margin", C.c_double)]
 
 
+def compile_source(src: str, out: str) -> str:
+    """Compile an oracle source with gcc: scalar FP64, no contraction, no fast-math."""
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+           "-shared", "-Wall", "-Wextra", "-I", _DIR, "-o", out + ".tmp", src, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(out + ".tmp", out)
+    return out
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc: scalar FP64, no contraction, no fast-math."""
+    """Compile the oracle into the package directory."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-               "-shared", "-Wall", "-Wextra", "-o", _LIB + ".tmp", _SRC, "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(_LIB + ".tmp", _LIB)
+        compile_source(_SRC, _LIB)
     return _LIB
 
 
@@ -49,46 +55,50 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build(force=True)
-        L = C.CDLL(_LIB)
-        L.semd_ref_serial_length.restype = C.c_int64
-        L.semd_ref_serial_length.argtypes = [C.c_int64] * 3
-        L.semd_ref_serialize.argtypes = [_d, C.c_int64, C.c_int64, C.c_int64, _d]
-        L.semd_ref_deserialize.argtypes = [_d, C.c_int64, C.c_int64, C.c_int64, _d]
-        L.semd_ref_extrema.argtypes = [_d, C.c_int64, _i64, _i64, _i64, _i64]
-        L.semd_ref_spline_solve.argtypes = [_d, _d, C.c_int64, _d]
-        L.semd_ref_spline_eval.argtypes = [_d, _d, _d, C.c_int64, C.c_int64, _d]
-        L.semd_ref_envelope.argtypes = [_d, C.c_int64, _i64, C.c_int64, _d]
-        L.semd_ref_emd.argtypes = [_d, C.c_int64, C.c_int, C.c_int, _d, _int, C.POINTER(Stats)]
-        L.semd_ref_emd_sd.argtypes = [_d, C.c_int64, C.c_int, C.c_int, C.c_double, _d, _int,
-                                      C.POINTER(Stats)]
-        L.semd_ref_decompose_sd.argtypes = [_d, C.c_int64, C.c_int64, C.c_int64, C.c_int,
-                                            C.c_int, C.c_double, _d, _int, C.POINTER(Stats)]
-        L.semd_ref_decompose.argtypes = [_d, C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_int,
-                                         _d, _int, C.POINTER(Stats)]
-        L.semd_ref_decompose_slices.argtypes = [_d, C.c_int64, C.c_int64, C.c_int, C.c_int,
-                                                _d, _int]
-        L.semd_ref_decompose_slices_sd.argtypes = [_d, C.c_int64, C.c_int64, C.c_int, C.c_int,
-                                                   C.c_double, _d, _int]
-        L.semd_ref_splitmix64.restype = C.c_uint64
-        L.semd_ref_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
-        L.semd_ref_noise.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.c_int64, _d]
-        L.semd_ref_eemd.argtypes = [_d, C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_int,
-                                    C.c_int, C.c_double, C.c_uint64, C.c_uint64, _d]
-        L.semd_ref_eemd_sd.argtypes = [_d, C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_int,
-                                       C.c_int, C.c_double, C.c_uint64, C.c_uint64, C.c_double,
-                                       _d]
-        L.semd_ref_ceemdan.argtypes = [_d, C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_int,
-                                       C.c_int, C.c_double, C.c_uint64, C.c_uint64, C.c_double,
-                                       _d, _int]
-        for name in ("semd_ref_ceemdan", "semd_ref_serialize", "semd_ref_deserialize", "semd_ref_extrema",
-                     "semd_ref_spline_solve", "semd_ref_spline_eval", "semd_ref_envelope",
-                     "semd_ref_emd", "semd_ref_decompose", "semd_ref_decompose_slices",
-                     "semd_ref_emd_sd", "semd_ref_decompose_sd",
-                     "semd_ref_decompose_slices_sd", "semd_ref_noise", "semd_ref_eemd",
-                     "semd_ref_eemd_sd"):
-            getattr(L, name).restype = C.c_int
-        _lib = L
+        _lib = bind(C.CDLL(_LIB))
     return _lib
+
+
+def bind(L):
+    """Declare the C signatures on a loaded oracle library and return it."""
+    L.semd_ref_serial_length.restype = C.c_int64
+    L.semd_ref_serial_length.argtypes = [C.c_int64] * 3
+    L.semd_ref_serialize.argtypes = [_d, C.c_int64, C.c_int64, C.c_int64, _d]
+    L.semd_ref_deserialize.argtypes = [_d, C.c_int64, C.c_int64, C.c_int64, _d]
+    L.semd_ref_extrema.argtypes = [_d, C.c_int64, _i64, _i64, _i64, _i64]
+    L.semd_ref_spline_solve.argtypes = [_d, _d, C.c_int64, _d]
+    L.semd_ref_spline_eval.argtypes = [_d, _d, _d, C.c_int64, C.c_int64, _d]
+    L.semd_ref_envelope.argtypes = [_d, C.c_int64, _i64, C.c_int64, _d]
+    L.semd_ref_emd.argtypes = [_d, C.c_int64, C.c_int, C.c_int, _d, _int, C.POINTER(Stats)]
+    L.semd_ref_emd_sd.argtypes = [_d, C.c_int64, C.c_int, C.c_int, C.c_double, _d, _int,
+                                  C.POINTER(Stats)]
+    L.semd_ref_decompose_sd.argtypes = [_d, C.c_int64, C.c_int64, C.c_int64, C.c_int,
+                                        C.c_int, C.c_double, _d, _int, C.POINTER(Stats)]
+    L.semd_ref_decompose.argtypes = [_d, C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_int,
+                                     _d, _int, C.POINTER(Stats)]
+    L.semd_ref_decompose_slices.argtypes = [_d, C.c_int64, C.c_int64, C.c_int, C.c_int,
+                                            _d, _int]
+    L.semd_ref_decompose_slices_sd.argtypes = [_d, C.c_int64, C.c_int64, C.c_int, C.c_int,
+                                               C.c_double, _d, _int]
+    L.semd_ref_splitmix64.restype = C.c_uint64
+    L.semd_ref_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
+    L.semd_ref_noise.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.c_int64, _d]
+    L.semd_ref_eemd.argtypes = [_d, C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_int,
+                                C.c_int, C.c_double, C.c_uint64, C.c_uint64, _d]
+    L.semd_ref_eemd_sd.argtypes = [_d, C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_int,
+                                   C.c_int, C.c_double, C.c_uint64, C.c_uint64, C.c_double,
+                                   _d]
+    L.semd_ref_ceemdan.argtypes = [_d, C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_int,
+                                   C.c_int, C.c_double, C.c_uint64, C.c_uint64, C.c_double,
+                                   _d, _int]
+    for name in ("semd_ref_ceemdan", "semd_ref_serialize", "semd_ref_deserialize", "semd_ref_extrema",
+                 "semd_ref_spline_solve", "semd_ref_spline_eval", "semd_ref_envelope",
+                 "semd_ref_emd", "semd_ref_decompose", "semd_ref_decompose_slices",
+                 "semd_ref_emd_sd", "semd_ref_decompose_sd",
+                 "semd_ref_decompose_slices_sd", "semd_ref_noise", "semd_ref_eemd",
+                 "semd_ref_eemd_sd"):
+        getattr(L, name).restype = C.c_int
+    return L
 
 
 def _p(a: np.ndarray):

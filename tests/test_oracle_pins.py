@@ -552,3 +552,23 @@ def test_ceemdan_first_stage_is_the_ensemble_first_mode():
     ee = oracle.eemd(it.X, M, N, D, 1, 10, 5, beta, 9, 4)
     assert n == 1
     assert np.abs(out[0] - ee[0]).max() <= 1e-12 * np.abs(it.X).max()
+
+
+def test_ceemdan_second_stage_uses_the_first_noise_mode():
+    # Sec. 2.2 CEEMDAN Step 3 for i = 2: c_2 is the ensemble mean of the first
+    # mode of r_1 + beta_1 E_1(w_m), where r_1 = x - c_1, beta_1 = eps std(r_1)
+    # and E_1(w_m) is the first mode of the EMD of noise realization m.
+    L, S, NR, eps, seed, item = 600, 10, 4, 0.2, 5, 1
+    k = np.arange(L)
+    x = (np.sin(2 * np.pi * k / 9.5) + 0.6 * np.sin(2 * np.pi * k / 47.0)
+         + 0.3 * np.cos(2 * np.pi * k / 173.0))
+    out, n = oracle.ceemdan(x, L, 1, 0, 2, S, NR, eps, seed, item)
+    assert n == 2
+    r1 = x - out[0]
+    beta1 = eps * float(np.sqrt(np.mean((r1 - np.mean(r1)) ** 2)))
+    acc = np.zeros(L)
+    for m in range(NR):
+        e1 = oracle.emd(oracle.noise(seed, item, m, L), 1, S)[0][0]
+        acc += oracle.emd(r1 + beta1 * e1, 1, S)[0][0]
+    assert np.abs(out[1] - acc / NR).max() <= 1e-12 * np.abs(x).max()
+    assert np.abs(out[2] - (r1 - out[1])).max() <= 1e-13 * np.abs(x).max()
