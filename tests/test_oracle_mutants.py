@@ -52,6 +52,9 @@ MUTANTS = [
      "double sub = g0, sup = g1;", "double sub = g1, sup = g0;"),
     ("spline_eval_wrong_index", "Sec. 2.1 Step 2, cubic pieces",
      "(y[j + 1] - Mpp[j + 1] * g2 / 6.0) * B / g", "(y[j + 1] - Mpp[j] * g2 / 6.0) * B / g"),
+    ("spline_eval_cubic_scale", "Sec. 2.1 Step 2, cubic pieces",
+     "double cub = (Mpp[j] * A3 + Mpp[j + 1] * B3) / (6.0 * g);",
+     "double cub = (Mpp[j] * A3 + Mpp[j + 1] * B3) / (6.0 * g2);"),
     ("mirror_about_length", "Sec. 2.1 Step 2, mirror boundary reading",
      "t[q] = (double)(2 * (L - 1) - idx[p]);", "t[q] = (double)(2 * L - idx[p]);"),
     ("mirror_one_knot", "Sec. 2.1 Step 2, mirror boundary reading",
@@ -71,6 +74,13 @@ MUTANTS = [
     ("noise_not_centred", "noise stream reading",
      "int64_t c = (int64_t)acc - (int64_t)(6ull << 53);",
      "int64_t c = (int64_t)acc - (int64_t)(5ull << 53);"),
+    ("noise_stream_key", "noise stream reading",
+     "uint64_t s1 = semd_ref_splitmix64(seed, item + 1);",
+     "uint64_t s1 = semd_ref_splitmix64(seed, item);"),
+    ("eemd_noise_subtracted", "Sec. 2.2 EEMD Step 1, x_m = x + beta w_m",
+     "xm[k] = x[k] + bw;", "xm[k] = x[k] - bw;"),
+    ("ceemdan_sample_std", "Sec. 2.2 CEEMDAN, std of the residue",
+     "return sqrt(q / (double)L);", "return sqrt(q / (double)(L - 1));"),
     ("eemd_mean_off_by_one", "Sec. 2.2 EEMD Step 3, ensemble mean",
      "acc[i] = acc[i] / (double)NR;", "acc[i] = acc[i] / (double)(NR + 1);"),
     ("ceemdan_noise_mode_index", "Sec. 2.2 CEEMDAN Step 3, E_{i-1}(w_m)",
