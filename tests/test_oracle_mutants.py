@@ -68,6 +68,12 @@ MUTANTS = [
      "den += h[k] * h[k];", "den += (h[k] - m) * (h[k] - m);"),
     ("sift_count_short", "S sifts per IMF",
      "for (int s = 0; s < S; ++s) {", "for (int s = 0; s < S - 1; ++s) {"),
+    ("sd_margin_over_den", "SD rule, distance of the closest decision",
+     "const double margin = fabs(num - lim) / lim;",
+     "const double margin = fabs(num - lim) / den;"),
+    # Sec. 4 opening: standard (slice-wise) EMD
+    ("slices_column_offset", "standard EMD, one column per signal",
+     "(size_t)(c * M), R + (size_t)k * (size_t)M,", "(size_t)c, R + (size_t)k * (size_t)M,"),
     # Sec. 2.2: EEMD and CEEMDAN
     ("splitmix_shift", "SplitMix64 definition",
      "z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;", "z = (z ^ (z >> 28)) * 0x94D049BB133111EBull;"),
