@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define SEMD_ABI_VERSION 2
+#define SEMD_ABI_VERSION 3
 
 typedef enum {
   SEMD_OK = 0,
@@ -69,9 +69,11 @@ typedef enum { SEMD_PATH_AUTO = 0, SEMD_PATH_ONCHIP = 1, SEMD_PATH_STREAM = 2 } 
 /* When an IMF's sifting stops (Sec. 2.1 Step 5 leaves the criterion open).
  * FIXED: after sift_iters sifts.  SD: also after the first sift whose mean
  * envelope m satisfies sum m^2 < sd_threshold * sum h^2, h the candidate
- * before that sift (the SD criterion of Huang et al. 1998), still at most
- * sift_iters sifts.  Either way an IMF ends early when its candidate has too
- * few extrema to sift. */
+ * before that sift, still at most sift_iters sifts.  This is the
+ * ratio-of-sums (Cauchy-type) form of the standard-deviation test between
+ * consecutive candidates (h - (h - m) = m), not the sum of per-sample ratios.
+ * Either way an IMF ends early when its candidate has too few extrema to
+ * sift. */
 typedef enum { SEMD_STOP_FIXED = 0, SEMD_STOP_SD = 1 } semd_stop;
 
 /* Method parameters.  transition_len is D of Sec. 3.2 (0 <= D <= M);
@@ -171,12 +173,33 @@ int semd_tune_reset(void);
 int semd_decompose(const double* signal, const int64_t* dims, int ndim, int max_imfs,
                    int sift_iters, int boundary_rule, double* imfs_out, hipStream_t stream);
 
-/* Serial-EMD of one signal with explicit parameters (p->ensemble is ignored),
- * launched on its own: the plain one-signal-per-launch path.  n_imfs_out:
- * device int32 or NULL.  p: [host]. */
+/* Device bytes of the workspace semd_decompose_ex needs for a signal of
+ * these dims under these parameters (dims: [host]; p: [host]): the signal's
+ * descriptor, on the streaming path its tile tables, and the path's state --
+ * the residue r and candidate h of Sec. 2.1 Steps 1-5 over the L = M*N +
+ * D*N - D serialized samples of Sec. 3.2, and the envelope knots.  Returns 0
+ * (message in semd_last_error()) when semd_decompose_ex would reject the
+ * arguments with SEMD_EINVAL or SEMD_EUNSUPPORTED. */
+size_t semd_workspace_bytes(const int64_t* dims, int ndim, const semd_params* p);
+
+/* Serial-EMD of one signal (Sec. 3: serialize with transition length D of
+ * Sec. 3.2, 1D EMD of Sec. 2.1, deserialize as in Sec. 3.3) with explicit
+ * parameters (p->ensemble is ignored), launched on its own: the plain
+ * one-signal-per-launch path.  signal: device, M*N doubles; imfs_out:
+ * device, (K+1)*M*N doubles; n_imfs_out: device int32 or NULL; dims, p:
+ * [host].
+ * workspace: device memory owned by the caller, at least
+ * semd_workspace_bytes(dims, ndim, p) bytes (ws_bytes), 256-byte aligned,
+ * not touched by anything else until the work enqueued on `stream` has
+ * finished; its contents need no initialization and are undefined after.
+ * With workspace == NULL (ws_bytes ignored) the library allocates and frees
+ * the workspace itself, stream-ordered (hipMallocAsync / hipFreeAsync).  An
+ * undersized or misaligned workspace returns SEMD_EINVAL with nothing
+ * enqueued.  With a workspace the call enqueues kernels only (no allocation,
+ * no copy, no memset), so it may be captured into a HIP graph. */
 int semd_decompose_ex(const double* signal, const int64_t* dims, int ndim,
                       const semd_params* p, double* imfs_out, int32_t* n_imfs_out,
-                      hipStream_t stream);
+                      void* workspace, size_t ws_bytes, hipStream_t stream);
 
 /* Standard (slice-wise) EMD, the baseline Serial-EMD is compared with (Sec. 4):
  * each of the N columns of X (length M each, dims as above) is decomposed by
@@ -268,7 +291,9 @@ int semd_engine_footprint(const semd_item* item, const semd_params* p, size_t* b
 /* Admit one request (item: [host]; its signal, imfs_out and n_imfs_out as in
  * semd_decompose_batch; noise fields ignored).  *ticket identifies it.
  * SEMD_EBUSY: the footprint does not fit the free budget or all request
- * slots are taken; retry after finished requests are polled. */
+ * slots are taken; retry after finished requests are polled.  SEMD_ENOMEM:
+ * the footprint exceeds the engine's whole budget, so the request can never
+ * be admitted. */
 int semd_engine_admit(semd_engine* e, const semd_item* item, const semd_params* p,
                       int64_t* ticket);
 

@@ -72,8 +72,10 @@ int semd_ref_emd(const double* x, int64_t L, int K, int S, double* imfs, int* n_
 /* Sec. 2.1 with a data-dependent stop (Step 5 leaves the criterion open): as
  * semd_ref_emd, but an IMF also ends after the sift whose mean m satisfies
  * sum_k m[k]^2 < sd_threshold * sum_k h[k]^2, h the candidate before that
- * sift (the SD criterion of Huang et al. 1998; both sums taken in k order),
- * with at most S sifts.  sd_threshold = 0 is the fixed-count rule. */
+ * sift (a standard-deviation test between consecutive candidates in its
+ * ratio-of-sums, Cauchy-type form, since h - (h - m) = m; both sums taken in
+ * k order), with at most S sifts.  sd_threshold = 0 is the fixed-count
+ * rule. */
 int semd_ref_emd_sd(const double* x, int64_t L, int K, int S, double sd_threshold,
                     double* imfs, int* n_imfs, semd_ref_stats* stats);
 

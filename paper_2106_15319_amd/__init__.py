@@ -69,9 +69,11 @@ _EXPORTS = {
     "semd_tune_reset": (C.c_int, []),
     "semd_decompose": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_int, C.c_int, C.c_int,
                                  C.c_int, C.c_void_p, C.c_void_p]),
+    "semd_workspace_bytes": (C.c_size_t, [C.POINTER(C.c_int64), C.c_int,
+                                          C.POINTER(semd_params)]),
     "semd_decompose_ex": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_int,
                                     C.POINTER(semd_params), C.c_void_p, C.c_void_p,
-                                    C.c_void_p]),
+                                    C.c_void_p, C.c_size_t, C.c_void_p]),
     "semd_decompose_batch": (C.c_int, [C.POINTER(semd_item), C.c_int, C.POINTER(semd_params),
                                        C.c_void_p]),
     "semd_decompose_slices": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_int,
@@ -137,17 +139,63 @@ def _stream(stream) -> int:
     return int(stream)
 
 
-def _dev_f64(t: torch.Tensor, name: str) -> int:
-    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+def _chk(t: torch.Tensor, name: str, dtype: torch.dtype, numel: int | None = None,
+         exact: bool = False) -> torch.Tensor:
+    """What the C ABI cannot see: `t` is a contiguous tensor of `dtype`
+    holding at least (exact: exactly) `numel` elements."""
+    if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a tensor on the HIP device")
-    if t.dtype != torch.float64 or not t.is_contiguous():
-        raise TypeError(f"{name} must be a contiguous float64 tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    if numel is not None:
+        if exact and t.numel() != numel:
+            raise ValueError(f"{name} has {t.numel()} elements, the dims ask for {numel}")
+        if t.numel() < numel:
+            raise ValueError(f"{name} has {t.numel()} elements, at least {numel} are needed")
+    return t
+
+
+def _ptr(t: torch.Tensor, name: str) -> int:
+    """Device pointer of `t`, which must live on the current HIP device."""
+    if not t.is_cuda:
+        raise TypeError(f"{name} must be a tensor on the HIP device")
+    if t.device.index is not None and t.device.index != torch.cuda.current_device():
+        raise ValueError(f"{name} is on {t.device}, not on the current device "
+                         f"cuda:{torch.cuda.current_device()}")
     return t.data_ptr()
 
 
+def _dev(t: torch.Tensor, name: str, dtype: torch.dtype, numel: int | None = None,
+         exact: bool = False) -> int:
+    return _ptr(_chk(t, name, dtype, numel, exact), name)
+
+
+def _dev_f64(t: torch.Tensor, name: str, numel: int | None = None, exact: bool = False) -> int:
+    return _dev(t, name, torch.float64, numel, exact)
+
+
 def _dims(dims: Sequence[int]):
-    arr = (C.c_int64 * len(dims))(*[int(d) for d in dims])
+    dims = [int(d) for d in dims]
+    if not 1 <= len(dims) <= 4:
+        raise ValueError("dims must have 1..4 entries")
+    if any(d < 1 for d in dims):
+        raise ValueError(f"every dim must be >= 1, got {dims}")
+    arr = (C.c_int64 * len(dims))(*dims)
     return arr, len(dims)
+
+
+def _mn(dims: Sequence[int]) -> tuple[int, int]:
+    """(M, N) of column-major dims: M = dims[0], N = product of the rest."""
+    M = int(dims[0])
+    N = 1
+    for v in dims[1:]:
+        N *= int(v)
+    return M, N
+
+
+def _check_shape_params(K: int, S: int) -> None:
+    if int(K) < 1 or int(S) < 1:
+        raise ValueError(f"max_imfs and sift_iters must be >= 1, got {K}, {S}")
 
 
 def _params(D: int, K: int, S: int, NR: int = 1, seed: int = 0,
@@ -221,36 +269,69 @@ def semd_decompose(signal: torch.Tensor, dims: Sequence[int], max_imfs: int, sif
                    stream=None) -> torch.Tensor:
     """Serial-EMD with D = round(0.2 M); returns imfs_out ((K+1) x M*N)."""
     d, nd = _dims(dims)
-    MN = 1
-    for v in dims:
-        MN *= int(v)
+    _check_shape_params(max_imfs, sift_iters)
+    M, N = _mn(dims)
     if imfs_out is None:
-        imfs_out = torch.empty((max_imfs + 1, MN), dtype=torch.float64, device=signal.device)
-    _check(lib().semd_decompose(_dev_f64(signal, "signal"), d, nd, max_imfs, sift_iters,
-                                boundary_rule, _dev_f64(imfs_out, "imfs_out"), _stream(stream)),
+        imfs_out = torch.empty((max_imfs + 1, M * N), dtype=torch.float64, device=signal.device)
+    _check(lib().semd_decompose(_dev_f64(signal, "signal", M * N, exact=True), d, nd, max_imfs,
+                                sift_iters, boundary_rule,
+                                _dev_f64(imfs_out, "imfs_out", (max_imfs + 1) * M * N),
+                                _stream(stream)),
            "semd_decompose")
     return imfs_out
+
+
+def semd_workspace_bytes(dims: Sequence[int], D: int, max_imfs: int, sift_iters: int,
+                         path: int = SEMD_PATH_AUTO, sd: float = 0.0) -> int:
+    """Device bytes of the workspace semd_decompose_ex needs for these dims
+    and parameters."""
+    d, nd = _dims(dims)
+    p = _params(D, max_imfs, sift_iters, path=path, sd=sd)
+    n = int(lib().semd_workspace_bytes(d, nd, C.byref(p)))
+    if n == 0:
+        raise SemdError(SEMD_EINVAL, "semd_workspace_bytes", lib().semd_last_error().decode())
+    return n
+
+
+def _single_args(signal, dims, max_imfs, sift_iters, imfs_out, n_imfs_out):
+    """Validated (dims array, ndim, signal, imfs_out, n_imfs_out pointers,
+    imfs_out, n_imfs_out) of a one-signal call, allocating missing outputs."""
+    d, nd = _dims(dims)
+    _check_shape_params(max_imfs, sift_iters)
+    M, N = _mn(dims)
+    dev = signal.device if isinstance(signal, torch.Tensor) else None
+    if imfs_out is None:
+        imfs_out = torch.empty((max_imfs + 1, M * N), dtype=torch.float64, device=dev)
+    if n_imfs_out is None:
+        n_imfs_out = torch.empty(1, dtype=torch.int32, device=dev)
+    bufs = ((_chk(signal, "signal", torch.float64, M * N, exact=True), "signal"),
+            (_chk(imfs_out, "imfs_out", torch.float64, (max_imfs + 1) * M * N), "imfs_out"),
+            (_chk(n_imfs_out, "n_imfs_out", torch.int32, 1), "n_imfs_out"))
+    ptrs = tuple(_ptr(t, name) for t, name in bufs)
+    return d, nd, ptrs, imfs_out, n_imfs_out
 
 
 def semd_decompose_ex(signal: torch.Tensor, dims: Sequence[int], D: int, max_imfs: int,
                       sift_iters: int, imfs_out: torch.Tensor | None = None,
                       n_imfs_out: torch.Tensor | None = None, stream=None,
-                      path: int = SEMD_PATH_AUTO, sd: float = 0.0):
+                      path: int = SEMD_PATH_AUTO, sd: float = 0.0,
+                      workspace: torch.Tensor | None = None):
     """Plain path: one signal per launch.  Returns (imfs_out, n_imfs_out).
-    sd > 0: SD stopping rule with that threshold."""
-    d, nd = _dims(dims)
-    MN = 1
-    for v in dims:
-        MN *= int(v)
-    dev = signal.device
-    if imfs_out is None:
-        imfs_out = torch.empty((max_imfs + 1, MN), dtype=torch.float64, device=dev)
-    if n_imfs_out is None:
-        n_imfs_out = torch.empty(1, dtype=torch.int32, device=dev)
+    sd > 0: SD stopping rule with that threshold.  workspace: a device
+    tensor of at least semd_workspace_bytes(...) bytes (256-byte aligned),
+    or None for a library-allocated one."""
+    d, nd, (ps, po, pn), imfs_out, n_imfs_out = _single_args(signal, dims, max_imfs, sift_iters,
+                                                             imfs_out, n_imfs_out)
     p = _params(D, max_imfs, sift_iters, path=path, sd=sd)
-    _check(lib().semd_decompose_ex(_dev_f64(signal, "signal"), d, nd, C.byref(p),
-                                   _dev_f64(imfs_out, "imfs_out"), n_imfs_out.data_ptr(),
-                                   _stream(stream)), "semd_decompose_ex")
+    ws, wsb = None, 0
+    if workspace is not None:
+        if not isinstance(workspace, torch.Tensor) or not workspace.is_cuda or \
+                not workspace.is_contiguous():
+            raise TypeError("workspace must be a contiguous tensor on the HIP device")
+        ws = _dev(workspace, "workspace", workspace.dtype)
+        wsb = workspace.numel() * workspace.element_size()
+    _check(lib().semd_decompose_ex(ps, d, nd, C.byref(p), po, pn, ws, wsb, _stream(stream)),
+           "semd_decompose_ex")
     return imfs_out, n_imfs_out
 
 
@@ -261,41 +342,76 @@ def semd_decompose_slices(signal: torch.Tensor, dims: Sequence[int], max_imfs: i
     """Standard (slice-wise) EMD: every column decomposed on its own.
     Returns (imfs_out (K+1, M*N), n_imfs_out (N,))."""
     d, nd = _dims(dims)
-    M = int(dims[0])
-    N = 1
-    for v in dims[1:]:
-        N *= int(v)
+    _check_shape_params(max_imfs, sift_iters)
+    M, N = _mn(dims)
     dev = signal.device
     if imfs_out is None:
         imfs_out = torch.empty((max_imfs + 1, M * N), dtype=torch.float64, device=dev)
     if n_imfs_out is None:
         n_imfs_out = torch.empty(N, dtype=torch.int32, device=dev)
     p = _params(0, max_imfs, sift_iters, path=path, sd=sd)
-    _check(lib().semd_decompose_slices(_dev_f64(signal, "signal"), d, nd, C.byref(p),
-                                       _dev_f64(imfs_out, "imfs_out"), n_imfs_out.data_ptr(),
-                                       _stream(stream)), "semd_decompose_slices")
+    _chk(signal, "signal", torch.float64, M * N, exact=True)
+    _chk(imfs_out, "imfs_out", torch.float64, (max_imfs + 1) * M * N)
+    _chk(n_imfs_out, "n_imfs_out", torch.int32, N)
+    _check(lib().semd_decompose_slices(_ptr(signal, "signal"), d, nd, C.byref(p),
+                                       _ptr(imfs_out, "imfs_out"), _ptr(n_imfs_out, "n_imfs_out"),
+                                       _stream(stream)),
+           "semd_decompose_slices")
     return imfs_out, n_imfs_out
 
 
-def _items(signals, dims_list, outs, counts, sigmas=None, item_ids=None, stats=None):
+def _items(signals, dims_list, outs, counts, K, sigmas=None, item_ids=None, stats=None):
+    """The semd_item array of a batch, every buffer checked against its dims:
+    signal i holds M*N doubles, its output (K+1)*M*N, its count view one
+    int32 and its stats view 3 int64."""
     n = len(signals)
+    if len(dims_list) != n or len(outs) != n:
+        raise ValueError(f"{n} signals, {len(dims_list)} dims and {len(outs)} outputs")
+    for name, seq in (("counts", counts), ("noise sigmas", sigmas), ("item ids", item_ids),
+                      ("stats", stats)):
+        if seq is not None and len(seq) != n:
+            raise ValueError(f"{n} signals but {len(seq)} {name}")
+    for i in range(n):
+        _dims(dims_list[i])
+        M, N = _mn(dims_list[i])
+        _chk(signals[i], f"signals[{i}]", torch.float64, M * N, exact=True)
+        _chk(outs[i], f"imfs_out[{i}]", torch.float64, (K + 1) * M * N)
+        if counts is not None:
+            _chk(counts[i], f"counts[{i}]", torch.int32, 1)
+        if stats is not None:
+            _chk(stats[i], f"stats[{i}]", torch.int64, 3)
     arr = (semd_item * max(n, 1))()
     for i in range(n):
         it = arr[i]
-        it.signal = _dev_f64(signals[i], f"signals[{i}]")
-        it.imfs_out = _dev_f64(outs[i], f"imfs_out[{i}]")
-        it.n_imfs_out = counts[i].data_ptr() if counts is not None else None
-        it.stats_out = stats[i].data_ptr() if stats is not None else None
-        dims = list(dims_list[i])
-        if not 1 <= len(dims) <= 4:
-            raise ValueError("dims must have 1..4 entries")
+        dims = [int(v) for v in dims_list[i]]
+        it.signal = _ptr(signals[i], f"signals[{i}]")
+        it.imfs_out = _ptr(outs[i], f"imfs_out[{i}]")
+        it.n_imfs_out = _ptr(counts[i], f"counts[{i}]") if counts is not None else None
+        it.stats_out = _ptr(stats[i], f"stats[{i}]") if stats is not None else None
         for k, v in enumerate(dims):
-            it.dims[k] = int(v)
+            it.dims[k] = v
         it.ndim = len(dims)
         it.reserved = 0
         it.noise_sigma = float(sigmas[i]) if sigmas is not None else 0.0
         it.item_id = int(item_ids[i]) if item_ids is not None else i
     return arr, n
+
+
+def _count_views(counts, n):
+    """One-entry views of an int32 count tensor of at least n entries."""
+    if counts is None:
+        return None
+    _chk(counts, "counts", torch.int32, n)
+    return [counts[i:i + 1] for i in range(n)]
+
+
+def _stats_views(stats, n):
+    if stats is None:
+        return None
+    _chk(stats, "stats", torch.int64, 3 * n)
+    if stats.dim() != 2 or stats.shape[1] != 3:
+        raise ValueError(f"stats must have shape (n, 3), got {tuple(stats.shape)}")
+    return [stats[i] for i in range(n)]
 
 
 def semd_decompose_batch(signals: Sequence[torch.Tensor], dims_list: Sequence[Sequence[int]],
@@ -305,9 +421,10 @@ def semd_decompose_batch(signals: Sequence[torch.Tensor], dims_list: Sequence[Se
     """Batched path: every signal in one launch.  counts: int32 tensor of
     len(signals) entries (or None); stats: int64 tensor (len(signals), 3) of
     (sifts, knots, sample-sifts) per signal (or None)."""
-    cviews = [counts[i:i + 1] for i in range(len(signals))] if counts is not None else None
-    sviews = [stats[i] for i in range(len(signals))] if stats is not None else None
-    arr, n = _items(signals, dims_list, outs, cviews, stats=sviews)
+    _check_shape_params(max_imfs, sift_iters)
+    cviews = _count_views(counts, len(signals))
+    sviews = _stats_views(stats, len(signals))
+    arr, n = _items(signals, dims_list, outs, cviews, max_imfs, stats=sviews)
     p = _params(D, max_imfs, sift_iters, path=path, sd=sd)
     _check(lib().semd_decompose_batch(arr, n, C.byref(p), _stream(stream)),
            "semd_decompose_batch")
@@ -319,8 +436,9 @@ def semd_eemd_batch(signals: Sequence[torch.Tensor], dims_list: Sequence[Sequenc
                     noise_sigmas: Sequence[float], item_ids: Sequence[int] | None = None,
                     stream=None, path: int = SEMD_PATH_AUTO, sd: float = 0.0) -> None:
     """Serial-EEMD of every signal (NR = ensemble realizations each)."""
-    cviews = [counts[i:i + 1] for i in range(len(signals))] if counts is not None else None
-    arr, n = _items(signals, dims_list, outs, cviews, noise_sigmas, item_ids)
+    _check_shape_params(max_imfs, sift_iters)
+    cviews = _count_views(counts, len(signals))
+    arr, n = _items(signals, dims_list, outs, cviews, max_imfs, noise_sigmas, item_ids)
     p = _params(D, max_imfs, sift_iters, ensemble, seed, path=path, sd=sd)
     _check(lib().semd_eemd_batch(arr, n, C.byref(p), _stream(stream)), "semd_eemd_batch")
 
@@ -332,44 +450,58 @@ def semd_ceemdan_batch(signals: Sequence[torch.Tensor], dims_list: Sequence[Sequ
                        stream=None, path: int = SEMD_PATH_AUTO, sd: float = 0.0) -> None:
     """Serial-CEEMDAN of every signal (NR = ensemble noise realizations, eps
     the relative noise amplitude of each item)."""
-    cviews = [counts[i:i + 1] for i in range(len(signals))] if counts is not None else None
-    arr, n = _items(signals, dims_list, outs, cviews, eps, item_ids)
+    _check_shape_params(max_imfs, sift_iters)
+    cviews = _count_views(counts, len(signals))
+    arr, n = _items(signals, dims_list, outs, cviews, max_imfs, eps, item_ids)
     p = _params(D, max_imfs, sift_iters, ensemble, seed, path=path, sd=sd)
     _check(lib().semd_ceemdan_batch(arr, n, C.byref(p), _stream(stream)), "semd_ceemdan_batch")
+
+
+def _serial_len(dims: Sequence[int], D: int) -> int:
+    M, N = _mn(dims)
+    L = semd_serial_length(M, N, int(D))
+    if L < 0:
+        raise ValueError(f"transition length {D} is outside [0, {M}]")
+    return L
 
 
 def semd_serialize(X: torch.Tensor, dims: Sequence[int], D: int, x: torch.Tensor | None = None,
                    stream=None) -> torch.Tensor:
     d, nd = _dims(dims)
-    M = int(dims[0])
-    N = X.numel() // M
+    M, N = _mn(dims)
+    L = _serial_len(dims, D)
     if x is None:
-        x = torch.empty(M * N + D * N - D, dtype=torch.float64, device=X.device)
-    _check(lib().semd_serialize(_dev_f64(X, "X"), d, nd, int(D), _dev_f64(x, "x"),
-                                _stream(stream)), "semd_serialize")
+        x = torch.empty(L, dtype=torch.float64, device=X.device)
+    _chk(X, "X", torch.float64, M * N, exact=True)
+    _chk(x, "x", torch.float64, L)
+    _check(lib().semd_serialize(_ptr(X, "X"), d, nd, int(D), _ptr(x, "x"), _stream(stream)),
+           "semd_serialize")
     return x
 
 
 def semd_deserialize(y: torch.Tensor, dims: Sequence[int], D: int,
                      out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     d, nd = _dims(dims)
-    MN = 1
-    for v in dims:
-        MN *= int(v)
+    M, N = _mn(dims)
+    L = _serial_len(dims, D)
     if out is None:
-        out = torch.empty(MN, dtype=torch.float64, device=y.device)
-    _check(lib().semd_deserialize(_dev_f64(y, "y"), d, nd, int(D), _dev_f64(out, "out"),
-                                  _stream(stream)), "semd_deserialize")
+        out = torch.empty(M * N, dtype=torch.float64, device=y.device)
+    _chk(y, "y", torch.float64, L, exact=True)
+    _chk(out, "out", torch.float64, M * N)
+    _check(lib().semd_deserialize(_ptr(y, "y"), d, nd, int(D), _ptr(out, "out"),
+                                  _stream(stream)),
+           "semd_deserialize")
     return out
 
 
 def semd_extrema(h: torch.Tensor, stream=None):
     """(maxima indices, minima indices) of a 1D device signal, as int32 tensors."""
     L = h.numel()
+    ph = _dev_f64(h, "h")
     imax = torch.empty(L // 2 + 1, dtype=torch.int32, device=h.device)
     imin = torch.empty(L // 2 + 1, dtype=torch.int32, device=h.device)
     counts = torch.empty(2, dtype=torch.int32, device=h.device)
-    _check(lib().semd_extrema(_dev_f64(h, "h"), L, imax.data_ptr(), imin.data_ptr(),
+    _check(lib().semd_extrema(ph, L, imax.data_ptr(), imin.data_ptr(),
                               counts.data_ptr(), _stream(stream)), "semd_extrema")
     c = counts.cpu()
     return imax[: int(c[0])], imin[: int(c[1])]
@@ -380,7 +512,7 @@ def semd_noise(seed: int, item: int, m: int, L: int, w: torch.Tensor | None = No
     if w is None:
         w = torch.empty(L, dtype=torch.float64, device=device)
     _check(lib().semd_noise(int(seed) & (2**64 - 1), int(item), int(m), int(L),
-                            _dev_f64(w, "w"), _stream(stream)), "semd_noise")
+                            _dev_f64(w, "w", int(L)), _stream(stream)), "semd_noise")
     return w
 
 
@@ -413,11 +545,12 @@ class PreparedBatch:
     def __init__(self, signals, dims_list, outs, counts=None, D=0, max_imfs=8, sift_iters=10,
                  stats=None, ensemble=1, seed=0, noise_sigmas=None, item_ids=None,
                  path=SEMD_PATH_AUTO, sd=0.0):
-        cviews = [counts[i:i + 1] for i in range(len(signals))] if counts is not None else None
-        sviews = [stats[i] for i in range(len(signals))] if stats is not None else None
+        _check_shape_params(max_imfs, sift_iters)
+        cviews = _count_views(counts, len(signals))
+        sviews = _stats_views(stats, len(signals))
         self._keep = (list(signals), list(outs), counts, stats)
-        self.items, self.n = _items(signals, dims_list, outs, cviews, noise_sigmas, item_ids,
-                                    sviews)
+        self.items, self.n = _items(signals, dims_list, outs, cviews, max_imfs, noise_sigmas,
+                                    item_ids, sviews)
         self.params = _params(D, max_imfs, sift_iters, ensemble, seed, path=path, sd=sd)
         self.eemd = ensemble > 1 or noise_sigmas is not None
 
@@ -461,13 +594,14 @@ class Engine:
               n_imfs: torch.Tensor | None, D: int, K: int, S: int,
               sd: float = 0.0) -> int | None:
         """Ticket of the admitted request, or None when it does not fit now."""
+        _check_shape_params(K, S)
         arr, _ = _items([signal], [dims], [out],
-                        [n_imfs] if n_imfs is not None else None)
+                        [n_imfs] if n_imfs is not None else None, K)
         p = _params(D, K, S, sd=sd)
         t = C.c_int64()
         rc = lib().semd_engine_admit(self._h, arr, C.byref(p), C.byref(t))
         if rc == SEMD_EBUSY:
-            return None
+            return None  # fits the budget once resident requests finish
         _check(rc, "semd_engine_admit")
         self._keep[t.value] = (signal, out, n_imfs)
         return int(t.value)

@@ -510,6 +510,60 @@ int run_work(std::vector<semd::WorkItem>& work, int K, int S, int path, hipStrea
   return rc;
 }
 
+// Workspace of one signal decomposed on its own (semd_decompose_ex): its
+// descriptor, on the streaming path its tile and solve-block tables, and the
+// path's buffers, carved from one region that starts 256-byte aligned.
+struct SingleLayout {
+  bool onchip;
+  int ntiles, nblocks;
+  size_t o_tiles, o_blocks, o_data, bytes;
+};
+
+SingleLayout single_layout(int64_t L, int path) {
+  SingleLayout s{};
+  s.onchip = path == SEMD_PATH_ONCHIP || (path == SEMD_PATH_AUTO && L <= semd::kResidentMaxL);
+  if (s.onchip) {
+    s.o_data = al256(sizeof(semd::WorkItem));
+    s.bytes = s.o_data + al256(sizeof(double) * (size_t)semd::resident_ws_doubles(L));
+  } else {
+    const int cap = (int)((L - 1) / 2 + 12);
+    s.ntiles = (int)((L + semd::kTile - 1) / semd::kTile);
+    s.nblocks = 2 * semd::stream_solve_blocks(cap);
+    s.o_tiles = al256(sizeof(semd::StreamSig));
+    s.o_blocks = s.o_tiles + al256(sizeof(int2) * (size_t)s.ntiles);
+    s.o_data = s.o_blocks + al256(sizeof(int4) * (size_t)s.nblocks);
+    s.bytes = s.o_data + al256(stream_bytes(L));
+  }
+  return s;
+}
+
+// Decompose one signal inside the workspace ws (single_layout's bytes, 256-byte
+// aligned): descriptors written by kernels from their arguments, then the
+// path's kernels launched directly on `stream` (one resident launch, or the
+// load and K*S streaming steps).  Enqueues nothing but kernels.
+int run_single(semd::WorkItem w, int K, int S, int path, unsigned char* ws, hipStream_t stream) {
+  const SingleLayout lay = single_layout(w.L, path);
+  hipError_t e;
+  if (lay.onchip) {
+    w.r = reinterpret_cast<double*>(ws + lay.o_data);
+    w.u = w.r + w.L;
+    auto* d = reinterpret_cast<semd::WorkItem*>(ws);
+    e = semd::launch_put_work(w, d, stream);
+    if (e == hipSuccess) e = semd::launch_resident(d, 1, w.L, class_for(w.L, 0), K, S, stream);
+    return e == hipSuccess ? SEMD_OK : hip_fail(e, "resident kernel launch");
+  }
+  const semd::StreamSig g = stream_sig(w, K, S, ws + lay.o_data);
+  auto* d_sig = reinterpret_cast<semd::StreamSig*>(ws);
+  auto* d_tiles = reinterpret_cast<int2*>(ws + lay.o_tiles);
+  auto* d_blocks = reinterpret_cast<int4*>(ws + lay.o_blocks);
+  e = semd::st_put_single(g, d_sig, d_tiles, d_blocks, stream);
+  if (e == hipSuccess) e = semd::st_load(d_sig, d_tiles, lay.ntiles, stream);
+  // every signal finishes within K*S steps (each step sifts it or ends an IMF)
+  for (int step = 0; step < K * S && e == hipSuccess; ++step)
+    e = semd::st_step(d_sig, 1, d_tiles, lay.ntiles, d_blocks, lay.nblocks, stream);
+  return e == hipSuccess ? SEMD_OK : hip_fail(e, "streaming kernel launch");
+}
+
 semd::WorkItem make_work(const double* X, double* out, int32_t* n_imfs, const Shape& sh, int D,
                          double sd, int64_t* stats = nullptr) {
   semd::WorkItem w{};
@@ -555,6 +609,15 @@ int check_items(const semd_item* items, int n, int D, int path, std::vector<Shap
     if (rc) return rc;
   }
   return SEMD_OK;
+}
+
+// Validated shape of one signal of semd_decompose_ex (and its workspace).
+int check_single(const int64_t* dims, int ndim, const semd_params* p, Shape* sh) {
+  int rc = check_params(p, false);
+  if (rc) return rc;
+  rc = shape_of(dims, ndim, p->transition_len, sh);
+  if (rc) return rc;
+  return check_length(sh->L, p->path, 0);
 }
 
 }  // namespace
@@ -731,20 +794,38 @@ int semd_tune_reset(void) {
   return SEMD_OK;
 }
 
-int semd_decompose_ex(const double* signal, const int64_t* dims, int ndim, const semd_params* p,
-                      double* imfs_out, int32_t* n_imfs_out, hipStream_t stream) {
+size_t semd_workspace_bytes(const int64_t* dims, int ndim, const semd_params* p) {
   g_err[0] = 0;
-  int rc = check_params(p, false);
+  Shape sh;
+  if (check_single(dims, ndim, p, &sh)) return 0;
+  return single_layout(sh.L, p->path).bytes;
+}
+
+int semd_decompose_ex(const double* signal, const int64_t* dims, int ndim, const semd_params* p,
+                      double* imfs_out, int32_t* n_imfs_out, void* workspace, size_t ws_bytes,
+                      hipStream_t stream) {
+  g_err[0] = 0;
+  Shape sh;
+  int rc = check_single(dims, ndim, p, &sh);
   if (rc) return rc;
   if (!signal || !imfs_out) return fail(SEMD_EINVAL, "NULL signal or output");
-  Shape sh;
-  rc = shape_of(dims, ndim, p->transition_len, &sh);
-  if (rc) return rc;
-  rc = check_length(sh.L, p->path, 0);
-  if (rc) return rc;
-  std::vector<semd::WorkItem> work{make_work(signal, imfs_out, n_imfs_out, sh, p->transition_len,
-                                               sd_of(p))};
-  return run_work(work, p->max_imfs, p->sift_iters, p->path, stream);
+  const size_t need = single_layout(sh.L, p->path).bytes;
+  const semd::WorkItem w = make_work(signal, imfs_out, n_imfs_out, sh, p->transition_len,
+                                     sd_of(p));
+  if (workspace) {
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+      return fail(SEMD_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < need)
+      return fail(SEMD_EINVAL, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    return run_single(w, p->max_imfs, p->sift_iters, p->path,
+                      static_cast<unsigned char*>(workspace), stream);
+  }
+  unsigned char* ws = nullptr;
+  if (hipMallocAsync(reinterpret_cast<void**>(&ws), need, stream) != hipSuccess)
+    return fail(SEMD_ENOMEM, "workspace of %zu bytes", need);
+  rc = run_single(w, p->max_imfs, p->sift_iters, p->path, ws, stream);
+  (void)hipFreeAsync(ws, stream);
+  return rc;
 }
 
 int semd_decompose_slices(const double* signal, const int64_t* dims, int ndim,
@@ -788,7 +869,7 @@ int semd_decompose(const double* signal, const int64_t* dims, int ndim, int max_
   p.sift_iters = sift_iters;
   p.boundary_rule = boundary_rule;
   p.ensemble = 1;
-  return semd_decompose_ex(signal, dims, ndim, &p, imfs_out, nullptr, stream);
+  return semd_decompose_ex(signal, dims, ndim, &p, imfs_out, nullptr, nullptr, 0, stream);
 }
 
 int semd_decompose_batch(const semd_item* items, int n, const semd_params* p,
@@ -1217,6 +1298,9 @@ int semd_engine_admit(semd_engine* e, const semd_item* item, const semd_params* 
   if ((int)e->reqs.size() >= e->max_requests)
     return fail(SEMD_EBUSY, "all %d request slots are taken", e->max_requests);
   const size_t bytes = al256(stream_bytes(sh.L));
+  if (bytes > e->budget)
+    return fail(SEMD_ENOMEM, "request needs %zu bytes, more than the whole engine budget %zu",
+                bytes, e->budget);
   size_t off = 0;
   if (e->alloc(bytes, &off))
     return fail(SEMD_EBUSY, "request needs %zu bytes, not free in the engine budget", bytes);

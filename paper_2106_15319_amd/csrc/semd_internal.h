@@ -78,6 +78,10 @@ int resident_classes(ResidentClass* out, int cap);
 hipError_t launch_resident(const WorkItem* d_items, int n, int maxL, ResidentClass c, int K,
                            int S, hipStream_t stream);
 
+// Write the descriptor w to device memory dst (stream-ordered, by a kernel:
+// no host staging buffer and no allocation).
+hipError_t launch_put_work(const WorkItem& w, WorkItem* dst, hipStream_t stream);
+
 // Extrema of one 1D signal (3 <= L <= kResidentMaxL) through the resident
 // detection/compaction code: indices to imax/imin, counts[0..1].
 hipError_t launch_extrema(const double* h, int L, int32_t* imax, int32_t* imin,

@@ -895,6 +895,12 @@ __global__ void __launch_bounds__(NT) extrema_kernel(const double* __restrict__ 
 // Streaming helper kernels
 // ---------------------------------------------------------------------------
 
+// dst[0] = w: the descriptor of a single-signal launch, handed over as a
+// kernel argument so that no host staging buffer is involved.
+__global__ void put_work_kernel(WorkItem w, WorkItem* __restrict__ dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = w;
+}
+
 __global__ void serialize_kernel(const double* __restrict__ X, int64_t M, int64_t N, int D,
                                  double* __restrict__ x) {
   const int64_t R = M + D, L = M * N + (int64_t)D * N - D;
@@ -1243,6 +1249,11 @@ hipError_t launch_resident(const WorkItem* d_items, int n, int maxL, ResidentCla
     case 102416: return launch_resident_cls<1024, 16>(d_items, n, maxL, K, S, stream);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_put_work(const WorkItem& w, WorkItem* dst, hipStream_t stream) {
+  hipLaunchKernelGGL(put_work_kernel, dim3(1), dim3(64), 0, stream, w, dst);
+  return hipGetLastError();
 }
 
 hipError_t launch_extrema(const double* h, int L, int32_t* imax, int32_t* imin,

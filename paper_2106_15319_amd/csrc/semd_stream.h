@@ -98,6 +98,11 @@ hipError_t st_load(const StreamSig* sigs, const int2* tiles, int ntiles, hipStre
 // compact and solve (sifting signals), eval (sift, IMF end, final outputs).
 hipError_t st_step(const StreamSig* sigs, int nsig, const int2* tiles, int ntiles,
                    const int4* blocks, int nblocks, hipStream_t s);
+// The descriptor of the one signal g and its tile and solve-block tables
+// (g.ntiles and 2 * stream_solve_blocks(g.cap) entries), written on the
+// device from a kernel argument: no host staging buffer, no allocation.
+hipError_t st_put_single(const StreamSig& g, StreamSig* dsig, int2* tiles, int4* blocks,
+                         hipStream_t s);
 // done[i] = status of signal i has its final outputs written.
 hipError_t st_gather_done(const StreamSig* sigs, int nsig, int32_t* done, hipStream_t s);
 // Solve blocks one envelope of `cap` knots needs.

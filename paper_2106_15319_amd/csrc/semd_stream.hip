@@ -907,6 +907,18 @@ __global__ void st_gather_done_kernel(const StreamSig* __restrict__ sigs, int n,
   if (i < n) done[i] = sigs[i].st->done;
 }
 
+// The descriptor of one signal and its tables, as stream_tables() lays them
+// out for a one-signal batch: tiles[t] = (0, t) and blocks[e * nb + b] =
+// (0, e, b) for the envelopes e = 0, 1 and their solve blocks b < nb.
+__global__ void st_put_single_kernel(StreamSig g, StreamSig* __restrict__ dsig,
+                                     int2* __restrict__ tiles, int ntiles,
+                                     int4* __restrict__ blocks, int nb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *dsig = g;
+  if (i < ntiles) tiles[i] = make_int2(0, i);
+  if (i < 2 * nb) blocks[i] = make_int4(0, i / nb, i - (i / nb) * nb, 0);
+}
+
 inline dim3 per_signal(int n) { return dim3((n + 255) / 256); }
 
 }  // namespace
@@ -928,6 +940,14 @@ hipError_t st_step(const StreamSig* sigs, int nsig, const int2* tiles, int ntile
   hipLaunchKernelGGL(st_compact_kernel, dim3(ntiles), dim3(kTT), 0, st, sigs, tiles);
   hipLaunchKernelGGL(st_solve_kernel, dim3(nblocks), dim3(kTT), 0, st, sigs, blocks);
   hipLaunchKernelGGL(st_eval_kernel, dim3(ntiles), dim3(kTT), 0, st, sigs, tiles);
+  return hipGetLastError();
+}
+hipError_t st_put_single(const StreamSig& g, StreamSig* dsig, int2* tiles, int4* blocks,
+                         hipStream_t s) {
+  const int nb = stream_solve_blocks(g.cap);
+  const int n = g.ntiles > 2 * nb ? g.ntiles : (2 * nb > 1 ? 2 * nb : 1);
+  hipLaunchKernelGGL(st_put_single_kernel, dim3((n + 255) / 256), dim3(256), 0, s, g, dsig,
+                     tiles, g.ntiles, blocks, nb);
   return hipGetLastError();
 }
 hipError_t st_gather_done(const StreamSig* sigs, int nsig, int32_t* done, hipStream_t s) {

@@ -208,6 +208,33 @@ def test_uneven_batch_mixed_lengths():
     assert len(ties) <= 1
 
 
+@pytest.mark.parametrize("path,M,N,D", [(semd.SEMD_PATH_ONCHIP, 1000, 3, 50),
+                                         (semd.SEMD_PATH_STREAM, 1000, 3, 50),
+                                         (semd.SEMD_PATH_AUTO, 20000, 2, 0),
+                                         (semd.SEMD_PATH_AUTO, 16384, 1, 0)])
+def test_caller_workspace_matches_library_workspace(path, M, N, D):
+    """semd_decompose_ex with a caller's workspace (filled with garbage
+    first, then reused dirty) gives bit-identical outputs to the
+    library-allocated one, and both match the oracle; an undersized
+    workspace is refused."""
+    K, S = 6, 10
+    X = workloads.series(workloads.rng_for(21, M + N), N, M)
+    need = semd.semd_workspace_bytes([M, N], D, K, S, path=path)
+    ws = torch.full((need,), 0xA5, dtype=torch.uint8, device=DEV)
+    assert ws.data_ptr() % 256 == 0
+    a, na = semd.semd_decompose_ex(dev(X), [M, N], D, K, S, path=path)
+    b, nb = semd.semd_decompose_ex(dev(X), [M, N], D, K, S, path=path, workspace=ws)
+    c, nc = semd.semd_decompose_ex(dev(X), [M, N], D, K, S, path=path, workspace=ws)
+    assert_same(host(a), host(b), "caller workspace")
+    assert_same(host(a), host(c), "reused workspace")
+    assert int(host(na)[0]) == int(host(nb)[0]) == int(host(nc)[0])
+    ties = []
+    _check_item(X, M, N, D, K, S, host(b), int(host(nb)[0]), ties)
+    with pytest.raises(semd.SemdError) as ei:
+        semd.semd_decompose_ex(dev(X), [M, N], D, K, S, path=path, workspace=ws[:need - 256])
+    assert ei.value.code == semd.SEMD_EINVAL
+
+
 def test_determinism():
     it = workloads.config2(1)[0]
     a, _ = semd.semd_decompose_ex(dev(it.X), [it.M, it.N], 20, 8, 10)
