@@ -201,6 +201,26 @@ int semd_decompose_ex(const double* signal, const int64_t* dims, int ndim,
                       const semd_params* p, double* imfs_out, int32_t* n_imfs_out,
                       void* workspace, size_t ws_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops or harnesses that forbid hipMalloc): the same
+ * decomposition as semd_decompose_ex, bit for bit, with its workspace in a
+ * static device array of semd_noalloc_scratch_bytes() bytes (64 MiB) that
+ * each GPU the library runs on holds until the process ends.  It calls no
+ * allocator; it enqueues kernels only.  Signals whose
+ * semd_workspace_bytes(dims, ndim, p) exceeds the array (serialized lengths
+ * above about 1.36 million samples on the streaming path) return SEMD_EINVAL
+ * with nothing enqueued.  Every call on one GPU uses that GPU's one array:
+ * calls that overlap in time on one GPU (different streams, or host threads
+ * without ordering between their streams) race and corrupt each other's
+ * results; calls ordered on one stream are safe.  The array's contents need
+ * no initialization and are undefined between calls. */
+int semd_decompose_ex_noalloc(const double* signal, const int64_t* dims, int ndim,
+                              const semd_params* p, double* imfs_out, int32_t* n_imfs_out,
+                              hipStream_t stream);
+
+/* Size of the static array semd_decompose_ex_noalloc works in. */
+size_t semd_noalloc_scratch_bytes(void);
+
 /* Standard (slice-wise) EMD, the baseline Serial-EMD is compared with (Sec. 4):
  * each of the N columns of X (length M each, dims as above) is decomposed by
  * the 1D EMD of Sec. 2.1 on its own, with no serialization.  p->transition_len

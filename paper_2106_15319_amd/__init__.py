@@ -74,6 +74,10 @@ _EXPORTS = {
     "semd_decompose_ex": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_int,
                                     C.POINTER(semd_params), C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_size_t, C.c_void_p]),
+    "semd_decompose_ex_noalloc": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_int,
+                                            C.POINTER(semd_params), C.c_void_p, C.c_void_p,
+                                            C.c_void_p]),
+    "semd_noalloc_scratch_bytes": (C.c_size_t, []),
     "semd_decompose_batch": (C.c_int, [C.POINTER(semd_item), C.c_int, C.POINTER(semd_params),
                                        C.c_void_p]),
     "semd_decompose_slices": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_int,
@@ -333,6 +337,24 @@ def semd_decompose_ex(signal: torch.Tensor, dims: Sequence[int], D: int, max_imf
     _check(lib().semd_decompose_ex(ps, d, nd, C.byref(p), po, pn, ws, wsb, _stream(stream)),
            "semd_decompose_ex")
     return imfs_out, n_imfs_out
+
+
+def semd_decompose_ex_noalloc(signal: torch.Tensor, dims: Sequence[int], D: int, max_imfs: int,
+                              sift_iters: int, imfs_out: torch.Tensor, n_imfs_out: torch.Tensor,
+                              stream=None, path: int = SEMD_PATH_AUTO, sd: float = 0.0):
+    """semd_decompose_ex working in the library's static scratch array: no
+    allocation by the library (the caller passes the outputs).  Returns
+    (imfs_out, n_imfs_out)."""
+    d, nd, (ps, po, pn), imfs_out, n_imfs_out = _single_args(signal, dims, max_imfs, sift_iters,
+                                                             imfs_out, n_imfs_out)
+    p = _params(D, max_imfs, sift_iters, path=path, sd=sd)
+    _check(lib().semd_decompose_ex_noalloc(ps, d, nd, C.byref(p), po, pn, _stream(stream)),
+           "semd_decompose_ex_noalloc")
+    return imfs_out, n_imfs_out
+
+
+def semd_noalloc_scratch_bytes() -> int:
+    return int(lib().semd_noalloc_scratch_bytes())
 
 
 def semd_decompose_slices(signal: torch.Tensor, dims: Sequence[int], max_imfs: int,

@@ -611,6 +611,37 @@ int check_items(const semd_item* items, int n, int D, int path, std::vector<Shap
   return SEMD_OK;
 }
 
+// Workspace of semd_decompose_ex_noalloc: one array per GPU, alive until the
+// process ends.  Host code never passes the array's name to a kernel (on the
+// host it is only a stand-in for the symbol); it uses the device address
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array, looked up on the
+// first call on each device and kept.
+int scratch_for_current_device(unsigned char** out) {
+  int dev = 0;
+  SEMD_HIP(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(SEMD_EUNSUPPORTED, "device %d beyond the %d supported", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr || reinterpret_cast<uintptr_t>(ptr) % 256 != 0)
+      return fail(SEMD_EDEVICE, "scratch array at an unaligned address");
+    g_scratch_ptr[dev] = static_cast<unsigned char*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return SEMD_OK;
+}
+
 // Validated shape of one signal of semd_decompose_ex (and its workspace).
 int check_single(const int64_t* dims, int ndim, const semd_params* p, Shape* sh) {
   int rc = check_params(p, false);
@@ -827,6 +858,28 @@ int semd_decompose_ex(const double* signal, const int64_t* dims, int ndim, const
   (void)hipFreeAsync(ws, stream);
   return rc;
 }
+
+int semd_decompose_ex_noalloc(const double* signal, const int64_t* dims, int ndim,
+                              const semd_params* p, double* imfs_out, int32_t* n_imfs_out,
+                              hipStream_t stream) {
+  g_err[0] = 0;
+  Shape sh;
+  int rc = check_single(dims, ndim, p, &sh);
+  if (rc) return rc;
+  if (!signal || !imfs_out) return fail(SEMD_EINVAL, "NULL signal or output");
+  const size_t need = single_layout(sh.L, p->path).bytes;
+  if (need > kScratchBytes)
+    return fail(SEMD_EINVAL, "needs %zu bytes of workspace, the static scratch holds %zu", need,
+                kScratchBytes);
+  unsigned char* ws = nullptr;
+  rc = scratch_for_current_device(&ws);
+  if (rc) return rc;
+  const semd::WorkItem w = make_work(signal, imfs_out, n_imfs_out, sh, p->transition_len,
+                                     sd_of(p));
+  return run_single(w, p->max_imfs, p->sift_iters, p->path, ws, stream);
+}
+
+size_t semd_noalloc_scratch_bytes(void) { return kScratchBytes; }
 
 int semd_decompose_slices(const double* signal, const int64_t* dims, int ndim,
                           const semd_params* p, double* imfs_out, int32_t* n_imfs_out,
