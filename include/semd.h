@@ -221,6 +221,24 @@ int semd_decompose_ex_noalloc(const double* signal, const int64_t* dims, int ndi
 /* Size of the static array semd_decompose_ex_noalloc works in. */
 size_t semd_noalloc_scratch_bytes(void);
 
+/* Parity instrumentation for the extremum decisions of Sec. 2.1 Step 1:
+ * semd_decompose_ex (library-allocated workspace) that also records every
+ * extremum detection the decomposition makes.  trace: device, trace_cap
+ * int32 (4 <= trace_cap < 2^31); afterwards trace[0] = entries used (the 4
+ * header entries included), trace[1] = 1 if every record fitted (0 once one
+ * did not; recording stops there), then one record per detection, in order:
+ *   imf, sift, nmax, nmin, maxima (nmax positions), minima (nmin positions)
+ * -- positions in the serialized signal of Sec. 3.2, increasing; sift 0 is
+ * the detection on the residue before IMF imf, sift s > 0 the one on the
+ * candidate before its sift s.  On the on-chip path the decomposition runs
+ * in its 1024-thread x 16-sample launch shape; outputs equal
+ * semd_decompose_ex's bit for bit on the streaming path and whenever
+ * semd_decompose_ex also takes a 1024-thread shape, within rounding
+ * otherwise. */
+int semd_decompose_trace(const double* signal, const int64_t* dims, int ndim,
+                         const semd_params* p, double* imfs_out, int32_t* n_imfs_out,
+                         int32_t* trace, int64_t trace_cap, hipStream_t stream);
+
 /* Standard (slice-wise) EMD, the baseline Serial-EMD is compared with (Sec. 4):
  * each of the N columns of X (length M each, dims as above) is decomposed by
  * the 1D EMD of Sec. 2.1 on its own, with no serialization.  p->transition_len

@@ -80,6 +80,8 @@ def bind(L):
                                             _d, _int]
     L.semd_ref_decompose_slices_sd.argtypes = [_d, C.c_int64, C.c_int64, C.c_int, C.c_int,
                                                C.c_double, _d, _int]
+    L.semd_ref_emd_trace.argtypes = [_d, C.c_int64, C.c_int, C.c_int, C.c_double, _d, _int,
+                                     _i64, C.c_int64, _i64, _int, C.c_int, C.c_int, _d, _int]
     L.semd_ref_splitmix64.restype = C.c_uint64
     L.semd_ref_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
     L.semd_ref_noise.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.c_int64, _d]
@@ -96,7 +98,7 @@ def bind(L):
                  "semd_ref_emd", "semd_ref_decompose", "semd_ref_decompose_slices",
                  "semd_ref_emd_sd", "semd_ref_decompose_sd",
                  "semd_ref_decompose_slices_sd", "semd_ref_noise", "semd_ref_eemd",
-                 "semd_ref_eemd_sd"):
+                 "semd_ref_eemd_sd", "semd_ref_emd_trace"):
         getattr(L, name).restype = C.c_int
     return L
 
@@ -189,6 +191,52 @@ def emd(x, K: int, S: int, with_stats: bool = False, sd: float = 0.0):
     if with_stats:
         return res + (_stats(st),)
     return res
+
+
+def parse_trace(buf) -> list[tuple[int, int, np.ndarray, np.ndarray]]:
+    """Records (imf, sift, maxima, minima) of a flat extremum-decision trace."""
+    buf = np.asarray(buf, dtype=np.int64)
+    recs, o = [], 0
+    while o + 4 <= buf.size:
+        imf, sift, na, ni = (int(v) for v in buf[o:o + 4])
+        if na < 0 or ni < 0 or o + 4 + na + ni > buf.size:
+            raise ValueError(f"malformed trace record at {o}")
+        recs.append((imf, sift, buf[o + 4:o + 4 + na].copy(),
+                     buf[o + 4 + na:o + 4 + na + ni].copy()))
+        o += 4 + na + ni
+    return recs
+
+
+def emd_trace(x, K: int, S: int, sd: float = 0.0, cap: int | None = None):
+    """Sec. 2.1 with every extremum detection recorded: ((K+1, L) slots,
+    n_imfs, records [(imf, sift, maxima, minima)], complete)."""
+    x = _f64(x)
+    L = x.size
+    cap = cap if cap is not None else (K * S) * (L + 8) + 64
+    buf = np.empty(max(cap, 1), dtype=np.int64)
+    out = np.empty((K + 1) * L)
+    n = C.c_int()
+    used, complete = C.c_int64(), C.c_int()
+    _check(lib().semd_ref_emd_trace(_p(x), L, K, S, float(sd), _p(out), C.byref(n),
+                                    buf.ctypes.data_as(_i64), cap, C.byref(used),
+                                    C.byref(complete), -1, -1, None, None), "emd_trace")
+    return out.reshape(K + 1, L), n.value, parse_trace(buf[: used.value]), bool(complete.value)
+
+
+def emd_tested(x, K: int, S: int, imf: int, sift: int, sd: float = 0.0):
+    """The array that detection (imf, sift) of the EMD of x tests (the
+    residue for sift 0, else the candidate before that sift), or None if the
+    decomposition makes no such detection."""
+    x = _f64(x)
+    L = x.size
+    out = np.empty((K + 1) * L)
+    h = np.empty(L)
+    n = C.c_int()
+    used, complete, found = C.c_int64(), C.c_int(), C.c_int()
+    _check(lib().semd_ref_emd_trace(_p(x), L, K, S, float(sd), _p(out), C.byref(n), None, 0,
+                                    C.byref(used), C.byref(complete), int(imf), int(sift),
+                                    _p(h), C.byref(found)), "emd_tested")
+    return h if found.value else None
 
 
 def decompose(Xcol, M: int, N: int, D: int, K: int, S: int, with_stats: bool = False,

@@ -230,13 +230,69 @@ static void note_gaps(const double* h, int64_t L, semd_ref_stats* st) {
   }
 }
 
+/* Where a traced decomposition writes its extremum decisions (see
+ * semd_ref_emd_trace); NULL for an untraced one. */
+typedef struct {
+  int64_t* buf;
+  int64_t cap, used;
+  int complete;
+  int want_imf, want_sift;
+  double* h_at;
+  int found;
+} trace_ctx;
+
+/* One detection: the record (imf, sift, counts, index lists), and the tested
+ * array itself when it is the one asked for. */
+static void trace_detection(trace_ctx* tc, int imf, int sift, const double* tested, int64_t L,
+                            const int64_t* imax, int64_t na, const int64_t* imin, int64_t ni) {
+  if (!tc) return;
+  if (tc->h_at && imf == tc->want_imf && sift == tc->want_sift) {
+    memcpy(tc->h_at, tested, sizeof(double) * (size_t)L);
+    tc->found = 1;
+  }
+  if (!tc->buf || !tc->complete) return;
+  const int64_t need = 4 + na + ni;
+  if (tc->used + need > tc->cap) {
+    tc->complete = 0;
+    return;
+  }
+  int64_t* o = tc->buf + tc->used;
+  o[0] = imf;
+  o[1] = sift;
+  o[2] = na;
+  o[3] = ni;
+  for (int64_t j = 0; j < na; ++j) o[4 + j] = imax[j];
+  for (int64_t j = 0; j < ni; ++j) o[4 + na + j] = imin[j];
+  tc->used += need;
+}
+
+static int emd_core(const double* x, int64_t L, int K, int S, double sd_threshold,
+                    double* imfs, int* n_imfs, semd_ref_stats* stats, trace_ctx* tc);
+
 int semd_ref_emd(const double* x, int64_t L, int K, int S, double* imfs, int* n_imfs,
                  semd_ref_stats* stats) {
-  return semd_ref_emd_sd(x, L, K, S, 0.0, imfs, n_imfs, stats);
+  return emd_core(x, L, K, S, 0.0, imfs, n_imfs, stats, NULL);
 }
 
 int semd_ref_emd_sd(const double* x, int64_t L, int K, int S, double sd_threshold,
                     double* imfs, int* n_imfs, semd_ref_stats* stats) {
+  return emd_core(x, L, K, S, sd_threshold, imfs, n_imfs, stats, NULL);
+}
+
+int semd_ref_emd_trace(const double* x, int64_t L, int K, int S, double sd_threshold,
+                       double* imfs, int* n_imfs, int64_t* buf, int64_t cap, int64_t* used,
+                       int* complete, int want_imf, int want_sift, double* h_at, int* found) {
+  if (!used || !complete || (cap > 0 && !buf) || cap < 0) return -1;
+  trace_ctx tc = {buf, cap, 0, 1, want_imf, want_sift, h_at, 0};
+  const int rc = emd_core(x, L, K, S, sd_threshold, imfs, n_imfs, NULL, &tc);
+  *used = tc.used;
+  *complete = tc.complete;
+  if (found) *found = tc.found;
+  return rc;
+}
+
+static int emd_core(const double* x, int64_t L, int K, int S, double sd_threshold,
+                    double* imfs, int* n_imfs, semd_ref_stats* stats, trace_ctx* tc) {
   if (!x || !imfs || !n_imfs || L < 1 || K < 1 || S < 1 || !(sd_threshold >= 0.0)) return -1;
   for (int64_t k = 0; k < L; ++k)
     if (!isfinite(x[k])) return -3;
@@ -267,12 +323,14 @@ int semd_ref_emd_sd(const double* x, int64_t L, int K, int S, double sd_threshol
     if (L < 3) break;
     if (!pristine) note_gaps(r, L, &st);
     semd_ref_extrema(r, L, imax, &na, imin, &ni);
+    trace_detection(tc, nimf, 0, r, L, imax, na, imin, ni);
     if (!siftable(na, ni)) break;
     memcpy(h, r, nb); /* h = r */
     for (int s = 0; s < S; ++s) {
       if (s > 0) {
         note_gaps(h, L, &st);
         semd_ref_extrema(h, L, imax, &na, imin, &ni);
+        trace_detection(tc, nimf, s, h, L, imax, na, imin, ni);
         if (!siftable(na, ni)) break;
       }
       /* Step 2: upper and lower envelopes; Step 3: local mean;

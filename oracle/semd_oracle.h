@@ -79,6 +79,19 @@ int semd_ref_emd(const double* x, int64_t L, int K, int S, double* imfs, int* n_
 int semd_ref_emd_sd(const double* x, int64_t L, int K, int S, double sd_threshold,
                     double* imfs, int* n_imfs, semd_ref_stats* stats);
 
+/* semd_ref_emd_sd with its extremum decisions recorded (Sec. 2.1 Step 1), for
+ * the per-sift parity comparison.  Every detection the loop makes -- on the
+ * residue before IMF i (sift index 0) and on the candidate before sift s > 0
+ * of IMF i -- appends the record
+ *   i, s, nmax, nmin, maxima (nmax indices), minima (nmin indices)
+ * to buf while the whole record fits in cap entries; *used receives the
+ * entries written, *complete 0 once a record did not fit.  When h_at is not
+ * NULL, the array tested by detection (want_imf, want_sift) is copied there
+ * (L doubles) and *found (if not NULL) set to 1, else to 0. */
+int semd_ref_emd_trace(const double* x, int64_t L, int K, int S, double sd_threshold,
+                       double* imfs, int* n_imfs, int64_t* buf, int64_t cap, int64_t* used,
+                       int* complete, int want_imf, int want_sift, double* h_at, int* found);
+
 /* Serial-EMD: serialize (Sec. 3.2), EMD (Sec. 2.1), deserialize (Sec. 3.3).
  * out: (K+1)*M*N doubles in the same slot convention. */
 int semd_ref_decompose(const double* X, int64_t M, int64_t N, int64_t D, int K, int S,

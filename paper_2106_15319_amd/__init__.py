@@ -78,6 +78,9 @@ _EXPORTS = {
                                             C.POINTER(semd_params), C.c_void_p, C.c_void_p,
                                             C.c_void_p]),
     "semd_noalloc_scratch_bytes": (C.c_size_t, []),
+    "semd_decompose_trace": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_int,
+                                       C.POINTER(semd_params), C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_int64, C.c_void_p]),
     "semd_decompose_batch": (C.c_int, [C.POINTER(semd_item), C.c_int, C.POINTER(semd_params),
                                        C.c_void_p]),
     "semd_decompose_slices": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_int,
@@ -351,6 +354,25 @@ def semd_decompose_ex_noalloc(signal: torch.Tensor, dims: Sequence[int], D: int,
     _check(lib().semd_decompose_ex_noalloc(ps, d, nd, C.byref(p), po, pn, _stream(stream)),
            "semd_decompose_ex_noalloc")
     return imfs_out, n_imfs_out
+
+
+def semd_decompose_trace(signal: torch.Tensor, dims: Sequence[int], D: int, max_imfs: int,
+                         sift_iters: int, trace_cap: int | None = None, stream=None,
+                         path: int = SEMD_PATH_AUTO, sd: float = 0.0):
+    """semd_decompose_ex recording every extremum detection.  Returns
+    (imfs_out, n_imfs_out, trace) with trace the int32 device buffer
+    (trace[0] entries used, trace[1] complete flag, then the records)."""
+    d, nd, (ps, po, pn), imfs_out, n_imfs_out = _single_args(signal, dims, max_imfs, sift_iters,
+                                                             None, None)
+    M, N = _mn(dims)
+    L = semd_serial_length(M, N, int(D))
+    if trace_cap is None:
+        trace_cap = min(max_imfs * sift_iters * (L + 8) + 64, 2**31 - 1)
+    trace = torch.zeros(int(trace_cap), dtype=torch.int32, device=signal.device)
+    p = _params(D, max_imfs, sift_iters, path=path, sd=sd)
+    _check(lib().semd_decompose_trace(ps, d, nd, C.byref(p), po, pn, trace.data_ptr(),
+                                      int(trace_cap), _stream(stream)), "semd_decompose_trace")
+    return imfs_out, n_imfs_out, trace
 
 
 def semd_noalloc_scratch_bytes() -> int:

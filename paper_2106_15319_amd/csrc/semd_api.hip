@@ -412,6 +412,8 @@ semd::StreamSig stream_sig(const semd::WorkItem& w, int K, int S, unsigned char*
         take(sizeof(double) * semd::kTileKnots * (size_t)g.ntiles));
   }
   g.st = reinterpret_cast<semd::SigStatus*>(take(sizeof(semd::SigStatus)));
+  g.trace = w.trace;
+  g.trace_cap = w.trace_cap;
   return g;
 }
 
@@ -549,7 +551,9 @@ int run_single(semd::WorkItem w, int K, int S, int path, unsigned char* ws, hipS
     w.u = w.r + w.L;
     auto* d = reinterpret_cast<semd::WorkItem*>(ws);
     e = semd::launch_put_work(w, d, stream);
-    if (e == hipSuccess) e = semd::launch_resident(d, 1, w.L, class_for(w.L, 0), K, S, stream);
+    if (e == hipSuccess)
+      e = w.trace ? semd::launch_resident_trace(d, 1, w.L, K, S, stream)
+                  : semd::launch_resident(d, 1, w.L, class_for(w.L, 0), K, S, stream);
     return e == hipSuccess ? SEMD_OK : hip_fail(e, "resident kernel launch");
   }
   const semd::StreamSig g = stream_sig(w, K, S, ws + lay.o_data);
@@ -560,7 +564,8 @@ int run_single(semd::WorkItem w, int K, int S, int path, unsigned char* ws, hipS
   if (e == hipSuccess) e = semd::st_load(d_sig, d_tiles, lay.ntiles, stream);
   // every signal finishes within K*S steps (each step sifts it or ends an IMF)
   for (int step = 0; step < K * S && e == hipSuccess; ++step)
-    e = semd::st_step(d_sig, 1, d_tiles, lay.ntiles, d_blocks, lay.nblocks, stream);
+    e = semd::st_step(d_sig, 1, d_tiles, lay.ntiles, d_blocks, lay.nblocks, stream,
+                      w.trace != nullptr);
   return e == hipSuccess ? SEMD_OK : hip_fail(e, "streaming kernel launch");
 }
 
@@ -880,6 +885,28 @@ int semd_decompose_ex_noalloc(const double* signal, const int64_t* dims, int ndi
 }
 
 size_t semd_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+int semd_decompose_trace(const double* signal, const int64_t* dims, int ndim,
+                         const semd_params* p, double* imfs_out, int32_t* n_imfs_out,
+                         int32_t* trace, int64_t trace_cap, hipStream_t stream) {
+  g_err[0] = 0;
+  Shape sh;
+  int rc = check_single(dims, ndim, p, &sh);
+  if (rc) return rc;
+  if (!signal || !imfs_out || !trace) return fail(SEMD_EINVAL, "NULL signal, output or trace");
+  if (trace_cap < 4 || trace_cap > INT32_MAX)
+    return fail(SEMD_EINVAL, "trace_cap must be in [4, 2^31 - 1]");
+  const size_t need = single_layout(sh.L, p->path).bytes;
+  semd::WorkItem w = make_work(signal, imfs_out, n_imfs_out, sh, p->transition_len, sd_of(p));
+  w.trace = trace;
+  w.trace_cap = (int32_t)trace_cap;
+  unsigned char* ws = nullptr;
+  if (hipMallocAsync(reinterpret_cast<void**>(&ws), need, stream) != hipSuccess)
+    return fail(SEMD_ENOMEM, "workspace of %zu bytes", need);
+  rc = run_single(w, p->max_imfs, p->sift_iters, p->path, ws, stream);
+  (void)hipFreeAsync(ws, stream);
+  return rc;
+}
 
 int semd_decompose_slices(const double* signal, const int64_t* dims, int ndim,
                           const semd_params* p, double* imfs_out, int32_t* n_imfs_out,

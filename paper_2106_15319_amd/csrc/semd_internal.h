@@ -29,6 +29,9 @@ struct WorkItem {
   double sd;         // SD stopping threshold; 0: fixed sift count
   const double* addend;  // device, L doubles added (scaled) under kAddBuffer
   const double* scale;   // device, one double replacing beta under kScaleOnDevice
+  int32_t* trace;        // device, trace_cap int32: extremum decisions, or nullptr
+  int32_t trace_cap;
+  int32_t pad2;
 };
 
 // What the first load adds to the serialized signal x (Sec. 2.2):
@@ -81,6 +84,14 @@ hipError_t launch_resident(const WorkItem* d_items, int n, int maxL, ResidentCla
 // Write the descriptor w to device memory dst (stream-ordered, by a kernel:
 // no host staging buffer and no allocation).
 hipError_t launch_put_work(const WorkItem& w, WorkItem* dst, hipStream_t stream);
+
+// The resident kernel with every extremum detection recorded in each item's
+// trace (launch shape 1024 threads x 16 samples, any L <= kResidentMaxL):
+// trace[0] entries used (4 header entries included), trace[1] 1 while every
+// record fitted, then one record per detection: imf, sift, nmax, nmin, the
+// maxima's and the minima's positions in increasing order.
+hipError_t launch_resident_trace(const WorkItem* d_items, int n, int maxL, int K, int S,
+                                 hipStream_t stream);
 
 // Extrema of one 1D signal (3 <= L <= kResidentMaxL) through the resident
 // detection/compaction code: indices to imax/imin, counts[0..1].

@@ -633,7 +633,7 @@ __device__ __forceinline__ void div_small(int k, int R, float invR, int& q, int&
 // solve, one fused evaluation, mean and update); else one envelope at a time
 // when each fits (the upper envelope parked in global memory); else both in
 // the item's global knot store.
-template <int NT, int C>
+template <int NT, int C, bool TRACE = false>
 __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __restrict__ items,
                                                           int K, int S, int area_bytes) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -691,10 +691,19 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
       if (c < nv0 && in_chunk(base0 + c, c0, c1)) h[c] = stage[stage_at<C>(base0 - c0) + c];
   }
   const int64_t SS = w.slot_stride;
+  // extremum-decision trace: entries used (the same in every thread) and
+  // whether every record so far fitted
+  int tr_used = 4, tr_ok = 1;
   if (__syncthreads_or(bad)) {
     for (int q = 0; q <= K; ++q)
       for (int o = tid0; o < MN; o += NT) w.out[q * SS + o] = 0.0;
     if (tid0 == 0 && w.n_imfs) *w.n_imfs = -5;
+    if constexpr (TRACE) {
+      if (tid0 == 0) {
+        w.trace[0] = tr_used;
+        w.trace[1] = tr_ok;
+      }
+    }
     return;
   }
 
@@ -727,6 +736,32 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
       opaque(excl);
       opaque(tot);
       const int nmax = tot >> 16, nmin = tot & 0xffff;
+      if constexpr (TRACE) {
+        // record (imf, sift, counts, positions) of this detection
+        const int need = 4 + nmax + nmin;
+        if (tr_ok && tr_used + need <= w.trace_cap) {
+          int32_t* rec = w.trace + tr_used;
+          if (tid == 0) {
+            rec[0] = nimf;
+            rec[1] = s;
+            rec[2] = nmax;
+            rec[3] = nmin;
+          }
+          const unsigned ne = Rm | Fm;
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            const unsigned below = (1u << c) - 1u;
+            if ((maxbits >> c) & 1u)
+              rec[4 + (excl >> 16) + __popc(maxbits & below)] = run_mid(ne, carry, base, c);
+            if ((minbits >> c) & 1u)
+              rec[4 + nmax + (excl & 0xffff) + __popc(minbits & below)] =
+                  run_mid(ne, carry, base, c);
+          }
+          tr_used += need;
+        } else {
+          tr_ok = 0;
+        }
+      }
       if (!(nmax >= 1 && nmin >= 1 && nmax + nmin >= 3)) {
         stop = (s == 0);  // the residue itself is not siftable: decomposition ends
         break;
@@ -844,6 +879,12 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
   for (int q = nimf; q < K; ++q)
     for (int o = tid0; o < MN; o += NT) w.out[q * SS + o] = 0.0;
   if (tid0 == 0 && w.n_imfs) *w.n_imfs = nimf;
+  if constexpr (TRACE) {
+    if (tid0 == 0) {
+      w.trace[0] = tr_used;
+      w.trace[1] = tr_ok;
+    }
+  }
   if (tid0 == 0 && w.stats) {
     w.stats[0] = n_sifts;
     w.stats[1] = n_knots;
@@ -985,10 +1026,10 @@ int device_cus() {
   return cus;
 }
 
-template <int NT, int C>
+template <int NT, int C, bool TRACE = false>
 hipError_t launch_resident_cls(const WorkItem* d_items, int n, int maxL, int K, int S,
                                hipStream_t stream) {
-  auto kern = resident_emd_kernel<NT, C>;
+  auto kern = resident_emd_kernel<NT, C, TRACE>;
   static const hipFuncAttributes attr = [&] {
     hipFuncAttributes a{};
     if (hipFuncGetAttributes(&a, reinterpret_cast<const void*>(kern)) != hipSuccess) {
@@ -1249,6 +1290,13 @@ hipError_t launch_resident(const WorkItem* d_items, int n, int maxL, ResidentCla
     case 102416: return launch_resident_cls<1024, 16>(d_items, n, maxL, K, S, stream);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_resident_trace(const WorkItem* d_items, int n, int maxL, int K, int S,
+                                 hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  if (maxL > kResidentMaxL) return hipErrorInvalidValue;
+  return launch_resident_cls<1024, 16, true>(d_items, n, maxL, K, S, stream);
 }
 
 hipError_t launch_put_work(const WorkItem& w, WorkItem* dst, hipStream_t stream) {

@@ -53,6 +53,9 @@ struct SigStatus {
   int32_t fin;      // this step writes the final outputs
   int32_t done;     // final outputs written
   int32_t n[2];     // maxima / minima of the current sift
+  int32_t tr_rec;   // trace entry of this step's detection record, -1 if none
+  int32_t tr_n[2];  //   and its maxima / minima counts
+  int32_t tr_pad;
   int64_t n_sifts;  // sifts performed
   int64_t n_knots;  // knots used, mirrored ones included
 };
@@ -89,6 +92,9 @@ struct StreamSig {
   int32_t* lpos[2]; // ntiles x kTileKnots: the tile's knots at tile-local ranks
   double* lval[2];  //   (positions and values), written by detection
   SigStatus* st;
+  int32_t* trace;   // extremum decisions (layout of launch_resident_trace), or nullptr
+  int32_t trace_cap;
+  int32_t pad2;
 };
 
 // h = r = serialized input (+ noise) and a fresh status, for the signals
@@ -96,8 +102,9 @@ struct StreamSig {
 hipError_t st_load(const StreamSig* sigs, const int2* tiles, int ntiles, hipStream_t s);
 // One step of every listed signal: detect, scan (decides the step's action),
 // compact and solve (sifting signals), eval (sift, IMF end, final outputs).
+// trace: also record each detection of the signals that carry a trace.
 hipError_t st_step(const StreamSig* sigs, int nsig, const int2* tiles, int ntiles,
-                   const int4* blocks, int nblocks, hipStream_t s);
+                   const int4* blocks, int nblocks, hipStream_t s, bool trace = false);
 // The descriptor of the one signal g and its tile and solve-block tables
 // (g.ntiles and 2 * stream_solve_blocks(g.cap) entries), written on the
 // device from a kernel argument: no host staging buffer, no allocation.

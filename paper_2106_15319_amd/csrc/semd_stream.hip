@@ -408,6 +408,7 @@ __global__ void __launch_bounds__(kTT) st_scan_kernel(const StreamSig* __restric
   __shared__ double wsum[2 * kNW];
   const StreamSig& S = sigs[blockIdx.x];
   SigStatus* st = S.st;
+  if (S.trace && threadIdx.x == 0) st->tr_rec = -1;  // no detection record (yet)
   if (!st->active) {
     if (threadIdx.x == 0) st->action = kIdle;
     return;
@@ -475,6 +476,23 @@ __global__ void __launch_bounds__(kTT) st_scan_kernel(const StreamSig* __restric
   }
   if (threadIdx.x == 0) {
     const int nmax = (int)(off_run >> 32), nmin = (int)(off_run & 0xffffffff);
+    if (S.trace) {
+      // the record's header; its positions are written by st_trace_kernel
+      int32_t* T = S.trace;
+      const int used = T[0], need = 4 + nmax + nmin;
+      if (T[1] && used + need <= S.trace_cap) {
+        T[used] = st->nimf;
+        T[used + 1] = st->sift;
+        T[used + 2] = nmax;
+        T[used + 3] = nmin;
+        T[0] = used + need;
+        st->tr_rec = used;
+        st->tr_n[0] = nmax;
+        st->tr_n[1] = nmin;
+      } else {
+        T[1] = 0;
+      }
+    }
     int action, fin = 0;
     if (nmax >= 1 && nmin >= 1 && nmax + nmin >= 3) {
       st->n[0] = nmax;
@@ -542,6 +560,28 @@ __global__ void __launch_bounds__(kTT) st_compact_kernel(const StreamSig* __rest
                ti.cont_y);
     for (int i = threadIdx.x; i < ti.cnt[e]; i += kTT)
       put_knot(S.kt[e], S.ky[e], ti.off[e] + ck + i, nk, L, S.lpos[e][lo + i], S.lval[e][lo + i]);
+  }
+}
+
+// The positions of this step's detection record (Sec. 2.1 Step 1), for the
+// signals that carry a trace: the tile's extrema at the ranks the scan gave
+// them, the continued run's extremum first, exactly as compaction places
+// the knots (without the mirrored ones).
+__global__ void __launch_bounds__(kTT) st_trace_kernel(const StreamSig* __restrict__ sigs,
+                                                       const int2* __restrict__ tiles) {
+  const int2 tv = tiles[blockIdx.x];
+  const StreamSig& S = sigs[tv.x];
+  if (!S.trace) return;
+  const int rec = S.st->tr_rec;
+  if (rec < 0) return;
+  const TileInfo ti = S.tinfo[tv.y];
+  const int64_t lo = (int64_t)tv.y * kTileKnots;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    int32_t* out = S.trace + rec + 4 + (e ? S.st->tr_n[0] : 0);
+    const int ck = (ti.cont_knot >> e) & 1;
+    if (ck && threadIdx.x == 0) out[ti.off[e]] = ((ti.carry >> 2) + ti.cont_pos) >> 1;
+    for (int i = threadIdx.x; i < ti.cnt[e]; i += kTT) out[ti.off[e] + ck + i] = S.lpos[e][lo + i];
   }
 }
 
@@ -915,6 +955,12 @@ __global__ void st_put_single_kernel(StreamSig g, StreamSig* __restrict__ dsig,
                                      int4* __restrict__ blocks, int nb) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) *dsig = g;
+  if (i == 0 && g.trace) {
+    g.trace[0] = 4;  // entries used: the header
+    g.trace[1] = 1;  // every record fitted
+    g.trace[2] = 0;
+    g.trace[3] = 0;
+  }
   if (i < ntiles) tiles[i] = make_int2(0, i);
   if (i < 2 * nb) blocks[i] = make_int4(0, i / nb, i - (i / nb) * nb, 0);
 }
@@ -933,10 +979,11 @@ hipError_t st_load(const StreamSig* sigs, const int2* tiles, int ntiles, hipStre
   return hipGetLastError();
 }
 hipError_t st_step(const StreamSig* sigs, int nsig, const int2* tiles, int ntiles,
-                   const int4* blocks, int nblocks, hipStream_t st) {
+                   const int4* blocks, int nblocks, hipStream_t st, bool trace) {
   if (nsig <= 0) return hipSuccess;
   hipLaunchKernelGGL(st_detect_kernel, dim3(ntiles), dim3(kTT), 0, st, sigs, tiles);
   hipLaunchKernelGGL(st_scan_kernel, dim3(nsig), dim3(kTT), 0, st, sigs);
+  if (trace) hipLaunchKernelGGL(st_trace_kernel, dim3(ntiles), dim3(kTT), 0, st, sigs, tiles);
   hipLaunchKernelGGL(st_compact_kernel, dim3(ntiles), dim3(kTT), 0, st, sigs, tiles);
   hipLaunchKernelGGL(st_solve_kernel, dim3(nblocks), dim3(kTT), 0, st, sigs, blocks);
   hipLaunchKernelGGL(st_eval_kernel, dim3(ntiles), dim3(kTT), 0, st, sigs, tiles);

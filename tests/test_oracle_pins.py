@@ -572,3 +572,76 @@ def test_ceemdan_second_stage_uses_the_first_noise_mode():
         acc += oracle.emd(r1 + beta1 * e1, 1, S)[0][0]
     assert np.abs(out[1] - acc / NR).max() <= 1e-12 * np.abs(x).max()
     assert np.abs(out[2] - (r1 - out[1])).max() <= 1e-13 * np.abs(x).max()
+
+
+def test_trace_records_every_detection_of_the_sifting_loop():
+    """The oracle's decision trace replays Sec. 2.1 Steps 1-5 as assembled
+    here from its pinned primitives (extrema, envelope): one record per
+    detection -- the residue's before each IMF, the candidate's before each
+    later sift -- with the same index sets, and the tested arrays bit-equal."""
+    rng = np.random.default_rng(8)
+    x = np.cumsum(rng.standard_normal(700)) + 2.0 * np.sin(np.arange(700) / 5.0)
+    K, S = 4, 3
+    slots, n, recs, complete = oracle.emd_trace(x, K, S)
+    ref, nr = oracle.emd(x, K, S)
+    assert complete and n == nr and np.array_equal(slots, ref)
+    want, tested = [], {}
+    r = x.copy()
+    for i in range(K):
+        mx, mn = oracle.extrema(r)
+        want.append((i, 0, mx, mn))
+        tested[(i, 0)] = r.copy()
+        if not (len(mx) >= 1 and len(mn) >= 1 and len(mx) + len(mn) >= 3):
+            break
+        h = r.copy()
+        for s in range(S):
+            if s > 0:
+                mx, mn = oracle.extrema(h)
+                want.append((i, s, mx, mn))
+                tested[(i, s)] = h.copy()
+                if not (len(mx) >= 1 and len(mn) >= 1 and len(mx) + len(mn) >= 3):
+                    break
+            up, lo = oracle.envelope(h, mx), oracle.envelope(h, mn)
+            h = h - 0.5 * (up + lo)
+        r = r - h
+    assert len(recs) == len(want)
+    for (i, s, a, b), (wi, ws, wa, wb) in zip(recs, want):
+        assert (i, s) == (wi, ws)
+        assert np.array_equal(a, wa) and np.array_equal(b, wb)
+        assert np.array_equal(oracle.emd_tested(x, K, S, i, s), tested[(i, s)])
+    assert oracle.emd_tested(x, K, S, K + 1, 0) is None
+    # a buffer too small for the second record keeps only the first
+    first = 4 + len(recs[0][2]) + len(recs[0][3])
+    _, _, part, complete = oracle.emd_trace(x, K, S, cap=first + 3)
+    assert not complete and len(part) == 1
+
+
+def test_decision_comparator_classifies_ties_and_failures():
+    """The parity comparator: equal records pass; a differing position whose
+    tested value is within 1e-12 * max|x| of a neighbour is a tie; a clear
+    difference, or an IMF ending elsewhere without an SD tie, fails."""
+    import parity
+    h = np.array([0.0, 1.0, 0.5, 2.0, 2.0 + 1e-15, 1.0, 3.0, 0.0])
+    rec = [(0, 0, np.array([1, 4]), np.array([2, 5]))]
+    tested = lambda i, s: h  # noqa: E731
+    assert parity.compare_decisions(rec, rec, tested, 3.0)["status"] == "equal"
+    # GPU saw the maximum at 3 instead of 4: positions 3 and 4 sit in a near-equal pair
+    g = [(0, 0, np.array([1, 3]), np.array([2, 5]))]
+    res = parity.compare_decisions(g, rec, tested, 3.0)
+    assert res["status"] == "tie" and res["positions"] == [3, 4]
+    # GPU missed the maximum at 1, whose steps are 1.0 and 0.5: a failure
+    g = [(0, 0, np.array([4]), np.array([2, 5]))]
+    assert parity.compare_decisions(g, rec, tested, 3.0)["status"] == "fail"
+    # equal-valued run: the margin is taken at the run's outer steps
+    hp = np.array([0.0, 1.0, 1.0, 1.0, 0.0])
+    assert parity.margin(hp, 2, 1.0) == 1.0
+    # an IMF ending at another sift is a tie only at an SD tie
+    a = [(0, 0, np.array([1]), np.array([2])), (0, 1, np.array([1]), np.array([2]))]
+    b = [(0, 0, np.array([1]), np.array([2])), (1, 0, np.array([1]), np.array([2]))]
+    assert parity.compare_decisions(a, b, tested, 3.0, sd_margin=1e-12)["status"] == "tie"
+    assert parity.compare_decisions(a, b, tested, 3.0, sd_margin=1e-3)["status"] == "fail"
+    assert parity.compare_decisions(a, a[:1], tested, 3.0)["status"] == "fail"
+    # the device trace layout: used, complete, 2 spare, then records
+    buf = np.array([4 + 6, 1, 0, 0, 0, 0, 1, 1, 7, 9], dtype=np.int32)
+    recs, complete = parity.parse_trace(buf)
+    assert complete and len(recs) == 1 and list(recs[0][2]) == [7] and list(recs[0][3]) == [9]

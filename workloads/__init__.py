@@ -158,6 +158,18 @@ def config3_item(i: int, shape: tuple[int, int]) -> Item:
     return Item(series(rng_for(3, i), ch, M), M, ch)
 
 
+# The uneven batch is processed in waves of consecutive series, each wave one
+# batched EEMD call whose realization buffers fit device memory comfortably.
+CONFIG3_SERIES = 4096
+CONFIG3_WAVES = 16
+
+
+def config3_wave(w: int, n: int = CONFIG3_SERIES, waves: int = CONFIG3_WAVES) -> range:
+    """Indices of the series in wave w (of `waves` equal consecutive groups)."""
+    per = (n + waves - 1) // waves
+    return range(w * per, min(n, (w + 1) * per))
+
+
 def serving_request(i: int) -> tuple[str, Item]:
     """Request i of the serving mix: 60% textures 64..512 px, 30% series
     (2..16 channels x 1e3..65536 samples), 10% 1024 x 1024 textures."""
