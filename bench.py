@@ -1,22 +1,23 @@
 #!/usr/bin/env python3
 """Serial-EMD throughput on one MI355X.
 
-Default workload (one step): the 1,024 face-like 112 x 92 images
-(uint8-valued, as float64) serialized column by column to 10,304-sample
-signals (D = 0), each decomposed into up to 8 IMFs with 10 sifts per IMF, all
-in one batched launch.  Inputs and outputs stay resident in HBM; the timed
-region holds K such steps between two synchronizations.
-
-Reported beside the batched throughput: the plain path (one launch per
-image, same images, same parameters), per-step and per-image latency
-percentiles, the roofline position of the dominant kernel, and the CPU
-oracle timed on the host over the same images.
+Default workload: the uneven multivariate batch at full size -- 4,096 series
+of 2-16 channels x 1e3-6.5e4 samples per channel (log-uniform), each
+serialized (D = 0) and decomposed as an EEMD ensemble of 64 white-noise
+realizations (noise sigma 0.2 std of the series), up to 6 IMFs with 10 sifts
+per IMF.  The batch runs in 16 waves of 256 consecutive series; one step is
+one wave (one semd_eemd_batch call), and the timed steps cycle through the
+waves.  Inputs and outputs stay resident in HBM.  `value` is input samples
+per second; the line also carries realization-samples per second, the
+per-kernel times (HIP events around every kernel in the timed region), the
+HBM roofline position of the dominant kernel (st_eval_kernel) and the CPU
+oracle timed on a seeded random sample of the series.
 
 Other workloads (--workload), each printing one line of the same shape:
+  faces     1,024 face-like 112 x 92 images (uint8-valued), one batched
+            launch per step, with the plain path (one launch per image)
   series    one 3 x 1000 multivariate series, plain path, latency over repeats
   textures  64 texture images 128 x 128, one launch per image (and batched)
-  eemd      a seeded subset of the uneven multivariate batch as an EEMD
-            ensemble of 64 realizations per series (streaming path)
   serving   the serving mix with Poisson arrivals: continuous-batching
             engine against plain per-request decompositions
   dsweep    the transition-length sweep of Sec. 4.1 (D = 1..500) on the
@@ -84,6 +85,38 @@ def measured_traffic(n_images: int, D: int):
         return None
 
 
+STREAM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "st_eval_kernel_eemd_uneven_traffic.txt")
+STREAM_SOURCES = ["semd_stream.hip", "semd_stream.h", "semd_device.h", "semd_internal.h"]
+
+
+def stream_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in STREAM_SOURCES:
+        with open(os.path.join(ROOT, "paper_2106_15319_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_stream_traffic(D: int):
+    """HBM bytes per st_eval_kernel launch from the committed counter summary
+    of the uneven EEMD workload, or None when it is absent, was taken on
+    another D, or the streaming kernels changed since."""
+    if not os.path.exists(STREAM_TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(STREAM_TRAFFIC_FILE):
+        if ":" in line and not line.lstrip().startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        if kv["source_sha256"] != stream_source_hash() or int(kv["D"]) != D:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def copy_probe(mib: int, reps: int) -> int:
     """A plain device-to-device copy of known size, for scaling the HBM
     byte counters: prints the bytes read (= bytes written) per copy."""
@@ -135,6 +168,8 @@ def work_stats(stats, counts):
 
 
 def cpu_threads():
+    """Host threads for the oracle: all logical CPUs up to 16, the host share
+    of one GPU on the measurement machines."""
     return min(16, os.cpu_count() or 1)
 
 
@@ -485,18 +520,68 @@ def run_textures(args, semd, torch, workloads):
     return res
 
 
+def host_cpu():
+    """(logical CPUs of the host, CPU model name)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return os.cpu_count() or 1, model
+
+
+def cpu_eemd_rate(items, D, K, S, NR, sigmas, seed, ids, threads):
+    """The oracle's EEMD of the given series on host threads, one realization
+    per task (the oracle's EMD of x + beta w_m; the mean over m is
+    negligible next to the decompositions and left out).  Returns input
+    samples per second, the wall time and the input samples."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+
+    oracle.lib()
+    xs = [oracle.serialize(it.X, it.M, it.N, D) for it in items]
+
+    def one(job):
+        i, m = job
+        x = xs[i] + sigmas[i] * oracle.noise(seed, ids[i], m, xs[i].size)
+        oracle.emd(x, K, S)
+
+    jobs = sorted(((i, m) for i in range(len(items)) for m in range(NR)),
+                  key=lambda j: -xs[j[0]].size)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(one, jobs))
+    dt = time.perf_counter() - t0
+    samples = sum(it.M * it.N for it in items)
+    return samples / dt, dt, samples
+
+
 def run_eemd(args, semd, torch, workloads):
-    """A seeded subset of the uneven multivariate batch, EEMD with 64
-    realizations per series, all series in one semd_eemd_batch call."""
+    """The uneven-series batch at full size: 4,096 series of 2-16 channels x
+    1e3-6.5e4 samples, each an EEMD ensemble of 64 noise realizations, in 16
+    waves of consecutive series.  One step is one wave (one semd_eemd_batch
+    call over its 256 series); the timed steps cycle through the waves, so
+    a whole number of passes covers every series."""
     dev = torch.device("cuda:0")
-    K, S, D, NR = 6, 10, args.D, 64
-    shapes = workloads.config3_shapes(4096)
-    pick = list(range(args.series))
-    items = [workloads.config3_item(i, shapes[i]) for i in pick]
+    K, S, D, NR, seed = 6, 10, args.D, 64, 2106
+    n, W = workloads.CONFIG3_SERIES, workloads.CONFIG3_WAVES
+    shapes = workloads.config3_shapes(n)
+    t_gen = time.perf_counter()
+    items = workloads.config3_items(range(n), shapes, threads=cpu_threads())
+    gen_s = time.perf_counter() - t_gen
+    MNs = [it.M * it.N for it in items]
+    # inputs and outputs resident in device memory for the whole run
     Xs = [torch.from_numpy(it.X).to(dev) for it in items]
-    outs = [torch.empty((K + 1, it.M * it.N), dtype=torch.float64, device=dev) for it in items]
-    cnt = torch.empty(len(items), dtype=torch.int32, device=dev)
-    # beta = 0.2 std of the serialized signal (D = 0: the samples themselves)
+    out_all = torch.empty(sum((K + 1) * mn for mn in MNs), dtype=torch.float64, device=dev)
+    outs, o = [], 0
+    for mn in MNs:
+        outs.append(out_all[o:o + (K + 1) * mn].view(K + 1, mn))
+        o += (K + 1) * mn
+    cnt = torch.zeros(n, dtype=torch.int32, device=dev)
+    stats = torch.zeros((n, 3), dtype=torch.int64, device=dev)
     sig = []
     for it, x in zip(items, Xs):
         if D == 0:
@@ -504,45 +589,114 @@ def run_eemd(args, semd, torch, workloads):
         else:
             xs = semd.semd_serialize(x, [it.M, it.N], D)
             sig.append(0.2 * float(xs.std(unbiased=False).item()))
-    ids = [int(i) for i in pick]
-    pb = semd.PreparedBatch(Xs, [[it.M, it.N] for it in items], outs, cnt, D, K, S,
-                            ensemble=NR, seed=2106, noise_sigmas=sig, item_ids=ids)
-    for _ in range(max(args.warmup, 1)):
-        pb.run()
+    waves = [list(workloads.config3_wave(w, n, W)) for w in range(W)]
+    pbs = []
+    for idx in waves:
+        a, b = idx[0], idx[-1] + 1
+        pbs.append(semd.PreparedBatch([Xs[i] for i in idx], [[items[i].M, items[i].N] for i in idx],
+                                      [outs[i] for i in idx], cnt[a:b], D, K, S,
+                                      stats=stats[a:b], ensemble=NR, seed=seed,
+                                      noise_sigmas=[sig[i] for i in idx], item_ids=idx))
+    wave_samples = [sum(MNs[i] for i in idx) for idx in waves]
     torch.cuda.synchronize()
-    steps = max(min(args.steps, 3), 1)
+    for k in range(args.warmup):
+        pbs[k % W].run()
+    torch.cuda.synchronize()
+    # timed region: HIP events around every kernel (on the library's launch
+    # stream, the current torch stream) and torch events around every step
+    stream = torch.cuda.current_stream()
+    semd.semd_profile_reset()
+    semd.semd_profile_enable(True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    order = [k % W for k in range(args.steps)]
+    host_ms = []
     t0 = time.perf_counter()
-    for _ in range(steps):
-        pb.run()
+    for (a, b), w in zip(ev, order):
+        a.record(stream)
+        th = time.perf_counter()
+        pbs[w].run()
+        host_ms.append((time.perf_counter() - th) * 1e3)
+        b.record(stream)
     torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
-    samples = sum(it.M * it.N for it in items)
-    res = base_record(args, samples / (ms / 1e3), ms)
-    res["steps"] = steps
-    res["config"] = {"workload": f"uneven multivariate series (2-16 channels x 1e3-6.5e4 "
-                                 f"samples), first {len(items)} of the 4,096-series batch, EEMD "
-                                 f"with {NR} realizations each, D={D}",
-                     "series": len(items), "input_samples": samples, "realizations": NR,
-                     "max_imfs": K, "sift_iters": S, "D": D}
-    res["realization_samples_per_s"] = samples * NR / (ms / 1e3)
-    res["roofline"] = None
+    wall = time.perf_counter() - t0
+    semd.semd_profile_enable(False)
+    kern = {}
+    for name in ("st_load_kernel", "st_detect_kernel", "st_scan_kernel", "st_compact_kernel",
+                 "st_solve_kernel", "st_eval_kernel", "resident_emd_kernel"):
+        nl, ms = semd.semd_profile_read(name)
+        kern[name] = {"launches": nl, "total_ms": ms, "avg_ms": ms / nl if nl else None}
+    host_phases = {}
+    for name in ("host_alloc", "host_tables", "host_upload", "host_launch", "host_batch_call"):
+        nl, ms = semd.semd_profile_read(name)
+        host_phases[name] = {"calls": nl, "total_ms": ms}
+    step_ms = [a.elapsed_time(b) for a, b in ev]
+    ms_per_step = wall * 1e3 / args.steps
+    samples = sum(wave_samples[w] for w in order)
+    value = samples / wall
+    st = stats.cpu().numpy()
+    wave_ss = [int(st[idx[0]:idx[-1] + 1, 2].sum()) for idx in waves]
+    wave_sifts = [int(st[idx[0]:idx[-1] + 1, 0].sum()) for idx in waves]
+    wave_knots = [int(st[idx[0]:idx[-1] + 1, 1].sum()) for idx in waves]
+    sample_sifts = sum(wave_ss[w] for w in order)
+    # the dominant kernel: the streaming evaluation, which reads and writes
+    # the candidate h once per sample and sift (16 bytes per sample-sift,
+    # the per-unit algorithmic bytes of the streaming path)
+    ev_k = kern["st_eval_kernel"]
+    alg_bytes = 16 * sample_sifts
+    roof = None
+    if ev_k["launches"]:
+        per_launch = alg_bytes / ev_k["launches"]
+        achieved = per_launch / (ev_k["avg_ms"] / 1e3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBPS,
+                "traffic": measured_stream_traffic(D),
+                "kernel": "st_eval_kernel", "kernel_avg_ms": ev_k["avg_ms"],
+                "launches": ev_k["launches"], "alg_bytes_per_launch": per_launch}
+    res = base_record(args, value, ms_per_step)
+    res["config"] = {"workload": f"uneven multivariate series, {n} series (2-16 channels x "
+                                 f"1e3-6.5e4 samples per channel, log-uniform), D={D}, EEMD with "
+                                 f"{NR} realizations each (noise sigma 0.2 std), K={K}, S={S}; "
+                                 f"{W} waves of {len(waves[0])} series, one wave per step",
+                     "series": n, "waves": W, "input_samples": sum(MNs), "realizations": NR,
+                     "max_imfs": K, "sift_iters": S, "D": D,
+                     "timed_waves": order, "timed_input_samples": samples}
+    res["realization_samples_per_s"] = value * NR
+    res["latency_ms"] = {"step_p50": pct(step_ms, 50), "step_p99": pct(step_ms, 99),
+                         "host_call_p50": pct(host_ms, 50), "host_call_max": max(host_ms)}
+    res["work"] = {"sample_sifts": sample_sifts,
+                   "sifts": sum(wave_sifts[w] for w in order),
+                   "knots": sum(wave_knots[w] for w in order),
+                   "mean_imfs_max_over_realizations": float(np.maximum(cnt.cpu().numpy(), 0).mean())}
+    res["roofline"] = roof
+    tot_k = sum(v["total_ms"] for v in kern.values())
+    res["kernels"] = {k: dict(v, share=(v["total_ms"] / tot_k if tot_k else None))
+                      for k, v in kern.items() if v["launches"]}
+    res["hbm"] = {"step_alg_GBps": alg_bytes / wall / 1e9,
+                  "step_alg_frac_of_peak": alg_bytes / wall / 1e9 / HBM_PEAK_GBPS,
+                  "note": "16 B per sample-sift over the whole timed region (all kernels, "
+                          "launch gaps included)"}
+    res["host_phases"] = host_phases
+    res["input_generation_s"] = gen_s
     if not args.no_cpu:
-        import oracle
-        from concurrent.futures import ThreadPoolExecutor
-        oracle.lib()
         threads = cpu_threads()
-        # a bounded sample: the shortest series of the subset, all realizations
-        order = sorted(range(len(items)), key=lambda i: items[i].M * items[i].N)[:threads]
-        t1 = time.perf_counter()
-        with ThreadPoolExecutor(max_workers=threads) as ex:
-            list(ex.map(lambda i: oracle.eemd(items[i].X, items[i].M, items[i].N, D, K, S, NR,
-                                              sig[i], 2106, ids[i]), order))
-        dt = time.perf_counter() - t1
-        cs = sum(items[i].M * items[i].N for i in order)
-        res["cpu_baseline"] = {"value": cs / dt, "unit": "samples/s", "cores": threads,
-                               "kind": "oracle",
-                               "sample": f"{len(order)} shortest series of the subset ({cs} input "
-                                         f"samples) x {NR} realizations, {dt:.1f} s wall"}
+        nproc, model = host_cpu()
+        rng = np.random.default_rng(2106_15319 + 33)
+        pick, tot = [], 0
+        for i in rng.permutation(n):
+            if tot >= args.cpu_samples:
+                break
+            pick.append(int(i))
+            tot += MNs[i]
+        sub = [items[i] for i in pick]
+        rate, dt, cs = cpu_eemd_rate(sub, D, K, S, NR, [sig[i] for i in pick], seed, pick,
+                                     threads)
+        res["cpu_baseline"] = {"value": rate, "unit": "samples/s", "cores": threads,
+                               "kind": "oracle", "host_cpus": nproc, "cpu_model": model,
+                               "sample": f"{len(pick)} seeded random series of the batch "
+                                         f"({cs} input samples) x {NR} realizations, one "
+                                         f"realization per task on {threads} threads "
+                                         f"(the GPU's host share), {dt:.1f} s wall"}
     return res
 
 
@@ -674,7 +828,7 @@ def main() -> int:
     ap.add_argument("--workload",
                     choices=["faces", "series", "textures", "eemd", "serving", "dsweep",
                              "ensembles"],
-                    default="faces")
+                    default="eemd")
     ap.add_argument("--sd", type=float, default=0.05, help="dsweep: SD stopping threshold")
     ap.add_argument("--batch", type=int, default=1024, help="faces: images per step")
     ap.add_argument("--D", type=int, default=0, help="transition length")
@@ -682,7 +836,8 @@ def main() -> int:
                     help="faces: images timed on the plain path")
     ap.add_argument("--cpu-items", type=int, default=1024,
                     help="faces: images timed with the oracle")
-    ap.add_argument("--series", type=int, default=32, help="eemd: series of the subset")
+    ap.add_argument("--cpu-samples", type=int, default=1_200_000,
+                    help="eemd: input samples of the oracle's random series sample")
     ap.add_argument("--requests", type=int, default=120, help="serving: requests")
     ap.add_argument("--qps", type=float, default=40.0,
                     help="serving: arrival rate (0: all requests queued at the start)")

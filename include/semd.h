@@ -99,7 +99,8 @@ typedef struct {
  * n_imfs_out: device, one int32, or NULL.  stats_out: device, 3 int64, or
  * NULL: receives the number of sifts performed, the number of envelope knots
  * used (mirrored knots included) and the number of sample-sifts (sum over
- * sifts of L); semd_decompose_batch only.  noise_sigma is the absolute EEMD
+ * sifts of L); semd_decompose_batch, and semd_eemd_batch (summed over the
+ * item's realizations).  noise_sigma is the absolute EEMD
  * noise amplitude beta of Sec. 2.2 for semd_eemd_batch, and the relative
  * amplitude eps for semd_ceemdan_batch; item_id selects the item's noise
  * streams. */
@@ -193,7 +194,7 @@ size_t semd_workspace_bytes(const int64_t* dims, int ndim, const semd_params* p)
  * not touched by anything else until the work enqueued on `stream` has
  * finished; its contents need no initialization and are undefined after.
  * With workspace == NULL (ws_bytes ignored) the library allocates and frees
- * the workspace itself, stream-ordered (hipMallocAsync / hipFreeAsync).  An
+ * the workspace itself, stream-ordered, from its memory pool.  An
  * undersized or misaligned workspace returns SEMD_EINVAL with nothing
  * enqueued.  With a workspace the call enqueues kernels only (no allocation,
  * no copy, no memset), so it may be captured into a HIP graph. */
@@ -304,15 +305,47 @@ int semd_extrema(const double* h, int64_t L, int32_t* imax, int32_t* imin, int32
 int semd_noise(uint64_t seed, uint64_t item, uint64_t m, int64_t L, double* w,
                hipStream_t stream);
 
+/* ---- memory --------------------------------------------------------------- */
+
+/* Workspaces the library allocates (every call but semd_decompose_ex with a
+ * caller's workspace and semd_decompose_ex_noalloc) come stream-ordered from
+ * a memory pool of the library's own per device, which keeps freed memory
+ * for the next call instead of returning it to the device.  This call
+ * returns every cached, unused byte of those pools to the device (for
+ * callers that need the memory elsewhere); later calls allocate anew. */
+int semd_release_cached_memory(void);
+
+/* ---- kernel timing (measurement) ---------------------------------------- */
+
+/* While enabled (on != 0), the batch calls (semd_decompose_batch,
+ * semd_eemd_batch, semd_decompose_slices, semd_ceemdan_batch) record HIP
+ * events on the launch stream around every on-chip launch and around each
+ * kernel of every streaming step; the streaming steps are then launched
+ * directly instead of replayed from a captured graph (same kernels, same
+ * order, same results).  semd_profile_read waits for the recorded events and
+ * returns, for one kernel ("st_load_kernel", "st_detect_kernel",
+ * "st_scan_kernel", "st_compact_kernel", "st_solve_kernel", "st_eval_kernel"
+ * or "resident_emd_kernel"), the launches timed since the last reset and
+ * their summed duration in milliseconds ([host] results).  Not meant to run
+ * concurrently with decompositions on other host threads. */
+int semd_profile_enable(int on);
+int semd_profile_reset(void);
+int semd_profile_read(const char* kernel, int64_t* launches, double* total_ms);
+
 /* ---- serving: continuous batching -------------------------------------- */
 
 /* An engine keeps decompositions of independent requests resident on the
- * device and advances all of them by one step per semd_engine_step: one
- * sift (Sec. 2.1) for each, whatever IMF or sift it is at, or the IMF end /
- * final output work a request reaches.  Requests join between steps when
- * their device footprint fits the engine's memory budget.  Every request is
- * decomposed exactly as semd_decompose_ex(path = SEMD_PATH_STREAM) would
- * (bit-identical outputs): its arithmetic does not depend on the others.
+ * device and advances all of them at every semd_engine_step.  Requests join
+ * between steps when their device footprint fits the engine's memory
+ * budget.  Each request is routed as semd_decompose_ex routes its path:
+ * on chip (path AUTO up to semd_resident_max_length() samples, or ONCHIP),
+ * the whole decomposition of every request admitted since the last step
+ * runs in one launch at the next step and completes with it; streaming
+ * (longer ones, or path STREAM), each step performs one sift (Sec. 2.1),
+ * whatever IMF or sift the request is at, or the IMF end / final output
+ * work it reaches.  Every request is decomposed exactly as
+ * semd_decompose_ex with the same parameters would (bit-identical outputs):
+ * its arithmetic does not depend on the others.
  * All engine calls on one engine must come from one host thread at a time
  * and all steps must use one stream.  The engine owns its device memory
  * (hbm_budget_bytes, allocated at creation); the caller owns every

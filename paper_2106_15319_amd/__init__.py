@@ -98,6 +98,10 @@ _EXPORTS = {
                                C.c_void_p]),
     "semd_noise": (C.c_int, [C.c_uint64, C.c_uint64, C.c_uint64, C.c_int64, C.c_void_p,
                              C.c_void_p]),
+    "semd_release_cached_memory": (C.c_int, []),
+    "semd_profile_enable": (C.c_int, [C.c_int]),
+    "semd_profile_reset": (C.c_int, []),
+    "semd_profile_read": (C.c_int, [C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "semd_engine_create": (C.c_int, [C.c_size_t, C.c_int, C.POINTER(C.c_void_p)]),
     "semd_engine_footprint": (C.c_int, [C.POINTER(semd_item), C.POINTER(semd_params),
                                         C.POINTER(C.c_size_t)]),
@@ -560,6 +564,27 @@ def semd_noise(seed: int, item: int, m: int, L: int, w: torch.Tensor | None = No
     return w
 
 
+def semd_release_cached_memory() -> None:
+    """Return the library pools' cached device memory to the device."""
+    _check(lib().semd_release_cached_memory(), "semd_release_cached_memory")
+
+
+def semd_profile_enable(on: bool = True) -> None:
+    _check(lib().semd_profile_enable(1 if on else 0), "semd_profile_enable")
+
+
+def semd_profile_reset() -> None:
+    _check(lib().semd_profile_reset(), "semd_profile_reset")
+
+
+def semd_profile_read(kernel: str) -> tuple[int, float]:
+    """(launches, summed milliseconds) of one kernel since the last reset."""
+    n, ms = C.c_int64(), C.c_double()
+    _check(lib().semd_profile_read(kernel.encode(), C.byref(n), C.byref(ms)),
+           "semd_profile_read")
+    return int(n.value), float(ms.value)
+
+
 # ---------------------------------------------------------------------------
 # conveniences
 # ---------------------------------------------------------------------------
@@ -621,14 +646,15 @@ class Engine:
         self._keep: dict[int, tuple] = {}
 
     @staticmethod
-    def footprint(dims: Sequence[int], D: int, K: int, S: int) -> int:
+    def footprint(dims: Sequence[int], D: int, K: int, S: int,
+                  path: int = SEMD_PATH_AUTO) -> int:
         it = semd_item()
         it.signal = 1
         it.imfs_out = 1
         for k, v in enumerate(dims):
             it.dims[k] = int(v)
         it.ndim = len(dims)
-        p = _params(D, K, S)
+        p = _params(D, K, S, path=path)
         b = C.c_size_t()
         _check(lib().semd_engine_footprint(C.byref(it), C.byref(p), C.byref(b)),
                "semd_engine_footprint")
@@ -636,12 +662,12 @@ class Engine:
 
     def admit(self, signal: torch.Tensor, dims: Sequence[int], out: torch.Tensor,
               n_imfs: torch.Tensor | None, D: int, K: int, S: int,
-              sd: float = 0.0) -> int | None:
+              sd: float = 0.0, path: int = SEMD_PATH_AUTO) -> int | None:
         """Ticket of the admitted request, or None when it does not fit now."""
         _check_shape_params(K, S)
         arr, _ = _items([signal], [dims], [out],
                         [n_imfs] if n_imfs is not None else None, K)
-        p = _params(D, K, S, sd=sd)
+        p = _params(D, K, S, sd=sd, path=path)
         t = C.c_int64()
         rc = lib().semd_engine_admit(self._h, arr, C.byref(p), C.byref(t))
         if rc == SEMD_EBUSY:

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -200,6 +201,146 @@ struct StepGraph {
   hipError_t launch(hipStream_t s) const { return hipGraphLaunch(exec, s); }
 };
 
+// ---------------------------------------------------------------------------
+// Kernel timing (semd_profile_*): HIP events on the launch stream around
+// each kernel, read back once they have completed
+// ---------------------------------------------------------------------------
+
+enum ProfKind {
+  kPLoad, kPDetect, kPScan, kPCompact, kPSolve, kPEval, kPResident,
+  // host time (wall clock of the calling thread) in phases of the batch calls
+  kHAlloc, kHTables, kHUpload, kHLaunch, kHBatch, kPKinds
+};
+const char* const kProfNames[kPKinds] = {
+    "st_load_kernel", "st_detect_kernel",    "st_scan_kernel", "st_compact_kernel",
+    "st_solve_kernel", "st_eval_kernel",     "resident_emd_kernel", "host_alloc",
+    "host_tables",     "host_upload",        "host_launch",    "host_batch_call"};
+
+struct ProfSpan {
+  int kind;
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfSpan> g_prof_spans;      // recorded, not yet read
+std::vector<hipEvent_t> g_prof_events;   // owned by the profiler
+std::vector<hipEvent_t> g_prof_free;     // of those, free for reuse
+double g_prof_ms[kPKinds] = {};
+int64_t g_prof_n[kPKinds] = {};
+
+bool profiling() {
+  std::lock_guard<std::mutex> lock(g_prof_mu);
+  return g_prof_on;
+}
+
+// n events for one launch sequence (nullptr on failure: timing skipped).
+bool prof_events(hipEvent_t* out, int n) {
+  std::lock_guard<std::mutex> lock(g_prof_mu);
+  for (int i = 0; i < n; ++i) {
+    if (g_prof_free.empty()) {
+      hipEvent_t ev = nullptr;
+      if (hipEventCreate(&ev) != hipSuccess) return false;
+      g_prof_events.push_back(ev);
+      g_prof_free.push_back(ev);
+    }
+    out[i] = g_prof_free.back();
+    g_prof_free.pop_back();
+  }
+  return true;
+}
+
+// Adds the host time of its scope to a phase while profiling is on.
+struct HostPhase {
+  int kind;
+  bool on;
+  std::chrono::steady_clock::time_point t0;
+  explicit HostPhase(int k);
+  ~HostPhase();
+};
+
+void prof_span(int kind, hipEvent_t a, hipEvent_t b) {
+  std::lock_guard<std::mutex> lock(g_prof_mu);
+  g_prof_spans.push_back({kind, a, b});
+}
+
+HostPhase::HostPhase(int k) : kind(k), on(profiling()), t0(std::chrono::steady_clock::now()) {}
+HostPhase::~HostPhase() {
+  if (!on) return;
+  const double ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  std::lock_guard<std::mutex> lock(g_prof_mu);
+  g_prof_ms[kind] += ms;
+  g_prof_n[kind] += 1;
+}
+
+// Waits for every recorded span and adds it to the totals; frees the events.
+void prof_collect() {
+  std::lock_guard<std::mutex> lock(g_prof_mu);
+  for (const ProfSpan& sp : g_prof_spans) {
+    float ms = 0.f;
+    if (hipEventSynchronize(sp.b) == hipSuccess &&
+        hipEventElapsedTime(&ms, sp.a, sp.b) == hipSuccess) {
+      g_prof_ms[sp.kind] += ms;
+      g_prof_n[sp.kind] += 1;
+    }
+  }
+  g_prof_spans.clear();
+  g_prof_free = g_prof_events;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace memory: stream-ordered allocations from a pool of the library's
+// own per device, which keeps freed memory for reuse (mapping fresh device
+// memory for every call would cost more than the work on large batches)
+// ---------------------------------------------------------------------------
+
+constexpr int kPoolDevices = 64;
+std::mutex g_pool_dev_mu;
+hipMemPool_t g_mem_pool[kPoolDevices] = {};
+
+// The current device's pool, created on first use (nullptr: use the
+// device's default pool).
+hipMemPool_t lib_pool() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kPoolDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_pool_dev_mu);
+  if (!g_mem_pool[dev]) {
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    hipMemPool_t pool = nullptr;
+    if (hipMemPoolCreate(&pool, &props) != hipSuccess) return nullptr;
+    uint64_t keep = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    g_mem_pool[dev] = pool;
+  }
+  return g_mem_pool[dev];
+}
+
+// Device bytes available to new workspaces: free device memory plus what
+// the library's pool holds without using.
+size_t available_device_bytes() {
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = size_t(8) << 30;
+  hipMemPool_t pool = lib_pool();
+  uint64_t reserved = 0, used = 0;
+  if (pool && hipMemPoolGetAttribute(pool, hipMemPoolAttrReservedMemCurrent, &reserved) ==
+                  hipSuccess &&
+      hipMemPoolGetAttribute(pool, hipMemPoolAttrUsedMemCurrent, &used) == hipSuccess &&
+      reserved > used)
+    free_b += (size_t)(reserved - used);
+  return free_b;
+}
+
+hipError_t dev_alloc(void** p, size_t bytes, hipStream_t s) {
+  HostPhase hp(kHAlloc);
+  hipMemPool_t pool = lib_pool();
+  if (pool) return hipMallocFromPoolAsync(p, bytes, pool, s);
+  return hipMallocAsync(p, bytes, s);
+}
+
 // Pinned staging blocks for host -> device descriptor uploads; a block is
 // reused once the copy recorded on it has completed.
 struct PinnedBlock {
@@ -210,7 +351,29 @@ struct PinnedBlock {
 std::mutex g_pool_mu;
 std::vector<std::unique_ptr<PinnedBlock>> g_pool;
 
-int upload(const void* src, size_t bytes, hipStream_t s, void** d_out) {
+size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Consecutive 256-byte-aligned regions handed out from one device buffer
+// (the workspace of a whole call, so that its parts need no allocation of
+// their own).
+struct Carve {
+  unsigned char* p = nullptr;
+  size_t left = 0;
+  unsigned char* take(size_t b) {
+    b = al256(std::max<size_t>(b, 1));
+    if (b > left) return nullptr;
+    unsigned char* q = p;
+    p += b;
+    left -= b;
+    return q;
+  }
+};
+
+// Copies bytes from src to device memory through a pinned staging block:
+// into a region of `into` when given, else into a new stream-ordered
+// allocation (*d_out).
+int upload(const void* src, size_t bytes, hipStream_t s, void** d_out, Carve* into = nullptr) {
+  HostPhase hp(kHUpload);
   PinnedBlock* blk = nullptr;
   {
     std::lock_guard<std::mutex> lock(g_pool_mu);
@@ -229,8 +392,15 @@ int upload(const void* src, size_t bytes, hipStream_t s, void** d_out) {
       g_pool.push_back(std::move(nb));
     }
     std::memcpy(blk->host, src, bytes);
-    hipError_t e = hipMallocAsync(d_out, bytes, s);
-    if (e != hipSuccess) return fail(SEMD_ENOMEM, "device allocation of %zu bytes failed", bytes);
+    hipError_t e = hipSuccess;
+    if (into) {
+      *d_out = into->take(bytes);
+      if (!*d_out) return fail(SEMD_ENOMEM, "call workspace too small for %zu bytes", bytes);
+    } else {
+      e = dev_alloc(d_out, bytes, s);
+      if (e != hipSuccess)
+        return fail(SEMD_ENOMEM, "device allocation of %zu bytes failed", bytes);
+    }
     e = hipMemcpyAsync(*d_out, blk->host, bytes, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "descriptor upload");
     e = hipEventRecord(blk->ev, s);
@@ -309,7 +479,7 @@ bool class_compiled(semd::ResidentClass c) {
 // of resident_ws_doubles(L) per item (residue, parked envelope or knot
 // store).  force: a launch shape for every item (else the table's choice).
 int run_resident(std::vector<semd::WorkItem>& work, int K, int S, hipStream_t stream,
-                 const semd::ResidentClass* force = nullptr) {
+                 const semd::ResidentClass* force = nullptr, Carve* into = nullptr) {
   if (work.empty()) return SEMD_OK;
   // longest first, so the tail of each launch holds the short items
   std::stable_sort(work.begin(), work.end(),
@@ -317,8 +487,14 @@ int run_resident(std::vector<semd::WorkItem>& work, int K, int S, hipStream_t st
   int64_t ws_doubles = 0;
   for (const auto& w : work) ws_doubles += semd::resident_ws_doubles(w.L);
   double* ws = nullptr;
-  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&ws),
-                                sizeof(double) * (size_t)std::max<int64_t>(ws_doubles, 1), stream);
+  const size_t ws_bytes = sizeof(double) * (size_t)std::max<int64_t>(ws_doubles, 1);
+  hipError_t e = hipSuccess;
+  if (into) {
+    ws = reinterpret_cast<double*>(into->take(ws_bytes));
+    if (!ws) return fail(SEMD_ENOMEM, "call workspace too small for the on-chip items");
+  } else {
+    e = dev_alloc(reinterpret_cast<void**>(&ws), ws_bytes, stream);
+  }
   if (e != hipSuccess)
     return fail(SEMD_ENOMEM, "workspace of %lld doubles", (long long)ws_doubles);
   int64_t off = 0;
@@ -328,8 +504,11 @@ int run_resident(std::vector<semd::WorkItem>& work, int K, int S, hipStream_t st
     off += semd::resident_ws_doubles(w.L);
   }
   void* d_items = nullptr;
-  int rc = upload(work.data(), work.size() * sizeof(semd::WorkItem), stream, &d_items);
-  if (rc) { (void)hipFreeAsync(ws, stream); return rc; }
+  int rc = upload(work.data(), work.size() * sizeof(semd::WorkItem), stream, &d_items, into);
+  if (rc) {
+    if (!into) (void)hipFreeAsync(ws, stream);
+    return rc;
+  }
   // one launch per launch-shape class, each with the LDS its longest item needs
   auto same = [](const semd::ResidentClass& a, const semd::ResidentClass& b) {
     return a.nt == b.nt && a.c == b.c;
@@ -342,19 +521,26 @@ int run_resident(std::vector<semd::WorkItem>& work, int K, int S, hipStream_t st
     size_t i1 = i0;
     while (i1 < work.size() && same(shape(work[i1].L), cls)) ++i1;
     const auto* d = static_cast<const semd::WorkItem*>(d_items) + i0;
+    hipEvent_t ev[2];
+    const bool timed = profiling() && prof_events(ev, 2);
+    if (timed) (void)hipEventRecord(ev[0], stream);
     e = semd::launch_resident(d, (int)(i1 - i0), work[i0].L, cls, K, S, stream);
+    if (timed) {
+      (void)hipEventRecord(ev[1], stream);
+      prof_span(kPResident, ev[0], ev[1]);
+    }
     if (e != hipSuccess) rc = hip_fail(e, "resident kernel launch");
     i0 = i1;
   }
-  (void)hipFreeAsync(d_items, stream);
-  (void)hipFreeAsync(ws, stream);
+  if (!into) {
+    (void)hipFreeAsync(d_items, stream);
+    (void)hipFreeAsync(ws, stream);
+  }
   return rc;
 }
 
 // Device bytes the streaming path needs for one signal of L samples, and
 // the carving of such a region into the signal's buffers.
-size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
-
 size_t stream_bytes(int64_t L) {
   const size_t cap = (size_t)((L - 1) / 2 + 12);
   const size_t ntiles = (size_t)((L + semd::kTile - 1) / semd::kTile);
@@ -448,7 +634,8 @@ std::vector<unsigned char> pack_tables(const std::vector<semd::StreamSig>& sigs,
 }
 
 // Decompose `work` on the streaming path: K*S steps of every signal.
-int run_stream(const std::vector<semd::WorkItem>& work, int K, int S, hipStream_t stream) {
+int run_stream(const std::vector<semd::WorkItem>& work, int K, int S, hipStream_t stream,
+               Carve* into = nullptr) {
   const int n = (int)work.size();
   if (n == 0) return SEMD_OK;
   size_t bytes = 0;
@@ -458,19 +645,30 @@ int run_stream(const std::vector<semd::WorkItem>& work, int K, int S, hipStream_
     bytes += al256(stream_bytes(work[i].L));
   }
   unsigned char* arena = nullptr;
-  if (hipMallocAsync(reinterpret_cast<void**>(&arena), std::max<size_t>(bytes, 1), stream) !=
-      hipSuccess)
+  if (into) {
+    arena = into->take(bytes);
+    if (!arena) return fail(SEMD_ENOMEM, "call workspace too small for the streaming items");
+  } else if (dev_alloc(reinterpret_cast<void**>(&arena), std::max<size_t>(bytes, 1), stream) !=
+             hipSuccess) {
     return fail(SEMD_ENOMEM, "streaming workspace of %zu bytes", bytes);
+  }
   std::vector<semd::StreamSig> sigs(n);
-  for (int i = 0; i < n; ++i) sigs[i] = stream_sig(work[i], K, S, arena + offs[i]);
   std::vector<int2> tiles;
   std::vector<int4> blocks;
-  stream_tables(sigs, tiles, blocks);
   size_t o_til, o_blk;
-  std::vector<unsigned char> pack = pack_tables(sigs, tiles, blocks, &o_til, &o_blk);
+  std::vector<unsigned char> pack;
+  {
+    HostPhase hp(kHTables);
+    for (int i = 0; i < n; ++i) sigs[i] = stream_sig(work[i], K, S, arena + offs[i]);
+    stream_tables(sigs, tiles, blocks);
+    pack = pack_tables(sigs, tiles, blocks, &o_til, &o_blk);
+  }
   void* d_pack = nullptr;
-  int rc = upload(pack.data(), pack.size(), stream, &d_pack);
-  if (rc) { (void)hipFreeAsync(arena, stream); return rc; }
+  int rc = upload(pack.data(), pack.size(), stream, &d_pack, into);
+  if (rc) {
+    if (!into) (void)hipFreeAsync(arena, stream);
+    return rc;
+  }
   unsigned char* dp = static_cast<unsigned char*>(d_pack);
   const auto* d_sigs = reinterpret_cast<const semd::StreamSig*>(dp);
   const auto* d_tiles = reinterpret_cast<const int2*>(dp + o_til);
@@ -481,6 +679,32 @@ int run_stream(const std::vector<semd::WorkItem>& work, int K, int S, hipStream_
   sweep_retired_graphs();
   CaptureStream cs;
   hipError_t e = cs.open(stream);
+  if (e == hipSuccess && profiling()) {
+    // timed: the same launches, issued directly with events between them
+    HostPhase hp(kHLaunch);
+    hipEvent_t ev[6];
+    bool timed = prof_events(ev, 2);
+    if (timed) (void)hipEventRecord(ev[0], cs.s);
+    e = semd::st_load(d_sigs, d_tiles, nt, cs.s);
+    if (timed) {
+      (void)hipEventRecord(ev[1], cs.s);
+      prof_span(kPLoad, ev[0], ev[1]);
+    }
+    for (int step = 0; step < K * S && e == hipSuccess; ++step) {
+      timed = prof_events(ev, 6);
+      e = semd::st_step(d_sigs, n, d_tiles, nt, d_blocks, nb, cs.s, false,
+                        timed ? ev : nullptr);
+      if (timed)
+        for (int k = 0; k < 5; ++k) prof_span(kPDetect + k, ev[k], ev[k + 1]);
+    }
+    if (e == hipSuccess) e = cs.join();
+    if (e != hipSuccess) rc = hip_fail(e, "streaming kernel launch");
+    if (!into) {
+      (void)hipFreeAsync(d_pack, stream);
+      (void)hipFreeAsync(arena, stream);
+    }
+    return rc;
+  }
   if (e == hipSuccess) e = semd::st_load(d_sigs, d_tiles, nt, cs.s);
   {
     StepGraph g;
@@ -493,23 +717,58 @@ int run_stream(const std::vector<semd::WorkItem>& work, int K, int S, hipStream_
     if (e == hipSuccess) e = cs.join();
   }
   if (e != hipSuccess) rc = hip_fail(e, "streaming kernel launch");
-  (void)hipFreeAsync(d_pack, stream);
-  (void)hipFreeAsync(arena, stream);
+  if (!into) {
+    (void)hipFreeAsync(d_pack, stream);
+    (void)hipFreeAsync(arena, stream);
+  }
   return rc;
 }
 
 // Route every item to the on-chip path (one workgroup per signal) or the
 // streaming path, by `path` and length.
-int run_work(std::vector<semd::WorkItem>& work, int K, int S, int path, hipStream_t stream) {
+bool routed_onchip(int64_t L, int path) {
+  return path == SEMD_PATH_ONCHIP || (path == SEMD_PATH_AUTO && L <= semd::kResidentMaxL);
+}
+
+int run_work(std::vector<semd::WorkItem>& work, int K, int S, int path, hipStream_t stream,
+             Carve* into = nullptr) {
   std::vector<semd::WorkItem> onchip, streamed;
   for (const auto& w : work) {
-    const bool fits = w.L <= semd::kResidentMaxL;
-    if (path == SEMD_PATH_STREAM || (path == SEMD_PATH_AUTO && !fits)) streamed.push_back(w);
-    else onchip.push_back(w);
+    if (routed_onchip(w.L, path)) onchip.push_back(w);
+    else streamed.push_back(w);
   }
-  int rc = run_resident(onchip, K, S, stream);
-  if (rc == SEMD_OK) rc = run_stream(streamed, K, S, stream);
+  int rc = run_resident(onchip, K, S, stream, nullptr, into);
+  if (rc == SEMD_OK) rc = run_stream(streamed, K, S, stream, into);
   return rc;
+}
+
+// Bytes of device workspace run_work takes from a Carve for these items
+// (the regions it carves, each rounded to 256 bytes).
+size_t work_scratch_bytes(const std::vector<semd::WorkItem>& work, int path) {
+  int64_t ws_doubles = 0;
+  size_t n_on = 0, arena = 0, n_st = 0, tiles = 0, blocks = 0;
+  for (const auto& w : work) {
+    if (routed_onchip(w.L, path)) {
+      ws_doubles += semd::resident_ws_doubles(w.L);
+      ++n_on;
+    } else {
+      arena += al256(stream_bytes(w.L));
+      ++n_st;
+      tiles += (size_t)((w.L + semd::kTile - 1) / semd::kTile);
+      blocks += 2 * (size_t)semd::stream_solve_blocks((int)((w.L - 1) / 2 + 12));
+    }
+  }
+  size_t b = 0;
+  if (n_on) {
+    b += al256(sizeof(double) * (size_t)std::max<int64_t>(ws_doubles, 1));
+    b += al256(sizeof(semd::WorkItem) * n_on);
+  }
+  if (n_st) {
+    b += al256(arena);
+    b += al256(std::max<size_t>(sizeof(semd::StreamSig) * n_st + sizeof(int2) * tiles +
+                                    sizeof(int4) * blocks, 16));
+  }
+  return b;
 }
 
 // Workspace of one signal decomposed on its own (semd_decompose_ex): its
@@ -857,7 +1116,7 @@ int semd_decompose_ex(const double* signal, const int64_t* dims, int ndim, const
                       static_cast<unsigned char*>(workspace), stream);
   }
   unsigned char* ws = nullptr;
-  if (hipMallocAsync(reinterpret_cast<void**>(&ws), need, stream) != hipSuccess)
+  if (dev_alloc(reinterpret_cast<void**>(&ws), need, stream) != hipSuccess)
     return fail(SEMD_ENOMEM, "workspace of %zu bytes", need);
   rc = run_single(w, p->max_imfs, p->sift_iters, p->path, ws, stream);
   (void)hipFreeAsync(ws, stream);
@@ -886,6 +1145,49 @@ int semd_decompose_ex_noalloc(const double* signal, const int64_t* dims, int ndi
 
 size_t semd_noalloc_scratch_bytes(void) { return kScratchBytes; }
 
+int semd_release_cached_memory(void) {
+  g_err[0] = 0;
+  std::lock_guard<std::mutex> lock(g_pool_dev_mu);
+  for (int d = 0; d < kPoolDevices; ++d) {
+    if (!g_mem_pool[d]) continue;
+    const hipError_t e = hipMemPoolTrimTo(g_mem_pool[d], 0);
+    if (e != hipSuccess) return hip_fail(e, "hipMemPoolTrimTo");
+  }
+  return SEMD_OK;
+}
+
+int semd_profile_enable(int on) {
+  g_err[0] = 0;
+  std::lock_guard<std::mutex> lock(g_prof_mu);
+  g_prof_on = on != 0;
+  return SEMD_OK;
+}
+
+int semd_profile_reset(void) {
+  g_err[0] = 0;
+  prof_collect();
+  std::lock_guard<std::mutex> lock(g_prof_mu);
+  for (int k = 0; k < kPKinds; ++k) {
+    g_prof_ms[k] = 0.0;
+    g_prof_n[k] = 0;
+  }
+  return SEMD_OK;
+}
+
+int semd_profile_read(const char* kernel, int64_t* launches, double* total_ms) {
+  g_err[0] = 0;
+  if (!kernel || !launches || !total_ms)
+    return fail(SEMD_EINVAL, "NULL kernel name or result pointer");
+  int k = 0;
+  while (k < kPKinds && std::strcmp(kernel, kProfNames[k]) != 0) ++k;
+  if (k == kPKinds) return fail(SEMD_EINVAL, "no timed kernel named '%s'", kernel);
+  prof_collect();
+  std::lock_guard<std::mutex> lock(g_prof_mu);
+  *launches = g_prof_n[k];
+  *total_ms = g_prof_ms[k];
+  return SEMD_OK;
+}
+
 int semd_decompose_trace(const double* signal, const int64_t* dims, int ndim,
                          const semd_params* p, double* imfs_out, int32_t* n_imfs_out,
                          int32_t* trace, int64_t trace_cap, hipStream_t stream) {
@@ -901,7 +1203,7 @@ int semd_decompose_trace(const double* signal, const int64_t* dims, int ndim,
   w.trace = trace;
   w.trace_cap = (int32_t)trace_cap;
   unsigned char* ws = nullptr;
-  if (hipMallocAsync(reinterpret_cast<void**>(&ws), need, stream) != hipSuccess)
+  if (dev_alloc(reinterpret_cast<void**>(&ws), need, stream) != hipSuccess)
     return fail(SEMD_ENOMEM, "workspace of %zu bytes", need);
   rc = run_single(w, p->max_imfs, p->sift_iters, p->path, ws, stream);
   (void)hipFreeAsync(ws, stream);
@@ -970,6 +1272,7 @@ int semd_decompose_batch(const semd_item* items, int n, const semd_params* p,
 
 int semd_eemd_batch(const semd_item* items, int n, const semd_params* p, hipStream_t stream) {
   g_err[0] = 0;
+  HostPhase hp(kHBatch);
   int rc = check_params(p, true);
   if (rc) return rc;
   std::vector<Shape> shapes;
@@ -978,67 +1281,93 @@ int semd_eemd_batch(const semd_item* items, int n, const semd_params* p, hipStre
   for (int i = 0; i < n; ++i)
     if (!std::isfinite(items[i].noise_sigma) || items[i].noise_sigma < 0)
       return fail(SEMD_EINVAL, "item %d: noise_sigma must be finite and >= 0", i);
+  if (n == 0) return SEMD_OK;
   const int K = p->max_imfs, NR = p->ensemble;
-  // Realization outputs are staged in waves of items that fit the budget.
-  size_t free_b = 0, total_b = 0;
-  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = size_t(8) << 30;
-  const size_t budget = std::max<size_t>(free_b / 4, size_t(256) << 20);
-  int i0 = 0;
-  while (i0 < n) {
-    size_t bytes = 0;
-    int i1 = i0;
-    while (i1 < n) {
-      const size_t b = (size_t)NR * (sizeof(double) * (size_t)(K + 1) * shapes[i1].M * shapes[i1].N +
-                                     stream_bytes(shapes[i1].L) + sizeof(int32_t));
-      if (i1 > i0 && bytes + b > budget) break;
-      bytes += b;
-      ++i1;
-    }
-    // per-realization slots and counts of this wave
-    size_t slots = 0;
-    for (int i = i0; i < i1; ++i) slots += (size_t)NR * (K + 1) * shapes[i].M * shapes[i].N;
-    double* buf = nullptr;
-    int32_t* cnt = nullptr;
-    if (hipMallocAsync(reinterpret_cast<void**>(&buf), sizeof(double) * std::max<size_t>(slots, 1),
-                       stream) != hipSuccess)
-      return fail(SEMD_ENOMEM, "EEMD realization buffer of %zu doubles", slots);
-    if (hipMallocAsync(reinterpret_cast<void**>(&cnt),
-                       sizeof(int32_t) * (size_t)NR * (i1 - i0), stream) != hipSuccess) {
-      (void)hipFreeAsync(buf, stream);
-      return fail(SEMD_ENOMEM, "EEMD count buffer");
-    }
+  bool want_stats = false;
+  for (int i = 0; i < n; ++i) want_stats |= items[i].stats_out != nullptr;
+  // The realizations of consecutive items are decomposed in waves that fit
+  // the budget; one workspace, sized for the largest wave, serves them all.
+  const size_t budget = std::max<size_t>(available_device_bytes() / 4, size_t(256) << 20);
+  auto realizations = [&](int i0, int i1) {
     std::vector<semd::WorkItem> work;
     work.reserve((size_t)NR * (i1 - i0));
-    size_t so = 0;
-    for (int i = i0; i < i1; ++i) {
-      const size_t per = (size_t)(K + 1) * shapes[i].M * shapes[i].N;
+    for (int i = i0; i < i1; ++i)
       for (int m = 0; m < NR; ++m) {
-        semd::WorkItem w = make_work(items[i].signal, buf + so + (size_t)m * per,
-                                     cnt + (size_t)(i - i0) * NR + m, shapes[i],
+        semd::WorkItem w = make_work(items[i].signal, nullptr, nullptr, shapes[i],
                                      p->transition_len, sd_of(p));
         w.beta = items[i].noise_sigma;
         w.key = semd::noise_key(p->seed, items[i].item_id, (uint64_t)m);
         w.flags = semd::kAddNoise;
         work.push_back(w);
       }
+    return work;
+  };
+  struct Wave {
+    int i0, i1;
+    size_t slots, bytes;
+  };
+  std::vector<Wave> waves;
+  size_t need = 0;
+  for (int i0 = 0; i0 < n;) {
+    size_t est = 0;
+    int i1 = i0;
+    while (i1 < n) {
+      const size_t b = (size_t)NR * (sizeof(double) * (size_t)(K + 1) * shapes[i1].M *
+                                         shapes[i1].N + stream_bytes(shapes[i1].L) +
+                                     sizeof(int32_t));
+      if (i1 > i0 && est + b > budget) break;
+      est += b;
+      ++i1;
+    }
+    Wave wv{i0, i1, 0, 0};
+    for (int i = i0; i < i1; ++i) wv.slots += (size_t)NR * (K + 1) * shapes[i].M * shapes[i].N;
+    wv.bytes = al256(sizeof(double) * std::max<size_t>(wv.slots, 1)) +
+               al256(sizeof(int32_t) * (size_t)NR * (i1 - i0)) +
+               (want_stats ? al256(sizeof(int64_t) * 3 * (size_t)NR * (i1 - i0)) : 0) +
+               work_scratch_bytes(realizations(i0, i1), p->path);
+    need = std::max(need, wv.bytes);
+    waves.push_back(wv);
+    i0 = i1;
+  }
+  unsigned char* ws = nullptr;
+  if (dev_alloc(reinterpret_cast<void**>(&ws), need, stream) != hipSuccess)
+    return fail(SEMD_ENOMEM, "EEMD workspace of %zu bytes", need);
+  for (const Wave& wv : waves) {
+    const int i0 = wv.i0, i1 = wv.i1;
+    Carve cv{ws, need};
+    double* buf = reinterpret_cast<double*>(cv.take(sizeof(double) * wv.slots));
+    int32_t* cnt = reinterpret_cast<int32_t*>(cv.take(sizeof(int32_t) * (size_t)NR * (i1 - i0)));
+    int64_t* wst = want_stats ? reinterpret_cast<int64_t*>(
+                                    cv.take(sizeof(int64_t) * 3 * (size_t)NR * (i1 - i0)))
+                              : nullptr;
+    std::vector<semd::WorkItem> work = realizations(i0, i1);
+    size_t so = 0, q = 0;
+    for (int i = i0; i < i1; ++i) {
+      const size_t per = (size_t)(K + 1) * shapes[i].M * shapes[i].N;
+      for (int m = 0; m < NR; ++m, ++q) {
+        work[q].out = buf + so + (size_t)m * per;
+        work[q].n_imfs = cnt + (size_t)(i - i0) * NR + m;
+        work[q].stats = items[i].stats_out ? wst + 3 * ((size_t)(i - i0) * NR + m) : nullptr;
+      }
       so += (size_t)NR * per;
     }
-    rc = run_work(work, K, p->sift_iters, p->path, stream);
+    rc = run_work(work, K, p->sift_iters, p->path, stream, &cv);
     so = 0;
     for (int i = i0; i < i1 && rc == SEMD_OK; ++i) {
       const int64_t per = (int64_t)(K + 1) * shapes[i].M * shapes[i].N;
       hipError_t e = semd::launch_ensemble_mean(buf + so, NR, per, items[i].imfs_out, stream);
       if (e == hipSuccess && items[i].n_imfs_out)
         e = semd::launch_max_count(cnt + (size_t)(i - i0) * NR, NR, items[i].n_imfs_out, stream);
+      if (e == hipSuccess && items[i].stats_out)
+        e = semd::launch_sum_stats(wst + 3 * (size_t)(i - i0) * NR, NR, items[i].stats_out,
+                                   stream);
       if (e != hipSuccess) rc = hip_fail(e, "ensemble mean launch");
       so += (size_t)NR * per;
     }
-    (void)hipFreeAsync(cnt, stream);
-    (void)hipFreeAsync(buf, stream);
-    if (rc) return rc;
-    i0 = i1;
+    if (rc) break;
   }
-  return SEMD_OK;
+  (void)hipFreeAsync(ws, stream);
+  return rc;
 }
 
 int semd_ceemdan_batch(const semd_item* items, int n, const semd_params* p,
@@ -1054,9 +1383,7 @@ int semd_ceemdan_batch(const semd_item* items, int n, const semd_params* p,
       return fail(SEMD_EINVAL, "item %d: noise_sigma (eps) must be finite and >= 0", i);
   const int K = p->max_imfs, NR = p->ensemble, S = p->sift_iters;
   const double sd = sd_of(p);
-  size_t free_b = 0, total_b = 0;
-  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = size_t(8) << 30;
-  const size_t budget = std::max<size_t>(free_b / 4, size_t(256) << 20);
+  const size_t budget = std::max<size_t>(available_device_bytes() / 4, size_t(256) << 20);
   // per item: residue, K mode slots, NR noise decompositions (K+1 slots),
   // NR stage outputs (2 slots), and the workspace of NR concurrent EMDs
   auto item_doubles = [&](int64_t L) {
@@ -1083,7 +1410,7 @@ int semd_ceemdan_batch(const semd_item* items, int n, const semd_params* p,
     const size_t st_off = total;
     total += al256(sizeof(semd::CeemdanState) * (size_t)nw);
     unsigned char* arena = nullptr;
-    if (hipMallocAsync(reinterpret_cast<void**>(&arena), total, stream) != hipSuccess)
+    if (dev_alloc(reinterpret_cast<void**>(&arena), total, stream) != hipSuccess)
       return fail(SEMD_ENOMEM, "CEEMDAN workspace of %zu bytes", total);
     auto* st = reinterpret_cast<semd::CeemdanState*>(arena + st_off);
     std::vector<semd::CeemdanJob> jobs(nw);
@@ -1236,9 +1563,12 @@ int semd_noise(uint64_t seed, uint64_t item, uint64_t m, int64_t L, double* w,
 struct semd_engine {
   struct Req {
     int64_t ticket;
-    semd::StreamSig sig;
+    bool onchip;           // decomposed whole by one on-chip launch
+    semd::StreamSig sig;   // streaming requests
+    semd::WorkItem work;   // on-chip requests (workspace in the arena)
+    int K, S;
     size_t off, bytes;
-    bool loaded;
+    bool loaded;           // streaming: h, r loaded; on-chip: launched
   };
   size_t budget = 0;
   int max_requests = 0;
@@ -1255,6 +1585,7 @@ struct semd_engine {
   hipEvent_t ev = nullptr;
   bool pending = false;            // a gather awaits processing
   std::vector<int64_t> pending_tickets;  // table order of that gather
+  std::vector<int64_t> pending_onchip;   // on-chip requests launched in that step
   std::vector<int64_t> finished;   // tickets ready for poll
   int64_t next_ticket = 1;
   hipStream_t last_stream = nullptr;
@@ -1289,23 +1620,26 @@ struct semd_engine {
       }
     }
   }
-  // Requests whose done flag was set in the last gathered step leave.
+  void retire(int64_t t) {
+    for (size_t j = 0; j < reqs.size(); ++j) {
+      if (reqs[j].ticket == t) {
+        release(reqs[j].off, reqs[j].bytes);
+        if (!reqs[j].onchip) dirty = true;  // the streaming tables change
+        reqs.erase(reqs.begin() + (ptrdiff_t)j);
+        finished.push_back(t);
+        break;
+      }
+    }
+  }
+  // Requests whose done flag was set in the last gathered step leave, and
+  // the on-chip requests launched in that step (complete with it).
   void process_gather() {
     if (!pending) return;
     pending = false;
-    for (size_t i = 0; i < pending_tickets.size(); ++i) {
-      if (!h_done[i]) continue;
-      const int64_t t = pending_tickets[i];
-      for (size_t j = 0; j < reqs.size(); ++j) {
-        if (reqs[j].ticket == t) {
-          release(reqs[j].off, reqs[j].bytes);
-          reqs.erase(reqs.begin() + (ptrdiff_t)j);
-          finished.push_back(t);
-          dirty = true;
-          break;
-        }
-      }
-    }
+    for (size_t i = 0; i < pending_tickets.size(); ++i)
+      if (h_done[i]) retire(pending_tickets[i]);
+    for (const int64_t t : pending_onchip) retire(t);
+    pending_onchip.clear();
   }
 };
 
@@ -1318,10 +1652,58 @@ int engine_check(const semd_item* it, const semd_params* p, Shape* sh) {
   if (rc) return rc;
   if (!it) return fail(SEMD_EINVAL, "item is NULL");
   std::vector<Shape> shapes;
-  rc = check_items(it, 1, p->transition_len, SEMD_PATH_STREAM, shapes);
+  rc = check_items(it, 1, p->transition_len, p->path, shapes);
   if (rc) return rc;
   *sh = shapes[0];
   return SEMD_OK;
+}
+
+// Route of an engine request: on chip (whole decomposition in one launch)
+// as semd_decompose_ex would route it, else streaming.
+bool engine_onchip(const Shape& sh, const semd_params* p) {
+  return p->path == SEMD_PATH_ONCHIP ||
+         (p->path == SEMD_PATH_AUTO && sh.L <= semd::kResidentMaxL);
+}
+
+size_t engine_bytes(const Shape& sh, const semd_params* p) {
+  if (engine_onchip(sh, p))
+    return al256(sizeof(double) * (size_t)semd::resident_ws_doubles(sh.L));
+  return al256(stream_bytes(sh.L));
+}
+
+// One on-chip launch per (K, S, launch shape) over a cohort of whole
+// decompositions whose workspaces are set; shapes as for a single signal
+// (semd_decompose_ex), so every result is bit-identical to its own call.
+int launch_cohort(std::vector<semd_engine::Req*>& cohort, hipStream_t stream) {
+  std::stable_sort(cohort.begin(), cohort.end(), [](const semd_engine::Req* a,
+                                                    const semd_engine::Req* b) {
+    if (a->K != b->K) return a->K < b->K;
+    if (a->S != b->S) return a->S < b->S;
+    return a->work.L > b->work.L;
+  });
+  std::vector<semd::WorkItem> items(cohort.size());
+  for (size_t i = 0; i < cohort.size(); ++i) items[i] = cohort[i]->work;
+  void* d = nullptr;
+  int rc = upload(items.data(), items.size() * sizeof(semd::WorkItem), stream, &d);
+  if (rc) return rc;
+  auto same = [](const semd::ResidentClass& a, const semd::ResidentClass& b) {
+    return a.nt == b.nt && a.c == b.c;
+  };
+  size_t i0 = 0;
+  while (i0 < cohort.size() && rc == SEMD_OK) {
+    const int K = cohort[i0]->K, S = cohort[i0]->S;
+    const semd::ResidentClass cls = class_for(items[i0].L, 0);
+    size_t i1 = i0;
+    while (i1 < cohort.size() && cohort[i1]->K == K && cohort[i1]->S == S &&
+           same(class_for(items[i1].L, 0), cls))
+      ++i1;
+    const hipError_t e = semd::launch_resident(static_cast<const semd::WorkItem*>(d) + i0,
+                                               (int)(i1 - i0), items[i0].L, cls, K, S, stream);
+    if (e != hipSuccess) rc = hip_fail(e, "engine on-chip launch");
+    i0 = i1;
+  }
+  (void)hipFreeAsync(d, stream);
+  return rc;
 }
 
 }  // namespace
@@ -1363,7 +1745,7 @@ int semd_engine_footprint(const semd_item* item, const semd_params* p, size_t* b
   Shape sh;
   const int rc = engine_check(item, p, &sh);
   if (rc) return rc;
-  *bytes = al256(stream_bytes(sh.L));
+  *bytes = engine_bytes(sh, p);
   return SEMD_OK;
 }
 
@@ -1377,7 +1759,7 @@ int semd_engine_admit(semd_engine* e, const semd_item* item, const semd_params* 
   if (rc) return rc;
   if ((int)e->reqs.size() >= e->max_requests)
     return fail(SEMD_EBUSY, "all %d request slots are taken", e->max_requests);
-  const size_t bytes = al256(stream_bytes(sh.L));
+  const size_t bytes = engine_bytes(sh, p);
   if (bytes > e->budget)
     return fail(SEMD_ENOMEM, "request needs %zu bytes, more than the whole engine budget %zu",
                 bytes, e->budget);
@@ -1388,12 +1770,21 @@ int semd_engine_admit(semd_engine* e, const semd_item* item, const semd_params* 
                                p->transition_len, sd_of(p), item->stats_out);
   semd_engine::Req r{};
   r.ticket = e->next_ticket++;
-  r.sig = stream_sig(w, p->max_imfs, p->sift_iters, e->arena + off);
+  r.onchip = engine_onchip(sh, p);
+  r.K = p->max_imfs;
+  r.S = p->sift_iters;
+  if (r.onchip) {
+    w.r = reinterpret_cast<double*>(e->arena + off);
+    w.u = w.r + w.L;
+    r.work = w;
+  } else {
+    r.sig = stream_sig(w, p->max_imfs, p->sift_iters, e->arena + off);
+    e->dirty = true;
+  }
   r.off = off;
   r.bytes = bytes;
   r.loaded = false;
   e->reqs.push_back(r);
-  e->dirty = true;
   *ticket = r.ticket;
   return SEMD_OK;
 }
@@ -1403,15 +1794,35 @@ int semd_engine_step(semd_engine* e, hipStream_t stream) {
   if (!e) return fail(SEMD_EINVAL, "engine is NULL");
   std::lock_guard<std::mutex> lock(g_engine_mu);
   e->last_stream = stream;
-  const int n = (int)e->reqs.size();
+  // on-chip requests admitted since the last step: whole decompositions,
+  // launched together; they complete with this step
+  std::vector<semd_engine::Req*> cohort;
+  std::vector<int64_t> cohort_tickets;
+  for (auto& r : e->reqs) {
+    if (r.onchip && !r.loaded) {
+      r.loaded = true;
+      cohort.push_back(&r);
+      cohort_tickets.push_back(r.ticket);
+    }
+  }
+  if (!cohort.empty()) {
+    const int rc = launch_cohort(cohort, stream);
+    if (rc) return rc;
+  }
+  // streaming requests: one step each
+  std::vector<semd_engine::Req*> sreqs;
+  for (auto& r : e->reqs)
+    if (!r.onchip) sreqs.push_back(&r);
+  const int n = (int)sreqs.size();
   hipError_t he = hipSuccess;
+  std::vector<int64_t> table_tickets;
   if (n > 0) {
     if (e->dirty) {
       std::vector<semd::StreamSig> sigs(n);
       std::vector<int2> new_tiles;
       for (int i = 0; i < n; ++i) {
-        sigs[i] = e->reqs[i].sig;
-        if (!e->reqs[i].loaded)
+        sigs[i] = sreqs[i]->sig;
+        if (!sreqs[i]->loaded)
           for (int t = 0; t < sigs[i].ntiles; ++t) new_tiles.push_back(make_int2(i, t));
       }
       std::vector<int2> tiles;
@@ -1436,14 +1847,14 @@ int semd_engine_step(semd_engine* e, hipStream_t stream) {
       unsigned char* dp = static_cast<unsigned char*>(d);
       he = semd::st_load(reinterpret_cast<const semd::StreamSig*>(dp),
                          reinterpret_cast<const int2*>(dp + o_new), (int)new_tiles.size(), stream);
-      for (auto& r : e->reqs) r.loaded = true;
+      for (auto* r : sreqs) r->loaded = true;
       e->dirty = false;
       e->graph_ok = false;
     }
     // ticket order of the table this step runs on (retirements below change
     // e->reqs, not the table)
-    std::vector<int64_t> table_tickets(n);
-    for (int i = 0; i < n; ++i) table_tickets[i] = e->reqs[i].ticket;
+    table_tickets.resize(n);
+    for (int i = 0; i < n; ++i) table_tickets[i] = sreqs[i]->ticket;
     unsigned char* dp = static_cast<unsigned char*>(e->d_tables);
     const auto* d_sigs = reinterpret_cast<const semd::StreamSig*>(dp);
     // one sift of every resident request and the gather of their done
@@ -1464,18 +1875,22 @@ int semd_engine_step(semd_engine* e, hipStream_t stream) {
     }
     if (he == hipSuccess) he = e->graph.launch(cs.s);
     if (he == hipSuccess) he = cs.join();
-    // the previous step's flags: requests that finished then leave now
-    if (e->pending) {
-      if (hipEventSynchronize(e->ev) != hipSuccess) return fail(SEMD_EDEVICE, "event wait");
-      e->process_gather();
-    }
-    if (he == hipSuccess)
+  }
+  if (he != hipSuccess) return hip_fail(he, "engine step");
+  // the previous step's flags: requests that finished then leave now
+  if (e->pending) {
+    if (hipEventSynchronize(e->ev) != hipSuccess) return fail(SEMD_EDEVICE, "event wait");
+    e->process_gather();
+  }
+  if (n > 0 || !cohort_tickets.empty()) {
+    if (n > 0)
       he = hipMemcpyAsync(e->h_done, e->d_done, sizeof(int32_t) * n, hipMemcpyDeviceToHost,
                           stream);
     if (he == hipSuccess) he = hipEventRecord(e->ev, stream);
     if (he == hipSuccess) {
       e->pending = true;
       e->pending_tickets = std::move(table_tickets);
+      e->pending_onchip = std::move(cohort_tickets);
     }
   }
   if (he != hipSuccess) return hip_fail(he, "engine step");

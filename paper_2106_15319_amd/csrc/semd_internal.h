@@ -112,6 +112,8 @@ hipError_t launch_ensemble_mean(const double* src, int NR, int64_t count, double
                                 hipStream_t stream);
 // n_out[0] = max over m of n_src[m] (error codes, negative, take precedence).
 hipError_t launch_max_count(const int32_t* n_src, int NR, int32_t* n_out, hipStream_t stream);
+// dst[0..2] = sums over m < NR of src[3m .. 3m+2] (work statistics).
+hipError_t launch_sum_stats(const int64_t* src, int NR, int64_t* dst, hipStream_t stream);
 
 // CEEMDAN (Sec. 2.2) per-item state and buffers, all device memory.
 struct CeemdanState {

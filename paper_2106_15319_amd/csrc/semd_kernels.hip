@@ -993,6 +993,17 @@ __global__ void ensemble_mean_kernel(const double* __restrict__ src, int NR, int
   }
 }
 
+// dst[j] = sum over m of src[3m + j], j < 3: work statistics of NR realizations.
+__global__ void sum_stats_kernel(const int64_t* __restrict__ src, int NR,
+                                 int64_t* __restrict__ dst) {
+  const int j = threadIdx.x;
+  if (blockIdx.x == 0 && j < 3) {
+    int64_t acc = 0;
+    for (int m = 0; m < NR; ++m) acc += src[3 * m + j];
+    dst[j] = acc;
+  }
+}
+
 __global__ void max_count_kernel(const int32_t* __restrict__ n_src, int NR,
                                  int32_t* __restrict__ n_out) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -1343,6 +1354,11 @@ hipError_t launch_ensemble_mean(const double* src, int NR, int64_t count, double
                                 hipStream_t stream) {
   hipLaunchKernelGGL(ensemble_mean_kernel, dim3(grid_for(count, 256)), dim3(256), 0, stream,
                      src, NR, count, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_stats(const int64_t* src, int NR, int64_t* dst, hipStream_t stream) {
+  hipLaunchKernelGGL(sum_stats_kernel, dim3(1), dim3(64), 0, stream, src, NR, dst);
   return hipGetLastError();
 }
 

@@ -103,8 +103,11 @@ hipError_t st_load(const StreamSig* sigs, const int2* tiles, int ntiles, hipStre
 // One step of every listed signal: detect, scan (decides the step's action),
 // compact and solve (sifting signals), eval (sift, IMF end, final outputs).
 // trace: also record each detection of the signals that carry a trace.
+// marks (6 events, or nullptr): recorded before the step and after each of
+// its detect, scan, compact, solve and eval launches, for kernel timing.
 hipError_t st_step(const StreamSig* sigs, int nsig, const int2* tiles, int ntiles,
-                   const int4* blocks, int nblocks, hipStream_t s, bool trace = false);
+                   const int4* blocks, int nblocks, hipStream_t s, bool trace = false,
+                   const hipEvent_t* marks = nullptr);
 // The descriptor of the one signal g and its tile and solve-block tables
 // (g.ntiles and 2 * stream_solve_blocks(g.cap) entries), written on the
 // device from a kernel argument: no host staging buffer, no allocation.

@@ -979,14 +979,22 @@ hipError_t st_load(const StreamSig* sigs, const int2* tiles, int ntiles, hipStre
   return hipGetLastError();
 }
 hipError_t st_step(const StreamSig* sigs, int nsig, const int2* tiles, int ntiles,
-                   const int4* blocks, int nblocks, hipStream_t st, bool trace) {
+                   const int4* blocks, int nblocks, hipStream_t st, bool trace,
+                   const hipEvent_t* marks) {
   if (nsig <= 0) return hipSuccess;
+  auto mark = [&](int i) { if (marks) (void)hipEventRecord(marks[i], st); };
+  mark(0);
   hipLaunchKernelGGL(st_detect_kernel, dim3(ntiles), dim3(kTT), 0, st, sigs, tiles);
+  mark(1);
   hipLaunchKernelGGL(st_scan_kernel, dim3(nsig), dim3(kTT), 0, st, sigs);
   if (trace) hipLaunchKernelGGL(st_trace_kernel, dim3(ntiles), dim3(kTT), 0, st, sigs, tiles);
+  mark(2);
   hipLaunchKernelGGL(st_compact_kernel, dim3(ntiles), dim3(kTT), 0, st, sigs, tiles);
+  mark(3);
   hipLaunchKernelGGL(st_solve_kernel, dim3(nblocks), dim3(kTT), 0, st, sigs, blocks);
+  mark(4);
   hipLaunchKernelGGL(st_eval_kernel, dim3(ntiles), dim3(kTT), 0, st, sigs, tiles);
+  mark(5);
   return hipGetLastError();
 }
 hipError_t st_put_single(const StreamSig& g, StreamSig* dsig, int2* tiles, int4* blocks,

@@ -681,12 +681,12 @@ def test_stream_eemd_long_signal():
 # serving engine
 # --------------------------------------------------------------------------
 
-def _engine_run(eng, reqs, K, S, D, sd=0.0):
+def _engine_run(eng, reqs, K, S, D, sd=0.0, path=semd.SEMD_PATH_AUTO):
     outs, tickets = [], {}
     for k, (X, M, N) in enumerate(reqs):
         out = torch.empty((K + 1, M * N), dtype=torch.float64, device=DEV)
         cnt = torch.empty(1, dtype=torch.int32, device=DEV)
-        t = eng.admit(dev(X), (M, N), out, cnt, D, K, S, sd=sd)
+        t = eng.admit(dev(X), (M, N), out, cnt, D, K, S, sd=sd, path=path)
         assert t is not None
         tickets[t] = k
         outs.append((out, cnt))
@@ -702,29 +702,67 @@ def _engine_run(eng, reqs, K, S, D, sd=0.0):
     return outs
 
 
-def test_engine_matches_stream_path_and_mix():
+@pytest.mark.parametrize("path", [semd.SEMD_PATH_AUTO, STREAM])
+def test_engine_matches_plain_path_and_mix(path):
+    """Each request's outputs are the same bits alone in the engine, in a mix
+    with others, and from semd_decompose_ex on the same path (AUTO: the short
+    requests run whole on chip, the long one streams), and match the oracle."""
     K, S, D = 6, 10, 10
     reqs = [(_series(15, k, M, N), M, N) for k, (M, N) in
             enumerate([(3000, 2), (500, 3), (12000, 4), (40, 1), (2049, 1)])]
     eng = semd.Engine(1 << 30, 64)
-    mixed = _engine_run(eng, reqs, K, S, D)
+    mixed = _engine_run(eng, reqs, K, S, D, path=path)
     for k, (X, M, N) in enumerate(reqs):
-        alone_eng = _engine_run(eng, [(X, M, N)], K, S, D)[0]
-        ref, nref = semd.semd_decompose_ex(dev(X), [M, N], D, K, S, path=STREAM)
-        # same arithmetic alone, in the mix and on the batch path: bit-identical
+        alone_eng = _engine_run(eng, [(X, M, N)], K, S, D, path=path)[0]
+        ref, nref = semd.semd_decompose_ex(dev(X), [M, N], D, K, S, path=path)
+        # same arithmetic alone, in the mix and on the plain path: bit-identical
         assert_same(host(mixed[k][0]), host(alone_eng[0]), "engine mix vs alone")
-        assert_same(host(mixed[k][0]), host(ref), "engine vs streaming batch path")
+        assert_same(host(mixed[k][0]), host(ref), "engine vs plain path")
         assert int(host(mixed[k][1])[0]) == int(host(nref)[0])
-        tally = Tally(f"engine request {k}")
+        tally = Tally(f"engine request {k} path={path}")
         _check_item(X, M, N, D, K, S, host(mixed[k][0]), int(host(mixed[k][1])[0]), tally,
-                    path=STREAM)
+                    path=path)
         tally.done()
+    eng.close()
+
+
+def test_engine_short_requests_finish_within_two_steps():
+    """A short request routed on chip completes with the step that launches
+    it (reported by the poll after the next step), whatever streaming work
+    is resident."""
+    K, S, D = 6, 10, 0
+    eng = semd.Engine(1 << 30, 16)
+    long_x = _series(17, 0, 20000, 2)
+    lo = torch.empty((K + 1, 40000), dtype=torch.float64, device=DEV)
+    tl = eng.admit(dev(long_x), (20000, 2), lo, None, D, K, S)
+    eng.step()
+    short_x = _series(17, 1, 1000, 3)
+    so = torch.empty((K + 1, 3000), dtype=torch.float64, device=DEV)
+    sc = torch.empty(1, dtype=torch.int32, device=DEV)
+    ts = eng.admit(dev(short_x), (1000, 3), so, sc, D, K, S)
+    done = set()
+    for _ in range(2):
+        eng.step()
+        done.update(eng.poll())
+    torch.cuda.synchronize()
+    done.update(eng.poll())
+    assert ts in done and tl not in done
+    ref, nref = semd.semd_decompose_ex(dev(short_x), [1000, 3], D, K, S)
+    assert_same(host(so), host(ref), "on-chip engine request")
+    for _ in range(K * S + 4):
+        if tl in done:
+            break
+        eng.step()
+        done.update(eng.poll())
+    torch.cuda.synchronize()
+    done.update(eng.poll())
+    assert tl in done
     eng.close()
 
 
 def test_engine_admission_budget_and_staggered_arrivals():
     K, S, D = 4, 6, 0
-    M, N = 6000, 2
+    M, N = 6000, 3  # 18,000 samples: streaming
     fp = semd.Engine.footprint([M, N], D, K, S)
     eng = semd.Engine(int(fp * 2.5), 8)  # room for two requests at a time
     Xs = [_series(16, k, M, N) for k in range(5)]
@@ -896,7 +934,7 @@ def test_sd_rule_stream_equals_onchip_and_engine():
     K, S, D, thr = 8, 30, 10, 0.05
     reqs = [(workloads.config2(1)[0].X, 112, 92), (_series(21, 0, 3000, 2), 3000, 2)]
     eng = semd.Engine(1 << 30, 16)
-    served = _engine_run(eng, reqs, K, S, D, sd=thr)
+    served = _engine_run(eng, reqs, K, S, D, sd=thr, path=STREAM)
     eng.close()
     for k, (X, M, N) in enumerate(reqs):
         a, na = semd.semd_decompose_ex(dev(X), [M, N], D, K, S, path=ONCHIP, sd=thr)

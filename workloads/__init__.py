@@ -158,6 +158,25 @@ def config3_item(i: int, shape: tuple[int, int]) -> Item:
     return Item(series(rng_for(3, i), ch, M), M, ch)
 
 
+def config3_items(indices, shapes, threads: int = 16) -> list[Item]:
+    """config3_item(i, shapes[i]) for every i in indices (the same arrays),
+    with the seed children spawned once and the series generated on host
+    threads."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    indices = list(indices)
+    if not indices:
+        return []
+    kids = np.random.SeedSequence(BASE_SEED + 3).spawn(max(indices) + 1)
+
+    def one(i):
+        M, ch = shapes[i]
+        return Item(series(np.random.default_rng(kids[i]), ch, M), M, ch)
+
+    with ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
+        return list(ex.map(one, indices))
+
+
 # The uneven batch is processed in waves of consecutive series, each wave one
 # batched EEMD call whose realization buffers fit device memory comfortably.
 CONFIG3_SERIES = 4096
