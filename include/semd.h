@@ -326,8 +326,11 @@ int semd_release_cached_memory(void);
  * returns, for one kernel ("st_load_kernel", "st_detect_kernel",
  * "st_scan_kernel", "st_compact_kernel", "st_solve_kernel", "st_eval_kernel"
  * or "resident_emd_kernel"), the launches timed since the last reset and
- * their summed duration in milliseconds ([host] results).  Not meant to run
- * concurrently with decompositions on other host threads. */
+ * their summed duration in milliseconds, or for one host phase of the batch
+ * calls ("host_alloc", "host_tables", "host_upload", "host_launch",
+ * "host_batch_call") the calls and their summed wall time ([host]
+ * results).  Not meant to run concurrently with decompositions on other
+ * host threads. */
 int semd_profile_enable(int on);
 int semd_profile_reset(void);
 int semd_profile_read(const char* kernel, int64_t* launches, double* total_ms);

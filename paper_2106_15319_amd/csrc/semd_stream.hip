@@ -265,27 +265,46 @@ __device__ __forceinline__ int run_mid(unsigned NE, int carry, int base, int c) 
 // What detection leaves for the scan, compaction and evaluation: each
 // thread's knots at tile-local ranks (positions and values), the knots each
 // thread's predecessors in the tile hold, the tile's counts and run keys, and
-// the continued run's end (its extremum is decided by the scan).
+// the continued run's end (its extremum is decided by the scan).  The knot
+// lists are assembled in `stage` (LDS of kTile doubles, free on entry), one
+// kind at a time, and written out as contiguous runs: written straight from
+// the threads, each store instruction would touch many partly written
+// cache lines.
 __device__ __forceinline__ void record_tile(const TileDet& d, const double (&h)[kTC], int a,
                                             int first_key, int cont_exit, int cont_pos,
                                             double cont_y, const StreamSig& S, int tile,
-                                            int64_t* scratch64, int* scratch) {
+                                            int64_t* scratch64, int* scratch, double* stage) {
   int64_t tot;
   const int64_t ex = block_excl_sum64(
       ((int64_t)__popc(d.maxbits) << 32) | (uint32_t)__popc(d.minbits), scratch64, tot);
-  int g[2] = {(int)(ex >> 32), (int)(ex & 0xffffffff)};
+  const int g0[2] = {(int)(ex >> 32), (int)(ex & 0xffffffff)};
+  const int cnt[2] = {(int)(tot >> 32), (int)(tot & 0xffffffff)};
   int32_t* tr = S.trank + 2 * ((int64_t)tile * kTT + threadIdx.x);
-  tr[0] = g[0];
-  tr[1] = g[1];
+  tr[0] = g0[0];
+  tr[1] = g0[1];
   const int base = a + threadIdx.x * kTC;
   const int64_t lo = (int64_t)tile * kTileKnots;
+  static_assert(kTileKnots * (sizeof(double) + sizeof(int32_t)) <= kTile * sizeof(double),
+                "one kind's knot list fits the staging area");
+  double* sval = stage;
+  int32_t* spos = reinterpret_cast<int32_t*>(stage + kTileKnots);
 #pragma unroll
-  for (int c = 0; c < kTC; ++c) {
-    if (((d.maxbits | d.minbits) >> c) & 1u) {
-      const int e = ((d.maxbits >> c) & 1u) ? 0 : 1;
-      S.lpos[e][lo + g[e]] = run_mid(d.NE, d.carry, base, c);
-      S.lval[e][lo + g[e]] = h[c];
-      ++g[e];
+  for (int e = 0; e < 2; ++e) {
+    const unsigned bits = e ? d.minbits : d.maxbits;
+    int g = g0[e];
+    __syncthreads();  // the staging area is free (tile buffer or previous kind)
+#pragma unroll
+    for (int c = 0; c < kTC; ++c) {
+      if ((bits >> c) & 1u) {
+        spos[g] = run_mid(d.NE, d.carry, base, c);
+        sval[g] = h[c];
+        ++g;
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt[e]; i += kTT) {
+      S.lpos[e][lo + i] = spos[i];
+      S.lval[e][lo + i] = sval[i];
     }
   }
   const int lastkey = block_max(d.last, scratch);
@@ -380,7 +399,8 @@ __global__ void __launch_bounds__(kTT) st_detect_kernel(const StreamSig* __restr
   tile_detect<kTC>(h, a, n, L, threadIdx.x, first_key, next, tbuf, pub_key,
                    &cont_exit, &cont_pos, &cont_y, d);
   __syncthreads();
-  record_tile(d, h, a, first_key, cont_exit, cont_pos, cont_y, S, tv.y, scratch64, scratch);
+  record_tile(d, h, a, first_key, cont_exit, cont_pos, cont_y, S, tv.y, scratch64, scratch,
+              tbuf);
 }
 
 // Ends the current IMF (its candidate is stored by the evaluation); reaching
@@ -898,7 +918,11 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
       tile_detect<kTC>(h, a, n, L, threadIdx.x, first_key, next, tbuf, pub_key,
                        &cont_exit, &cont_pos, &cont_y, d);
       __syncthreads();
-      record_tile(d, h, a, first_key, cont_exit, cont_pos, cont_y, S, tv.y, scratch64, scratch);
+      // the sifted candidate goes out now; the tile buffer then stages the
+      // knot lists
+      for (int i = threadIdx.x; i < n; i += kTT) S.h[a + i] = tbuf[tsw(i)];
+      record_tile(d, h, a, first_key, cont_exit, cont_pos, cont_y, S, tv.y, scratch64, scratch,
+                  tbuf);
     }
   }
   __syncthreads();
@@ -936,7 +960,7 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
       }
       S.st->done = 1;
     }
-  } else {
+  } else if (action != kSift) {  // (a sift step wrote h before detection's lists)
     for (int i = threadIdx.x; i < n; i += kTT) S.h[a + i] = tbuf[tsw(i)];
   }
 }
