@@ -285,10 +285,11 @@ def run_faces(args, semd, torch, workloads):
                   "stream_equivalent_GBps": b_stream / (kern_ms / 1e3) / 1e9}
     if not args.no_cpu:
         threads = cpu_threads()
+        nproc, model = host_cpu()
         ncpu = min(args.cpu_items, n)
         rate, dt, samples = cpu_decompose_rate(items[:ncpu], D, K, S, threads)
         res["cpu_baseline"] = {"value": rate, "unit": "samples/s", "cores": threads,
-                               "kind": "oracle",
+                               "kind": "oracle", "host_cpus": nproc, "cpu_model": model,
                                "sample": f"{ncpu} of the {n} images, {samples} input samples, "
                                          f"{dt:.1f} s wall on {threads} threads"}
     return res
@@ -307,7 +308,7 @@ def run_series(args, semd, torch, workloads):
     semd.PreparedBatch([X], [[M, N]], [out], cnt, D, K, S, stats=st).run()
     torch.cuda.synchronize()
     work = work_stats(st, cnt)
-    reps = max(args.steps, 1)
+    reps = max(args.repeats, 1)
     stream = torch.cuda.current_stream()
     for _ in range(max(args.warmup, 1)):
         semd.semd_decompose_ex(X, [M, N], D, K, S, out, cnt)
@@ -773,7 +774,10 @@ def run_ensembles(args, semd, torch, workloads):
 
 
 def run_serving(args, semd, torch, workloads):
-    """Poisson arrivals of the serving mix: engine against plain."""
+    """Poisson arrivals of the serving mix: the continuous-batching engine
+    against the plain per-request path.  With --sweep: the saturation rate
+    (every request queued at once, engine), then Poisson arrivals at 0.05
+    (light load), 0.25, 0.5, 0.75 and 0.9 of it, each point served by both."""
     from paper_2106_15319_amd import serving
 
     dev = torch.device("cuda:0")
@@ -789,33 +793,69 @@ def run_serving(args, semd, torch, workloads):
         reqs.append(serving.Request(x, (it.M, it.N), out, cnt, D, K, S))
         kinds.append(kind)
     samples = sum(r.dims[0] * r.dims[1] for r in reqs)
-    rng = np.random.default_rng(2106_15319 + 4)
-    if args.qps > 0:
-        arrivals = np.cumsum(rng.exponential(1.0 / args.qps, size=nreq)).tolist()
-    else:  # saturation: every request queued at the start
-        arrivals = [0.0] * nreq
+    budget = args.budget_gib << 30
     # warm both paths on the first requests
     serving.serve_plain(reqs[:2], [0.0, 0.0], semd.SEMD_PATH_AUTO)
-    serving.serve_engine(reqs[:2], [0.0, 0.0], args.budget_gib << 30, 256)
-    eng = serving.serve_engine(reqs, arrivals, args.budget_gib << 30, 256)
-    plain = serving.serve_plain(reqs, arrivals, semd.SEMD_PATH_AUTO)
-    res = base_record(args, samples / eng["wall"], eng["wall"] * 1e3)
-    res["steps"] = eng["steps"]
+    serving.serve_engine(reqs[:2], [0.0, 0.0], budget, 256)
+
+    def point(qps, with_plain=True):
+        rng = np.random.default_rng(2106_15319 + 4)
+        if qps > 0:
+            arrivals = np.cumsum(rng.exponential(1.0 / qps, size=nreq)).tolist()
+        else:  # saturation: every request queued at the start
+            arrivals = [0.0] * nreq
+        eng = serving.serve_engine(reqs, arrivals, budget, 256)
+        r = {"qps": qps,
+             "engine": {"req_per_s": nreq / eng["wall"], "samples_per_s": samples / eng["wall"],
+                        "wall_s": eng["wall"], "p50_ms": 1e3 * pct(eng["latency"], 50),
+                        "p99_ms": 1e3 * pct(eng["latency"], 99), "steps": eng["steps"],
+                        "max_resident": eng["max_resident"]}}
+        if with_plain:
+            plain = serving.serve_plain(reqs, arrivals, semd.SEMD_PATH_AUTO)
+            r["plain"] = {"req_per_s": nreq / plain["wall"],
+                          "samples_per_s": samples / plain["wall"], "wall_s": plain["wall"],
+                          "p50_ms": 1e3 * pct(plain["latency"], 50),
+                          "p99_ms": 1e3 * pct(plain["latency"], 99)}
+            r["engine_over_plain_throughput"] = plain["wall"] / eng["wall"]
+        return r
+
+    res = base_record(args, 0.0, 0.0)
     res["warmup"] = 0
-    res["config"] = {"workload": f"serving mix (60% textures 64-512 px, 30% series 2-16 x "
-                                 f"1e3-65536, 10% 1024x1024), {nreq} requests, "
-                                 + (f"Poisson arrivals at {args.qps} req/s" if args.qps > 0
-                                    else "all queued at the start"), "requests": nreq,
-                     "qps": args.qps, "input_samples": samples,
-                     "mix": {k: kinds.count(k) for k in sorted(set(kinds))}}
-    res["latency_ms"] = {"p50": 1e3 * pct(eng["latency"], 50),
-                         "p99": 1e3 * pct(eng["latency"], 99)}
-    res["served"] = {"value": samples / eng["wall"], "wall_s": eng["wall"],
-                     "engine_steps": eng["steps"], "max_resident": eng["max_resident"]}
-    res["plain"] = {"value": samples / plain["wall"], "wall_s": plain["wall"],
-                    "p50_ms": 1e3 * pct(plain["latency"], 50),
-                    "p99_ms": 1e3 * pct(plain["latency"], 99),
-                    "served_over_plain": plain["wall"] / eng["wall"]}
+    mix = {k: kinds.count(k) for k in sorted(set(kinds))}
+    if args.sweep:
+        sat = point(0.0)
+        lam = sat["engine"]["req_per_s"]
+        # 0.05: light load, below the plain path's own capacity
+        fracs = (0.05, 0.25, 0.5, 0.75, 0.9)
+        pts = [point(f * lam) for f in fracs]
+        for f, q in zip(fracs, pts):
+            q["fraction_of_saturation"] = f
+        top = pts[-1]
+        res["value"] = top["engine"]["samples_per_s"]
+        res["ms_per_step"] = 1e3 * top["engine"]["wall_s"] / max(1, top["engine"]["steps"])
+        res["steps"] = top["engine"]["steps"]
+        res["config"] = {"workload": f"serving mix (60% textures 64-512 px, 30% series 2-16 x "
+                                     f"1e3-65536, 10% 1024x1024), {nreq} requests per point, "
+                                     "Poisson arrivals at 0.05/0.25/0.5/0.75/0.9 x the "
+                                     "engine's saturation rate; value at 0.9",
+                         "requests": nreq,
+                         "input_samples": samples, "mix": mix}
+        res["saturation"] = sat
+        res["sweep"] = pts
+        res["latency_ms"] = {"p50": top["engine"]["p50_ms"], "p99": top["engine"]["p99_ms"]}
+    else:
+        q = point(args.qps)
+        res["value"] = q["engine"]["samples_per_s"]
+        res["ms_per_step"] = 1e3 * q["engine"]["wall_s"] / max(1, q["engine"]["steps"])
+        res["steps"] = q["engine"]["steps"]
+        res["config"] = {"workload": f"serving mix (60% textures 64-512 px, 30% series 2-16 x "
+                                     f"1e3-65536, 10% 1024x1024), {nreq} requests, "
+                                     + (f"Poisson arrivals at {args.qps} req/s" if args.qps > 0
+                                        else "all queued at the start"), "requests": nreq,
+                         "qps": args.qps, "input_samples": samples, "mix": mix}
+        res["latency_ms"] = {"p50": q["engine"]["p50_ms"], "p99": q["engine"]["p99_ms"]}
+        res["served"] = q["engine"]
+        res["plain"] = q["plain"]
     res["roofline"] = None
     return res
 
@@ -838,10 +878,14 @@ def main() -> int:
                     help="faces: images timed with the oracle")
     ap.add_argument("--cpu-samples", type=int, default=1_200_000,
                     help="eemd: input samples of the oracle's random series sample")
-    ap.add_argument("--requests", type=int, default=120, help="serving: requests")
+    ap.add_argument("--requests", type=int, default=2000, help="serving: requests")
+    ap.add_argument("--repeats", type=int, default=1000,
+                    help="series: decompositions timed one by one (latency percentiles)")
     ap.add_argument("--qps", type=float, default=40.0,
                     help="serving: arrival rate (0: all requests queued at the start)")
     ap.add_argument("--budget-gib", type=int, default=32, help="serving: engine HBM budget")
+    ap.add_argument("--sweep", action="store_true",
+                    help="serving: saturation, then 0.25/0.5/0.75/0.9 of it")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--path", choices=["auto", "onchip", "stream"], default="auto",
                     help="faces: execution path of the batched decomposition")

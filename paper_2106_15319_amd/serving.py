@@ -2,9 +2,10 @@
 
 Requests arrive at given times (seconds from the start); each is admitted
 to the engine as soon as its device footprint fits (otherwise it waits in a
-FIFO queue), every engine step advances all resident requests by one sift,
-and a request's latency runs from its arrival to the poll that reports its
-outputs complete.  The plain comparator serves the same arrivals one request
+FIFO queue).  Every engine step decomposes the short requests admitted since
+the last step whole on chip and advances every long (streaming) request by
+one sift; a request's latency runs from its arrival to the poll that reports
+its outputs complete.  The plain comparator serves the same arrivals one request
 at a time, each with its own launch sequence (semd_decompose_ex).
 
 Inputs and outputs are device tensors allocated before the loop starts.
