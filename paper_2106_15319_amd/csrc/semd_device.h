@@ -12,6 +12,19 @@
 namespace semd {
 namespace dev {
 
+// A pointer into device memory, typed as the global address space.  Pointers
+// read out of a descriptor in memory are otherwise generic, and accesses
+// through them compile to flat instructions, which count against the LDS wait
+// counter as well: every wait for an LDS result then also waits for the
+// memory accesses in flight.  Through a global pointer they are global
+// instructions, which also take a scalar base with a 32-bit lane offset.
+template <class T>
+using global_ptr = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ global_ptr<T> gmem(T* p) {
+  return (global_ptr<T>)p;
+}
+
 constexpr int kWave = 64;
 constexpr int kHalo = 32;    // rows a streaming solve window reaches beyond its block
 constexpr int kRise = 1;

@@ -279,7 +279,7 @@ __device__ __forceinline__ void record_tile(const TileDet& d, const double (&h)[
       ((int64_t)__popc(d.maxbits) << 32) | (uint32_t)__popc(d.minbits), scratch64, tot);
   const int g0[2] = {(int)(ex >> 32), (int)(ex & 0xffffffff)};
   const int cnt[2] = {(int)(tot >> 32), (int)(tot & 0xffffffff)};
-  int32_t* tr = S.trank + 2 * ((int64_t)tile * kTT + threadIdx.x);
+  const global_ptr<int32_t> tr = gmem(S.trank) + 2 * ((int64_t)tile * kTT + threadIdx.x);
   tr[0] = g0[0];
   tr[1] = g0[1];
   const int base = a + threadIdx.x * kTC;
@@ -302,14 +302,16 @@ __device__ __forceinline__ void record_tile(const TileDet& d, const double (&h)[
       }
     }
     __syncthreads();
+    const global_ptr<int32_t> lp = gmem(S.lpos[e]) + lo;
+    const global_ptr<double> lv = gmem(S.lval[e]) + lo;
     for (int i = threadIdx.x; i < cnt[e]; i += kTT) {
-      S.lpos[e][lo + i] = spos[i];
-      S.lval[e][lo + i] = sval[i];
+      lp[i] = spos[i];
+      lv[i] = sval[i];
     }
   }
   const int lastkey = block_max(d.last, scratch);
   if (threadIdx.x == 0) {
-    TileInfo& t = S.tinfo[tile];
+    auto& t = gmem(S.tinfo)[tile];
     t.cnt[0] = (int)(tot >> 32);
     t.cnt[1] = (int)(tot & 0xffffffff);
     t.lastkey = (lastkey & 3) == kCont ? -1 : lastkey;
@@ -761,19 +763,33 @@ __global__ void __launch_bounds__(kTT) st_solve_kernel(const StreamSig* __restri
 //   b_j = (y_{j+1} - y_j) / g - g (2 m_j + m_{j+1}) / 6,
 // and the walker evaluates half of it (the envelope mean is the sum of two
 // halves).
+//
+// The knot after the right one, (t2, y2, m2), is loaded one crossing ahead,
+// so a crossing computes from registers and its loads complete while the
+// walker moves on.
 struct StWalk {
-  int j, t1;
-  double y1, m1, B, q0, q1, q2, q3;
+  int j, t1, t2;
+  double y1, m1, y2, m2, B, q0, q1, q2, q3;
 };
 
+// One envelope's knots (positions, values, second derivatives) in global
+// memory, and the index of its last knot.
+struct KnotView {
+  global_ptr<const int32_t> t;
+  global_ptr<const double> y, m;
+  int last;
+};
+
+__device__ __forceinline__ KnotView knot_view(const StreamSig& S, int e, int nk) {
+  const int Pp = nk < 2 ? nk : 2;
+  return {gmem<const int32_t>(S.kt[e]), gmem<const double>(S.ky[e]),
+          gmem<const double>(S.km[e]), nk + 2 * Pp - 1};
+}
+
 // The coefficients of segment j from its left knot (t0, y0, m0) and the
-// right knot loaded here.
-__device__ __forceinline__ void st_walk_segment(StWalk& w, const StreamSig& S, int e, int j,
-                                                int t0, double y0, double m0) {
+// right knot (w.t1, w.y1, w.m1).
+__device__ __forceinline__ void st_walk_coefs(StWalk& w, int j, int t0, double y0, double m0) {
   w.j = j;
-  w.t1 = S.kt[e][j + 1];
-  w.y1 = S.ky[e][j + 1];
-  w.m1 = S.km[e][j + 1];
   const double g = (double)(w.t1 - t0);
   const double ig = recip(g);
   const double b = (w.y1 - y0) * ig - g * fma(2.0, m0, w.m1) * (1.0 / 6.0);
@@ -783,25 +799,42 @@ __device__ __forceinline__ void st_walk_segment(StWalk& w, const StreamSig& S, i
   w.q3 = (w.m1 - m0) * ig * (1.0 / 12.0);
 }
 
+// Knot i (clamped to the last one) into the walker's look-ahead registers.
+__device__ __forceinline__ void st_walk_ahead(StWalk& w, const KnotView& K, int i) {
+  i = min(i, K.last);
+  w.t2 = K.t[i];
+  w.y2 = K.y[i];
+  w.m2 = K.m[i];
+}
+
 // Position at the segment holding sample k from segment j (whose left knot
 // lies at or before k; the last knot lies beyond the signal).
-__device__ __forceinline__ void st_walk_init(StWalk& w, const StreamSig& S, int e, int j, int k) {
-  const int32_t* kt = S.kt[e];
-  int t0 = kt[j], t1 = kt[j + 1];
+__device__ __forceinline__ void st_walk_init(StWalk& w, const KnotView& K, int j, int k) {
+  int t0 = K.t[j], t1 = K.t[j + 1];
   while (t1 <= k) {
     ++j;
     t0 = t1;
-    t1 = kt[j + 1];
+    t1 = K.t[j + 1];
   }
-  st_walk_segment(w, S, e, j, t0, S.ky[e][j], S.km[e][j]);
+  w.t1 = t1;
+  w.y1 = K.y[j + 1];
+  w.m1 = K.m[j + 1];
+  st_walk_ahead(w, K, j + 2);
+  st_walk_coefs(w, j, t0, K.y[j], K.m[j]);
   w.B = (double)(k - t0);
 }
 
 // Half the envelope at sample k (one step from k-1 crosses at most one knot).
-__device__ __forceinline__ double st_walk_at(StWalk& w, const StreamSig& S, int e, int k) {
+__device__ __forceinline__ double st_walk_at(StWalk& w, const KnotView& K, int k) {
   if (w.t1 <= k) {
-    w.B = (double)(k - w.t1);
-    st_walk_segment(w, S, e, w.j + 1, w.t1, w.y1, w.m1);
+    const int t0 = w.t1;
+    const double y0 = w.y1, m0 = w.m1;
+    w.B = (double)(k - t0);
+    w.t1 = w.t2;
+    w.y1 = w.y2;
+    w.m1 = w.m2;
+    st_walk_coefs(w, w.j + 1, t0, y0, m0);
+    st_walk_ahead(w, K, w.j + 2);
   }
   return fma(fma(fma(w.q3, w.B, w.q2), w.B, w.q1), w.B, w.q0);
 }
@@ -830,12 +863,13 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
   __shared__ double cont_y;
   const int2 tv = tiles[blockIdx.x];
   const StreamSig& S = sigs[tv.x];
-  const SigStatus* st = S.st;
+  const global_ptr<const SigStatus> st = gmem<const SigStatus>(S.st);
   const int action = st->action;
   if (action == kIdle) return;
   const int L = S.L;
   const int a = tv.y * kTile, n = min(kTile, L - a);
-  for (int i = threadIdx.x; i < n; i += kTT) tbuf[tsw(i)] = S.h[a + i];
+  const global_ptr<double> hg = gmem(S.h);
+  for (int i = threadIdx.x; i < n; i += kTT) tbuf[tsw(i)] = hg[a + i];
   if (action == kSift || action == kSiftLast) {
     const int lb = threadIdx.x * kTC;
     const int nv = max(0, min(kTC, n - lb));
@@ -843,9 +877,11 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
     // thread 0 starts one sample early for the previous tile's last sample
     const int ks = (threadIdx.x == 0 && a > 0) ? k0 - 1 : k0;
     StWalk wk[2];
+    const KnotView kv[2] = {knot_view(S, 0, st->n[0]), knot_view(S, 1, st->n[1])};
     if (nv > 0) {
-      const int32_t* tr = S.trank + 2 * ((int64_t)tv.y * kTT + threadIdx.x);
-      const TileInfo& ti = S.tinfo[tv.y];
+      const global_ptr<const int32_t> tr =
+          gmem<const int32_t>(S.trank) + 2 * ((int64_t)tv.y * kTT + threadIdx.x);
+      const auto& ti = gmem<const TileInfo>(S.tinfo)[tv.y];
       // the continued run's extremum precedes this thread's knots when the
       // run ends in an earlier thread of the tile
       const bool cont_before = ti.cont_pos >= 0 && ti.cont_pos < k0;
@@ -857,12 +893,12 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
         // the last knot of earlier threads lies before the thread's first
         // sample (and before sample a-1 for thread 0: it lies in an earlier
         // tile or is a mirrored knot)
-        st_walk_init(wk[e], S, e, Pp + rank - 1, ks);
+        st_walk_init(wk[e], kv[e], Pp + rank - 1, ks);
       }
       if (ks < k0) {
-        const double up = st_walk_at(wk[0], S, 0, ks);
-        const double lo = st_walk_at(wk[1], S, 1, ks);
-        halo[0] = S.edge[2 * tv.y - 1] - (up + lo);
+        const double up = st_walk_at(wk[0], kv[0], ks);
+        const double lo = st_walk_at(wk[1], kv[1], ks);
+        halo[0] = gmem(S.edge)[2 * tv.y - 1] - (up + lo);
         wk[0].B += 1.0;
         wk[1].B += 1.0;
       }
@@ -875,8 +911,8 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
       for (int c = 0; c < kTC; ++c) {
         if (c < nv) {
           const int k = k0 + c;
-          const double up = st_walk_at(wk[0], S, 0, k);
-          const double lo = st_walk_at(wk[1], S, 1, k);
+          const double up = st_walk_at(wk[0], kv[0], k);
+          const double lo = st_walk_at(wk[1], kv[1], k);
           const double m = up + lo, hk = tbuf[tsw(lb + c)];
           num = fma(m, m, num);
           den = fma(hk, hk, den);
@@ -889,9 +925,9 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
       // tile's first sample
       if (lb + nv == n && a + n < L) {
         const int k = a + n;
-        const double up = st_walk_at(wk[0], S, 0, k);
-        const double lo = st_walk_at(wk[1], S, 1, k);
-        halo[1] = S.edge[2 * tv.y + 2] - (up + lo);
+        const double up = st_walk_at(wk[0], kv[0], k);
+        const double lo = st_walk_at(wk[1], kv[1], k);
+        halo[1] = gmem(S.edge)[2 * tv.y + 2] - (up + lo);
       }
     }
     if (action == kSift) {
@@ -900,8 +936,8 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
         block_sum2<kNW>(num, den, wsum, threadIdx.x & (kWave - 1), threadIdx.x / kWave, tnum,
                         tden);
         if (threadIdx.x == 0) {
-          S.tinfo[tv.y].sd_num = tnum;
-          S.tinfo[tv.y].sd_den = tden;
+          gmem(S.tinfo)[tv.y].sd_num = tnum;
+          gmem(S.tinfo)[tv.y].sd_den = tden;
         }
       }
       // the sifted candidate stays the candidate: its extrema now, while
@@ -920,7 +956,7 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
       __syncthreads();
       // the sifted candidate goes out now; the tile buffer then stages the
       // knot lists
-      for (int i = threadIdx.x; i < n; i += kTT) S.h[a + i] = tbuf[tsw(i)];
+      for (int i = threadIdx.x; i < n; i += kTT) hg[a + i] = tbuf[tsw(i)];
       record_tile(d, h, a, first_key, cont_exit, cont_pos, cont_y, S, tv.y, scratch64, scratch,
                   tbuf);
     }
@@ -928,12 +964,13 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
   __syncthreads();
   const int64_t M = S.M, R = S.M + S.D;
   if (action == kSiftLast || action == kEndImf) {
-    double* slot = S.out + (int64_t)st->slot * S.slot_stride;
+    const global_ptr<double> slot = gmem(S.out) + (int64_t)st->slot * S.slot_stride;
+    const global_ptr<double> rg = gmem(S.r);
     for (int i = threadIdx.x; i < n; i += kTT) {
       const int k = a + i;
       const double hk = tbuf[tsw(i)];
-      const double nr = S.r[k] - hk;
-      S.r[k] = nr;
+      const double nr = rg[k] - hk;
+      rg[k] = nr;
       tbuf[tsw(i)] = nr;
       const int64_t ii = k / R, m = k - ii * R;
       if (m < M) slot[ii * M + m] = hk;
@@ -947,8 +984,9 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
       const int64_t ii = k / R, m = k - ii * R;
       if (m < M) {
         const int64_t o = ii * M + m;
-        for (int q = nimf; q < K; ++q) S.out[q * S.slot_stride + o] = 0.0;
-        S.out[(int64_t)K * S.slot_stride + o] = bad ? 0.0 : tbuf[tsw(i)];
+        const global_ptr<double> og = gmem(S.out);
+        for (int q = nimf; q < K; ++q) og[q * S.slot_stride + o] = 0.0;
+        og[(int64_t)K * S.slot_stride + o] = bad ? 0.0 : tbuf[tsw(i)];
       }
     }
     if (tv.y == 0 && threadIdx.x == 0) {
@@ -958,10 +996,10 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
         S.stats[1] = st->n_knots;
         S.stats[2] = st->n_sifts * (int64_t)S.L;
       }
-      S.st->done = 1;
+      gmem(S.st)->done = 1;
     }
   } else if (action != kSift) {  // (a sift step wrote h before detection's lists)
-    for (int i = threadIdx.x; i < n; i += kTT) S.h[a + i] = tbuf[tsw(i)];
+    for (int i = threadIdx.x; i < n; i += kTT) hg[a + i] = tbuf[tsw(i)];
   }
 }
 
