@@ -34,8 +34,10 @@ constexpr int kTT = kTileThreads;     // threads per tile workgroup
 constexpr int kTC = kTile / kTT;      // samples per thread
 constexpr int kSB = 2048;             // interior rows per solve block
 constexpr int kNW = kTT / kWave;
+constexpr int kCompactThreads = kWave;  // threads per compaction workgroup (one tile)
 
-__device__ __forceinline__ bool sifting(const SigStatus& st) {
+template <class Status>
+__device__ __forceinline__ bool sifting(const Status& st) {
   return st.action == kSift || st.action == kSiftLast;
 }
 
@@ -542,8 +544,8 @@ __global__ void __launch_bounds__(kTT) st_scan_kernel(const StreamSig* __restric
 // boundary): the knot list of one envelope is
 //   [-k_P', ..., -k_1, k_1, ..., k_n, 2(L-1)-k_n, ..., 2(L-1)-k_{n-P'+1}],
 // P' = min(2, n), mirrored knots carrying their source's value.
-__device__ __forceinline__ void put_knot(int32_t* kt, double* ky, int g, int n, int L, int pos,
-                                         double y) {
+__device__ __forceinline__ void put_knot(global_ptr<int32_t> kt, global_ptr<double> ky, int g,
+                                         int n, int L, int pos, double y) {
   const int Pp = n < 2 ? n : 2;
   kt[Pp + g] = pos;
   ky[Pp + g] = y;
@@ -559,29 +561,37 @@ __device__ __forceinline__ void put_knot(int32_t* kt, double* ky, int g, int n, 
 // The knots of the tile at their ranks (Sec. 2.1 Step 1 -> Step 2): the
 // continued run's extremum, when the scan found one, then the tile's own
 // knots as detection listed them.  Also the tile's edge samples before this
-// sift, for the evaluation of the neighbouring tiles.
-__global__ void __launch_bounds__(kTT) st_compact_kernel(const StreamSig* __restrict__ sigs,
-                                                         const int2* __restrict__ tiles) {
+// sift, for the evaluation of the neighbouring tiles.  One wave per tile: a
+// tile holds a few hundred knots at most, and the time of a launch over
+// every tile of a batch goes to each workgroup's chain of dependent
+// descriptor reads, so more, smaller workgroups keep more tiles in flight.
+__global__ void __launch_bounds__(kCompactThreads) st_compact_kernel(
+    const StreamSig* __restrict__ sigs, const int2* __restrict__ tiles) {
   const int2 tv = tiles[blockIdx.x];
   const StreamSig& S = sigs[tv.x];
-  if (!sifting(*S.st)) return;
+  const global_ptr<const SigStatus> st = gmem<const SigStatus>(S.st);
+  if (!sifting(*st)) return;
   const int L = S.L;
   const int a = tv.y * kTile, n = min(kTile, L - a);
-  const TileInfo ti = S.tinfo[tv.y];
+  const auto& ti = gmem<const TileInfo>(S.tinfo)[tv.y];
   if (threadIdx.x == 0) {
-    S.edge[2 * tv.y] = S.h[a];
-    S.edge[2 * tv.y + 1] = S.h[a + n - 1];
+    const global_ptr<const double> hg = gmem<const double>(S.h);
+    gmem(S.edge)[2 * tv.y] = hg[a];
+    gmem(S.edge)[2 * tv.y + 1] = hg[a + n - 1];
   }
   const int64_t lo = (int64_t)tv.y * kTileKnots;
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
-    const int nk = S.st->n[e];
+    const int nk = st->n[e];
     const int ck = (ti.cont_knot >> e) & 1;
+    const global_ptr<int32_t> kt = gmem(S.kt[e]);
+    const global_ptr<double> ky = gmem(S.ky[e]);
     if (ck && threadIdx.x == 0)
-      put_knot(S.kt[e], S.ky[e], ti.off[e], nk, L, ((ti.carry >> 2) + ti.cont_pos) >> 1,
-               ti.cont_y);
-    for (int i = threadIdx.x; i < ti.cnt[e]; i += kTT)
-      put_knot(S.kt[e], S.ky[e], ti.off[e] + ck + i, nk, L, S.lpos[e][lo + i], S.lval[e][lo + i]);
+      put_knot(kt, ky, ti.off[e], nk, L, ((ti.carry >> 2) + ti.cont_pos) >> 1, ti.cont_y);
+    const global_ptr<const int32_t> lp = gmem<const int32_t>(S.lpos[e]) + lo;
+    const global_ptr<const double> lv = gmem<const double>(S.lval[e]) + lo;
+    for (int i = threadIdx.x; i < ti.cnt[e]; i += kCompactThreads)
+      put_knot(kt, ky, ti.off[e] + ck + i, nk, L, lp[i], lv[i]);
   }
 }
 
@@ -1051,7 +1061,8 @@ hipError_t st_step(const StreamSig* sigs, int nsig, const int2* tiles, int ntile
   hipLaunchKernelGGL(st_scan_kernel, dim3(nsig), dim3(kTT), 0, st, sigs);
   if (trace) hipLaunchKernelGGL(st_trace_kernel, dim3(ntiles), dim3(kTT), 0, st, sigs, tiles);
   mark(2);
-  hipLaunchKernelGGL(st_compact_kernel, dim3(ntiles), dim3(kTT), 0, st, sigs, tiles);
+  hipLaunchKernelGGL(st_compact_kernel, dim3(ntiles), dim3(kCompactThreads), 0, st, sigs,
+                     tiles);
   mark(3);
   hipLaunchKernelGGL(st_solve_kernel, dim3(nblocks), dim3(kTT), 0, st, sigs, blocks);
   mark(4);
