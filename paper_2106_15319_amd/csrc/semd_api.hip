@@ -608,11 +608,14 @@ void stream_tables(const std::vector<semd::StreamSig>& sigs, std::vector<int2>& 
                    std::vector<int4>& blocks) {
   tiles.clear();
   blocks.clear();
+  int64_t total = 0;
+  for (const auto& g : sigs) total += 2 * (int64_t)semd::stream_solve_blocks(g.cap);
+  const int fold = semd::stream_solve_fold(total);
   for (int i = 0; i < (int)sigs.size(); ++i) {
     for (int t = 0; t < sigs[i].ntiles; ++t) tiles.push_back(make_int2(i, t));
-    const int nb = semd::stream_solve_blocks(sigs[i].cap);
+    const int G = semd::stream_solve_groups(sigs[i].cap, fold);
     for (int e = 0; e < 2; ++e)
-      for (int b = 0; b < nb; ++b) blocks.push_back(make_int4(i, e, b, 0));
+      for (int z = 0; z < G; ++z) blocks.push_back(make_int4(i, e, z, G));
   }
 }
 
@@ -789,7 +792,8 @@ SingleLayout single_layout(int64_t L, int path) {
   } else {
     const int cap = (int)((L - 1) / 2 + 12);
     s.ntiles = (int)((L + semd::kTile - 1) / semd::kTile);
-    s.nblocks = 2 * semd::stream_solve_blocks(cap);
+    s.nblocks = 2 * semd::stream_solve_groups(
+                        cap, semd::stream_solve_fold(2 * semd::stream_solve_blocks(cap)));
     s.o_tiles = al256(sizeof(semd::StreamSig));
     s.o_blocks = s.o_tiles + al256(sizeof(int2) * (size_t)s.ntiles);
     s.o_data = s.o_blocks + al256(sizeof(int4) * (size_t)s.nblocks);

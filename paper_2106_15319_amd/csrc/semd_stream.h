@@ -109,13 +109,20 @@ hipError_t st_step(const StreamSig* sigs, int nsig, const int2* tiles, int ntile
                    const int4* blocks, int nblocks, hipStream_t s, bool trace = false,
                    const hipEvent_t* marks = nullptr);
 // The descriptor of the one signal g and its tile and solve-block tables
-// (g.ntiles and 2 * stream_solve_blocks(g.cap) entries), written on the
+// (g.ntiles entries, and two per solve workgroup: stream_solve_groups(g.cap,
+// stream_solve_fold(2 * stream_solve_blocks(g.cap))) each), written on the
 // device from a kernel argument: no host staging buffer, no allocation.
 hipError_t st_put_single(const StreamSig& g, StreamSig* dsig, int2* tiles, int4* blocks,
                          hipStream_t s);
 // done[i] = status of signal i has its final outputs written.
 hipError_t st_gather_done(const StreamSig* sigs, int nsig, int32_t* done, hipStream_t s);
-// Solve blocks one envelope of `cap` knots needs.
+// Solve blocks one envelope of `cap` knots spans (an upper bound on the
+// solve-table entries it takes).
 int stream_solve_blocks(int cap);
+// The fold of a launch whose envelopes span `total_blocks` solve blocks, and
+// the workgroups (solve-table entries) one envelope of `cap` knots takes
+// under it: workgroup z of G handles blocks z, z + G, ...
+int stream_solve_fold(int64_t total_blocks);
+int stream_solve_groups(int cap, int fold);
 
 }  // namespace semd

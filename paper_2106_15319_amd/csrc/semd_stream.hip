@@ -33,6 +33,15 @@ using namespace dev;
 constexpr int kTT = kTileThreads;     // threads per tile workgroup
 constexpr int kTC = kTile / kTT;      // samples per thread
 constexpr int kSB = 2048;             // interior rows per solve block
+// An envelope's solve blocks are sized for its largest possible knot count
+// (about L/2), and in most sifts most of them are empty.  A launch over many
+// blocks folds them: each workgroup takes every G-th block of its envelope,
+// so an empty block costs a loop test instead of a workgroup.  The fold
+// (kSolveTarget unfolded blocks per workgroup slot, at most kSolveFoldMax)
+// leaves a launch over few signals unfolded, so it keeps its parallelism.
+constexpr int kSolveTarget = 4096;
+constexpr int kSolveFoldMax = 32;
+__host__ __device__ constexpr int solve_blocks(int cap) { return (cap + kSB - 1) / kSB; }
 constexpr int kNW = kTT / kWave;
 constexpr int kCompactThreads = kWave;  // threads per compaction workgroup (one tile)
 
@@ -643,121 +652,127 @@ __global__ void __launch_bounds__(kTT) st_solve_kernel(const StreamSig* __restri
   __shared__ double ly[kW];
   __shared__ __align__(16) double fwd_lds[kFwdStride * kNW];
   __shared__ double bwd_lds[2 * kNW];
-  const int4 bv = blocks[blockIdx.x];  // (signal, envelope, block)
+  const int4 bv = blocks[blockIdx.x];  // (signal, envelope, first block, stride)
   const StreamSig& S = sigs[bv.x];
   if (!sifting(*S.st)) return;
   const int env = bv.y;
   const int n = S.st->n[env];
   const int Pp = n < 2 ? n : 2;
   const int n2 = n + 2 * Pp;
-  const int r0 = 1 + bv.z * kSB;
-  if (n2 < 3 || r0 > n2 - 2) return;
-  const int r1 = min(r0 + kSB, n2 - 1);  // rows r0 .. r1-1
-  const int a0 = max(1, r0 - kHalo), a1 = min(n2 - 2, r1 - 1 + kHalo);
-  const int w0 = a0 - 1, w1 = a1 + 1;    // knots read
-  const int32_t* kt = S.kt[env];
-  const double* ky = S.ky[env];
-  for (int i = threadIdx.x; i <= w1 - w0; i += kTT) {
-    lt[i] = kt[w0 + i];
-    ly[i] = ky[w0 + i];
-  }
-  __syncthreads();
-#define T(j) ((double)lt[(j) - w0])
-#define Y(j) (ly[(j) - w0])
-  const int rows = a1 - a0 + 1;
-  // (<= kRMax; a multiple of 4 is raised by one: row blocks whose starts
-  // lie a multiple of 8 doubles apart would share LDS banks 4 ways or more)
-  int R = (rows + kTT - 1) / kTT;
-  R += (R & 3) == 0 ? 1 : 0;
-  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  const int j0 = a0 + threadIdx.x * R;
-  // row j's equation a M_{j-1} + b M_j + c M_{j+1} = r
-  auto row = [&](int j, double& a, double& b, double& c, double& r) {
-    const double tm = T(j - 1), t0 = T(j), tp = T(j + 1);
-    a = t0 - tm;
-    c = tp - t0;
-    b = 2.0 * (a + c);
-    r = 6.0 * ((Y(j + 1) - Y(j)) * recip(c) - (Y(j) - Y(j - 1)) * recip(a));
-  };
-  FwdMap G = fwd_identity();
-#pragma unroll
-  for (int q = 0; q < kRMax; ++q) {
-    const int j = j0 + q;
-    if (q < R && j <= a1) {
-      double a, b, c, r;
-      row(j, a, b, c, r);
-      G = fwd_row_after(a, b, c, r, G);
-      if ((q & 3) == 3) fwd_normalize(G);
+  // this workgroup's blocks: bv.z, bv.z + G, ... (G = bv.w workgroups per
+  // envelope)
+  const int nbt = solve_blocks(S.cap), G = max(bv.w, 1);
+  for (int blk = bv.z; blk < nbt; blk += G) {
+    const int r0 = 1 + blk * kSB;
+    if (n2 < 3 || r0 > n2 - 2) break;
+    if (blk != bv.z) __syncthreads();  // the previous block is done with the LDS
+    const int r1 = min(r0 + kSB, n2 - 1);  // rows r0 .. r1-1
+    const int a0 = max(1, r0 - kHalo), a1 = min(n2 - 2, r1 - 1 + kHalo);
+    const int w0 = a0 - 1, w1 = a1 + 1;    // knots read
+    const int32_t* kt = S.kt[env];
+    const double* ky = S.ky[env];
+    for (int i = threadIdx.x; i <= w1 - w0; i += kTT) {
+      lt[i] = kt[w0 + i];
+      ly[i] = ky[w0 + i];
     }
-  }
-  fwd_normalize(G);
-  G = fwd_wave_scan(G);
-  if (lane == kWave - 1) {
-    double* o = fwd_lds + kFwdStride * wid;
-    o[0] = G.a00; o[1] = G.a01; o[2] = G.a10; o[3] = G.a11;
-    o[4] = G.v0; o[5] = G.v1; o[6] = G.s;
-  }
-  __syncthreads();
-  double cpa[kRMax], dpa[kRMax];
-  {
-    double Q, P, D;
-    fwd_enter(fwd_lds, wid, Q, P, D);
-    const FwdMap Y1 = fwd_dpp<kDppWaveShr1, 0xf>(G);
-    if (lane > 0) {
-      fwd_apply(Y1, Q, P, D);
-      vec_normalize(Q, P, D);
-    }
-#pragma unroll
+    __syncthreads();
+  #define T(j) ((double)lt[(j) - w0])
+  #define Y(j) (ly[(j) - w0])
+    const int rows = a1 - a0 + 1;
+    // (<= kRMax; a multiple of 4 is raised by one: row blocks whose starts
+    // lie a multiple of 8 doubles apart would share LDS banks 4 ways or more)
+    int R = (rows + kTT - 1) / kTT;
+    R += (R & 3) == 0 ? 1 : 0;
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int j0 = a0 + threadIdx.x * R;
+    // row j's equation a M_{j-1} + b M_j + c M_{j+1} = r
+    auto row = [&](int j, double& a, double& b, double& c, double& r) {
+      const double tm = T(j - 1), t0 = T(j), tp = T(j + 1);
+      a = t0 - tm;
+      c = tp - t0;
+      b = 2.0 * (a + c);
+      r = 6.0 * ((Y(j + 1) - Y(j)) * recip(c) - (Y(j) - Y(j - 1)) * recip(a));
+    };
+    FwdMap G = fwd_identity();
+  #pragma unroll
     for (int q = 0; q < kRMax; ++q) {
-      cpa[q] = 0.0;
-      dpa[q] = 0.0;
       const int j = j0 + q;
       if (q < R && j <= a1) {
         double a, b, c, r;
         row(j, a, b, c, r);
-        const double qn = fma(b, Q, -a * P);
-        D = fma(r, Q, -a * D);
-        P = c * Q;
-        Q = qn;
+        G = fwd_row_after(a, b, c, r, G);
+        if ((q & 3) == 3) fwd_normalize(G);
+      }
+    }
+    fwd_normalize(G);
+    G = fwd_wave_scan(G);
+    if (lane == kWave - 1) {
+      double* o = fwd_lds + kFwdStride * wid;
+      o[0] = G.a00; o[1] = G.a01; o[2] = G.a10; o[3] = G.a11;
+      o[4] = G.v0; o[5] = G.v1; o[6] = G.s;
+    }
+    __syncthreads();
+    double cpa[kRMax], dpa[kRMax];
+    {
+      double Q, P, D;
+      fwd_enter(fwd_lds, wid, Q, P, D);
+      const FwdMap Y1 = fwd_dpp<kDppWaveShr1, 0xf>(G);
+      if (lane > 0) {
+        fwd_apply(Y1, Q, P, D);
         vec_normalize(Q, P, D);
-        const double iq = recip(Q);
-        cpa[q] = P * iq;
-        dpa[q] = D * iq;
+      }
+  #pragma unroll
+      for (int q = 0; q < kRMax; ++q) {
+        cpa[q] = 0.0;
+        dpa[q] = 0.0;
+        const int j = j0 + q;
+        if (q < R && j <= a1) {
+          double a, b, c, r;
+          row(j, a, b, c, r);
+          const double qn = fma(b, Q, -a * P);
+          D = fma(r, Q, -a * D);
+          P = c * Q;
+          Q = qn;
+          vec_normalize(Q, P, D);
+          const double iq = recip(Q);
+          cpa[q] = P * iq;
+          dpa[q] = D * iq;
+        }
       }
     }
-  }
-  // back-substitution maps composed from the thread's last row down
-  double al = 0.0, be = 1.0;
-#pragma unroll
-  for (int q = kRMax - 1; q >= 0; --q) {
-    if (q < R && j0 + q <= a1) {
-      al = fma(-cpa[q], al, dpa[q]);
-      be = -cpa[q] * be;
-    }
-  }
-  bwd_wave_scan<false>(al, be, lane);  // (the fill raises this kernel's registers)
-  if (lane == 0) {
-    bwd_lds[2 * wid] = al;
-    bwd_lds[2 * wid + 1] = be;
-  }
-  __syncthreads();
-  double Mn = bwd_after(bwd_lds, wid, kNW);
-  {
-    const double a2 = dpp_move<kDppWaveShl1, 0xf>(al), b2 = dpp_move<kDppWaveShl1, 0xf>(be);
-    if (lane + 1 < kWave) Mn = fma(b2, Mn, a2);
-  }
-  double* km = S.km[env];
-#pragma unroll
-  for (int q = kRMax - 1; q >= 0; --q) {
-    const int j = j0 + q;
-    if (q < R && j <= a1) {
-      const double Mj = fma(-cpa[q], Mn, dpa[q]);
-      if (j >= r0 && j < r1) {
-        km[j] = Mj;
-        if (j == 1) km[0] = 0.0;            // natural end conditions
-        if (j == n2 - 2) km[n2 - 1] = 0.0;
+    // back-substitution maps composed from the thread's last row down
+    double al = 0.0, be = 1.0;
+  #pragma unroll
+    for (int q = kRMax - 1; q >= 0; --q) {
+      if (q < R && j0 + q <= a1) {
+        al = fma(-cpa[q], al, dpa[q]);
+        be = -cpa[q] * be;
       }
-      Mn = Mj;
+    }
+    bwd_wave_scan<false>(al, be, lane);  // (the fill raises this kernel's registers)
+    if (lane == 0) {
+      bwd_lds[2 * wid] = al;
+      bwd_lds[2 * wid + 1] = be;
+    }
+    __syncthreads();
+    double Mn = bwd_after(bwd_lds, wid, kNW);
+    {
+      const double a2 = dpp_move<kDppWaveShl1, 0xf>(al), b2 = dpp_move<kDppWaveShl1, 0xf>(be);
+      if (lane + 1 < kWave) Mn = fma(b2, Mn, a2);
+    }
+    double* km = S.km[env];
+  #pragma unroll
+    for (int q = kRMax - 1; q >= 0; --q) {
+      const int j = j0 + q;
+      if (q < R && j <= a1) {
+        const double Mj = fma(-cpa[q], Mn, dpa[q]);
+        if (j >= r0 && j < r1) {
+          km[j] = Mj;
+          if (j == 1) km[0] = 0.0;            // natural end conditions
+          if (j == n2 - 2) km[n2 - 1] = 0.0;
+        }
+        Mn = Mj;
+      }
     }
   }
 #undef T
@@ -1020,8 +1035,8 @@ __global__ void st_gather_done_kernel(const StreamSig* __restrict__ sigs, int n,
 }
 
 // The descriptor of one signal and its tables, as stream_tables() lays them
-// out for a one-signal batch: tiles[t] = (0, t) and blocks[e * nb + b] =
-// (0, e, b) for the envelopes e = 0, 1 and their solve blocks b < nb.
+// out for a one-signal batch: tiles[t] = (0, t) and blocks[e * nb + z] =
+// (0, e, z, nb) for the envelopes e = 0, 1 and their solve workgroups z < nb.
 __global__ void st_put_single_kernel(StreamSig g, StreamSig* __restrict__ dsig,
                                      int2* __restrict__ tiles, int ntiles,
                                      int4* __restrict__ blocks, int nb) {
@@ -1034,7 +1049,7 @@ __global__ void st_put_single_kernel(StreamSig g, StreamSig* __restrict__ dsig,
     g.trace[3] = 0;
   }
   if (i < ntiles) tiles[i] = make_int2(0, i);
-  if (i < 2 * nb) blocks[i] = make_int4(0, i / nb, i - (i / nb) * nb, 0);
+  if (i < 2 * nb) blocks[i] = make_int4(0, i / nb, i - (i / nb) * nb, nb);
 }
 
 inline dim3 per_signal(int n) { return dim3((n + 255) / 256); }
@@ -1072,7 +1087,7 @@ hipError_t st_step(const StreamSig* sigs, int nsig, const int2* tiles, int ntile
 }
 hipError_t st_put_single(const StreamSig& g, StreamSig* dsig, int2* tiles, int4* blocks,
                          hipStream_t s) {
-  const int nb = stream_solve_blocks(g.cap);
+  const int nb = stream_solve_groups(g.cap, stream_solve_fold(2 * stream_solve_blocks(g.cap)));
   const int n = g.ntiles > 2 * nb ? g.ntiles : (2 * nb > 1 ? 2 * nb : 1);
   hipLaunchKernelGGL(st_put_single_kernel, dim3((n + 255) / 256), dim3(256), 0, s, g, dsig,
                      tiles, g.ntiles, blocks, nb);
@@ -1084,6 +1099,14 @@ hipError_t st_gather_done(const StreamSig* sigs, int nsig, int32_t* done, hipStr
   return hipGetLastError();
 }
 
-int stream_solve_blocks(int cap) { return (cap + kSB - 1) / kSB; }
+int stream_solve_blocks(int cap) { return solve_blocks(cap); }
+
+int stream_solve_fold(int64_t total_blocks) {
+  return (int)std::min<int64_t>(kSolveFoldMax, std::max<int64_t>(1, total_blocks / kSolveTarget));
+}
+
+int stream_solve_groups(int cap, int fold) {
+  return (stream_solve_blocks(cap) + fold - 1) / fold;
+}
 
 }  // namespace semd
