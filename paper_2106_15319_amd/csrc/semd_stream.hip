@@ -42,6 +42,10 @@ constexpr int kSB = 2048;             // interior rows per solve block
 constexpr int kSolveTarget = 4096;
 constexpr int kSolveFoldMax = 32;
 __host__ __device__ constexpr int solve_blocks(int cap) { return (cap + kSB - 1) / kSB; }
+// Units (blocks, tiles) per workgroup of a folded launch over `units`.
+inline int launch_fold(int64_t units) {
+  return (int)std::min<int64_t>(kSolveFoldMax, std::max<int64_t>(1, units / kSolveTarget));
+}
 constexpr int kNW = kTT / kWave;
 constexpr int kCompactThreads = kWave;  // threads per compaction workgroup (one tile)
 
@@ -379,21 +383,10 @@ __global__ void __launch_bounds__(kTT) st_load_kernel(const StreamSig* __restric
   }
 }
 
-// Extremum counts of a tile whose candidate the previous step did not
-// detect (a fresh signal, or a new IMF's first candidate h = r; a sift step
-// detects its result itself).  The tile's first run may have started in an
-// earlier tile (kind kCont); its extremum, if any, is resolved by the scan.
-__global__ void __launch_bounds__(kTT) st_detect_kernel(const StreamSig* __restrict__ sigs,
-                                                        const int2* __restrict__ tiles) {
-  __shared__ double tbuf[kTile];
-  __shared__ int pub_key[kTT];
-  __shared__ int scratch[kNW];
-  __shared__ int64_t scratch64[kNW];
-  __shared__ int cont_exit, cont_pos;
-  __shared__ double cont_y;
-  const int2 tv = tiles[blockIdx.x];
-  const StreamSig& S = sigs[tv.x];
-  if (!S.st->active || S.st->action == kSift) return;
+// Extremum detection of one tile (st_detect_kernel's work per tile).
+__device__ __forceinline__ void detect_tile(const StreamSig& S, int2 tv, double* tbuf,
+                                            int* pub_key, int* scratch, int64_t* scratch64,
+                                            int& cont_exit, int& cont_pos, double& cont_y) {
   const int L = S.L;
   const int a = tv.y * kTile, n = min(kTile, L - a);
   double prev, next;
@@ -414,6 +407,47 @@ __global__ void __launch_bounds__(kTT) st_detect_kernel(const StreamSig* __restr
   __syncthreads();
   record_tile(d, h, a, first_key, cont_exit, cont_pos, cont_y, S, tv.y, scratch64, scratch,
               tbuf);
+}
+
+// Extremum counts of a tile whose candidate the previous step did not
+// detect (a fresh signal, or a new IMF's first candidate h = r; a sift step
+// detects its result itself).  The tile's first run may have started in an
+// earlier tile (kind kCont); its extremum, if any, is resolved by the scan.
+// Most steps are sift steps, in which no tile needs this.  The launch is
+// folded (launch_fold): workgroup b takes the table entries b, b + G, ...
+// (G = gridDim.x, at most kSolveFoldMax of them), tests all their statuses
+// at once, one lane each, and detects only the tiles that need it, so a
+// step without detections costs one round of status reads per workgroup.
+__global__ void __launch_bounds__(kTT) st_detect_kernel(const StreamSig* __restrict__ sigs,
+                                                        const int2* __restrict__ tiles,
+                                                        int ntiles) {
+  static_assert(kSolveFoldMax <= kWave, "one lane of the first wave per folded entry");
+  __shared__ double tbuf[kTile];
+  __shared__ int pub_key[kTT];
+  __shared__ int scratch[kNW];
+  __shared__ int64_t scratch64[kNW];
+  __shared__ int cont_exit, cont_pos;
+  __shared__ double cont_y;
+  __shared__ unsigned long long need_mask;
+  if (threadIdx.x < kWave) {
+    const int64_t ti = blockIdx.x + (int64_t)threadIdx.x * gridDim.x;
+    bool need = false;
+    if (threadIdx.x < kSolveFoldMax && ti < ntiles) {
+      const global_ptr<const SigStatus> st = gmem<const SigStatus>(sigs[tiles[ti].x].st);
+      need = st->active && st->action != kSift;
+    }
+    const unsigned long long m = __ballot(need);
+    if (threadIdx.x == 0) need_mask = m;
+  }
+  __syncthreads();
+  unsigned long long m = need_mask;
+  while (m) {
+    const int k = __ffsll((long long)m) - 1;
+    m &= m - 1;
+    const int2 tv = tiles[blockIdx.x + (int64_t)k * gridDim.x];
+    detect_tile(sigs[tv.x], tv, tbuf, pub_key, scratch, scratch64, cont_exit, cont_pos, cont_y);
+    if (m) __syncthreads();  // this tile is done with the LDS
+  }
 }
 
 // Ends the current IMF (its candidate is stored by the evaluation); reaching
@@ -1071,7 +1105,9 @@ hipError_t st_step(const StreamSig* sigs, int nsig, const int2* tiles, int ntile
   if (nsig <= 0) return hipSuccess;
   auto mark = [&](int i) { if (marks) (void)hipEventRecord(marks[i], st); };
   mark(0);
-  hipLaunchKernelGGL(st_detect_kernel, dim3(ntiles), dim3(kTT), 0, st, sigs, tiles);
+  const int dfold = launch_fold(ntiles);
+  hipLaunchKernelGGL(st_detect_kernel, dim3((ntiles + dfold - 1) / dfold), dim3(kTT), 0, st,
+                     sigs, tiles, ntiles);
   mark(1);
   hipLaunchKernelGGL(st_scan_kernel, dim3(nsig), dim3(kTT), 0, st, sigs);
   if (trace) hipLaunchKernelGGL(st_trace_kernel, dim3(ntiles), dim3(kTT), 0, st, sigs, tiles);
@@ -1101,9 +1137,7 @@ hipError_t st_gather_done(const StreamSig* sigs, int nsig, int32_t* done, hipStr
 
 int stream_solve_blocks(int cap) { return solve_blocks(cap); }
 
-int stream_solve_fold(int64_t total_blocks) {
-  return (int)std::min<int64_t>(kSolveFoldMax, std::max<int64_t>(1, total_blocks / kSolveTarget));
-}
+int stream_solve_fold(int64_t total_blocks) { return launch_fold(total_blocks); }
 
 int stream_solve_groups(int cap, int fold) {
   return (stream_solve_blocks(cap) + fold - 1) / fold;
