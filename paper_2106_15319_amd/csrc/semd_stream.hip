@@ -821,14 +821,11 @@ __global__ void __launch_bounds__(kTT) st_solve_kernel(const StreamSig* __restri
 //   y_j + b_j B + (m_j / 2) B^2 + ((m_{j+1} - m_j) / (6 g)) B^3,
 //   b_j = (y_{j+1} - y_j) / g - g (2 m_j + m_{j+1}) / 6,
 // and the walker evaluates half of it (the envelope mean is the sum of two
-// halves).
-//
-// The knot after the right one, (t2, y2, m2), is loaded one crossing ahead,
-// so a crossing computes from registers and its loads complete while the
-// walker moves on.
+// halves).  (Waves whose segments fit one per lane take the wave-shared walk
+// in st_eval_kernel instead; this walker serves the denser ones.)
 struct StWalk {
-  int j, t1, t2;
-  double y1, m1, y2, m2, B, q0, q1, q2, q3;
+  int j, t1;
+  double y1, m1, B, q0, q1, q2, q3;
 };
 
 // One envelope's knots (positions, values, second derivatives) in global
@@ -859,28 +856,55 @@ __device__ __forceinline__ void st_walk_coefs(StWalk& w, int j, int t0, double y
 }
 
 // Knot i (clamped to the last one) into the walker's look-ahead registers.
-__device__ __forceinline__ void st_walk_ahead(StWalk& w, const KnotView& K, int i) {
-  i = min(i, K.last);
-  w.t2 = K.t[i];
-  w.y2 = K.y[i];
-  w.m2 = K.m[i];
-}
 
-// Position at the segment holding sample k from segment j (whose left knot
-// lies at or before k; the last knot lies beyond the signal).
-__device__ __forceinline__ void st_walk_init(StWalk& w, const KnotView& K, int j, int k) {
-  int t0 = K.t[j], t1 = K.t[j + 1];
+
+// The segment holding sample k, searched forward from segment j (whose left
+// knot lies at or before k; the last knot lies beyond the signal), and its
+// left knot's position t0.
+__device__ __forceinline__ int st_walk_find(const KnotView& K, int j, int k, int& t0) {
+  t0 = K.t[j];
+  int t1 = K.t[j + 1];
   while (t1 <= k) {
     ++j;
     t0 = t1;
     t1 = K.t[j + 1];
   }
-  w.t1 = t1;
+  return j;
+}
+
+// A walker on segment j, at sample k.
+__device__ __forceinline__ void st_walk_init(StWalk& w, const KnotView& K, int j, int k) {
+  const int t0 = K.t[j];
+  w.t1 = K.t[j + 1];
   w.y1 = K.y[j + 1];
   w.m1 = K.m[j + 1];
-  st_walk_ahead(w, K, j + 2);
   st_walk_coefs(w, j, t0, K.y[j], K.m[j]);
   w.B = (double)(k - t0);
+}
+
+// A segment's halved power-form coefficients and its right knot's
+// position, as one lane of a wave holds them for the others (the
+// wave-shared walk).
+struct SegCoefs {
+  double q0, q1, q2, q3;
+  int t1;
+};
+
+// Segment j's coefficients, formed as a walker forms them at a crossing.
+__device__ __forceinline__ SegCoefs seg_coefs(const KnotView& K, int j) {
+  StWalk w;
+  const int t0 = K.t[j];
+  w.t1 = K.t[j + 1];
+  w.y1 = K.y[j + 1];
+  w.m1 = K.m[j + 1];
+  st_walk_coefs(w, j, t0, K.y[j], K.m[j]);
+  return {w.q0, w.q1, w.q2, w.q3, w.t1};
+}
+
+// Lane `src`'s segment (every lane of the wave active).
+__device__ __forceinline__ SegCoefs seg_from_lane(const SegCoefs& own, int src) {
+  return {__shfl(own.q0, src), __shfl(own.q1, src), __shfl(own.q2, src), __shfl(own.q3, src),
+          __shfl(own.t1, src)};
 }
 
 // Half the envelope at sample k (one step from k-1 crosses at most one knot).
@@ -889,11 +913,10 @@ __device__ __forceinline__ double st_walk_at(StWalk& w, const KnotView& K, int k
     const int t0 = w.t1;
     const double y0 = w.y1, m0 = w.m1;
     w.B = (double)(k - t0);
-    w.t1 = w.t2;
-    w.y1 = w.y2;
-    w.m1 = w.m2;
+    w.t1 = K.t[w.j + 2];
+    w.y1 = K.y[w.j + 2];
+    w.m1 = K.m[w.j + 2];
     st_walk_coefs(w, w.j + 1, t0, y0, m0);
-    st_walk_ahead(w, K, w.j + 2);
   }
   return fma(fma(fma(w.q3, w.B, w.q2), w.B, w.q1), w.B, w.q0);
 }
@@ -935,8 +958,11 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
     const int k0 = a + lb;
     // thread 0 starts one sample early for the previous tile's last sample
     const int ks = (threadIdx.x == 0 && a > 0) ? k0 - 1 : k0;
-    StWalk wk[2];
     const KnotView kv[2] = {knot_view(S, 0, st->n[0]), knot_view(S, 1, st->n[1])};
+    // the thread holding the tile's last sample continues to the next
+    // tile's first sample
+    const bool tail = nv > 0 && lb + nv == n && a + n < L;
+    int js[2] = {0, 0}, jt0[2] = {0, 0};  // the segments holding sample ks, their left knots
     if (nv > 0) {
       const global_ptr<const int32_t> tr =
           gmem<const int32_t>(S.trank) + 2 * ((int64_t)tv.y * kTT + threadIdx.x);
@@ -952,8 +978,78 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
         // the last knot of earlier threads lies before the thread's first
         // sample (and before sample a-1 for thread 0: it lies in an earlier
         // tile or is a mirrored knot)
-        st_walk_init(wk[e], kv[e], Pp + rank - 1, ks);
+        js[e] = st_walk_find(kv[e], Pp + rank - 1, ks, jt0[e]);
       }
+    }
+    if (threadIdx.x == 0) cont_exit = 0;
+    __syncthreads();
+    double num = 0.0, den = 0.0;  // the tile's sums for the SD criterion
+    // The wave-shared walk: when the segments the wave's samples fall in
+    // number at most 64 for each envelope, lane i forms the coefficients of
+    // the wave's i-th segment once, and a lane that crosses a knot takes its
+    // new segment from the lane holding it.  A wave runs the crossing code
+    // at a sample whenever any of its lanes crosses there; this way that
+    // code is a few lane exchanges instead of the coefficients' arithmetic.
+    // A lane's samples k0 .. k0+kTC (with the tail sample) hold at most 5
+    // knots of an envelope (knots of one envelope lie at least two samples
+    // apart).  The arithmetic is the walkers', value for value.
+    const unsigned long long live = __ballot(nv > 0);
+    const int hi = live ? 63 - __clzll((long long)live) : 0;
+    int J0[2];
+    bool shared = live != 0;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      J0[e] = __builtin_amdgcn_readfirstlane(js[e]);
+      const int jhi = __builtin_amdgcn_readlane(js[e], hi);
+      shared = shared && jhi + 5 - J0[e] <= kWave - 1;
+    }
+    if (shared) {
+      const int lane = threadIdx.x & (kWave - 1);
+      SegCoefs own[2], cur[2];
+      int sidx[2], t0[2];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        own[e] = seg_coefs(kv[e], min(J0[e] + lane, kv[e].last - 1));
+        sidx[e] = js[e] - J0[e];
+        cur[e] = seg_from_lane(own[e], sidx[e]);
+        t0[e] = jt0[e];
+      }
+      // positions c = -1 (thread 0's sample a-1), 0 .. nv-1 (the thread's
+      // samples), nv (the tail sample)
+#pragma unroll
+      for (int c = -1; c <= kTC; ++c) {
+        const int k = k0 + c;
+        const bool act = c < 0 ? ks < k0 : (c < nv || (c == nv && tail));
+        double m = 0.0;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const bool cross = act && cur[e].t1 <= k;
+          if (__any(cross)) {
+            if (cross) t0[e] = cur[e].t1;  // the new segment starts at the old one's end
+            sidx[e] += cross ? 1 : 0;
+            cur[e] = seg_from_lane(own[e], sidx[e]);
+          }
+          const double B = (double)(k - t0[e]);
+          const double v = fma(fma(fma(cur[e].q3, B, cur[e].q2), B, cur[e].q1), B, cur[e].q0);
+          m = e == 0 ? v : m + v;
+        }
+        if (act) {
+          if (c < 0) {
+            halo[0] = gmem(S.edge)[2 * tv.y - 1] - m;
+          } else if (c < nv) {
+            const double hk = tbuf[tsw(lb + c)];
+            num = fma(m, m, num);
+            den = fma(hk, hk, den);
+            tbuf[tsw(lb + c)] = hk - m;
+          } else {
+            halo[1] = gmem(S.edge)[2 * tv.y + 2] - m;
+          }
+        }
+      }
+    } else if (nv > 0) {
+      StWalk wk[2];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) st_walk_init(wk[e], kv[e], js[e], ks);
       if (ks < k0) {
         const double up = st_walk_at(wk[0], kv[0], ks);
         const double lo = st_walk_at(wk[1], kv[1], ks);
@@ -961,11 +1057,6 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
         wk[0].B += 1.0;
         wk[1].B += 1.0;
       }
-    }
-    if (threadIdx.x == 0) cont_exit = 0;
-    __syncthreads();
-    double num = 0.0, den = 0.0;  // the tile's sums for the SD criterion
-    if (nv > 0) {
 #pragma unroll
       for (int c = 0; c < kTC; ++c) {
         if (c < nv) {
@@ -980,9 +1071,7 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
           wk[1].B += 1.0;
         }
       }
-      // the thread holding the tile's last sample continues to the next
-      // tile's first sample
-      if (lb + nv == n && a + n < L) {
+      if (tail) {
         const int k = a + n;
         const double up = st_walk_at(wk[0], kv[0], k);
         const double lo = st_walk_at(wk[1], kv[1], k);
