@@ -612,29 +612,50 @@ __global__ void __launch_bounds__(kCompactThreads) st_compact_kernel(
     const StreamSig* __restrict__ sigs, const int2* __restrict__ tiles) {
   const int2 tv = tiles[blockIdx.x];
   const StreamSig& S = sigs[tv.x];
-  const global_ptr<const SigStatus> st = gmem<const SigStatus>(S.st);
-  if (!sifting(*st)) return;
   const int L = S.L;
   const int a = tv.y * kTile, n = min(kTile, L - a);
-  const auto& ti = gmem<const TileInfo>(S.tinfo)[tv.y];
-  if (threadIdx.x == 0) {
-    const global_ptr<const double> hg = gmem<const double>(S.h);
-    gmem(S.edge)[2 * tv.y] = hg[a];
-    gmem(S.edge)[2 * tv.y + 1] = hg[a + n - 1];
-  }
   const int64_t lo = (int64_t)tv.y * kTileKnots;
+  // The status, the tile's counts and ranks, the first list entries and the
+  // edge samples are read together, before the status decides whether the
+  // tile has work: a chain of dependent reads is what a launch over every
+  // tile of a batch waits on.  (All of them lie in the signal's buffers
+  // whatever the step.)
+  const global_ptr<const SigStatus> st = gmem<const SigStatus>(S.st);
+  const auto& ti = gmem<const TileInfo>(S.tinfo)[tv.y];
+  const int action = st->action, nk[2] = {st->n[0], st->n[1]};
+  const int cnt[2] = {ti.cnt[0], ti.cnt[1]}, off[2] = {ti.off[0], ti.off[1]};
+  const int cont_knot = ti.cont_knot;
+  int p0[2];
+  double v0[2];
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
-    const int nk = st->n[e];
-    const int ck = (ti.cont_knot >> e) & 1;
+    p0[e] = gmem<const int32_t>(S.lpos[e])[lo + threadIdx.x];
+    v0[e] = gmem<const double>(S.lval[e])[lo + threadIdx.x];
+  }
+  double ea = 0.0, eb = 0.0;
+  if (threadIdx.x == 0) {
+    const global_ptr<const double> hg = gmem<const double>(S.h);
+    ea = hg[a];
+    eb = hg[a + n - 1];
+  }
+  asm volatile("" ::"v"(p0[0]), "v"(p0[1]), "v"(v0[0]), "v"(v0[1]), "v"(ea), "v"(eb));
+  if (action != kSift && action != kSiftLast) return;
+  if (threadIdx.x == 0) {
+    gmem(S.edge)[2 * tv.y] = ea;
+    gmem(S.edge)[2 * tv.y + 1] = eb;
+  }
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int ck = (cont_knot >> e) & 1;
     const global_ptr<int32_t> kt = gmem(S.kt[e]);
     const global_ptr<double> ky = gmem(S.ky[e]);
     if (ck && threadIdx.x == 0)
-      put_knot(kt, ky, ti.off[e], nk, L, ((ti.carry >> 2) + ti.cont_pos) >> 1, ti.cont_y);
+      put_knot(kt, ky, off[e], nk[e], L, ((ti.carry >> 2) + ti.cont_pos) >> 1, ti.cont_y);
+    if ((int)threadIdx.x < cnt[e]) put_knot(kt, ky, off[e] + ck + threadIdx.x, nk[e], L, p0[e], v0[e]);
     const global_ptr<const int32_t> lp = gmem<const int32_t>(S.lpos[e]) + lo;
     const global_ptr<const double> lv = gmem<const double>(S.lval[e]) + lo;
-    for (int i = threadIdx.x; i < ti.cnt[e]; i += kCompactThreads)
-      put_knot(kt, ky, ti.off[e] + ck + i, nk, L, lp[i], lv[i]);
+    for (int i = threadIdx.x + kCompactThreads; i < cnt[e]; i += kCompactThreads)
+      put_knot(kt, ky, off[e] + ck + i, nk[e], L, lp[i], lv[i]);
   }
 }
 
