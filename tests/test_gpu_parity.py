@@ -559,6 +559,40 @@ def test_stream_small_matches_oracle(M, N, D):
     tally.done()
 
 
+_WALK_KINDS = ["chirp", "noise", "burst"]
+_WALK_LENGTHS = [4097, 6143, 16385, 18433]
+
+
+def _walk_inputs(L: int, kind: str) -> np.ndarray:
+    """Inputs for the two forms of the streaming evaluation's walk: a wave
+    whose 512 samples fall in at most 64 segments of each envelope shares
+    its segments across lanes; denser waves walk per lane."""
+    t = np.arange(L, dtype=np.float64)
+    rng = workloads.rng_for(12, _WALK_LENGTHS.index(L) * 3 + _WALK_KINDS.index(kind))
+    if kind == "chirp":
+        # extremum spacing from ~L/8 down to 3 samples along the signal, so
+        # the per-wave segment count crosses 64 inside it
+        f = 1.0 / 2000.0 + (1.0 / 6.0 - 1.0 / 2000.0) * (t / L) ** 2
+        return np.sin(2.0 * np.pi * np.cumsum(f)) + 0.3 * np.sin(t / 97.0)
+    if kind == "noise":
+        return rng.standard_normal(L)
+    # smooth, with a white-noise burst inside one wave of the second tile
+    x = np.sin(t / 131.0) + 0.5 * np.sin(t / 17.0)
+    b0 = min(L - 1, 2048 + 700)
+    x[b0:b0 + 300] += rng.standard_normal(len(x[b0:b0 + 300]))
+    return x
+
+
+@pytest.mark.parametrize("L", _WALK_LENGTHS)
+@pytest.mark.parametrize("kind", _WALK_KINDS)
+def test_stream_walk_forms_match_oracle(L, kind):
+    x = _walk_inputs(L, kind)
+    out, n = semd.semd_decompose_ex(dev(x), [L, 1], 0, 6, 10, path=STREAM)
+    tally = Tally(f"streaming walk L={L} {kind}")
+    _check_item(x, L, 1, 0, 6, 10, host(out), int(host(n)[0]), tally, path=STREAM)
+    tally.done()
+
+
 def test_stream_faces_and_textures():
     items = workloads.config2(4) + workloads.config1(2)
     shapes = [(i.M, i.N) for i in items]
