@@ -297,6 +297,10 @@ void prof_collect() {
 constexpr int kPoolDevices = 64;
 std::mutex g_pool_dev_mu;
 hipMemPool_t g_mem_pool[kPoolDevices] = {};
+// The largest block each device's pool has handed out for a large
+// workspace (cleared when the pool is trimmed).
+size_t g_pool_big[kPoolDevices] = {};
+constexpr size_t kStickyMin = size_t(256) << 20;
 
 // The current device's pool, created on first use (nullptr: use the
 // device's default pool).
@@ -334,11 +338,23 @@ size_t available_device_bytes() {
   return free_b;
 }
 
+// A large workspace takes the size of the largest block the pool has handed
+// out when that is at most twice its own: consecutive calls of varying size
+// (the waves of a batch) then reuse one block in stream order, where each
+// larger size would have the pool map new memory, and the call wait for it.
 hipError_t dev_alloc(void** p, size_t bytes, hipStream_t s) {
   HostPhase hp(kHAlloc);
   hipMemPool_t pool = lib_pool();
-  if (pool) return hipMallocFromPoolAsync(p, bytes, pool, s);
-  return hipMallocAsync(p, bytes, s);
+  if (!pool) return hipMallocAsync(p, bytes, s);
+  int dev = 0;
+  if (bytes >= kStickyMin && hipGetDevice(&dev) == hipSuccess && dev >= 0 &&
+      dev < kPoolDevices) {
+    std::lock_guard<std::mutex> lock(g_pool_dev_mu);
+    size_t& big = g_pool_big[dev];
+    if (bytes <= big && big / 2 <= bytes) bytes = big;
+    else if (bytes > big) big = bytes;
+  }
+  return hipMallocFromPoolAsync(p, bytes, pool, s);
 }
 
 // Pinned staging blocks for host -> device descriptor uploads; a block is
@@ -1154,6 +1170,7 @@ int semd_release_cached_memory(void) {
   std::lock_guard<std::mutex> lock(g_pool_dev_mu);
   for (int d = 0; d < kPoolDevices; ++d) {
     if (!g_mem_pool[d]) continue;
+    g_pool_big[d] = 0;
     const hipError_t e = hipMemPoolTrimTo(g_mem_pool[d], 0);
     if (e != hipSuccess) return hip_fail(e, "hipMemPoolTrimTo");
   }
