@@ -347,14 +347,20 @@ hipError_t dev_alloc(void** p, size_t bytes, hipStream_t s) {
   hipMemPool_t pool = lib_pool();
   if (!pool) return hipMallocAsync(p, bytes, s);
   int dev = 0;
+  size_t take = bytes;
   if (bytes >= kStickyMin && hipGetDevice(&dev) == hipSuccess && dev >= 0 &&
       dev < kPoolDevices) {
     std::lock_guard<std::mutex> lock(g_pool_dev_mu);
     size_t& big = g_pool_big[dev];
-    if (bytes <= big && big / 2 <= bytes) bytes = big;
+    if (bytes <= big && big / 2 <= bytes) take = big;
     else if (bytes > big) big = bytes;
   }
-  return hipMallocFromPoolAsync(p, bytes, pool, s);
+  hipError_t e = hipMallocFromPoolAsync(p, take, pool, s);
+  if (e != hipSuccess && take > bytes) {
+    (void)hipGetLastError();  // the rounded size did not fit; the exact one may
+    e = hipMallocFromPoolAsync(p, bytes, pool, s);
+  }
+  return e;
 }
 
 // Pinned staging blocks for host -> device descriptor uploads; a block is
