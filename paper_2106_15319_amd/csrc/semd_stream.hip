@@ -699,8 +699,9 @@ __global__ void __launch_bounds__(kTT) st_trace_kernel(const StreamSig* __restri
 // m_j of its rows in r0..r1-1, and the zeros of the two end knots when it
 // holds row 1 or row n-2; the evaluation forms each segment's cubic from
 // the knots at its ends.
-__global__ void __launch_bounds__(kTT) st_solve_kernel(const StreamSig* __restrict__ sigs,
-                                                       const int4* __restrict__ blocks) {
+// (bounded to 128 VGPRs: four waves per SIMD)
+__global__ void __launch_bounds__(kTT, 4) st_solve_kernel(const StreamSig* __restrict__ sigs,
+                                                          const int4* __restrict__ blocks) {
   constexpr int kW = kSB + 2 * kHalo + 4;
   constexpr int kRMax = (kSB + 2 * kHalo + kTT - 1) / kTT;
   __shared__ int32_t lt[kW];
@@ -740,21 +741,28 @@ __global__ void __launch_bounds__(kTT) st_solve_kernel(const StreamSig* __restri
     R += (R & 3) == 0 ? 1 : 0;
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     const int j0 = a0 + threadIdx.x * R;
-    // row j's equation a M_{j-1} + b M_j + c M_{j+1} = r
-    auto row = [&](int j, double& a, double& b, double& c, double& r) {
+    // row j's equation a M_{j-1} + b M_j + c M_{j+1} = r; sl brings in the
+    // slope of segment j-1 and takes out that of segment j (a thread's
+    // consecutive rows share a segment's slope: one reciprocal per row)
+    auto row = [&](int j, double& sl, double& a, double& b, double& c, double& r) {
       const double tm = T(j - 1), t0 = T(j), tp = T(j + 1);
       a = t0 - tm;
       c = tp - t0;
       b = 2.0 * (a + c);
-      r = 6.0 * ((Y(j + 1) - Y(j)) * recip(c) - (Y(j) - Y(j - 1)) * recip(a));
+      const double sn = (Y(j + 1) - Y(j)) * recip(c);
+      r = 6.0 * (sn - sl);
+      sl = sn;
     };
+    // the slope of segment j-1, which enters row j
+    auto slope_into = [&](int j) { return (Y(j) - Y(j - 1)) * recip(T(j) - T(j - 1)); };
     FwdMap G = fwd_identity();
+    double sl = j0 <= a1 ? slope_into(j0) : 0.0;
   #pragma unroll
     for (int q = 0; q < kRMax; ++q) {
       const int j = j0 + q;
       if (q < R && j <= a1) {
         double a, b, c, r;
-        row(j, a, b, c, r);
+        row(j, sl, a, b, c, r);
         G = fwd_row_after(a, b, c, r, G);
         if ((q & 3) == 3) fwd_normalize(G);
       }
@@ -776,6 +784,7 @@ __global__ void __launch_bounds__(kTT) st_solve_kernel(const StreamSig* __restri
         fwd_apply(Y1, Q, P, D);
         vec_normalize(Q, P, D);
       }
+      double sl2 = j0 <= a1 ? slope_into(j0) : 0.0;
   #pragma unroll
       for (int q = 0; q < kRMax; ++q) {
         cpa[q] = 0.0;
@@ -783,7 +792,7 @@ __global__ void __launch_bounds__(kTT) st_solve_kernel(const StreamSig* __restri
         const int j = j0 + q;
         if (q < R && j <= a1) {
           double a, b, c, r;
-          row(j, a, b, c, r);
+          row(j, sl2, a, b, c, r);
           const double qn = fma(b, Q, -a * P);
           D = fma(r, Q, -a * D);
           P = c * Q;
