@@ -593,6 +593,41 @@ def test_stream_walk_forms_match_oracle(L, kind):
     tally.done()
 
 
+def _random_stream_case(i: int) -> np.ndarray:
+    """Seeded streaming inputs of random length and kind (noise, chirp,
+    stepped plateaus, sinusoid mixes, and sums of them)."""
+    rng = workloads.rng_for(13, i)
+    L = int(rng.integers(16385, 70000))
+    t = np.arange(L, dtype=np.float64)
+    kind = i % 4
+    if kind == 0:
+        x = rng.standard_normal(L)
+    elif kind == 1:
+        f = rng.uniform(1e-4, 1e-3) + rng.uniform(0.05, 0.2) * (t / L) ** rng.uniform(1, 3)
+        x = np.sin(2.0 * np.pi * np.cumsum(f))
+    elif kind == 2:
+        edges = np.sort(rng.integers(0, L, size=int(rng.integers(20, 200))))
+        x = np.zeros(L)
+        for e in edges:
+            x[e:] += rng.normal()
+        x += 0.1 * np.sin(t / rng.uniform(20, 400))
+    else:
+        x = sum(rng.uniform(0.3, 2.0) * np.sin(2 * np.pi * t * rng.uniform(1e-4, 0.2) +
+                                               rng.uniform(0, 2 * np.pi)) for _ in range(4))
+        x += 0.05 * rng.standard_normal(L)
+    return x
+
+
+@pytest.mark.parametrize("i", range(12))
+def test_stream_random_lengths_match_oracle(i):
+    x = _random_stream_case(i)
+    L = x.size
+    out, n = semd.semd_decompose_ex(dev(x), [L, 1], 0, 5, 6, path=STREAM)
+    tally = Tally(f"streaming random case {i} L={L}")
+    _check_item(x, L, 1, 0, 5, 6, host(out), int(host(n)[0]), tally, path=STREAM)
+    tally.done()
+
+
 def test_stream_faces_and_textures():
     items = workloads.config2(4) + workloads.config1(2)
     shapes = [(i.M, i.N) for i in items]
