@@ -569,7 +569,7 @@ size_t stream_bytes(int64_t L) {
   return 2 * al256(sizeof(double) * (size_t)L) +
          2 * (al256(sizeof(int32_t) * cap) + 2 * al256(sizeof(double) * cap)) +
          al256(sizeof(semd::TileInfo) * ntiles) + al256(sizeof(double) * 2 * ntiles) +
-         al256(sizeof(int32_t) * 2 * semd::kTileThreads * ntiles) +
+         al256(sizeof(int32_t) * semd::kTileThreads * ntiles) +
          2 * (al256(sizeof(int32_t) * semd::kTileKnots * ntiles) +
               al256(sizeof(double) * semd::kTileKnots * ntiles)) +
          al256(sizeof(semd::SigStatus));
@@ -612,7 +612,7 @@ semd::StreamSig stream_sig(const semd::WorkItem& w, int K, int S, unsigned char*
   g.tinfo = reinterpret_cast<semd::TileInfo*>(take(sizeof(semd::TileInfo) * (size_t)g.ntiles));
   g.edge = reinterpret_cast<double*>(take(sizeof(double) * 2 * (size_t)g.ntiles));
   g.trank = reinterpret_cast<int32_t*>(
-      take(sizeof(int32_t) * 2 * semd::kTileThreads * (size_t)g.ntiles));
+      take(sizeof(int32_t) * semd::kTileThreads * (size_t)g.ntiles));
   for (int e = 0; e < 2; ++e) {
     g.lpos[e] = reinterpret_cast<int32_t*>(
         take(sizeof(int32_t) * semd::kTileKnots * (size_t)g.ntiles));
@@ -699,6 +699,8 @@ int run_stream(const std::vector<semd::WorkItem>& work, int K, int S, hipStream_
   const auto* d_tiles = reinterpret_cast<const int2*>(dp + o_til);
   const auto* d_blocks = reinterpret_cast<const int4*>(dp + o_blk);
   const int nt = (int)tiles.size(), nb = (int)blocks.size();
+  bool any_sd = false;
+  for (const auto& w : work) any_sd |= w.sd > 0.0;
   // every signal finishes within K*S steps (each step sifts it or ends an
   // IMF): the step is captured once and replayed K*S times
   sweep_retired_graphs();
@@ -717,7 +719,7 @@ int run_stream(const std::vector<semd::WorkItem>& work, int K, int S, hipStream_
     }
     for (int step = 0; step < K * S && e == hipSuccess; ++step) {
       timed = prof_events(ev, 6);
-      e = semd::st_step(d_sigs, n, d_tiles, nt, d_blocks, nb, cs.s, false,
+      e = semd::st_step(d_sigs, n, d_tiles, nt, d_blocks, nb, cs.s, any_sd, false,
                         timed ? ev : nullptr);
       if (timed)
         for (int k = 0; k < 5; ++k) prof_span(kPDetect + k, ev[k], ev[k + 1]);
@@ -735,7 +737,7 @@ int run_stream(const std::vector<semd::WorkItem>& work, int K, int S, hipStream_
     StepGraph g;
     if (e == hipSuccess)
       e = g.capture(cs.s, [&](hipStream_t s) {
-        return semd::st_step(d_sigs, n, d_tiles, nt, d_blocks, nb, s);
+        return semd::st_step(d_sigs, n, d_tiles, nt, d_blocks, nb, s, any_sd);
       });
     for (int step = 0; step < K * S && e == hipSuccess; ++step) e = g.launch(cs.s);
     g.retire(cs.s);
@@ -849,7 +851,7 @@ int run_single(semd::WorkItem w, int K, int S, int path, unsigned char* ws, hipS
   if (e == hipSuccess) e = semd::st_load(d_sig, d_tiles, lay.ntiles, stream);
   // every signal finishes within K*S steps (each step sifts it or ends an IMF)
   for (int step = 0; step < K * S && e == hipSuccess; ++step)
-    e = semd::st_step(d_sig, 1, d_tiles, lay.ntiles, d_blocks, lay.nblocks, stream,
+    e = semd::st_step(d_sig, 1, d_tiles, lay.ntiles, d_blocks, lay.nblocks, stream, w.sd > 0.0,
                       w.trace != nullptr);
   return e == hipSuccess ? SEMD_OK : hip_fail(e, "streaming kernel launch");
 }
@@ -1892,9 +1894,12 @@ int semd_engine_step(semd_engine* e, hipStream_t stream) {
     if (he == hipSuccess && !e->graph_ok) {
       const int nt = e->n_tiles, nb = e->n_blocks;
       int32_t* d_done = e->d_done;
+      bool any_sd = false;
+      for (const auto* r : sreqs) any_sd |= r->sig.sd > 0.0;
       he = e->graph.capture(cs.s, [&](hipStream_t s) {
         hipError_t le = semd::st_step(d_sigs, n, reinterpret_cast<const int2*>(dp + e->o_til),
-                                      nt, reinterpret_cast<const int4*>(dp + e->o_blk), nb, s);
+                                      nt, reinterpret_cast<const int4*>(dp + e->o_blk), nb, s,
+                                      any_sd);
         if (le == hipSuccess) le = semd::st_gather_done(d_sigs, n, d_done, s);
         return le;
       });

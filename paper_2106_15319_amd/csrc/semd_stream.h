@@ -87,8 +87,9 @@ struct StreamSig {
   int32_t pad;
   TileInfo* tinfo;  // ntiles
   double* edge;     // ntiles x 2: a tile's first and last sample before the sift
-  int32_t* trank;   // ntiles x kTileThreads x 2: knots of each kind the tile's
-                    // earlier threads hold (ranks within the tile)
+  int32_t* trank;   // ntiles x kTileThreads: knots of each kind the tile's earlier
+                    // threads hold (ranks within the tile; maxima in the low 16 bits,
+                    // minima in the high 16)
   int32_t* lpos[2]; // ntiles x kTileKnots: the tile's knots at tile-local ranks
   double* lval[2];  //   (positions and values), written by detection
   SigStatus* st;
@@ -102,11 +103,12 @@ struct StreamSig {
 hipError_t st_load(const StreamSig* sigs, const int2* tiles, int ntiles, hipStream_t s);
 // One step of every listed signal: detect, scan (decides the step's action),
 // compact and solve (sifting signals), eval (sift, IMF end, final outputs).
+// sd: some signal uses the SD stopping rule (its sums are accumulated).
 // trace: also record each detection of the signals that carry a trace.
 // marks (6 events, or nullptr): recorded before the step and after each of
 // its detect, scan, compact, solve and eval launches, for kernel timing.
 hipError_t st_step(const StreamSig* sigs, int nsig, const int2* tiles, int ntiles,
-                   const int4* blocks, int nblocks, hipStream_t s, bool trace = false,
+                   const int4* blocks, int nblocks, hipStream_t s, bool sd, bool trace = false,
                    const hipEvent_t* marks = nullptr);
 // The descriptor of the one signal g and its tile and solve-block tables
 // (g.ntiles entries, and two per solve workgroup: stream_solve_groups(g.cap,

@@ -294,11 +294,12 @@ __device__ __forceinline__ void record_tile(const TileDet& d, const double (&h)[
       ((int64_t)__popc(d.maxbits) << 32) | (uint32_t)__popc(d.minbits), scratch64, tot);
   const int g0[2] = {(int)(ex >> 32), (int)(ex & 0xffffffff)};
   const int cnt[2] = {(int)(tot >> 32), (int)(tot & 0xffffffff)};
-  const global_ptr<int32_t> tr = gmem(S.trank) + 2 * ((int64_t)tile * kTT + threadIdx.x);
-  tr[0] = g0[0];
-  tr[1] = g0[1];
+  // (tile-local ranks are below 2^16: maxima in the low half, minima high)
+  gmem(S.trank)[(int64_t)tile * kTT + threadIdx.x] = (int32_t)((uint32_t)g0[0] |
+                                                               ((uint32_t)g0[1] << 16));
   const int base = a + threadIdx.x * kTC;
   const int64_t lo = (int64_t)tile * kTileKnots;
+  static_assert(kTileKnots < (1 << 16), "tile-local ranks fit 16 bits");
   static_assert(kTileKnots * (sizeof(double) + sizeof(int32_t)) <= kTile * sizeof(double),
                 "one kind's knot list fits the staging area");
   double* sval = stage;
@@ -963,6 +964,11 @@ __device__ __forceinline__ double st_walk_at(StWalk& w, const KnotView& K, int k
 //                     (deserialized, Sec. 3.3), r <- r - h, h <- r;
 //   final             residue into slot K, unused IMF slots zero (Sec. 4.3),
 //                     IMF count and statistics.
+//
+// SD: some signal of the launch stops its IMFs by the SD rule, whose sums
+// the sift accumulates; the instance without them holds fewer registers
+// through the walk.
+template <bool SD>
 __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restrict__ sigs,
                                                       const int2* __restrict__ tiles) {
   __shared__ double tbuf[kTile];
@@ -994,8 +1000,8 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
     const bool tail = nv > 0 && lb + nv == n && a + n < L;
     int js[2] = {0, 0}, jt0[2] = {0, 0};  // the segments holding sample ks, their left knots
     if (nv > 0) {
-      const global_ptr<const int32_t> tr =
-          gmem<const int32_t>(S.trank) + 2 * ((int64_t)tv.y * kTT + threadIdx.x);
+      const uint32_t tr =
+          (uint32_t)gmem<const int32_t>(S.trank)[(int64_t)tv.y * kTT + threadIdx.x];
       const auto& ti = gmem<const TileInfo>(S.tinfo)[tv.y];
       // the continued run's extremum precedes this thread's knots when the
       // run ends in an earlier thread of the tile
@@ -1004,7 +1010,8 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
       for (int e = 0; e < 2; ++e) {
         const int nk = st->n[e];
         const int Pp = nk < 2 ? nk : 2;
-        const int rank = ti.off[e] + (cont_before ? ((ti.cont_knot >> e) & 1) : 0) + tr[e];
+        const int rank = ti.off[e] + (cont_before ? ((ti.cont_knot >> e) & 1) : 0) +
+                         (int)(e ? tr >> 16 : tr & 0xffffu);
         // the last knot of earlier threads lies before the thread's first
         // sample (and before sample a-1 for thread 0: it lies in an earlier
         // tile or is a mirrored knot)
@@ -1025,13 +1032,13 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
     // apart).  The arithmetic is the walkers', value for value.
     const unsigned long long live = __ballot(nv > 0);
     const int hi = live ? 63 - __clzll((long long)live) : 0;
-    int J0[2];
+    int J0[2], Jn[2];  // the wave's segments: J0 .. J0 + Jn - 1
     bool shared = live != 0;
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       J0[e] = __builtin_amdgcn_readfirstlane(js[e]);
-      const int jhi = __builtin_amdgcn_readlane(js[e], hi);
-      shared = shared && jhi + 5 - J0[e] <= kWave - 1;
+      Jn[e] = __builtin_amdgcn_readlane(js[e], hi) + 6 - J0[e];
+      shared = shared && Jn[e] <= kWave;
     }
     if (shared) {
       const int lane = threadIdx.x & (kWave - 1);
@@ -1039,7 +1046,8 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
       int sidx[2], t0[2];
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
-        own[e] = seg_coefs(kv[e], min(J0[e] + lane, kv[e].last - 1));
+        own[e] = lane < Jn[e] ? seg_coefs(kv[e], min(J0[e] + lane, kv[e].last - 1))
+                              : SegCoefs{0.0, 0.0, 0.0, 0.0, 0};
         sidx[e] = js[e] - J0[e];
         cur[e] = seg_from_lane(own[e], sidx[e]);
         t0[e] = jt0[e];
@@ -1068,8 +1076,10 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
             halo[0] = gmem(S.edge)[2 * tv.y - 1] - m;
           } else if (c < nv) {
             const double hk = tbuf[tsw(lb + c)];
-            num = fma(m, m, num);
-            den = fma(hk, hk, den);
+            if constexpr (SD) {
+              num = fma(m, m, num);
+              den = fma(hk, hk, den);
+            }
             tbuf[tsw(lb + c)] = hk - m;
           } else {
             halo[1] = gmem(S.edge)[2 * tv.y + 2] - m;
@@ -1094,8 +1104,10 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
           const double up = st_walk_at(wk[0], kv[0], k);
           const double lo = st_walk_at(wk[1], kv[1], k);
           const double m = up + lo, hk = tbuf[tsw(lb + c)];
-          num = fma(m, m, num);
-          den = fma(hk, hk, den);
+          if constexpr (SD) {
+            num = fma(m, m, num);
+            den = fma(hk, hk, den);
+          }
           tbuf[tsw(lb + c)] = hk - m;
           wk[0].B += 1.0;
           wk[1].B += 1.0;
@@ -1109,7 +1121,7 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
       }
     }
     if (action == kSift) {
-      if (S.sd > 0.0) {
+      if (SD && S.sd > 0.0) {
         double tnum, tden;
         block_sum2<kNW>(num, den, wsum, threadIdx.x & (kWave - 1), threadIdx.x / kWave, tnum,
                         tden);
@@ -1219,7 +1231,7 @@ hipError_t st_load(const StreamSig* sigs, const int2* tiles, int ntiles, hipStre
   return hipGetLastError();
 }
 hipError_t st_step(const StreamSig* sigs, int nsig, const int2* tiles, int ntiles,
-                   const int4* blocks, int nblocks, hipStream_t st, bool trace,
+                   const int4* blocks, int nblocks, hipStream_t st, bool sd, bool trace,
                    const hipEvent_t* marks) {
   if (nsig <= 0) return hipSuccess;
   auto mark = [&](int i) { if (marks) (void)hipEventRecord(marks[i], st); };
@@ -1236,7 +1248,10 @@ hipError_t st_step(const StreamSig* sigs, int nsig, const int2* tiles, int ntile
   mark(3);
   hipLaunchKernelGGL(st_solve_kernel, dim3(nblocks), dim3(kTT), 0, st, sigs, blocks);
   mark(4);
-  hipLaunchKernelGGL(st_eval_kernel, dim3(ntiles), dim3(kTT), 0, st, sigs, tiles);
+  if (sd)
+    hipLaunchKernelGGL(st_eval_kernel<true>, dim3(ntiles), dim3(kTT), 0, st, sigs, tiles);
+  else
+    hipLaunchKernelGGL(st_eval_kernel<false>, dim3(ntiles), dim3(kTT), 0, st, sigs, tiles);
   mark(5);
   return hipGetLastError();
 }
