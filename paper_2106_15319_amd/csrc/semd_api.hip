@@ -1315,8 +1315,9 @@ int semd_eemd_batch(const semd_item* items, int n, const semd_params* p, hipStre
   bool want_stats = false;
   for (int i = 0; i < n; ++i) want_stats |= items[i].stats_out != nullptr;
   // The realizations of consecutive items are decomposed in waves that fit
-  // the budget; one workspace, sized for the largest wave, serves them all.
-  const size_t budget = std::max<size_t>(available_device_bytes() / 4, size_t(256) << 20);
+  // the budget (a third of the free device memory: larger waves take fewer
+  // launches); one workspace, sized for the largest wave, serves them all.
+  const size_t budget = std::max<size_t>(available_device_bytes() / 3, size_t(256) << 20);
   auto realizations = [&](int i0, int i1) {
     std::vector<semd::WorkItem> work;
     work.reserve((size_t)NR * (i1 - i0));
