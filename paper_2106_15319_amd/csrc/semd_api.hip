@@ -568,7 +568,7 @@ size_t stream_bytes(int64_t L) {
   const size_t ntiles = (size_t)((L + semd::kTile - 1) / semd::kTile);
   return 2 * al256(sizeof(double) * (size_t)L) +
          2 * (al256(sizeof(int32_t) * cap) + 2 * al256(sizeof(double) * cap)) +
-         al256(sizeof(semd::TileInfo) * ntiles) + al256(sizeof(double) * 2 * ntiles) +
+         al256(sizeof(semd::TileInfo) * ntiles) + al256(sizeof(double) * 4 * ntiles) +
          al256(sizeof(int32_t) * semd::kTileThreads * ntiles) +
          2 * (al256(sizeof(int32_t) * semd::kTileKnots * ntiles) +
               al256(sizeof(double) * semd::kTileKnots * ntiles)) +
@@ -610,7 +610,7 @@ semd::StreamSig stream_sig(const semd::WorkItem& w, int K, int S, unsigned char*
     g.km[e] = reinterpret_cast<double*>(take(sizeof(double) * (size_t)g.cap));
   }
   g.tinfo = reinterpret_cast<semd::TileInfo*>(take(sizeof(semd::TileInfo) * (size_t)g.ntiles));
-  g.edge = reinterpret_cast<double*>(take(sizeof(double) * 2 * (size_t)g.ntiles));
+  g.edge = reinterpret_cast<double*>(take(sizeof(double) * 4 * (size_t)g.ntiles));
   g.trank = reinterpret_cast<int32_t*>(
       take(sizeof(int32_t) * semd::kTileThreads * (size_t)g.ntiles));
   for (int e = 0; e < 2; ++e) {

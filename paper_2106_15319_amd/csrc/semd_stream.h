@@ -55,7 +55,7 @@ struct SigStatus {
   int32_t n[2];     // maxima / minima of the current sift
   int32_t tr_rec;   // trace entry of this step's detection record, -1 if none
   int32_t tr_n[2];  //   and its maxima / minima counts
-  int32_t tr_pad;
+  int32_t in_r;     // this step's candidate is in r, not h (set by the scan)
   int64_t n_sifts;  // sifts performed
   int64_t n_knots;  // knots used, mirrored ones included
 };
@@ -86,7 +86,8 @@ struct StreamSig {
   int32_t cap;      // knots per envelope
   int32_t pad;
   TileInfo* tinfo;  // ntiles
-  double* edge;     // ntiles x 2: a tile's first and last sample before the sift
+  double* edge;     // ntiles x 2: a tile's first and last sample before the sift,
+                    // then ntiles x 2: the same of the residue before an IMF-ending sift
   int32_t* trank;   // ntiles x kTileThreads: knots of each kind the tile's earlier
                     // threads hold (ranks within the tile; maxima in the low 16 bits,
                     // minima in the high 16)

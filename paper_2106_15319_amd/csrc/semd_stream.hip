@@ -342,16 +342,60 @@ __device__ __forceinline__ void record_tile(const TileDet& d, const double (&h)[
 // Setup, load, detect, scan, compact
 // ---------------------------------------------------------------------------
 
+// Extremum detection of a tile staged in tbuf (samples a .. a+n-1), its
+// neighbours' samples being prev and next (0 where the signal ends).
+__device__ __forceinline__ void detect_staged(const StreamSig& S, int tile, int a, int n,
+                                              double prev, double next, double* tbuf,
+                                              int* pub_key, int* scratch, int64_t* scratch64,
+                                              int& cont_exit, int& cont_pos, double& cont_y) {
+  const int L = S.L;
+  if (threadIdx.x == 0) cont_exit = 0;
+  __syncthreads();
+  const int first_key =
+      a == 0 ? 0 : (prev != tbuf[tsw(0)] ? a * 4 + step_kind(prev, tbuf[tsw(0)]) : kCont);
+  double h[kTC];
+#pragma unroll
+  for (int c = 0; c < kTC; ++c) {
+    const int i = threadIdx.x * kTC + c;
+    h[c] = i < n ? tbuf[tsw(i)] : 0.0;
+  }
+  TileDet d;
+  tile_detect<kTC>(h, a, n, L, threadIdx.x, first_key, next, tbuf, pub_key,
+                   &cont_exit, &cont_pos, &cont_y, d);
+  __syncthreads();
+  record_tile(d, h, a, first_key, cont_exit, cont_pos, cont_y, S, tile, scratch64, scratch,
+              tbuf);
+}
+
+// Extremum detection of one tile of h (st_detect_kernel's work per tile).
+__device__ __forceinline__ void detect_tile(const StreamSig& S, int2 tv, double* tbuf,
+                                            int* pub_key, int* scratch, int64_t* scratch64,
+                                            int& cont_exit, int& cont_pos, double& cont_y) {
+  const int a = tv.y * kTile, n = min(kTile, S.L - a);
+  double prev, next;
+  stage_tile(S.h, a, n, S.L, tbuf, prev, next);
+  detect_staged(S, tv.y, a, n, prev, next, tbuf, pub_key, scratch, scratch64, cont_exit,
+                cont_pos, cont_y);
+}
+
 // Serialize (Sec. 3.2) and add the realization's noise (Sec. 2.2 Step 1):
-// h = r = x for the tile; a non-finite sample marks the tile.
+// h = r = x for the tile; a non-finite sample marks the tile.  The tile's
+// extrema are detected while it is on chip (the neighbours' samples are
+// computed alongside), so the first step's detection skips it.
 __global__ void __launch_bounds__(kTT) st_load_kernel(const StreamSig* __restrict__ sigs,
                                                       const int2* __restrict__ tiles) {
+  __shared__ double tbuf[kTile];
+  __shared__ int pub_key[kTT];
+  __shared__ int scratch[kNW];
+  __shared__ int64_t scratch64[kNW];
+  __shared__ int cont_exit, cont_pos;
+  __shared__ double cont_y;
   const int2 tv = tiles[blockIdx.x];
   const StreamSig& S = sigs[tv.x];
-  const int a = tv.y * kTile, b = min(a + kTile, S.L);
+  const int L = S.L;
+  const int a = tv.y * kTile, n = min(kTile, L - a);
   const int64_t R = S.M + S.D;
-  int bad = 0;
-  for (int k = a + threadIdx.x; k < b; k += kTT) {
+  auto sample = [&](int k) {
     const int64_t i = k / R, m = k - i * R;
     double v = (S.flags & kNoSignal) ? 0.0 : serial_at(S.X, S.M, S.D, i, m);
     if (S.flags & (kAddNoise | kAddBuffer)) {
@@ -359,10 +403,18 @@ __global__ void __launch_bounds__(kTT) st_load_kernel(const StreamSig* __restric
       const double e = (S.flags & kAddNoise) ? noise_at(S.key, k) : S.addend[k];
       v = __dadd_rn(v, __dmul_rn(b, e));
     }
+    return v;
+  };
+  int bad = 0;
+  for (int i = threadIdx.x; i < n; i += kTT) {
+    const double v = sample(a + i);
     bad |= !isfinite(v);
-    S.h[k] = v;
-    S.r[k] = v;
+    S.h[a + i] = v;
+    S.r[a + i] = v;
+    tbuf[tsw(i)] = v;
   }
+  const double prev = a > 0 ? sample(a - 1) : 0.0;
+  const double next = a + n < L ? sample(a + n) : 0.0;
   bad = __syncthreads_or(bad);
   if (threadIdx.x == 0) {
     S.tinfo[tv.y].bad = bad ? 1 : 0;
@@ -380,39 +432,17 @@ __global__ void __launch_bounds__(kTT) st_load_kernel(const StreamSig* __restric
       st->n[1] = 0;
       st->n_sifts = 0;
       st->n_knots = 0;
+      st->in_r = 0;
     }
   }
-}
-
-// Extremum detection of one tile (st_detect_kernel's work per tile).
-__device__ __forceinline__ void detect_tile(const StreamSig& S, int2 tv, double* tbuf,
-                                            int* pub_key, int* scratch, int64_t* scratch64,
-                                            int& cont_exit, int& cont_pos, double& cont_y) {
-  const int L = S.L;
-  const int a = tv.y * kTile, n = min(kTile, L - a);
-  double prev, next;
-  stage_tile(S.h, a, n, L, tbuf, prev, next);
-  if (threadIdx.x == 0) cont_exit = 0;
-  __syncthreads();
-  const int first_key =
-      a == 0 ? 0 : (prev != tbuf[tsw(0)] ? a * 4 + step_kind(prev, tbuf[tsw(0)]) : kCont);
-  double h[kTC];
-#pragma unroll
-  for (int c = 0; c < kTC; ++c) {
-    const int i = threadIdx.x * kTC + c;
-    h[c] = i < n ? tbuf[tsw(i)] : 0.0;
-  }
-  TileDet d;
-  tile_detect<kTC>(h, a, n, L, threadIdx.x, first_key, next, tbuf, pub_key,
-                   &cont_exit, &cont_pos, &cont_y, d);
-  __syncthreads();
-  record_tile(d, h, a, first_key, cont_exit, cont_pos, cont_y, S, tv.y, scratch64, scratch,
-              tbuf);
+  detect_staged(S, tv.y, a, n, prev, next, tbuf, pub_key, scratch, scratch64, cont_exit,
+                cont_pos, cont_y);
 }
 
 // Extremum counts of a tile whose candidate the previous step did not
-// detect (a fresh signal, or a new IMF's first candidate h = r; a sift step
-// detects its result itself).  The tile's first run may have started in an
+// detect: a new IMF's first candidate h = r after an IMF end without a sift
+// (the load detects a fresh signal, a sift step its result, and an
+// IMF-ending sift the new IMF's first candidate).  The tile's first run may have started in an
 // earlier tile (kind kCont); its extremum, if any, is resolved by the scan.
 // Most steps are sift steps, in which no tile needs this.  The launch is
 // folded (launch_fold): workgroup b takes the table entries b, b + G, ...
@@ -435,7 +465,7 @@ __global__ void __launch_bounds__(kTT) st_detect_kernel(const StreamSig* __restr
     bool need = false;
     if (threadIdx.x < kSolveFoldMax && ti < ntiles) {
       const global_ptr<const SigStatus> st = gmem<const SigStatus>(sigs[tiles[ti].x].st);
-      need = st->active && st->action != kSift;
+      need = st->active && st->action == kEndImf;
     }
     const unsigned long long m = __ballot(need);
     if (threadIdx.x == 0) need_mask = m;
@@ -481,6 +511,8 @@ __global__ void __launch_bounds__(kTT) st_scan_kernel(const StreamSig* __restric
     if (threadIdx.x == 0) st->action = kIdle;
     return;
   }
+  // an IMF-ending sift left the new IMF's first candidate in r only
+  if (threadIdx.x == 0) st->in_r = st->action == kSiftLast;
   const int nt = S.ntiles;
   if (S.sd > 0.0 && st->action == kSift) {
     // SD criterion over the whole signal: the tiles' sums of the last sift
@@ -605,7 +637,8 @@ __device__ __forceinline__ void put_knot(global_ptr<int32_t> kt, global_ptr<doub
 // The knots of the tile at their ranks (Sec. 2.1 Step 1 -> Step 2): the
 // continued run's extremum, when the scan found one, then the tile's own
 // knots as detection listed them.  Also the tile's edge samples before this
-// sift, for the evaluation of the neighbouring tiles.  One wave per tile: a
+// sift (and, when the sift ends the IMF, the residue's), for the evaluation
+// of the neighbouring tiles.  One wave per tile: a
 // tile holds a few hundred knots at most, and the time of a launch over
 // every tile of a batch goes to each workgroup's chain of dependent
 // descriptor reads, so more, smaller workgroups keep more tiles in flight.
@@ -623,7 +656,7 @@ __global__ void __launch_bounds__(kCompactThreads) st_compact_kernel(
   // whatever the step.)
   const global_ptr<const SigStatus> st = gmem<const SigStatus>(S.st);
   const auto& ti = gmem<const TileInfo>(S.tinfo)[tv.y];
-  const int action = st->action, nk[2] = {st->n[0], st->n[1]};
+  const int action = st->action, in_r = st->in_r, nk[2] = {st->n[0], st->n[1]};
   const int cnt[2] = {ti.cnt[0], ti.cnt[1]}, off[2] = {ti.off[0], ti.off[1]};
   const int cont_knot = ti.cont_knot;
   int p0[2];
@@ -633,17 +666,26 @@ __global__ void __launch_bounds__(kCompactThreads) st_compact_kernel(
     p0[e] = gmem<const int32_t>(S.lpos[e])[lo + threadIdx.x];
     v0[e] = gmem<const double>(S.lval[e])[lo + threadIdx.x];
   }
-  double ea = 0.0, eb = 0.0;
+  double ea = 0.0, eb = 0.0, ra = 0.0, rb = 0.0;
   if (threadIdx.x == 0) {
     const global_ptr<const double> hg = gmem<const double>(S.h);
+    const global_ptr<const double> rg = gmem<const double>(S.r);
     ea = hg[a];
     eb = hg[a + n - 1];
+    ra = rg[a];
+    rb = rg[a + n - 1];
   }
-  asm volatile("" ::"v"(p0[0]), "v"(p0[1]), "v"(v0[0]), "v"(v0[1]), "v"(ea), "v"(eb));
+  asm volatile("" ::"v"(p0[0]), "v"(p0[1]), "v"(v0[0]), "v"(v0[1]), "v"(ea), "v"(eb), "v"(ra),
+               "v"(rb));
   if (action != kSift && action != kSiftLast) return;
   if (threadIdx.x == 0) {
-    gmem(S.edge)[2 * tv.y] = ea;
-    gmem(S.edge)[2 * tv.y + 1] = eb;
+    gmem(S.edge)[2 * tv.y] = in_r ? ra : ea;
+    gmem(S.edge)[2 * tv.y + 1] = in_r ? rb : eb;
+    if (action == kSiftLast) {  // and the residue's, for the new residue's detection
+      const global_ptr<double> re = gmem(S.edge) + 2 * (int64_t)S.ntiles;
+      re[2 * tv.y] = ra;
+      re[2 * tv.y + 1] = rb;
+    }
   }
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
@@ -959,9 +1001,11 @@ __device__ __forceinline__ double st_walk_at(StWalk& w, const KnotView& K, int k
 // One step's work on the tile's samples:
 //   kSift, kSiftLast  envelope means removed (Sec. 2.1 Steps 2-4): each
 //                     thread walks the knots covering its samples, starting
-//                     from the ranks compaction recorded;
+//                     from its rank (detection's in-tile ranks plus the
+//                     scan's tile offsets);
 //   kSiftLast, kEndImf  IMF end: the candidate is stored in its output slot
-//                     (deserialized, Sec. 3.3), r <- r - h, h <- r;
+//                     (deserialized, Sec. 3.3), r <- r - h, h <- r (after
+//                     kSiftLast the next step reads its candidate from r);
 //   final             residue into slot K, unused IMF slots zero (Sec. 4.3),
 //                     IMF count and statistics.
 //
@@ -987,7 +1031,10 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
   const int L = S.L;
   const int a = tv.y * kTile, n = min(kTile, L - a);
   const global_ptr<double> hg = gmem(S.h);
-  for (int i = threadIdx.x; i < n; i += kTT) tbuf[tsw(i)] = hg[a + i];
+  {
+    const global_ptr<const double> cand = st->in_r ? gmem<const double>(S.r) : hg;
+    for (int i = threadIdx.x; i < n; i += kTT) tbuf[tsw(i)] = cand[a + i];
+  }
   if (action == kSift || action == kSiftLast) {
     const int lb = threadIdx.x * kTC;
     const int nv = max(0, min(kTC, n - lb));
@@ -1120,35 +1167,14 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
         halo[1] = gmem(S.edge)[2 * tv.y + 2] - (up + lo);
       }
     }
-    if (action == kSift) {
-      if (SD && S.sd > 0.0) {
-        double tnum, tden;
-        block_sum2<kNW>(num, den, wsum, threadIdx.x & (kWave - 1), threadIdx.x / kWave, tnum,
-                        tden);
-        if (threadIdx.x == 0) {
-          gmem(S.tinfo)[tv.y].sd_num = tnum;
-          gmem(S.tinfo)[tv.y].sd_den = tden;
-        }
+    if (action == kSift && SD && S.sd > 0.0) {
+      double tnum, tden;
+      block_sum2<kNW>(num, den, wsum, threadIdx.x & (kWave - 1), threadIdx.x / kWave, tnum,
+                      tden);
+      if (threadIdx.x == 0) {
+        gmem(S.tinfo)[tv.y].sd_num = tnum;
+        gmem(S.tinfo)[tv.y].sd_den = tden;
       }
-      // the sifted candidate stays the candidate: its extrema now, while
-      // it is on chip (the next step's detection is skipped)
-      __syncthreads();
-      const double prev = a > 0 ? halo[0] : 0.0;
-      const double next = a + n < L ? halo[1] : 0.0;
-      const int first_key =
-          a == 0 ? 0 : (prev != tbuf[tsw(0)] ? a * 4 + step_kind(prev, tbuf[tsw(0)]) : kCont);
-      double h[kTC];
-#pragma unroll
-      for (int c = 0; c < kTC; ++c) h[c] = lb + c < n ? tbuf[tsw(lb + c)] : 0.0;
-      TileDet d;
-      tile_detect<kTC>(h, a, n, L, threadIdx.x, first_key, next, tbuf, pub_key,
-                       &cont_exit, &cont_pos, &cont_y, d);
-      __syncthreads();
-      // the sifted candidate goes out now; the tile buffer then stages the
-      // knot lists
-      for (int i = threadIdx.x; i < n; i += kTT) hg[a + i] = tbuf[tsw(i)];
-      record_tile(d, h, a, first_key, cont_exit, cont_pos, cont_y, S, tv.y, scratch64, scratch,
-                  tbuf);
     }
   }
   __syncthreads();
@@ -1166,7 +1192,41 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
       if (m < M) slot[ii * M + m] = hk;
     }
   }
-  if (st->fin) {
+  // The next step's candidate is on chip now: the sifted candidate (kSift),
+  // or the next IMF's first candidate h = r after an IMF-ending sift
+  // (kSiftLast).  Its extrema are detected here and the next step's
+  // detection skips the tile.  The neighbours' edge samples of the new
+  // residue are their residue before this step (kept by compaction) less
+  // their sifted samples.
+  const bool fin = st->fin;
+  const bool detect = action == kSift || (action == kSiftLast && !fin);
+  if (detect) {
+    if (action == kSiftLast) {
+      const global_ptr<const double> re = gmem<const double>(S.edge) + 2 * (int64_t)S.ntiles;
+      if (threadIdx.x == 0 && a > 0) halo[0] = re[2 * tv.y - 1] - halo[0];
+      if (threadIdx.x == kWave && a + n < L) halo[1] = re[2 * tv.y + 2] - halo[1];
+      __syncthreads();
+    }
+    const double prev = a > 0 ? halo[0] : 0.0;
+    const double next = a + n < L ? halo[1] : 0.0;
+    const int first_key =
+        a == 0 ? 0 : (prev != tbuf[tsw(0)] ? a * 4 + step_kind(prev, tbuf[tsw(0)]) : kCont);
+    const int lb = threadIdx.x * kTC;
+    double h[kTC];
+#pragma unroll
+    for (int c = 0; c < kTC; ++c) h[c] = lb + c < n ? tbuf[tsw(lb + c)] : 0.0;
+    TileDet d;
+    tile_detect<kTC>(h, a, n, L, threadIdx.x, first_key, next, tbuf, pub_key,
+                     &cont_exit, &cont_pos, &cont_y, d);
+    __syncthreads();
+    // the sifted candidate goes out now (a new IMF's first candidate is in r
+    // already); the tile buffer then stages the knot lists
+    if (action == kSift)
+      for (int i = threadIdx.x; i < n; i += kTT) hg[a + i] = tbuf[tsw(i)];
+    record_tile(d, h, a, first_key, cont_exit, cont_pos, cont_y, S, tv.y, scratch64, scratch,
+                tbuf);
+  }
+  if (fin) {
     const int K = S.K, bad = st->bad;
     const int nimf = bad ? 0 : st->nimf;
     for (int i = threadIdx.x; i < n; i += kTT) {
@@ -1188,7 +1248,7 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
       }
       gmem(S.st)->done = 1;
     }
-  } else if (action != kSift) {  // (a sift step wrote h before detection's lists)
+  } else if (!detect) {
     for (int i = threadIdx.x; i < n; i += kTT) hg[a + i] = tbuf[tsw(i)];
   }
 }

@@ -628,6 +628,26 @@ def test_stream_random_lengths_match_oracle(i):
     tally.done()
 
 
+@pytest.mark.parametrize("K,S,noisy", [(12, 1, False), (12, 1, True), (12, 2, True),
+                                        (24, 3, False), (4, 1, True)])
+def test_stream_short_imfs_to_final_residue(K, S, noisy):
+    """IMFs of one to three sifts on the streaming path, most of them ended
+    by the residue running out of extrema before K: every IMF-ending sift
+    detects the new residue's extrema itself and the next step takes its
+    candidate from r, including a final step right after an IMF end."""
+    L = 20000
+    t = np.arange(L, dtype=np.float64)
+    x = (np.sin(2 * np.pi * t / 37.0) + 0.6 * np.sin(2 * np.pi * t / 523.0) +
+         0.3 * np.sin(2 * np.pi * t / 4111.0) + 2e-4 * t)
+    if noisy:
+        x = x + 0.2 * np.random.default_rng(31).standard_normal(L)
+    out, n = semd.semd_decompose_ex(dev(x), [L, 1], 0, K, S, path=STREAM)
+    tally = Tally(f"streaming short IMFs K={K} S={S} noisy={noisy}")
+    res = _check_item(x, L, 1, 0, K, S, host(out), int(host(n)[0]), tally, path=STREAM)
+    tally.done()
+    assert res["n"] >= 3
+
+
 def test_stream_faces_and_textures():
     items = workloads.config2(4) + workloads.config1(2)
     shapes = [(i.M, i.N) for i in items]
