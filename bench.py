@@ -626,7 +626,7 @@ def run_eemd(args, semd, torch, workloads):
     wall = time.perf_counter() - t0
     semd.semd_profile_enable(False)
     kern = {}
-    for name in ("st_load_kernel", "st_detect_kernel", "st_scan_kernel", "st_compact_kernel",
+    for name in ("st_load_kernel", "st_scan_kernel", "st_compact_kernel",
                  "st_solve_kernel", "st_eval_kernel", "resident_emd_kernel"):
         nl, ms = semd.semd_profile_read(name)
         kern[name] = {"launches": nl, "total_ms": ms, "avg_ms": ms / nl if nl else None}

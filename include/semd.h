@@ -323,9 +323,9 @@ int semd_release_cached_memory(void);
  * kernel of every streaming step; the streaming steps are then launched
  * directly instead of replayed from a captured graph (same kernels, same
  * order, same results).  semd_profile_read waits for the recorded events and
- * returns, for one kernel ("st_load_kernel", "st_detect_kernel",
- * "st_scan_kernel", "st_compact_kernel", "st_solve_kernel", "st_eval_kernel"
- * or "resident_emd_kernel"), the launches timed since the last reset and
+ * returns, for one kernel ("st_load_kernel", "st_scan_kernel",
+ * "st_compact_kernel", "st_solve_kernel", "st_eval_kernel" or
+ * "resident_emd_kernel"), the launches timed since the last reset and
  * their summed duration in milliseconds, or for one host phase of the batch
  * calls ("host_alloc", "host_tables", "host_upload", "host_launch",
  * "host_batch_call") the calls and their summed wall time ([host]

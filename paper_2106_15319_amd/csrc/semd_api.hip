@@ -207,14 +207,14 @@ struct StepGraph {
 // ---------------------------------------------------------------------------
 
 enum ProfKind {
-  kPLoad, kPDetect, kPScan, kPCompact, kPSolve, kPEval, kPResident,
+  kPLoad, kPScan, kPCompact, kPSolve, kPEval, kPResident,
   // host time (wall clock of the calling thread) in phases of the batch calls
   kHAlloc, kHTables, kHUpload, kHLaunch, kHBatch, kPKinds
 };
 const char* const kProfNames[kPKinds] = {
-    "st_load_kernel", "st_detect_kernel",    "st_scan_kernel", "st_compact_kernel",
-    "st_solve_kernel", "st_eval_kernel",     "resident_emd_kernel", "host_alloc",
-    "host_tables",     "host_upload",        "host_launch",    "host_batch_call"};
+    "st_load_kernel",  "st_scan_kernel", "st_compact_kernel", "st_solve_kernel",
+    "st_eval_kernel",  "resident_emd_kernel", "host_alloc",    "host_tables",
+    "host_upload",     "host_launch",    "host_batch_call"};
 
 struct ProfSpan {
   int kind;
@@ -709,7 +709,7 @@ int run_stream(const std::vector<semd::WorkItem>& work, int K, int S, hipStream_
   if (e == hipSuccess && profiling()) {
     // timed: the same launches, issued directly with events between them
     HostPhase hp(kHLaunch);
-    hipEvent_t ev[6];
+    hipEvent_t ev[5];
     bool timed = prof_events(ev, 2);
     if (timed) (void)hipEventRecord(ev[0], cs.s);
     e = semd::st_load(d_sigs, d_tiles, nt, cs.s);
@@ -718,11 +718,11 @@ int run_stream(const std::vector<semd::WorkItem>& work, int K, int S, hipStream_
       prof_span(kPLoad, ev[0], ev[1]);
     }
     for (int step = 0; step < K * S && e == hipSuccess; ++step) {
-      timed = prof_events(ev, 6);
+      timed = prof_events(ev, 5);
       e = semd::st_step(d_sigs, n, d_tiles, nt, d_blocks, nb, cs.s, any_sd, false,
                         timed ? ev : nullptr);
       if (timed)
-        for (int k = 0; k < 5; ++k) prof_span(kPDetect + k, ev[k], ev[k + 1]);
+        for (int k = 0; k < 4; ++k) prof_span(kPScan + k, ev[k], ev[k + 1]);
     }
     if (e == hipSuccess) e = cs.join();
     if (e != hipSuccess) rc = hip_fail(e, "streaming kernel launch");

@@ -99,15 +99,16 @@ struct StreamSig {
   int32_t pad2;
 };
 
-// h = r = serialized input (+ noise) and a fresh status, for the signals
-// whose tiles are listed.
+// h = r = serialized input (+ noise), its extrema detected, and a fresh
+// status, for the signals whose tiles are listed.
 hipError_t st_load(const StreamSig* sigs, const int2* tiles, int ntiles, hipStream_t s);
-// One step of every listed signal: detect, scan (decides the step's action),
-// compact and solve (sifting signals), eval (sift, IMF end, final outputs).
+// One step of every listed signal: scan (decides the step's action), compact
+// and solve (sifting signals), eval (sift, IMF end, final outputs, and the
+// next candidate's extrema).
 // sd: some signal uses the SD stopping rule (its sums are accumulated).
 // trace: also record each detection of the signals that carry a trace.
-// marks (6 events, or nullptr): recorded before the step and after each of
-// its detect, scan, compact, solve and eval launches, for kernel timing.
+// marks (5 events, or nullptr): recorded before the step and after each of
+// its scan, compact, solve and eval launches, for kernel timing.
 hipError_t st_step(const StreamSig* sigs, int nsig, const int2* tiles, int ntiles,
                    const int4* blocks, int nblocks, hipStream_t s, bool sd, bool trace = false,
                    const hipEvent_t* marks = nullptr);

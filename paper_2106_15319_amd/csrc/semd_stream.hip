@@ -3,9 +3,11 @@
 // Signals too long for one workgroup's LDS are sifted in passes over global
 // memory.  A batch's signals are cut into tiles of kTile samples; every tile
 // kernel runs one workgroup per (signal, tile) pair of the whole batch, so a
-// launch holds all the batch's parallelism.  One sift of every signal is
-//   detect   (tiles)    extrema counts per tile, plus what the scan needs to
-//                       resolve equal-valued runs that cross tile ends;
+// launch holds all the batch's parallelism.  A step starts with the extrema
+// of every tile's candidate detected (extrema counts and lists per tile,
+// plus what the scan needs to resolve equal-valued runs that cross tile
+// ends), by the load or the previous step's evaluation.  One sift of every
+// signal is
 //   scan     (signals)  run-start carries and knot ranks across the tiles of
 //                       a signal, knot totals, siftability, stop flags;
 //   compact  (tiles)    knots (and mirrored end knots) written at their ranks;
@@ -13,8 +15,8 @@
 //                       records, each block's window of knots staged in LDS
 //                       and solved exactly by block-wide scans;
 //   eval     (tiles)    both envelopes walked per thread over the segment
-//                       records, mean removed from h, the sifted tile's
-//                       extrema detected while it is on chip.
+//                       records, mean removed from h, IMF ends, and the next
+//                       candidate's extrema detected while it is on chip.
 // Every signal carries its own phase (sift index, IMFs ended); the scan
 // decides each step's action per signal, and the evaluation also performs
 // IMF ends and final outputs, so signals in different phases share one
@@ -42,7 +44,7 @@ constexpr int kSB = 2048;             // interior rows per solve block
 constexpr int kSolveTarget = 4096;
 constexpr int kSolveFoldMax = 32;
 __host__ __device__ constexpr int solve_blocks(int cap) { return (cap + kSB - 1) / kSB; }
-// Units (blocks, tiles) per workgroup of a folded launch over `units`.
+// Solve blocks per workgroup of a folded launch over `units` blocks.
 inline int launch_fold(int64_t units) {
   return (int)std::min<int64_t>(kSolveFoldMax, std::max<int64_t>(1, units / kSolveTarget));
 }
@@ -134,14 +136,6 @@ __device__ __forceinline__ int block_excl_max(int v, int* scratch, int& total) {
 // stay within their block.
 static_assert(kTC == 8, "tile buffer swizzle assumes 8 samples per thread");
 __device__ __forceinline__ int tsw(int i) { return i ^ ((i >> 5) & 7); }
-
-// Stage samples a .. a+n-1 of h in LDS and return the halo neighbours.
-__device__ __forceinline__ void stage_tile(const double* __restrict__ h, int a, int n, int L,
-                                           double* tbuf, double& prev, double& next) {
-  for (int i = threadIdx.x; i < n; i += kTT) tbuf[tsw(i)] = h[a + i];
-  prev = a > 0 ? h[a - 1] : 0.0;
-  next = a + n < L ? h[a + n] : 0.0;
-}
 
 // ---------------------------------------------------------------------------
 // Extrema of a tile (Sec. 2.1 Step 1) from per-thread step masks
@@ -339,7 +333,7 @@ __device__ __forceinline__ void record_tile(const TileDet& d, const double (&h)[
 }
 
 // ---------------------------------------------------------------------------
-// Setup, load, detect, scan, compact
+// Setup, load, scan, compact
 // ---------------------------------------------------------------------------
 
 // Extremum detection of a tile staged in tbuf (samples a .. a+n-1), its
@@ -367,21 +361,10 @@ __device__ __forceinline__ void detect_staged(const StreamSig& S, int tile, int 
               tbuf);
 }
 
-// Extremum detection of one tile of h (st_detect_kernel's work per tile).
-__device__ __forceinline__ void detect_tile(const StreamSig& S, int2 tv, double* tbuf,
-                                            int* pub_key, int* scratch, int64_t* scratch64,
-                                            int& cont_exit, int& cont_pos, double& cont_y) {
-  const int a = tv.y * kTile, n = min(kTile, S.L - a);
-  double prev, next;
-  stage_tile(S.h, a, n, S.L, tbuf, prev, next);
-  detect_staged(S, tv.y, a, n, prev, next, tbuf, pub_key, scratch, scratch64, cont_exit,
-                cont_pos, cont_y);
-}
-
 // Serialize (Sec. 3.2) and add the realization's noise (Sec. 2.2 Step 1):
 // h = r = x for the tile; a non-finite sample marks the tile.  The tile's
 // extrema are detected while it is on chip (the neighbours' samples are
-// computed alongside), so the first step's detection skips it.
+// computed alongside).
 __global__ void __launch_bounds__(kTT) st_load_kernel(const StreamSig* __restrict__ sigs,
                                                       const int2* __restrict__ tiles) {
   __shared__ double tbuf[kTile];
@@ -439,48 +422,6 @@ __global__ void __launch_bounds__(kTT) st_load_kernel(const StreamSig* __restric
                 cont_pos, cont_y);
 }
 
-// Extremum counts of a tile whose candidate the previous step did not
-// detect: a new IMF's first candidate h = r after an IMF end without a sift
-// (the load detects a fresh signal, a sift step its result, and an
-// IMF-ending sift the new IMF's first candidate).  The tile's first run may have started in an
-// earlier tile (kind kCont); its extremum, if any, is resolved by the scan.
-// Most steps are sift steps, in which no tile needs this.  The launch is
-// folded (launch_fold): workgroup b takes the table entries b, b + G, ...
-// (G = gridDim.x, at most kSolveFoldMax of them), tests all their statuses
-// at once, one lane each, and detects only the tiles that need it, so a
-// step without detections costs one round of status reads per workgroup.
-__global__ void __launch_bounds__(kTT) st_detect_kernel(const StreamSig* __restrict__ sigs,
-                                                        const int2* __restrict__ tiles,
-                                                        int ntiles) {
-  static_assert(kSolveFoldMax <= kWave, "one lane of the first wave per folded entry");
-  __shared__ double tbuf[kTile];
-  __shared__ int pub_key[kTT];
-  __shared__ int scratch[kNW];
-  __shared__ int64_t scratch64[kNW];
-  __shared__ int cont_exit, cont_pos;
-  __shared__ double cont_y;
-  __shared__ unsigned long long need_mask;
-  if (threadIdx.x < kWave) {
-    const int64_t ti = blockIdx.x + (int64_t)threadIdx.x * gridDim.x;
-    bool need = false;
-    if (threadIdx.x < kSolveFoldMax && ti < ntiles) {
-      const global_ptr<const SigStatus> st = gmem<const SigStatus>(sigs[tiles[ti].x].st);
-      need = st->active && st->action == kEndImf;
-    }
-    const unsigned long long m = __ballot(need);
-    if (threadIdx.x == 0) need_mask = m;
-  }
-  __syncthreads();
-  unsigned long long m = need_mask;
-  while (m) {
-    const int k = __ffsll((long long)m) - 1;
-    m &= m - 1;
-    const int2 tv = tiles[blockIdx.x + (int64_t)k * gridDim.x];
-    detect_tile(sigs[tv.x], tv, tbuf, pub_key, scratch, scratch64, cont_exit, cont_pos, cont_y);
-    if (m) __syncthreads();  // this tile is done with the LDS
-  }
-}
-
 // Ends the current IMF (its candidate is stored by the evaluation); reaching
 // K IMFs finishes the decomposition.
 __device__ __forceinline__ void end_imf(SigStatus* st, int K) {
@@ -511,8 +452,8 @@ __global__ void __launch_bounds__(kTT) st_scan_kernel(const StreamSig* __restric
     if (threadIdx.x == 0) st->action = kIdle;
     return;
   }
-  // an IMF-ending sift left the new IMF's first candidate in r only
-  if (threadIdx.x == 0) st->in_r = st->action == kSiftLast;
+  // an IMF end left the new IMF's first candidate in r only
+  if (threadIdx.x == 0) st->in_r = st->action == kSiftLast || st->action == kEndImf;
   const int nt = S.ntiles;
   if (S.sd > 0.0 && st->action == kSift) {
     // SD criterion over the whole signal: the tiles' sums of the last sift
@@ -637,7 +578,7 @@ __device__ __forceinline__ void put_knot(global_ptr<int32_t> kt, global_ptr<doub
 // The knots of the tile at their ranks (Sec. 2.1 Step 1 -> Step 2): the
 // continued run's extremum, when the scan found one, then the tile's own
 // knots as detection listed them.  Also the tile's edge samples before this
-// sift (and, when the sift ends the IMF, the residue's), for the evaluation
+// step (and, when the step ends the IMF, the residue's), for the evaluation
 // of the neighbouring tiles.  One wave per tile: a
 // tile holds a few hundred knots at most, and the time of a launch over
 // every tile of a batch goes to each workgroup's chain of dependent
@@ -666,27 +607,32 @@ __global__ void __launch_bounds__(kCompactThreads) st_compact_kernel(
     p0[e] = gmem<const int32_t>(S.lpos[e])[lo + threadIdx.x];
     v0[e] = gmem<const double>(S.lval[e])[lo + threadIdx.x];
   }
-  double ea = 0.0, eb = 0.0, ra = 0.0, rb = 0.0;
+  double ea = 0.0, eb = 0.0;
   if (threadIdx.x == 0) {
     const global_ptr<const double> hg = gmem<const double>(S.h);
-    const global_ptr<const double> rg = gmem<const double>(S.r);
     ea = hg[a];
     eb = hg[a + n - 1];
-    ra = rg[a];
-    rb = rg[a + n - 1];
   }
-  asm volatile("" ::"v"(p0[0]), "v"(p0[1]), "v"(v0[0]), "v"(v0[1]), "v"(ea), "v"(eb), "v"(ra),
-               "v"(rb));
-  if (action != kSift && action != kSiftLast) return;
+  asm volatile("" ::"v"(p0[0]), "v"(p0[1]), "v"(v0[0]), "v"(v0[1]), "v"(ea), "v"(eb));
+  if (action != kSift && action != kSiftLast && action != kEndImf) return;
   if (threadIdx.x == 0) {
+    // the residue's edge samples: the candidate's when it is in r, and, when
+    // the step ends the IMF, for the new residue's detection
+    double ra = 0.0, rb = 0.0;
+    if (in_r || action != kSift) {
+      const global_ptr<const double> rg = gmem<const double>(S.r);
+      ra = rg[a];
+      rb = rg[a + n - 1];
+    }
     gmem(S.edge)[2 * tv.y] = in_r ? ra : ea;
     gmem(S.edge)[2 * tv.y + 1] = in_r ? rb : eb;
-    if (action == kSiftLast) {  // and the residue's, for the new residue's detection
+    if (action != kSift) {
       const global_ptr<double> re = gmem(S.edge) + 2 * (int64_t)S.ntiles;
       re[2 * tv.y] = ra;
       re[2 * tv.y + 1] = rb;
     }
   }
+  if (action == kEndImf) return;  // no knots: the candidate is the IMF
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
     const int ck = (cont_knot >> e) & 1;
@@ -1004,8 +950,8 @@ __device__ __forceinline__ double st_walk_at(StWalk& w, const KnotView& K, int k
 //                     from its rank (detection's in-tile ranks plus the
 //                     scan's tile offsets);
 //   kSiftLast, kEndImf  IMF end: the candidate is stored in its output slot
-//                     (deserialized, Sec. 3.3), r <- r - h, h <- r (after
-//                     kSiftLast the next step reads its candidate from r);
+//                     (deserialized, Sec. 3.3), r <- r - h, and r is the
+//                     next step's candidate (h is not written);
 //   final             residue into slot K, unused IMF slots zero (Sec. 4.3),
 //                     IMF count and statistics.
 //
@@ -1193,18 +1139,23 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
     }
   }
   // The next step's candidate is on chip now: the sifted candidate (kSift),
-  // or the next IMF's first candidate h = r after an IMF-ending sift
-  // (kSiftLast).  Its extrema are detected here and the next step's
-  // detection skips the tile.  The neighbours' edge samples of the new
-  // residue are their residue before this step (kept by compaction) less
-  // their sifted samples.
+  // or the next IMF's first candidate h = r after an IMF end.  Its extrema
+  // are detected here, so a step starts with its candidate's extrema known.
+  // The neighbours' edge samples of a new residue are their residue before
+  // this step (kept by compaction) less their candidate (sifted by the walk
+  // under kSiftLast, as compaction kept it under kEndImf).
   const bool fin = st->fin;
-  const bool detect = action == kSift || (action == kSiftLast && !fin);
+  const bool detect = !fin;  // (kSift never finishes)
   if (detect) {
-    if (action == kSiftLast) {
-      const global_ptr<const double> re = gmem<const double>(S.edge) + 2 * (int64_t)S.ntiles;
-      if (threadIdx.x == 0 && a > 0) halo[0] = re[2 * tv.y - 1] - halo[0];
-      if (threadIdx.x == kWave && a + n < L) halo[1] = re[2 * tv.y + 2] - halo[1];
+    if (action != kSift) {
+      const global_ptr<const double> eg = gmem<const double>(S.edge);
+      const global_ptr<const double> re = eg + 2 * (int64_t)S.ntiles;
+      if (threadIdx.x == 0) {
+        cont_exit = 0;
+        if (a > 0) halo[0] = re[2 * tv.y - 1] - (action == kEndImf ? eg[2 * tv.y - 1] : halo[0]);
+      }
+      if (threadIdx.x == kWave && a + n < L)
+        halo[1] = re[2 * tv.y + 2] - (action == kEndImf ? eg[2 * tv.y + 2] : halo[1]);
       __syncthreads();
     }
     const double prev = a > 0 ? halo[0] : 0.0;
@@ -1248,8 +1199,6 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
       }
       gmem(S.st)->done = 1;
     }
-  } else if (!detect) {
-    for (int i = threadIdx.x; i < n; i += kTT) hg[a + i] = tbuf[tsw(i)];
   }
 }
 
@@ -1296,23 +1245,19 @@ hipError_t st_step(const StreamSig* sigs, int nsig, const int2* tiles, int ntile
   if (nsig <= 0) return hipSuccess;
   auto mark = [&](int i) { if (marks) (void)hipEventRecord(marks[i], st); };
   mark(0);
-  const int dfold = launch_fold(ntiles);
-  hipLaunchKernelGGL(st_detect_kernel, dim3((ntiles + dfold - 1) / dfold), dim3(kTT), 0, st,
-                     sigs, tiles, ntiles);
-  mark(1);
   hipLaunchKernelGGL(st_scan_kernel, dim3(nsig), dim3(kTT), 0, st, sigs);
   if (trace) hipLaunchKernelGGL(st_trace_kernel, dim3(ntiles), dim3(kTT), 0, st, sigs, tiles);
-  mark(2);
+  mark(1);
   hipLaunchKernelGGL(st_compact_kernel, dim3(ntiles), dim3(kCompactThreads), 0, st, sigs,
                      tiles);
-  mark(3);
+  mark(2);
   hipLaunchKernelGGL(st_solve_kernel, dim3(nblocks), dim3(kTT), 0, st, sigs, blocks);
-  mark(4);
+  mark(3);
   if (sd)
     hipLaunchKernelGGL(st_eval_kernel<true>, dim3(ntiles), dim3(kTT), 0, st, sigs, tiles);
   else
     hipLaunchKernelGGL(st_eval_kernel<false>, dim3(ntiles), dim3(kTT), 0, st, sigs, tiles);
-  mark(5);
+  mark(4);
   return hipGetLastError();
 }
 hipError_t st_put_single(const StreamSig& g, StreamSig* dsig, int2* tiles, int4* blocks,
