@@ -688,8 +688,9 @@ __global__ void __launch_bounds__(kTT) st_trace_kernel(const StreamSig* __restri
 // m_j of its rows in r0..r1-1, and the zeros of the two end knots when it
 // holds row 1 or row n-2; the evaluation forms each segment's cubic from
 // the knots at its ends.
-// (bounded to 128 VGPRs: four waves per SIMD)
-__global__ void __launch_bounds__(kTT, 4) st_solve_kernel(const StreamSig* __restrict__ sigs,
+// (bounded to 96 VGPRs, which it fits without spilling: five waves per
+// SIMD, and the LDS window takes five workgroups per CU)
+__global__ void __launch_bounds__(kTT, 5) st_solve_kernel(const StreamSig* __restrict__ sigs,
                                                           const int4* __restrict__ blocks) {
   constexpr int kW = kSB + 2 * kHalo + 4;
   constexpr int kRMax = (kSB + 2 * kHalo + kTT - 1) / kTT;
