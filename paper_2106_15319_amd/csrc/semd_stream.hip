@@ -49,7 +49,8 @@ inline int launch_fold(int64_t units) {
   return (int)std::min<int64_t>(kSolveFoldMax, std::max<int64_t>(1, units / kSolveTarget));
 }
 constexpr int kNW = kTT / kWave;
-constexpr int kCompactThreads = kWave;  // threads per compaction workgroup (one tile)
+constexpr int kCompactWaves = 4;  // tiles per compaction workgroup, one wave each
+constexpr int kCompactThreads = kWave * kCompactWaves;
 
 template <class Status>
 __device__ __forceinline__ bool sifting(const Status& st) {
@@ -579,13 +580,17 @@ __device__ __forceinline__ void put_knot(global_ptr<int32_t> kt, global_ptr<doub
 // continued run's extremum, when the scan found one, then the tile's own
 // knots as detection listed them.  Also the tile's edge samples before this
 // step (and, when the step ends the IMF, the residue's), for the evaluation
-// of the neighbouring tiles.  One wave per tile: a
-// tile holds a few hundred knots at most, and the time of a launch over
-// every tile of a batch goes to each workgroup's chain of dependent
-// descriptor reads, so more, smaller workgroups keep more tiles in flight.
+// of the neighbouring tiles.  One wave per tile (kCompactWaves tiles per
+// workgroup, independent of each other): a tile holds a few hundred knots
+// at most, and the time of a launch over every tile of a batch goes to each
+// tile's chain of dependent descriptor reads, so more tiles in flight is
+// what counts.
 __global__ void __launch_bounds__(kCompactThreads) st_compact_kernel(
-    const StreamSig* __restrict__ sigs, const int2* __restrict__ tiles) {
-  const int2 tv = tiles[blockIdx.x];
+    const StreamSig* __restrict__ sigs, const int2* __restrict__ tiles, int ntiles) {
+  const int64_t tix = (int64_t)blockIdx.x * kCompactWaves + threadIdx.x / kWave;
+  if (tix >= ntiles) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int2 tv = tiles[tix];
   const StreamSig& S = sigs[tv.x];
   const int L = S.L;
   const int a = tv.y * kTile, n = min(kTile, L - a);
@@ -604,18 +609,18 @@ __global__ void __launch_bounds__(kCompactThreads) st_compact_kernel(
   double v0[2];
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
-    p0[e] = gmem<const int32_t>(S.lpos[e])[lo + threadIdx.x];
-    v0[e] = gmem<const double>(S.lval[e])[lo + threadIdx.x];
+    p0[e] = gmem<const int32_t>(S.lpos[e])[lo + lane];
+    v0[e] = gmem<const double>(S.lval[e])[lo + lane];
   }
   double ea = 0.0, eb = 0.0;
-  if (threadIdx.x == 0) {
+  if (lane == 0) {
     const global_ptr<const double> hg = gmem<const double>(S.h);
     ea = hg[a];
     eb = hg[a + n - 1];
   }
   asm volatile("" ::"v"(p0[0]), "v"(p0[1]), "v"(v0[0]), "v"(v0[1]), "v"(ea), "v"(eb));
   if (action != kSift && action != kSiftLast && action != kEndImf) return;
-  if (threadIdx.x == 0) {
+  if (lane == 0) {
     // the residue's edge samples: the candidate's when it is in r, and, when
     // the step ends the IMF, for the new residue's detection
     double ra = 0.0, rb = 0.0;
@@ -638,12 +643,12 @@ __global__ void __launch_bounds__(kCompactThreads) st_compact_kernel(
     const int ck = (cont_knot >> e) & 1;
     const global_ptr<int32_t> kt = gmem(S.kt[e]);
     const global_ptr<double> ky = gmem(S.ky[e]);
-    if (ck && threadIdx.x == 0)
+    if (ck && lane == 0)
       put_knot(kt, ky, off[e], nk[e], L, ((ti.carry >> 2) + ti.cont_pos) >> 1, ti.cont_y);
-    if ((int)threadIdx.x < cnt[e]) put_knot(kt, ky, off[e] + ck + threadIdx.x, nk[e], L, p0[e], v0[e]);
+    if (lane < cnt[e]) put_knot(kt, ky, off[e] + ck + lane, nk[e], L, p0[e], v0[e]);
     const global_ptr<const int32_t> lp = gmem<const int32_t>(S.lpos[e]) + lo;
     const global_ptr<const double> lv = gmem<const double>(S.lval[e]) + lo;
-    for (int i = threadIdx.x + kCompactThreads; i < cnt[e]; i += kCompactThreads)
+    for (int i = lane + kWave; i < cnt[e]; i += kWave)
       put_knot(kt, ky, off[e] + ck + i, nk[e], L, lp[i], lv[i]);
   }
 }
@@ -1249,8 +1254,8 @@ hipError_t st_step(const StreamSig* sigs, int nsig, const int2* tiles, int ntile
   hipLaunchKernelGGL(st_scan_kernel, dim3(nsig), dim3(kTT), 0, st, sigs);
   if (trace) hipLaunchKernelGGL(st_trace_kernel, dim3(ntiles), dim3(kTT), 0, st, sigs, tiles);
   mark(1);
-  hipLaunchKernelGGL(st_compact_kernel, dim3(ntiles), dim3(kCompactThreads), 0, st, sigs,
-                     tiles);
+  hipLaunchKernelGGL(st_compact_kernel, dim3((ntiles + kCompactWaves - 1) / kCompactWaves),
+                     dim3(kCompactThreads), 0, st, sigs, tiles, ntiles);
   mark(2);
   hipLaunchKernelGGL(st_solve_kernel, dim3(nblocks), dim3(kTT), 0, st, sigs, blocks);
   mark(3);
