@@ -99,8 +99,9 @@ struct StreamSig {
   int32_t pad2;
 };
 
-// h = r = serialized input (+ noise), its extrema detected, and a fresh
-// status, for the signals whose tiles are listed.
+// r = serialized input (+ noise), the first candidate (read from r by the
+// first step), its extrema detected, and a fresh status, for the signals
+// whose tiles are listed.
 hipError_t st_load(const StreamSig* sigs, const int2* tiles, int ntiles, hipStream_t s);
 // One step of every listed signal: scan (decides the step's action), compact
 // and solve (sifting signals), eval (sift, IMF end, final outputs, and the

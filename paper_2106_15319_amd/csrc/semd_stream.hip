@@ -363,7 +363,8 @@ __device__ __forceinline__ void detect_staged(const StreamSig& S, int tile, int 
 }
 
 // Serialize (Sec. 3.2) and add the realization's noise (Sec. 2.2 Step 1):
-// h = r = x for the tile; a non-finite sample marks the tile.  The tile's
+// r = x for the tile (the first step reads its candidate h = r there); a
+// non-finite sample marks the tile.  The tile's
 // extrema are detected while it is on chip (the neighbours' samples are
 // computed alongside).
 __global__ void __launch_bounds__(kTT) st_load_kernel(const StreamSig* __restrict__ sigs,
@@ -393,7 +394,6 @@ __global__ void __launch_bounds__(kTT) st_load_kernel(const StreamSig* __restric
   for (int i = threadIdx.x; i < n; i += kTT) {
     const double v = sample(a + i);
     bad |= !isfinite(v);
-    S.h[a + i] = v;
     S.r[a + i] = v;
     tbuf[tsw(i)] = v;
   }
@@ -453,8 +453,8 @@ __global__ void __launch_bounds__(kTT) st_scan_kernel(const StreamSig* __restric
     if (threadIdx.x == 0) st->action = kIdle;
     return;
   }
-  // an IMF end left the new IMF's first candidate in r only
-  if (threadIdx.x == 0) st->in_r = st->action == kSiftLast || st->action == kEndImf;
+  // a load or an IMF end left the IMF's first candidate in r only
+  if (threadIdx.x == 0) st->in_r = st->action != kSift;
   const int nt = S.ntiles;
   if (S.sd > 0.0 && st->action == kSift) {
     // SD criterion over the whole signal: the tiles' sums of the last sift
