@@ -34,7 +34,7 @@ using namespace dev;
 
 constexpr int kTT = kTileThreads;     // threads per tile workgroup
 constexpr int kTC = kTile / kTT;      // samples per thread
-constexpr int kSB = 2048;             // interior rows per solve block
+constexpr int kSB = 1536;             // interior rows per solve block
 // An envelope's solve blocks are sized for its largest possible knot count
 // (about L/2), and in most sifts most of them are empty.  A launch over many
 // blocks folds them: each workgroup takes every G-th block of its envelope,
@@ -693,9 +693,9 @@ __global__ void __launch_bounds__(kTT) st_trace_kernel(const StreamSig* __restri
 // m_j of its rows in r0..r1-1, and the zeros of the two end knots when it
 // holds row 1 or row n-2; the evaluation forms each segment's cubic from
 // the knots at its ends.
-// (bounded to 96 VGPRs, which it fits without spilling: five waves per
-// SIMD, and the LDS window takes five workgroups per CU)
-__global__ void __launch_bounds__(kTT, 5) st_solve_kernel(const StreamSig* __restrict__ sigs,
+// (bounded to 80 VGPRs, which it fits without spilling: six waves per
+// SIMD; the LDS window would allow eight workgroups per CU)
+__global__ void __launch_bounds__(kTT, 6) st_solve_kernel(const StreamSig* __restrict__ sigs,
                                                           const int4* __restrict__ blocks) {
   constexpr int kW = kSB + 2 * kHalo + 4;
   constexpr int kRMax = (kSB + 2 * kHalo + kTT - 1) / kTT;
