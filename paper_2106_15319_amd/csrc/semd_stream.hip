@@ -50,6 +50,7 @@ inline int launch_fold(int64_t units) {
 }
 constexpr int kNW = kTT / kWave;
 constexpr int kCompactWaves = 4;  // tiles per compaction workgroup, one wave each
+constexpr int kCompactBatch = 4;  // list entries per lane and list loaded per round
 constexpr int kCompactThreads = kWave * kCompactWaves;
 
 template <class Status>
@@ -587,7 +588,10 @@ __device__ __forceinline__ void put_knot(global_ptr<int32_t> kt, global_ptr<doub
 // what counts.
 __global__ void __launch_bounds__(kCompactThreads) st_compact_kernel(
     const StreamSig* __restrict__ sigs, const int2* __restrict__ tiles, int ntiles) {
-  const int64_t tix = (int64_t)blockIdx.x * kCompactWaves + threadIdx.x / kWave;
+  // (the wave index read as wave-uniform: the tile's descriptor fields then
+  // live in scalar registers)
+  const int64_t tix = (int64_t)blockIdx.x * kCompactWaves +
+                      __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   if (tix >= ntiles) return;
   const int lane = threadIdx.x & (kWave - 1);
   const int2 tv = tiles[tix];
@@ -638,18 +642,48 @@ __global__ void __launch_bounds__(kCompactThreads) st_compact_kernel(
     }
   }
   if (action == kEndImf) return;  // no knots: the candidate is the IMF
+  global_ptr<int32_t> kt[2];
+  global_ptr<double> ky[2];
+  global_ptr<const int32_t> lp[2];
+  global_ptr<const double> lv[2];
+  int ck[2];
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
-    const int ck = (cont_knot >> e) & 1;
-    const global_ptr<int32_t> kt = gmem(S.kt[e]);
-    const global_ptr<double> ky = gmem(S.ky[e]);
-    if (ck && lane == 0)
-      put_knot(kt, ky, off[e], nk[e], L, ((ti.carry >> 2) + ti.cont_pos) >> 1, ti.cont_y);
-    if (lane < cnt[e]) put_knot(kt, ky, off[e] + ck + lane, nk[e], L, p0[e], v0[e]);
-    const global_ptr<const int32_t> lp = gmem<const int32_t>(S.lpos[e]) + lo;
-    const global_ptr<const double> lv = gmem<const double>(S.lval[e]) + lo;
-    for (int i = lane + kWave; i < cnt[e]; i += kWave)
-      put_knot(kt, ky, off[e] + ck + i, nk[e], L, lp[i], lv[i]);
+    ck[e] = (cont_knot >> e) & 1;
+    kt[e] = gmem(S.kt[e]);
+    ky[e] = gmem(S.ky[e]);
+    lp[e] = gmem<const int32_t>(S.lpos[e]) + lo;
+    lv[e] = gmem<const double>(S.lval[e]) + lo;
+    if (ck[e] && lane == 0)
+      put_knot(kt[e], ky[e], off[e], nk[e], L, ((ti.carry >> 2) + ti.cont_pos) >> 1,
+               ti.cont_y);
+    if (lane < cnt[e]) put_knot(kt[e], ky[e], off[e] + ck[e] + lane, nk[e], L, p0[e], v0[e]);
+  }
+  // The rest of both lists in rounds of kCompactBatch entries per lane and
+  // list, every round's loads issued before its stores: a dense tile holds
+  // several hundred knots, and one load-store trip per entry would leave the
+  // wave waiting on one load at a time.
+  const int most = max(cnt[0], cnt[1]);
+  for (int i0 = lane + kWave; i0 < most; i0 += kCompactBatch * kWave) {
+    int p[2][kCompactBatch];
+    double v[2][kCompactBatch];
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+#pragma unroll
+      for (int u = 0; u < kCompactBatch; ++u) {
+        const int i = i0 + u * kWave;
+        if (i < cnt[e]) {
+          p[e][u] = lp[e][i];
+          v[e][u] = lv[e][i];
+        }
+      }
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+#pragma unroll
+      for (int u = 0; u < kCompactBatch; ++u) {
+        const int i = i0 + u * kWave;
+        if (i < cnt[e]) put_knot(kt[e], ky[e], off[e] + ck[e] + i, nk[e], L, p[e][u], v[e][u]);
+      }
   }
 }
 
