@@ -1168,14 +1168,27 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
   if (action == kSiftLast || action == kEndImf) {
     const global_ptr<double> slot = gmem(S.out) + (int64_t)st->slot * S.slot_stride;
     const global_ptr<double> rg = gmem(S.r);
-    for (int i = threadIdx.x; i < n; i += kTT) {
-      const int k = a + i;
-      const double hk = tbuf[tsw(i)];
-      const double nr = rg[k] - hk;
-      rg[k] = nr;
-      tbuf[tsw(i)] = nr;
-      const int64_t ii = k / R, m = k - ii * R;
-      if (m < M) slot[ii * M + m] = hk;
+    // all of the thread's residue samples are loaded before any store (the
+    // compiler cannot move a load above a store to the output, which might
+    // alias it)
+    double rv[kTC];
+#pragma unroll
+    for (int c = 0; c < kTC; ++c) {
+      const int i = threadIdx.x + c * kTT;
+      rv[c] = i < n ? rg[a + i] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < kTC; ++c) {
+      const int i = threadIdx.x + c * kTT;
+      if (i < n) {
+        const int k = a + i;
+        const double hk = tbuf[tsw(i)];
+        const double nr = rv[c] - hk;
+        rg[k] = nr;
+        tbuf[tsw(i)] = nr;
+        const int64_t ii = k / R, m = k - ii * R;
+        if (m < M) slot[ii * M + m] = hk;
+      }
     }
   }
   // The next step's candidate is on chip now: the sifted candidate (kSift),
