@@ -672,18 +672,34 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
   for (int c0 = 0; c0 < L; c0 += scap) {
     const int c1 = min(L, c0 + scap);
     __syncthreads();
-    for (int k = c0 + tid0; k < c1; k += NT) {
-      int i, m;
-      div_small(k, R, invR, i, m);
-      double v = (w.flags & kNoSignal) ? 0.0 : serial_at(w.X, M, D, i, m);
-      if (w.flags & (kAddNoise | kAddBuffer)) {
-        const double b = (w.flags & kScaleOnDevice) ? *w.scale : w.beta;
-        const double e = (w.flags & kAddNoise) ? noise_at(w.key, k) : w.addend[k];
-        v = __dadd_rn(v, __dmul_rn(b, e));
+    for (int k0 = c0 + tid0; k0 < c1; k0 += 4 * NT) {
+      // four elements per pass, formed before any of their stores (an input
+      // read cannot move above a store to r, which might alias the input)
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + u * NT;
+        v[u] = 0.0;
+        if (k < c1) {
+          int i, m;
+          div_small(k, R, invR, i, m);
+          v[u] = (w.flags & kNoSignal) ? 0.0 : serial_at(w.X, M, D, i, m);
+          if (w.flags & (kAddNoise | kAddBuffer)) {
+            const double b = (w.flags & kScaleOnDevice) ? *w.scale : w.beta;
+            const double e = (w.flags & kAddNoise) ? noise_at(w.key, k) : w.addend[k];
+            v[u] = __dadd_rn(v[u], __dmul_rn(b, e));
+          }
+        }
       }
-      bad |= !isfinite(v);
-      stage[stage_at<C>(k - c0)] = v;
-      w.r[k] = v;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + u * NT;
+        if (k < c1) {
+          bad |= !isfinite(v[u]);
+          stage[stage_at<C>(k - c0)] = v[u];
+          w.r[k] = v[u];
+        }
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -871,10 +887,22 @@ __global__ void __launch_bounds__(NT) resident_emd_kernel(const WorkItem* __rest
   // residue into slot K (every r[k] was last written by this same thread),
   // unused IMF slots zero (Sec. 4.3 zero fill)
   double* rslot = w.out + (int64_t)K * SS;
-  for (int k = tid0; k < L; k += NT) {
-    int i, m;
-    div_small(k, R, invR, i, m);
-    if (m < M) rslot[i * M + m] = w.r[k];
+  for (int k0 = tid0; k0 < L; k0 += 4 * NT) {
+    double rk[4];  // (loaded together, before the stores)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + u * NT;
+      rk[u] = k < L ? w.r[k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + u * NT;
+      if (k < L) {
+        int i, m;
+        div_small(k, R, invR, i, m);
+        if (m < M) rslot[i * M + m] = rk[u];
+      }
+    }
   }
   for (int q = nimf; q < K; ++q)
     for (int o = tid0; o < MN; o += NT) w.out[q * SS + o] = 0.0;
