@@ -914,9 +914,6 @@ __device__ __forceinline__ void st_walk_coefs(StWalk& w, int j, int t0, double y
   w.q3 = (w.m1 - m0) * ig * (1.0 / 12.0);
 }
 
-// Knot i (clamped to the last one) into the walker's look-ahead registers.
-
-
 // The segment holding sample k, searched forward from segment j (whose left
 // knot lies at or before k; the last knot lies beyond the signal), and its
 // left knot's position t0.
