@@ -139,6 +139,24 @@ __device__ __forceinline__ int block_excl_max(int v, int* scratch, int& total) {
 static_assert(kTC == 8, "tile buffer swizzle assumes 8 samples per thread");
 __device__ __forceinline__ int tsw(int i) { return i ^ ((i >> 5) & 7); }
 
+// Two consecutive samples, moved by one 16-byte access.
+struct alignas(16) SamplePair {
+  double x, y;
+};
+
+// Samples 0..n-1 of the tile buffer to dst (a tile's first sample: 16-byte
+// aligned), in sample pairs.
+__device__ __forceinline__ void store_tile(global_ptr<double> dst, int n, const double* tbuf) {
+  const global_ptr<SamplePair> d2 = (global_ptr<SamplePair>)dst;
+  for (int j = threadIdx.x; j < n / 2; j += kTileThreads) {
+    const int s0 = tsw(2 * j);
+    auto& d = d2[j];  // (one 16-byte store)
+    d.x = tbuf[s0];
+    d.y = tbuf[s0 ^ 1];
+  }
+  if ((n & 1) && threadIdx.x == 0) dst[n - 1] = tbuf[tsw(n - 1)];
+}
+
 // ---------------------------------------------------------------------------
 // Extrema of a tile (Sec. 2.1 Step 1) from per-thread step masks
 // ---------------------------------------------------------------------------
@@ -1016,7 +1034,18 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
   const global_ptr<double> hg = gmem(S.h);
   {
     const global_ptr<const double> cand = st->in_r ? gmem<const double>(S.r) : hg;
-    for (int i = threadIdx.x; i < n; i += kTT) tbuf[tsw(i)] = cand[a + i];
+    // sample pairs in 16-byte loads (a tile starts at an even sample of a
+    // 256-byte-aligned buffer); samples 2j and 2j+1 land at tsw(2j) and
+    // tsw(2j) ^ 1
+    const global_ptr<const SamplePair> c2 = (global_ptr<const SamplePair>)(cand + a);
+    for (int j = threadIdx.x; j < n / 2; j += kTT) {
+      const auto& v = c2[j];  // (one 16-byte load)
+      const double x = v.x, y = v.y;
+      const int s0 = tsw(2 * j);
+      tbuf[s0] = x;
+      tbuf[s0 ^ 1] = y;
+    }
+    if ((n & 1) && threadIdx.x == 0) tbuf[tsw(n - 1)] = cand[a + n - 1];
   }
   if (action == kSift || action == kSiftLast) {
     const int lb = threadIdx.x * kTC;
@@ -1223,7 +1252,7 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
     // the sifted candidate goes out now (a new IMF's first candidate is in r
     // already); the tile buffer then stages the knot lists
     if (action == kSift)
-      for (int i = threadIdx.x; i < n; i += kTT) hg[a + i] = tbuf[tsw(i)];
+      store_tile(hg + a, n, tbuf);
     record_tile(d, h, a, first_key, cont_exit, cont_pos, cont_y, S, tv.y, scratch64, scratch,
                 tbuf);
   }
