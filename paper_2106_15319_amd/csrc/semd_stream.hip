@@ -871,19 +871,25 @@ __global__ void __launch_bounds__(kTT, 6) st_solve_kernel(const StreamSig* __res
       const double a2 = dpp_move<kDppWaveShl1, 0xf>(al), b2 = dpp_move<kDppWaveShl1, 0xf>(be);
       if (lane + 1 < kWave) Mn = fma(b2, Mn, a2);
     }
-    double* km = S.km[env];
+    // The block's second derivatives go through the LDS window (its values
+    // are no longer read: every thread is past the forward passes) and out
+    // in coalesced stores; a thread's own rows lie R doubles apart from its
+    // neighbours'.
   #pragma unroll
     for (int q = kRMax - 1; q >= 0; --q) {
       const int j = j0 + q;
       if (q < R && j <= a1) {
         const double Mj = fma(-cpa[q], Mn, dpa[q]);
-        if (j >= r0 && j < r1) {
-          km[j] = Mj;
-          if (j == 1) km[0] = 0.0;            // natural end conditions
-          if (j == n2 - 2) km[n2 - 1] = 0.0;
-        }
+        if (j >= r0 && j < r1) ly[j - w0] = Mj;
         Mn = Mj;
       }
+    }
+    __syncthreads();
+    const global_ptr<double> km = gmem(S.km[env]);
+    for (int j = r0 + threadIdx.x; j < r1; j += kTT) km[j] = ly[j - w0];
+    if (threadIdx.x == 0) {  // natural end conditions
+      if (r0 == 1) km[0] = 0.0;
+      if (r1 == n2 - 1) km[n2 - 1] = 0.0;
     }
   }
 #undef T
