@@ -139,9 +139,13 @@ __device__ __forceinline__ int block_excl_max(int v, int* scratch, int& total) {
 static_assert(kTC == 8, "tile buffer swizzle assumes 8 samples per thread");
 __device__ __forceinline__ int tsw(int i) { return i ^ ((i >> 5) & 7); }
 
-// Two consecutive samples, moved by one 16-byte access.
+// Two consecutive samples (or knot values), moved by one 16-byte access,
+// and two consecutive knot positions.
 struct alignas(16) SamplePair {
   double x, y;
+};
+struct alignas(8) RankPair {
+  int32_t x, y;
 };
 
 // Samples 0..n-1 of the tile buffer to dst (a tile's first sample: 16-byte
@@ -745,9 +749,9 @@ __global__ void __launch_bounds__(kTT) st_trace_kernel(const StreamSig* __restri
 // m_j of its rows in r0..r1-1, and the zeros of the two end knots when it
 // holds row 1 or row n-2; the evaluation forms each segment's cubic from
 // the knots at its ends.
-// (bounded to 80 VGPRs, which it fits without spilling: six waves per
+// (bounded to 72 VGPRs, which it fits without spilling: seven waves per
 // SIMD; the LDS window would allow eight workgroups per CU)
-__global__ void __launch_bounds__(kTT, 6) st_solve_kernel(const StreamSig* __restrict__ sigs,
+__global__ void __launch_bounds__(kTT, 7) st_solve_kernel(const StreamSig* __restrict__ sigs,
                                                           const int4* __restrict__ blocks) {
   constexpr int kW = kSB + 2 * kHalo + 4;
   constexpr int kRMax = (kSB + 2 * kHalo + kTT - 1) / kTT;
@@ -772,11 +776,33 @@ __global__ void __launch_bounds__(kTT, 6) st_solve_kernel(const StreamSig* __res
     const int r1 = min(r0 + kSB, n2 - 1);  // rows r0 .. r1-1
     const int a0 = max(1, r0 - kHalo), a1 = min(n2 - 2, r1 - 1 + kHalo);
     const int w0 = a0 - 1, w1 = a1 + 1;    // knots read
-    const int32_t* kt = S.kt[env];
-    const double* ky = S.ky[env];
-    for (int i = threadIdx.x; i <= w1 - w0; i += kTT) {
-      lt[i] = kt[w0 + i];
-      ly[i] = ky[w0 + i];
+    const global_ptr<const int32_t> kt = gmem<const int32_t>(S.kt[env]);
+    const global_ptr<const double> ky = gmem<const double>(S.ky[env]);
+    {
+      // knot pairs from an even index (16-byte value loads), the window's
+      // first knot alone when w0 is odd and its last when a pair is left
+      const int nw = w1 - w0 + 1, head = w0 & 1, np = (nw - head) / 2;
+      const global_ptr<const RankPair> t2 = (global_ptr<const RankPair>)(kt + w0 + head);
+      const global_ptr<const SamplePair> y2 = (global_ptr<const SamplePair>)(ky + w0 + head);
+      for (int p = threadIdx.x; p < np; p += kTT) {
+        const auto& tp = t2[p];
+        const auto& yp = y2[p];
+        const int32_t ta = tp.x, tb = tp.y;
+        const double ya = yp.x, yb = yp.y;
+        const int i = head + 2 * p;
+        lt[i] = ta;
+        lt[i + 1] = tb;
+        ly[i] = ya;
+        ly[i + 1] = yb;
+      }
+      if (threadIdx.x == 0 && head) {
+        lt[0] = kt[w0];
+        ly[0] = ky[w0];
+      }
+      if (threadIdx.x == kWave && ((nw - head) & 1)) {
+        lt[nw - 1] = kt[w1];
+        ly[nw - 1] = ky[w1];
+      }
     }
     __syncthreads();
   #define T(j) ((double)lt[(j) - w0])
