@@ -85,6 +85,9 @@ def measured_traffic(n_images: int, D: int):
         return None
 
 
+# longest serialized signal the automatic path decomposes on chip
+ONCHIP_MAX_LENGTH = 16384
+
 STREAM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "st_eval_kernel_eemd_uneven_traffic.txt")
 STREAM_SOURCES = ["semd_stream.hip", "semd_stream.h", "semd_device.h", "semd_internal.h"]
 
@@ -124,10 +127,19 @@ def copy_probe(mib: int, reps: int) -> int:
     n = mib * (1 << 20) // 8
     a = torch.ones(n, dtype=torch.float64, device="cuda:0")
     b = torch.empty_like(a)
+    b.copy_(a)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
     for _ in range(reps):
         b.copy_(a)
+    t1.record()
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes": n * 8, "reps": reps}), flush=True)
+    ms = t0.elapsed_time(t1) / reps
+    # read plus written bytes over the copy's average time: the bandwidth a
+    # plain streaming kernel reaches, beside the 8 TB/s peak
+    print(json.dumps({"copy_bytes": n * 8, "reps": reps, "avg_ms": ms,
+                      "read_plus_write_GBps": 2 * n * 8 / (ms / 1e3) / 1e9}), flush=True)
     return 0
 
 
@@ -513,8 +525,14 @@ def run_textures(args, semd, torch, workloads):
                       "batched_over_plain": ms / bms}
     res["work"] = work
     flops = FLOPS_PER_SAMPLE_SIFT * work["sample_sifts"] + FLOPS_PER_KNOT * work["knots"]
-    res["roofline"] = roofline_alu(flops / n, float(np.mean(lat)),
-                                   "resident_emd_kernel (1 workgroup per launch)")
+    if L <= ONCHIP_MAX_LENGTH:
+        res["roofline"] = roofline_alu(flops / n, float(np.mean(lat)),
+                                       "resident_emd_kernel (1 workgroup per launch)")
+    else:
+        # beyond the on-chip limit one call is a whole streaming decomposition
+        # (many kernels), so no single kernel's roofline describes it
+        res["roofline"] = None
+        res["path"] = "streaming"
     if not args.no_cpu:
         threads = cpu_threads()
         rate, dt, samples = cpu_decompose_rate(items, D, K, S, threads)
