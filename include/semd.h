@@ -374,6 +374,16 @@ int semd_engine_admit(semd_engine* e, const semd_item* item, const semd_params* 
 /* One step of every resident request, enqueued on `stream`. */
 int semd_engine_step(semd_engine* e, hipStream_t stream);
 
+/* n_steps consecutive steps in one call, enqueued on `stream`: the requests
+ * admitted since the last call (on chip: whole) start with the first, and
+ * every streaming request advances by n_steps sifts (Sec. 2.1), or less
+ * when it finishes on the way; outputs are the same as from n_steps calls
+ * of semd_engine_step.  Completions are gathered once, after the last step,
+ * so a caller with no request waiting for admission saves the per-step host
+ * round trip.  n_steps outside [1, SEMD_ENGINE_MAX_STEPS] is SEMD_EINVAL. */
+#define SEMD_ENGINE_MAX_STEPS 64
+int semd_engine_step_n(semd_engine* e, int n_steps, hipStream_t stream);
+
 /* Up to cap tickets ([host] done) of requests whose outputs are complete in
  * stream order; n_done receives their number.  Does not wait for the device
  * except for the step before the last one issued. */

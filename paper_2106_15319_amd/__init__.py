@@ -36,6 +36,7 @@ SEMD_PATH_ONCHIP = 1
 SEMD_PATH_STREAM = 2
 SEMD_STOP_FIXED = 0
 SEMD_STOP_SD = 1
+SEMD_ENGINE_MAX_STEPS = 64  # steps per semd_engine_step_n call
 
 
 class SemdError(RuntimeError):
@@ -108,6 +109,7 @@ _EXPORTS = {
     "semd_engine_admit": (C.c_int, [C.c_void_p, C.POINTER(semd_item), C.POINTER(semd_params),
                                     C.POINTER(C.c_int64)]),
     "semd_engine_step": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "semd_engine_step_n": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
     "semd_engine_poll": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_int,
                                    C.POINTER(C.c_int)]),
     "semd_engine_resident": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
@@ -678,6 +680,11 @@ class Engine:
 
     def step(self, stream=None) -> None:
         _check(lib().semd_engine_step(self._h, _stream(stream)), "semd_engine_step")
+
+    def step_n(self, n_steps: int, stream=None) -> None:
+        """n_steps steps in one call; completions are gathered after the last."""
+        _check(lib().semd_engine_step_n(self._h, int(n_steps), _stream(stream)),
+               "semd_engine_step_n")
 
     def poll(self, cap: int = 4096) -> list[int]:
         buf = (C.c_int64 * cap)()

@@ -1820,8 +1820,14 @@ int semd_engine_admit(semd_engine* e, const semd_item* item, const semd_params* 
 }
 
 int semd_engine_step(semd_engine* e, hipStream_t stream) {
+  return semd_engine_step_n(e, 1, stream);
+}
+
+int semd_engine_step_n(semd_engine* e, int n_steps, hipStream_t stream) {
   g_err[0] = 0;
   if (!e) return fail(SEMD_EINVAL, "engine is NULL");
+  if (n_steps < 1 || n_steps > SEMD_ENGINE_MAX_STEPS)
+    return fail(SEMD_EINVAL, "n_steps %d outside [1, %d]", n_steps, SEMD_ENGINE_MAX_STEPS);
   std::lock_guard<std::mutex> lock(g_engine_mu);
   e->last_stream = stream;
   // on-chip requests admitted since the last step: whole decompositions,
@@ -1906,7 +1912,9 @@ int semd_engine_step(semd_engine* e, hipStream_t stream) {
       });
       e->graph_ok = he == hipSuccess;
     }
-    if (he == hipSuccess) he = e->graph.launch(cs.s);
+    // (a request that finishes within the replays idles through the rest:
+    // every kernel returns at once on a finished signal)
+    for (int k = 0; k < n_steps && he == hipSuccess; ++k) he = e->graph.launch(cs.s);
     if (he == hipSuccess) he = cs.join();
   }
   if (he != hipSuccess) return hip_fail(he, "engine step");

@@ -148,6 +148,8 @@ def test_engine_validation_without_device():
     t = C.c_int64()
     assert L.semd_engine_admit(None, C.byref(it), C.byref(p), C.byref(t)) == semd.SEMD_EINVAL
     assert L.semd_engine_step(None, None) == semd.SEMD_EINVAL
+    assert L.semd_engine_step_n(None, 1, None) == semd.SEMD_EINVAL
+    assert L.semd_engine_step_n(None, 0, None) == semd.SEMD_EINVAL
     h = C.c_void_p()
     assert L.semd_engine_create(1 << 30, 0, C.byref(h)) == semd.SEMD_EINVAL
     assert L.semd_engine_create(10, 4, C.byref(h)) == semd.SEMD_EINVAL

@@ -849,6 +849,44 @@ def test_engine_short_requests_finish_within_two_steps():
     eng.close()
 
 
+def test_engine_multi_step_calls_match_single_steps():
+    """semd_engine_step_n: several steps per call give each request the same
+    bits as semd_decompose_ex, with a request admitted between bursts and
+    bursts that run past a request's end; n_steps outside [1, 64] is
+    rejected."""
+    K, S, D = 5, 8, 4
+    shapes = [(9000, 3), (1500, 2), (30000, 1), (700, 4)]
+    Xs = [_series(19, k, M, N) for k, (M, N) in enumerate(shapes)]
+    outs = [torch.empty((K + 1, M * N), dtype=torch.float64, device=DEV) for M, N in shapes]
+    cnts = [torch.empty(1, dtype=torch.int32, device=DEV) for _ in shapes]
+    eng = semd.Engine(1 << 30, 16)
+    with pytest.raises(RuntimeError):
+        eng.step_n(0)
+    with pytest.raises(RuntimeError):
+        eng.step_n(semd.SEMD_ENGINE_MAX_STEPS + 1)
+    owner = {}
+    for k in (0, 1, 2):
+        M, N = shapes[k]
+        owner[eng.admit(dev(Xs[k]), (M, N), outs[k], cnts[k], D, K, S)] = k
+    eng.step_n(7)
+    M, N = shapes[3]
+    owner[eng.admit(dev(Xs[3]), (M, N), outs[3], cnts[3], D, K, S)] = 3
+    done = set()
+    for _ in range(K * S):
+        eng.step_n(13)
+        done.update(eng.poll())
+        if len(done) == len(shapes):
+            break
+    torch.cuda.synchronize()
+    done.update(eng.poll())
+    assert done == set(owner)
+    eng.close()
+    for k, (M, N) in enumerate(shapes):
+        ref, nref = semd.semd_decompose_ex(dev(Xs[k]), [M, N], D, K, S)
+        assert_same(host(outs[k]), host(ref), f"engine burst request {k}")
+        assert int(host(cnts[k])[0]) == int(host(nref)[0])
+
+
 def test_engine_admission_budget_and_staggered_arrivals():
     K, S, D = 4, 6, 0
     M, N = 6000, 3  # 18,000 samples: streaming
