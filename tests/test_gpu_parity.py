@@ -703,6 +703,23 @@ def test_stream_long_signals(M, N, K, S):
     tally.done()
 
 
+@pytest.mark.timeout(900)
+def test_stream_longest_signal():
+    """The longest serialized signal the library takes, 2^28 samples of
+    white noise (the densest knot sets, about L/3 knots per envelope): two
+    IMFs of one sift each, element by element against the oracle."""
+    L, K, S = 1 << 28, 2, 1
+    x = np.random.default_rng(2828).standard_normal(L)
+    print(f"longest signal: L={L} K={K} S={S}", flush=True)
+    out, n = semd.semd_decompose_ex(dev(x), [L, 1], 0, K, S)
+    o = host(out)
+    del out
+    torch.cuda.empty_cache()
+    tally = Tally("white noise at the longest length")
+    _check_item(x, L, 1, 0, K, S, o, int(host(n)[0]), tally)
+    tally.done()
+
+
 def test_auto_routes_mixed_batch():
     shapes = [(100, 3), (30000, 2), (5000, 2), (11, 1), (40000, 1)]
     Xs = [_series(13, k, M, N) for k, (M, N) in enumerate(shapes)]
