@@ -462,7 +462,13 @@ static_assert(kBuckets[kNBuckets - 1] == semd::kResidentMaxL, "buckets cover the
 struct TuneTable {
   semd::ResidentClass cls[2][kNBuckets];
   bool set[2][kNBuckets];
+  // streaming batches: unfolded solve blocks per workgroup slot (0: the
+  // built-in value)
+  int solve_target;
 };
+// candidates the tuner times for it
+constexpr int kSolveTargets[] = {1024, 2048, 4096, 8192, 16384};
+constexpr int kMaxSolveTarget = 1 << 20;
 std::mutex g_tune_mu;
 TuneTable g_tune{};
 
@@ -626,13 +632,19 @@ semd::StreamSig stream_sig(const semd::WorkItem& w, int K, int S, unsigned char*
 }
 
 // Tile and solve-block tables of a list of streaming signals.
+// solve_target: unfolded solve blocks per workgroup slot, or < 0 for the
+// tuned table's value.
 void stream_tables(const std::vector<semd::StreamSig>& sigs, std::vector<int2>& tiles,
-                   std::vector<int4>& blocks) {
+                   std::vector<int4>& blocks, int solve_target = -1) {
   tiles.clear();
   blocks.clear();
+  if (solve_target < 0) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    solve_target = g_tune.solve_target;
+  }
   int64_t total = 0;
   for (const auto& g : sigs) total += 2 * (int64_t)semd::stream_solve_blocks(g.cap);
-  const int fold = semd::stream_solve_fold(total);
+  const int fold = semd::stream_solve_fold(total, solve_target);
   for (int i = 0; i < (int)sigs.size(); ++i) {
     for (int t = 0; t < sigs[i].ntiles; ++t) tiles.push_back(make_int2(i, t));
     const int G = semd::stream_solve_groups(sigs[i].cap, fold);
@@ -660,7 +672,7 @@ std::vector<unsigned char> pack_tables(const std::vector<semd::StreamSig>& sigs,
 
 // Decompose `work` on the streaming path: K*S steps of every signal.
 int run_stream(const std::vector<semd::WorkItem>& work, int K, int S, hipStream_t stream,
-               Carve* into = nullptr) {
+               Carve* into = nullptr, int solve_target = -1) {
   const int n = (int)work.size();
   if (n == 0) return SEMD_OK;
   size_t bytes = 0;
@@ -685,7 +697,7 @@ int run_stream(const std::vector<semd::WorkItem>& work, int K, int S, hipStream_
   {
     HostPhase hp(kHTables);
     for (int i = 0; i < n; ++i) sigs[i] = stream_sig(work[i], K, S, arena + offs[i]);
-    stream_tables(sigs, tiles, blocks);
+    stream_tables(sigs, tiles, blocks, solve_target);
     pack = pack_tables(sigs, tiles, blocks, &o_til, &o_blk);
   }
   void* d_pack = nullptr;
@@ -1028,6 +1040,49 @@ int semd_autotune(int64_t max_length, int batch, hipStream_t stream) {
       }
     }
   }
+  // Streaming batches: the solve launch's fold, timed on a batch of 2 x CUs
+  // synthetic signals of 65,536 samples (three sifts of two IMFs), one
+  // candidate target after another.  The fold maps blocks to workgroups
+  // and leaves the arithmetic as it is.
+  if (rc == SEMD_OK) {
+    const int64_t L = 65536;
+    const int n = 2 * cus, Ks = 2, Ss = 3;
+    double *X = nullptr, *out = nullptr;
+    if (hipMalloc(reinterpret_cast<void**>(&X), sizeof(double) * L * n) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&out), sizeof(double) * L * (Ks + 1) * n) !=
+            hipSuccess) {
+      if (X) (void)hipFree(X);
+      rc = fail(SEMD_ENOMEM, "tuning buffers for %d signals of %lld samples", n, (long long)L);
+    } else {
+      std::vector<semd::WorkItem> work;
+      Shape sh{L, 1, L};
+      for (int i = 0; i < n; ++i)
+        work.push_back(make_work(X + i * L, out + i * L * (Ks + 1), nullptr, sh, 0, 0.0));
+      hipError_t he = semd::launch_synth(X, L, n, 2106, stream);
+      float best_ms = 0.0f;
+      int best = 0;
+      for (int target : kSolveTargets) {
+        if (he != hipSuccess || rc != SEMD_OK) break;
+        rc = run_stream(work, Ks, Ss, stream, nullptr, target);  // warm-up
+        if (rc == SEMD_OK) he = hipEventRecord(e0, stream);
+        for (int r = 0; r < 2 && rc == SEMD_OK && he == hipSuccess; ++r)
+          rc = run_stream(work, Ks, Ss, stream, nullptr, target);
+        if (rc == SEMD_OK && he == hipSuccess) he = hipEventRecord(e1, stream);
+        if (rc == SEMD_OK && he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (rc == SEMD_OK && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (rc == SEMD_OK && he == hipSuccess && (best == 0 || ms < best_ms)) {
+          best = target;
+          best_ms = ms;
+        }
+      }
+      if (he != hipSuccess && rc == SEMD_OK) rc = hip_fail(he, "tuning run");
+      (void)hipStreamSynchronize(stream);
+      (void)hipFree(X);
+      (void)hipFree(out);
+      if (rc == SEMD_OK && best > 0) t.solve_target = best;
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc == SEMD_OK) {
@@ -1040,6 +1095,7 @@ int semd_autotune(int64_t max_length, int batch, hipStream_t stream) {
 // Text form of the table:
 //   semd-tune <abi> <gfx arch>
 //   latency|throughput <bucket bound> <threads> <samples per thread>
+//   stream-solve <unfolded solve blocks per workgroup slot>
 int semd_tune_get(char* buf, size_t cap, size_t* needed) {
   g_err[0] = 0;
   if (!needed) return fail(SEMD_EINVAL, "needed is NULL");
@@ -1057,6 +1113,8 @@ int semd_tune_get(char* buf, size_t cap, size_t* needed) {
           text += std::string(r == 0 ? "latency " : "throughput ") +
                   std::to_string(kBuckets[b]) + " " + std::to_string(g_tune.cls[r][b].nt) + " " +
                   std::to_string(g_tune.cls[r][b].c) + "\n";
+    if (g_tune.solve_target > 0)
+      text += "stream-solve " + std::to_string(g_tune.solve_target) + "\n";
   }
   *needed = text.size() + 1;
   if (buf && cap > 0) {
@@ -1088,10 +1146,21 @@ int semd_tune_set(const char* text) {
   p += used;
   for (;;) {
     char word[16] = "";
+    if (std::sscanf(p, "%15s%n", word, &used) != 1) break;
+    p += used;
+    if (std::strcmp(word, "stream-solve") == 0) {
+      int target = 0;
+      if (std::sscanf(p, "%d%n", &target, &used) != 1)
+        return fail(SEMD_EINVAL, "malformed tuning entry");
+      p += used;
+      if (target < 1 || target > kMaxSolveTarget)
+        return fail(SEMD_EINVAL, "invalid tuning entry stream-solve %d", target);
+      t.solve_target = target;
+      continue;
+    }
     int bound = 0, nt = 0, c = 0;
-    const int got = std::sscanf(p, "%15s %d %d %d%n", word, &bound, &nt, &c, &used);
-    if (got == EOF || got <= 0) break;
-    if (got != 4) return fail(SEMD_EINVAL, "malformed tuning entry");
+    if (std::sscanf(p, "%d %d %d%n", &bound, &nt, &c, &used) != 3)
+      return fail(SEMD_EINVAL, "malformed tuning entry");
     p += used;
     const int r = std::strcmp(word, "latency") == 0 ? 0
                   : std::strcmp(word, "throughput") == 0 ? 1

@@ -126,8 +126,10 @@ hipError_t st_gather_done(const StreamSig* sigs, int nsig, int32_t* done, hipStr
 int stream_solve_blocks(int cap);
 // The fold of a launch whose envelopes span `total_blocks` solve blocks, and
 // the workgroups (solve-table entries) one envelope of `cap` knots takes
-// under it: workgroup z of G handles blocks z, z + G, ...
-int stream_solve_fold(int64_t total_blocks);
+// under it: workgroup z of G handles blocks z, z + G, ...  The fold gives
+// one workgroup slot per `target` blocks (a tuned value; 0 takes the
+// built-in one), at most the compiled maximum.
+int stream_solve_fold(int64_t total_blocks, int target = 0);
 int stream_solve_groups(int cap, int fold);
 
 }  // namespace semd

@@ -45,8 +45,8 @@ constexpr int kSolveTarget = 4096;
 constexpr int kSolveFoldMax = 32;
 __host__ __device__ constexpr int solve_blocks(int cap) { return (cap + kSB - 1) / kSB; }
 // Solve blocks per workgroup of a folded launch over `units` blocks.
-inline int launch_fold(int64_t units) {
-  return (int)std::min<int64_t>(kSolveFoldMax, std::max<int64_t>(1, units / kSolveTarget));
+inline int launch_fold(int64_t units, int target = kSolveTarget) {
+  return (int)std::min<int64_t>(kSolveFoldMax, std::max<int64_t>(1, units / target));
 }
 constexpr int kNW = kTT / kWave;
 constexpr int kCompactWaves = 4;  // tiles per compaction workgroup, one wave each
@@ -1387,7 +1387,9 @@ hipError_t st_gather_done(const StreamSig* sigs, int nsig, int32_t* done, hipStr
 
 int stream_solve_blocks(int cap) { return solve_blocks(cap); }
 
-int stream_solve_fold(int64_t total_blocks) { return launch_fold(total_blocks); }
+int stream_solve_fold(int64_t total_blocks, int target) {
+  return launch_fold(total_blocks, target > 0 ? target : kSolveTarget);
+}
 
 int stream_solve_groups(int cap, int fold) {
   return (stream_solve_blocks(cap) + fold - 1) / fold;

@@ -980,17 +980,43 @@ def test_every_launch_shape_gives_identical_results():
         semd.semd_tune_reset()
 
 
+@pytest.mark.parametrize("target", [1, 1024, 65536])
+def test_stream_solve_target_gives_identical_results(target):
+    """The tuned streaming solve target changes how solve blocks map to
+    workgroups (the launch's fold), not the decomposition: a streaming batch
+    gives the same bits under it as under the built-in value."""
+    rng = np.random.default_rng(31)
+    shapes = [(30000, 2), (17000, 1), (9000, 4), (120000, 1)]
+    items = [(rng.standard_normal(M * N) + np.sin(np.arange(M * N) / 7.0), M, N)
+             for M, N in shapes]
+    Xs = [dev(x) for x, _, _ in items]
+    try:
+        semd.semd_tune_reset()
+        ref, rc = semd.decompose_batch(Xs, [(M, N) for _, M, N in items], 0, 5, 6)
+        header = semd.semd_tune_get().splitlines()[0]
+        semd.semd_tune_set(f"{header}\nstream-solve {target}\n")
+        assert semd.semd_tune_get().splitlines()[1:] == [f"stream-solve {target}"]
+        got, gc = semd.decompose_batch(Xs, [(M, N) for _, M, N in items], 0, 5, 6)
+    finally:
+        semd.semd_tune_reset()
+    for k in range(len(items)):
+        assert_same(host(got[k]), host(ref[k]), f"solve target {target}, item {k}")
+    assert np.array_equal(host(gc), host(rc))
+
+
 def test_autotune_round_trip():
     try:
         semd.semd_autotune(4096, 256)
         text = semd.semd_tune_get()
         lines = text.splitlines()
         assert lines[0].startswith(f"semd-tune {semd.semd_abi_version()} gfx")
-        entries = [l.split() for l in lines[1:]]
+        entries = [l.split() for l in lines[1:] if not l.startswith("stream-solve")]
         assert {e[0] for e in entries} == {"latency", "throughput"}
         assert {int(e[1]) for e in entries} == {1024, 2048, 3072, 4096}
         for e in entries:
             assert int(e[2]) * int(e[3]) >= int(e[1])
+        solve = [l.split() for l in lines[1:] if l.startswith("stream-solve")]
+        assert len(solve) == 1 and int(solve[0][1]) in (1024, 2048, 4096, 8192, 16384)
         semd.semd_tune_reset()
         assert semd.semd_tune_get().splitlines()[1:] == []
         semd.semd_tune_set(text)
@@ -999,6 +1025,10 @@ def test_autotune_round_trip():
             semd.semd_tune_set(text.replace("gfx", "gfy", 1))
         with pytest.raises(semd.SemdError):
             semd.semd_tune_set(lines[0] + "\nlatency 4096 256 4\n")  # too small a shape
+        with pytest.raises(semd.SemdError):
+            semd.semd_tune_set(lines[0] + "\nstream-solve 0\n")
+        with pytest.raises(semd.SemdError):
+            semd.semd_tune_set(lines[0] + "\nstream-solve\n")
         assert semd.semd_tune_get() == text  # unchanged by the rejected tables
         # decompositions under the tuned table still match the oracle
         it = workloads.config0()
