@@ -1046,7 +1046,7 @@ __device__ __forceinline__ double st_walk_at(StWalk& w, const KnotView& K, int k
 // the sift accumulates; the instance without them holds fewer registers
 // through the walk.
 template <bool SD>
-__global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restrict__ sigs,
+__global__ void __launch_bounds__(kTT, 8) st_eval_kernel(const StreamSig* __restrict__ sigs,
                                                       const int2* __restrict__ tiles) {
   __shared__ double tbuf[kTile];
   __shared__ int pub_key[kTT];
@@ -1064,51 +1064,71 @@ __global__ void __launch_bounds__(kTT) st_eval_kernel(const StreamSig* __restric
   const int L = S.L;
   const int a = tv.y * kTile, n = min(kTile, L - a);
   const global_ptr<double> hg = gmem(S.h);
+  // The candidate tile's sample pairs are loaded into registers first, and
+  // stored to the tile buffer only after the walk's start below has issued
+  // its own reads (ranks, tile counts, knot positions), so that the two
+  // latencies overlap.  Pairs are 16-byte loads (a tile starts at an even
+  // sample of a 256-byte-aligned buffer); samples 2j and 2j+1 land at
+  // tsw(2j) and tsw(2j) ^ 1.
+  constexpr int kPairs = kTile / 2 / kTT;
+  static_assert(kPairs * 2 * kTT == kTile, "a tile is whole pairs per thread");
+  double px[kPairs], py[kPairs];
+  double odd = 0.0;
   {
     const global_ptr<const double> cand = st->in_r ? gmem<const double>(S.r) : hg;
-    // sample pairs in 16-byte loads (a tile starts at an even sample of a
-    // 256-byte-aligned buffer); samples 2j and 2j+1 land at tsw(2j) and
-    // tsw(2j) ^ 1
     const global_ptr<const SamplePair> c2 = (global_ptr<const SamplePair>)(cand + a);
-    for (int j = threadIdx.x; j < n / 2; j += kTT) {
-      const auto& v = c2[j];  // (one 16-byte load)
-      const double x = v.x, y = v.y;
-      const int s0 = tsw(2 * j);
-      tbuf[s0] = x;
-      tbuf[s0 ^ 1] = y;
-    }
-    if ((n & 1) && threadIdx.x == 0) tbuf[tsw(n - 1)] = cand[a + n - 1];
-  }
-  if (action == kSift || action == kSiftLast) {
-    const int lb = threadIdx.x * kTC;
-    const int nv = max(0, min(kTC, n - lb));
-    const int k0 = a + lb;
-    // thread 0 starts one sample early for the previous tile's last sample
-    const int ks = (threadIdx.x == 0 && a > 0) ? k0 - 1 : k0;
-    const KnotView kv[2] = {knot_view(S, 0, st->n[0]), knot_view(S, 1, st->n[1])};
-    // the thread holding the tile's last sample continues to the next
-    // tile's first sample
-    const bool tail = nv > 0 && lb + nv == n && a + n < L;
-    int js[2] = {0, 0}, jt0[2] = {0, 0};  // the segments holding sample ks, their left knots
-    if (nv > 0) {
-      const uint32_t tr =
-          (uint32_t)gmem<const int32_t>(S.trank)[(int64_t)tv.y * kTT + threadIdx.x];
-      const auto& ti = gmem<const TileInfo>(S.tinfo)[tv.y];
-      // the continued run's extremum precedes this thread's knots when the
-      // run ends in an earlier thread of the tile
-      const bool cont_before = ti.cont_pos >= 0 && ti.cont_pos < k0;
 #pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const int nk = st->n[e];
-        const int Pp = nk < 2 ? nk : 2;
-        const int rank = ti.off[e] + (cont_before ? ((ti.cont_knot >> e) & 1) : 0) +
-                         (int)(e ? tr >> 16 : tr & 0xffffu);
-        // the last knot of earlier threads lies before the thread's first
-        // sample (and before sample a-1 for thread 0: it lies in an earlier
-        // tile or is a mirrored knot)
-        js[e] = st_walk_find(kv[e], Pp + rank - 1, ks, jt0[e]);
+    for (int u = 0; u < kPairs; ++u) {
+      const int j = threadIdx.x + u * kTT;
+      if (j < n / 2) {
+        const auto& v = c2[j];  // (one 16-byte load)
+        px[u] = v.x;
+        py[u] = v.y;
       }
     }
+    if ((n & 1) && threadIdx.x == 0) odd = cand[a + n - 1];
+  }
+  const bool sift = action == kSift || action == kSiftLast;
+  const int lb = threadIdx.x * kTC;
+  const int nv = max(0, min(kTC, n - lb));
+  const int k0 = a + lb;
+  // thread 0 starts one sample early for the previous tile's last sample
+  const int ks = (threadIdx.x == 0 && a > 0) ? k0 - 1 : k0;
+  const KnotView kv[2] = {knot_view(S, 0, st->n[0]), knot_view(S, 1, st->n[1])};
+  // the thread holding the tile's last sample continues to the next tile's
+  // first sample
+  const bool tail = nv > 0 && lb + nv == n && a + n < L;
+  int js[2] = {0, 0}, jt0[2] = {0, 0};  // the segments holding sample ks, their left knots
+  if (sift && nv > 0) {
+    const uint32_t tr =
+        (uint32_t)gmem<const int32_t>(S.trank)[(int64_t)tv.y * kTT + threadIdx.x];
+    const auto& ti = gmem<const TileInfo>(S.tinfo)[tv.y];
+    // the continued run's extremum precedes this thread's knots when the
+    // run ends in an earlier thread of the tile
+    const bool cont_before = ti.cont_pos >= 0 && ti.cont_pos < k0;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int nk = st->n[e];
+      const int Pp = nk < 2 ? nk : 2;
+      const int rank = ti.off[e] + (cont_before ? ((ti.cont_knot >> e) & 1) : 0) +
+                       (int)(e ? tr >> 16 : tr & 0xffffu);
+      // the last knot of earlier threads lies before the thread's first
+      // sample (and before sample a-1 for thread 0: it lies in an earlier
+      // tile or is a mirrored knot)
+      js[e] = st_walk_find(kv[e], Pp + rank - 1, ks, jt0[e]);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kPairs; ++u) {
+    const int j = threadIdx.x + u * kTT;
+    if (j < n / 2) {
+      const int s0 = tsw(2 * j);
+      tbuf[s0] = px[u];
+      tbuf[s0 ^ 1] = py[u];
+    }
+  }
+  if ((n & 1) && threadIdx.x == 0) tbuf[tsw(n - 1)] = odd;
+  if (sift) {
     if (threadIdx.x == 0) cont_exit = 0;
     __syncthreads();
     double num = 0.0, den = 0.0;  // the tile's sums for the SD criterion
